@@ -1,0 +1,261 @@
+"""ctypes binding of the FP64 CPU oracle (``oracle/lbm_oracle.cpp``).
+
+TEST INFRASTRUCTURE. Only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. The GPU
+library and its Python binding never import it, and it never imports them.
+
+Parity status of each oracle function (what pins it, see tests/):
+  stencil, weights            golden table typed from Section 2 + isotropy
+  feq_incomp (Eq. 2)          closed-form moments
+  mrt_collide (Eq. 12)        conservation, fixed point, all-rates-1 and BGK
+                              reductions, basis orthogonality (d'Humieres)
+  smagorinsky_tau (Eqs.16-21) Chapman-Enskog strain state, quadratic identity
+  central_moments (Eq. 15)    Table 2 printed raw->central polynomials
+  fclb_collide                conservation, product-equilibrium fixed point,
+                              omega = 1 map, moment self-consistency, symmetry
+  run (streaming + BCs)       exact first-moment transport law, shear-wave
+                              and Taylor-Green decay rates, Couette profile
+  splitmix64                  published test vector
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.cpp")
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+MRT19, FCLB27 = 1, 2
+BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
+PERIODIC, WALL, INLET, OUTFLOW = 0, 1, 2, 3
+
+DHUMIERES_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
+TABLE1_RATES = (1.0, 1.0, 1.0, 1.0)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["g++", "-std=c++17", "-O3", "-fopenmp", "-ffp-contract=off",
+               "-shared", "-fPIC", "-o", LIB + ".tmp", SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("nu", ctypes.c_double),
+        ("cs_smag", ctypes.c_double),
+        ("mrt_basis", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("rates", ctypes.c_double * 8),
+        ("face_type", ctypes.c_int32 * 6),
+        ("face_u", (ctypes.c_double * 3) * 6),
+        ("inlet_u", ctypes.POINTER(ctypes.c_double)),
+        ("inlet_mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("inlet_amp", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("origin", ctypes.c_int32 * 3),
+        ("inlet_na", ctypes.c_int32), ("inlet_nb", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        pp = ctypes.POINTER(Params)
+        L.orc_stencil.argtypes = [ctypes.c_int, ip, dp, ip]
+        L.orc_feq_incomp.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_feq_product.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_mrt_basis.argtypes = [ctypes.c_int, dp]
+        L.orc_smagorinsky_tau.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_smagorinsky_tau.restype = ctypes.c_double
+        L.orc_mrt_collide.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                      dp, dp, dp]
+        L.orc_central_moments.argtypes = [dp, dp, dp, dp]
+        L.orc_fclb_collide.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_inlet_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int]
+        L.orc_inlet_uniform.restype = ctypes.c_double
+        L.orc_collide_lattice.argtypes = [pp, dp, dp]
+        L.orc_run.argtypes = [pp, dp, ctypes.c_int64, ctypes.c_int64]
+        L.orc_macroscopic.argtypes = [pp, dp, dp, dp]
+        L.orc_init_equilibrium.argtypes = [pp, dp, dp, dp]
+        L.orc_reduce.argtypes = [pp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def q_of(model):
+    return 19 if model == MRT19 else 27
+
+
+def stencil(Q):
+    e = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q)
+    opp = np.zeros(Q, dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = lib().orc_stencil(Q, e.ctypes.data_as(ip), _dp(w), opp.ctypes.data_as(ip))
+    assert rc == 0
+    return e, w, opp
+
+
+def feq_incomp(Q, drho, u):
+    out = np.zeros(Q)
+    lib().orc_feq_incomp(Q, float(drho), _dp(_f64(u)), _dp(out))
+    return out
+
+
+def feq_product(rho, u):
+    out = np.zeros(27)
+    lib().orc_feq_product(float(rho), _dp(_f64(u)), _dp(out))
+    return out
+
+
+def mrt_basis(basis):
+    M = np.zeros((19, 19))
+    lib().orc_mrt_basis(basis, _dp(M))
+    return M
+
+
+def smagorinsky_tau(f19, tau0, cs):
+    Q = np.zeros(1)
+    t = lib().orc_smagorinsky_tau(_dp(_f64(f19)), tau0, cs, _dp(Q))
+    return t, float(Q[0])
+
+
+def mrt_collide(f19, tau0, cs=0.0, basis=BASIS_TABLE1, rates=None):
+    if rates is None:
+        rates = TABLE1_RATES if basis == BASIS_TABLE1 else DHUMIERES_RATES
+    r = np.zeros(8)
+    r[:len(rates)] = rates
+    out = np.zeros(19)
+    tau = np.zeros(1)
+    lib().orc_mrt_collide(_dp(_f64(f19)), tau0, cs, basis, _dp(r), _dp(out), _dp(tau))
+    return out, float(tau[0])
+
+
+def central_moments(F):
+    rho = np.zeros(1)
+    u = np.zeros(3)
+    k = np.zeros(27)
+    lib().orc_central_moments(_dp(_f64(F)), _dp(rho), _dp(u), _dp(k))
+    return float(rho[0]), u, k.reshape(3, 3, 3)
+
+
+def fclb_collide(f27, omega):
+    out = np.zeros(27)
+    lib().orc_fclb_collide(_dp(_f64(f27)), float(omega), _dp(out))
+    return out
+
+
+def splitmix64(state):
+    return int(lib().orc_splitmix64(ctypes.c_uint64(state & 0xFFFFFFFFFFFFFFFF)))
+
+
+def inlet_uniform(seed, t, a, b, c):
+    return float(lib().orc_inlet_uniform(seed, t, a, b, c))
+
+
+class Lattice:
+    """Configuration of an oracle lattice (or window of one).
+
+    faces: six of PERIODIC/WALL/INLET/OUTFLOW for x-, x+, y-, y+, z-, z+.
+    """
+
+    def __init__(self, model, nx, ny, nz, nu, cs_smag=0.0, basis=BASIS_TABLE1,
+                 rates=None, faces=(PERIODIC,) * 6, face_u=None, inlet_u=None,
+                 inlet_mask=None, inlet_amp=0.0, seed=0, origin=(0, 0, 0),
+                 inlet_extent=None):
+        p = Params()
+        p.model = model
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.nu = nu
+        p.cs_smag = cs_smag
+        p.mrt_basis = basis
+        if rates is None:
+            rates = TABLE1_RATES if basis == BASIS_TABLE1 else DHUMIERES_RATES
+        for k, v in enumerate(rates):
+            p.rates[k] = v
+        for k in range(6):
+            p.face_type[k] = faces[k]
+        if face_u is not None:
+            for k in range(6):
+                for c in range(3):
+                    p.face_u[k][c] = face_u[k][c]
+        self._keep = []
+        if inlet_u is not None:
+            iu = _f64(inlet_u)
+            self._keep.append(iu)
+            p.inlet_u = _dp(iu)
+            p.inlet_nb, p.inlet_na = iu.shape[1], iu.shape[2]
+        if inlet_extent is not None:
+            p.inlet_na, p.inlet_nb = inlet_extent
+        if inlet_mask is not None:
+            im = np.ascontiguousarray(inlet_mask, dtype=np.uint8)
+            self._keep.append(im)
+            p.inlet_mask = im.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.inlet_amp = inlet_amp
+        p.seed = seed
+        for k in range(3):
+            p.origin[k] = origin[k]
+        self.p = p
+        self.model = model
+        self.Q = q_of(model)
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+
+    def run(self, f, t0, nsteps):
+        f = _f64(f).copy()
+        assert f.shape == (self.Q,) + self.shape
+        lib().orc_run(ctypes.byref(self.p), _dp(f), int(t0), int(nsteps))
+        return f
+
+    def collide(self, f):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().orc_collide_lattice(ctypes.byref(self.p), _dp(f), _dp(out))
+        return out
+
+    def macroscopic(self, f):
+        f = _f64(f)
+        drho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        lib().orc_macroscopic(ctypes.byref(self.p), _dp(f), _dp(drho), _dp(u))
+        return drho, u
+
+    def init_equilibrium(self, drho, u):
+        f = np.zeros((self.Q,) + self.shape)
+        lib().orc_init_equilibrium(ctypes.byref(self.p), _dp(_f64(drho)), _dp(_f64(u)),
+                                   _dp(f))
+        return f
+
+    def reduce(self, f):
+        out = np.zeros(5)
+        lib().orc_reduce(ctypes.byref(self.p), _dp(_f64(f)), _dp(out))
+        return out

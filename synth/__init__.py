@@ -1,0 +1,113 @@
+"""Seeded synthetic inputs shared by the HIP path and the FP64 oracle.
+
+This module only draws numbers and lays out fields. It holds none of the
+lattice Boltzmann arithmetic: no equilibria, moments, collisions or
+streaming. Each side turns these fields into populations with its own code.
+
+Layouts
+-------
+* scalar field: float64 array of shape (nz, ny, nx), x fastest.
+* vector field: float64 array of shape (3, nz, ny, nx).
+* populations:  float64 array of shape (Q, nz, ny, nx), the deviations
+  f_i - w_i, population index in the order of the velocity tables of
+  Section 2 of the paper.
+* inlet face fields: index (b, a) over the two tangential axes of the face
+  in increasing axis order (for a z face: shape (ny, nx)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def random_populations(q: int, shape, amp: float = 1e-2, seed: int = 0):
+    """Uniform noise in [-amp, amp] for every population deviation.
+
+    The state is far from equilibrium, which both collisions accept; it
+    exercises every term of a collision at once.
+    """
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    return rng.uniform(-amp, amp, size=(q, nz, ny, nx))
+
+
+def taylor_green(n, u0: float):
+    """Taylor-Green vortex on an n^3 periodic box (x = 2 pi i / n).
+
+    u = u0 sin x cos y cos z, v = -u0 cos x sin y cos z, w = 0 and the
+    incompressible pressure p' = u0^2/16 (cos 2x + cos 2y)(cos 2z + 2);
+    returns (drho, u) with drho = 3 p' (lattice sound speed squared 1/3).
+    """
+    if np.isscalar(n):
+        nx = ny = nz = int(n)
+    else:
+        nx, ny, nz = (int(v) for v in n)
+    x = 2.0 * np.pi * np.arange(nx) / nx
+    y = 2.0 * np.pi * np.arange(ny) / ny
+    z = 2.0 * np.pi * np.arange(nz) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u = np.empty((3, nz, ny, nx))
+    u[0] = u0 * np.sin(X) * np.cos(Y) * np.cos(Z)
+    u[1] = -u0 * np.cos(X) * np.sin(Y) * np.cos(Z)
+    u[2] = 0.0
+    p = (u0 * u0 / 16.0) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    return 3.0 * p, u
+
+
+def shear_wave(nx, ny, nz, u0: float, axis_u: int = 0, axis_k: int = 1, m: int = 1):
+    """u_{axis_u} = u0 sin(2 pi m x_{axis_k} / n_{axis_k}), drho = 0."""
+    n = (nx, ny, nz)
+    coords = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = {0: coords[2], 1: coords[1], 2: coords[0]}[axis_k]
+    u = np.zeros((3, nz, ny, nx))
+    u[axis_u] = u0 * np.sin(2.0 * np.pi * m * c / n[axis_k])
+    return np.zeros((nz, ny, nx)), u
+
+
+def jet_inlet(na: int, nb: int, diameter: float, u_jet: float, u_coflow: float,
+              axis: int = 2):
+    """Top-hat round-jet inlet on a face of na x nb nodes.
+
+    Nodes whose centre lies within diameter/2 of the face centre
+    ((na-1)/2, (nb-1)/2) get u_jet along the face normal ``axis``, the rest
+    the co-flow u_coflow.  Returns (u_face[3, nb, na], disk_mask[nb, na]).
+    """
+    a = np.arange(na) - 0.5 * (na - 1)
+    b = np.arange(nb) - 0.5 * (nb - 1)
+    B, A = np.meshgrid(b, a, indexing="ij")
+    mask = (A * A + B * B) <= (0.5 * diameter) ** 2
+    u = np.zeros((3, nb, na))
+    u[axis] = np.where(mask, u_jet, u_coflow)
+    return u, mask.astype(np.uint8)
+
+
+def uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.0), drho: float = 0.0):
+    f = np.full((nz, ny, nx), float(drho))
+    uu = np.empty((3, nz, ny, nx))
+    for c in range(3):
+        uu[c] = u[c]
+    return f, uu
+
+
+def gaussian_field(shape, sigma: float, seed: int):
+    """Seeded N(0, sigma^2) field (numpy PCG64 + its standard normal)."""
+    rng = np.random.default_rng(seed)
+    return sigma * rng.standard_normal(size=shape)
+
+
+def smooth_random_fields(nx, ny, nz, u_amp: float, rho_amp: float, seed: int,
+                         modes: int = 3):
+    """A smooth periodic (drho, u) field: a few random low Fourier modes."""
+    rng = np.random.default_rng(seed)
+    Z, Y, X = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny,
+                          np.arange(nx) / nx, indexing="ij")
+    def field(amp):
+        out = np.zeros((nz, ny, nx))
+        for _ in range(modes):
+            k = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            a = rng.uniform(-1, 1)
+            out += a * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        return amp * out / modes
+    drho = field(rho_amp)
+    u = np.stack([field(u_amp), field(u_amp), field(u_amp)])
+    return drho, u
