@@ -1,0 +1,214 @@
+"""Throughput benchmark: MLUPS and fraction of the MI355X HBM roofline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-others] [--workload NAME]
+
+Default workload (one step = one fused collide-and-stream update of every
+node, boundary rules included): the round jet, D3Q27 FCLB on a uniform
+256 x 256 x 512 lattice, FP32 deviation storage, D = 32 top-hat inlet at
+u = 0.05 with a seeded 1 % per-step perturbation, co-flow 0.002 on moving
+side walls, zero-gradient outflow, nu = 1e-4. Inputs are synthetic and
+resident in HBM before timing starts; K steps are timed with HIP events on
+the stream the kernels run on, bracketed by device synchronisation.
+
+Prints one JSON line. ``roofline`` prices the step kernel's algorithmic
+traffic, 2 Q b bytes per node update (Q populations of b bytes read and
+written once), against the 8 TB/s HBM peak. ``others`` holds the same
+measurement for the other model/storage combinations. ``cpu_baseline`` is
+the FP64 oracle timed on the host cores on a cut-down of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % of HBM roofline, D3Q19-MRT and D3Q27-FCLB, FP32/FP16 vs FP64"
+BYTES = {"f64": 8, "f32": 4, "f16": 2}
+# traffic measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE for the default
+# workload's step kernel, in bytes per launch (None until profiled again).
+MEASURED_TRAFFIC = None
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--workload", default="jet256-fclb-f32")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-others", action="store_true")
+    p.add_argument("--other-steps", type=int, default=50)
+    return p.parse_args()
+
+
+def workload(name):
+    """(model, storage, shape, kind) from a name like jet256-fclb-f32."""
+    kind, model, storage = name.split("-")
+    shapes = {"jet256": (256, 256, 512), "tgv256": (256, 256, 512), "tgv128": (128, 128, 128),
+              "jet128": (128, 128, 256)}
+    return model, storage, shapes[kind], kind
+
+
+def make_lattice(name, P, torch, synth):
+    import numpy as np
+    model, storage, shape, kind = workload(name)
+    nx, ny, nz = shape
+    if kind.startswith("jet"):
+        nu, cs = 1e-4, 0.1
+        lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs)
+        diam = 32.0 if nx >= 256 else 16.0
+        iu, im = synth.jet_inlet(nx, ny, diam, 0.05, 0.002)
+        fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
+        faces = [P.WALL, P.WALL, P.WALL, P.WALL, P.INLET, P.OUTFLOW]
+        lat.set_boundaries(faces, face_u=fu, inlet_u=torch.from_numpy(iu),
+                           inlet_mask=torch.from_numpy(im), inlet_amp=0.01 * 0.05, seed=12060389)
+        d, u = synth.uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.002), dtype=np.float32)
+        desc = {"workload": "round jet %dx%dx%d, D=%d inlet u=0.05 +1%% seeded perturbation, "
+                            "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4"
+                            % (nx, ny, nz, int(diam)),
+                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "cs_smag": cs if model == "mrt" else None}
+    else:
+        nu, cs = (4.0e-3 if nx == 128 else 1e-3), 0.1
+        lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs)
+        d, u = synth.taylor_green((nx, ny, nz), 0.05)
+        d, u = d.astype(np.float32), u.astype(np.float32)
+        desc = {"workload": "periodic Taylor-Green %dx%dx%d, u0=0.05, nu=%g" % (nx, ny, nz, nu),
+                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "cs_smag": cs if model == "mrt" else None}
+    lat.init_equilibrium(torch.from_numpy(d), torch.from_numpy(u))
+    del d, u
+    return lat, desc
+
+
+def time_steps(lat, torch, steps, warmup):
+    stream = torch.cuda.current_stream()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def measure(name, P, torch, synth, steps, warmup):
+    lat, desc = make_lattice(name, P, torch, synth)
+    ms = time_steps(lat, torch, steps, warmup)
+    red = lat.reduce(check=False)
+    model, storage, shape, _ = workload(name)
+    q = 27 if model == "fclb" else 19
+    n = shape[0] * shape[1] * shape[2]
+    alg_bytes = 2 * q * BYTES[storage] * n
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    out = {"name": name, "mlups": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+           "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
+           "bytes_per_lup": 2 * q * BYTES[storage], "finite": all(map(lambda v: v == v, red)),
+           "config": desc}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_bandwidth(P, torch, nbytes=4 << 30, reps=10):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    P.stream_copy(b, a, nbytes)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.stream_copy(b, a, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(model_name, target_s=15.0):
+    """The FP64 oracle on the host cores, on a 64^3 cut-down of the jet."""
+    if "OMP_NUM_THREADS" not in os.environ:
+        os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
+    cores = int(os.environ["OMP_NUM_THREADS"])
+    import oracle
+    import synth
+    model = oracle.FCLB27 if model_name == "fclb" else oracle.MRT19
+    n = 64
+    iu, im = synth.jet_inlet(n, n, 8.0, 0.05, 0.002)
+    fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
+    lat = oracle.Lattice(model, n, n, n, nu=1e-4, cs_smag=0.1,
+                         faces=[oracle.WALL] * 4 + [oracle.INLET, oracle.OUTFLOW], face_u=fu,
+                         inlet_u=iu, inlet_mask=im, inlet_amp=5e-4, seed=12060389)
+    d, u = synth.uniform_fields(n, n, n, u=(0.0, 0.0, 0.002))
+    f = lat.init_equilibrium(d, u)
+    t0 = time.perf_counter()
+    f = lat.run(f, 0, 1)
+    per = time.perf_counter() - t0
+    steps = max(1, min(200, int(target_s / max(per, 1e-3))))
+    t0 = time.perf_counter()
+    lat.run(f, 1, steps)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": "FP64 oracle, %s, jet cut-down %d^3 (D=8), %d steps in %.1f s"
+                      % (model_name, n, steps, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1206_0389_amd as P
+    import synth
+
+    torch.cuda.set_device(0)
+    print("bench: workload", args.workload, flush=True)
+    main_res = measure(args.workload, P, torch, synth, args.steps, args.warmup)
+    print("bench: main done %.1f MLUPS" % main_res["mlups"], flush=True)
+    others = []
+    if not args.no_others:
+        for name in ["jet256-fclb-f16", "jet256-fclb-f64", "tgv256-mrt-f32", "tgv256-mrt-f16",
+                     "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32"]:
+            if name == args.workload:
+                continue
+            r = measure(name, P, torch, synth, args.other_steps, 10)
+            print("bench: %s %.1f MLUPS" % (name, r["mlups"]), flush=True)
+            others.append(r)
+    copy_gbs = copy_bandwidth(P, torch)
+    model, storage, shape, _ = workload(args.workload)
+    alg_per_launch = main_res["bytes_per_lup"] * shape[0] * shape[1] * shape[2]
+    roof = {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": main_res["achieved_GBs"] / HBM_PEAK_GBS,
+            "traffic": MEASURED_TRAFFIC,
+            "kernel": "step_kernel<%s,%s>" % (model, storage),
+            "algorithmic_bytes_per_launch": alg_per_launch,
+            "copy_probe_GBs": copy_gbs,
+            "frac_of_copy_probe": main_res["achieved_GBs"] / copy_gbs}
+    line = {"metric": METRIC, "value": main_res["mlups"], "unit": "MLUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": storage, "data": "synthetic", "config": main_res["config"],
+            "roofline": roof, "others": others}
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", flush=True)
+        line["cpu_baseline"] = cpu_baseline(model)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library.
+ *
+ * The library advances the fused collide-and-stream update of the two
+ * collision models compared by Geller, Uphoff & Krafczyk, "Turbulent jet
+ * computations based on MRT and Cascaded Lattice Boltzmann models"
+ * (arXiv:1206.0389):
+ *   - D3Q19 MRT with a Smagorinsky eddy viscosity (Section 2, Eq. (12),
+ *     Table 1, Eqs. (16)-(21));
+ *   - D3Q27 factorized cascaded LB, FCLB (Section 2, Eqs. (14)-(15),
+ *     Table 2), with no explicit turbulence model.
+ * Populations live in device memory as deviations f_i - w_i from the rest
+ * equilibrium, stored in FP64, FP32 or FP16; arithmetic runs in FP64 for
+ * FP64 storage and in FP32 otherwise; global sums always run in FP64.
+ *
+ * Conventions shared by every call
+ *   - Population order at the ABI is the order of the velocity tables of
+ *     Section 2 (D3Q27 indices 0..18 coincide with D3Q19).
+ *   - Field layout: x fastest, then y, then z. Scalar fields have nx*ny*nz
+ *     entries; vector fields are [3][nz][ny][nx]; population fields are
+ *     [Q][nz][ny][nx].
+ *   - All pointers marked "device" must be device memory of the current HIP
+ *     device (for example a torch tensor's data pointer). The caller owns
+ *     every buffer; the library never allocates device memory, it only
+ *     uses the block handed over by lbm_bind_memory.
+ *   - Calls are asynchronous on the stream given in lbm_config (or set by
+ *     lbm_set_stream), except where a call is documented as blocking.
+ *   - Every call returns LBM_OK (0) or a negative status. Arguments are
+ *     validated before anything is launched; a failing call changes
+ *     nothing. lbm_strerror() gives a message; for LBM_EHIP it returns the
+ *     HIP error text of the last failure on the calling thread.
+ *   - A lattice handle must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)      /* bad argument or configuration            */
+#define LBM_ENOMEM (-2)      /* bound block smaller than required         */
+#define LBM_EUNBOUND (-3)    /* no device memory bound yet                */
+#define LBM_EHIP (-4)        /* a HIP call or launch failed               */
+#define LBM_ENONFINITE (-5)  /* a global sum is NaN or infinite           */
+#define LBM_ESTATE (-6)      /* call not valid in the lattice's state     */
+
+/* ---- enumerations ----------------------------------------------------- */
+#define LBM_D3Q19_MRT_LES 1  /* Eq. (12) + Eqs. (16)-(21), incompressible */
+#define LBM_D3Q27_FCLB 2     /* Table 2 central moments, compressible     */
+
+#define LBM_F64 1            /* population storage types                  */
+#define LBM_F32 2
+#define LBM_F16 3
+
+#define LBM_DTYPE_F64 1      /* element type of caller field buffers      */
+#define LBM_DTYPE_F32 2
+
+#define LBM_BASIS_TABLE1 0   /* MRT moments grouped as in Table 1         */
+#define LBM_BASIS_DHUMIERES 1 /* d'Humieres et al. (2002) orthogonal basis */
+
+#define LBM_PERIODIC 0       /* face types                                */
+#define LBM_WALL 1           /* halfway bounce-back, optional velocity    */
+#define LBM_INLET 2          /* halfway bounce-back with inlet velocity   */
+#define LBM_OUTFLOW 3        /* zero-gradient: ghost copy of last plane   */
+
+#define LBM_RHO_FULL 0       /* lbm_get_macroscopic: write rho            */
+#define LBM_RHO_DEVIATION 1  /* ... write rho - 1                         */
+
+typedef struct lbm_lattice lbm_lattice;
+
+/*
+ * Lattice configuration (copied at create; no pointer is kept).
+ *   model      LBM_D3Q19_MRT_LES or LBM_D3Q27_FCLB.
+ *   storage    LBM_F64, LBM_F32 or LBM_F16 (population deviations).
+ *   nx,ny,nz   lattice nodes, each >= 1; nx*ny*nz < 2^31.
+ *   nu         lattice kinematic viscosity, > 0; the molecular relaxation
+ *              time is tau0 = 3 nu + 1/2 (Eq. (13), c = 1), so omega =
+ *              1/tau0 must be < 2.
+ *   cs_smag    Smagorinsky constant C_S >= 0 (MRT only; 0 switches the
+ *              eddy viscosity off). Eq. (20) gives tau_total.
+ *   mrt_basis  LBM_BASIS_TABLE1 (the paper's choice) or LBM_BASIS_DHUMIERES.
+ *   rates      non-shear relaxation rates, used when use_default_rates = 0:
+ *              TABLE1: s2 (trace), s3, s4, s7 (all 4th-order rows);
+ *              DHUMIERES: s_e, s_eps, s_q, s_pi, s_m.
+ *              Defaults: TABLE1 all 1 (Section 2: s_i = 1 for i != 1);
+ *              DHUMIERES 1.19, 1.4, 1.2, 1.4, 1.98.
+ *              The FCLB model ignores them (all non-shear rates are 1).
+ *   stream     hipStream_t for every asynchronous call (0 = null stream).
+ */
+typedef struct lbm_config {
+  int32_t model;
+  int32_t storage;
+  int32_t nx, ny, nz;
+  int32_t mrt_basis;
+  double nu;
+  double cs_smag;
+  double rates[8];
+  int32_t use_default_rates;
+  int32_t reserved0;
+  void* stream;
+} lbm_config;
+
+/*
+ * Boundary description, one entry per face in the order
+ * x-, x+, y-, y+, z-, z+ (the "-" face holds coordinate 0).
+ *   face_type  LBM_PERIODIC | LBM_WALL | LBM_INLET | LBM_OUTFLOW. Opposite
+ *              faces must both be periodic or both non-periodic.
+ *              At most one LBM_INLET face and one LBM_OUTFLOW face.
+ *   face_u     wall velocity of LBM_WALL faces (lattice units).
+ *   inlet_u    device, velocity on the inlet face, [3][nb][na] of
+ *              inlet_dtype, where (a, b) are the face's two tangential
+ *              coordinates in increasing axis order (z face: a = x, b = y).
+ *   inlet_mask device uint8 [nb][na] or NULL; where 1, each component gets
+ *              a seeded uniform perturbation inlet_amp * (2U - 1) drawn
+ *              per time step from SplitMix64 (see DESIGN notes).
+ *   seed       perturbation seed.
+ * The streaming rule at a face (population i arriving from outside at
+ * node x, post-collision values f*):
+ *   WALL, INLET  f_i(x) = f*_opp(i)(x) + 6 w_i (e_i . u)   (u = wall or inlet)
+ *   OUTFLOW      f_i(x) = f*_i(x - e_i with the face-normal coordinate kept)
+ * Where a source lies beyond several faces, WALL wins over INLET over
+ * OUTFLOW. The inlet buffers must stay valid while the lattice steps.
+ */
+typedef struct lbm_boundaries {
+  int32_t face_type[6];
+  double face_u[6][3];
+  const void* inlet_u;
+  int32_t inlet_dtype;
+  int32_t reserved0;
+  const uint8_t* inlet_mask;
+  double inlet_amp;
+  uint64_t seed;
+} lbm_boundaries;
+
+/* Validate cfg and create a handle (host memory only). On error *out is
+ * left untouched. */
+int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out);
+
+/* Bytes of device memory the lattice needs (populations, the outflow ghost
+ * plane, reduction partials), 256-byte aligned. */
+int lbm_required_bytes(const lbm_lattice* lat, size_t* bytes);
+
+/* Hand over a device block of at least lbm_required_bytes bytes, 256-byte
+ * aligned. It must outlive the lattice (or the next bind). Resets the
+ * time to 0 and the populations' contents are undefined until
+ * lbm_init_equilibrium or lbm_set_populations. */
+int lbm_bind_memory(lbm_lattice* lat, void* dev, size_t bytes);
+
+/* Set the boundary description (default: all periodic). Host struct; the
+ * device buffers it names are used, not copied. Only valid at an even
+ * number of steps since the last set/init/load (LBM_ESTATE otherwise). */
+int lbm_set_boundaries(lbm_lattice* lat, const lbm_boundaries* bc);
+
+/* Populations := the model's equilibrium for fields drho (device, rho - 1,
+ * nx*ny*nz) and u (device, [3][N]) of dtype LBM_DTYPE_F64/F32: Eq. (2) for
+ * MRT, the product equilibrium with the Table 2 central moments for FCLB.
+ * Sets the time to t0. */
+int lbm_init_equilibrium(lbm_lattice* lat, const void* drho, const void* u,
+                         int dtype, int64_t t0);
+
+/* Populations := f (device, [Q][N] deviations f_i - w_i, ABI order, dtype
+ * LBM_DTYPE_F64/F32), rounded to the storage type. Sets the time to t0. */
+int lbm_set_populations(lbm_lattice* lat, const void* f, int dtype, int64_t t0);
+
+/* f (device, [Q][N]) := current pre-collision populations (deviations, ABI
+ * order), whatever the in-place streaming parity. */
+int lbm_get_populations(lbm_lattice* lat, void* f, int dtype);
+
+/* Advance n >= 0 collide-and-stream steps (asynchronous). */
+int lbm_step(lbm_lattice* lat, int64_t n);
+
+/* rho (device, N) and u (device, [3][N]) of the current state: MRT
+ * Eqs. (3)-(5) with rho0 = 1 (u = j), FCLB Eqs. (6)-(8) (u = j / rho).
+ * rho_mode LBM_RHO_FULL writes rho, LBM_RHO_DEVIATION writes rho - 1.
+ * Either pointer may be NULL. */
+int lbm_get_macroscopic(lbm_lattice* lat, void* rho, void* u, int dtype,
+                        int rho_mode);
+
+/* Blocking. FP64 sums over all nodes in a fixed order (deterministic):
+ * out[0] = sum (rho - 1), out[1..3] = sum j, out[4] = sum |j|^2 / (2 rho)
+ * (rho = 1 for MRT). Returns LBM_ENONFINITE if any sum is not finite
+ * (out is still written). */
+int lbm_reduce(lbm_lattice* lat, double out[5]);
+
+/* Size in bytes of a state snapshot (populations + outflow ghost plane). */
+int lbm_state_bytes(const lbm_lattice* lat, size_t* bytes);
+
+/* Copy the state into / out of a device buffer of lbm_state_bytes bytes
+ * (asynchronous device-to-device copy). save returns the time and the
+ * in-place streaming parity; load takes them back. */
+int lbm_save_state(lbm_lattice* lat, void* dev, size_t bytes, int64_t* t,
+                   int32_t* parity);
+int lbm_load_state(lbm_lattice* lat, const void* dev, size_t bytes, int64_t t,
+                   int32_t parity);
+
+/* Current time (number of steps since time 0 as set by init/set/load). */
+int lbm_get_time(const lbm_lattice* lat, int64_t* t);
+
+/* Replace the stream used by later asynchronous calls. */
+int lbm_set_stream(lbm_lattice* lat, void* stream);
+
+/* Destroy the handle (device memory stays with the caller). NULL is OK. */
+int lbm_destroy(lbm_lattice* lat);
+
+/* Static message for a status code; for LBM_EHIP the HIP error text of the
+ * last failure on this thread. */
+const char* lbm_strerror(int status);
+
+/* Device-to-device copy of n bytes through a plain vectorised kernel on the
+ * given stream: the achievable-bandwidth probe used for roofline scaling.
+ * Both buffers device, 16-byte aligned, non-overlapping. */
+int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

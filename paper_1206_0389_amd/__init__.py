@@ -1,0 +1,364 @@
+"""Python binding of the MI355X lattice Boltzmann library (``liblbm.so``).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+kernels of ``csrc/``. PyTorch supplies device memory and the HIP stream.
+The module-level functions carry the C ABI names of ``include/lbm.h``
+(without the ``lbm_`` prefix); :class:`Lattice` bundles them with the
+torch-owned device block.
+
+The library must be built (``python -m paper_1206_0389_amd.build``); there
+is no CPU fallback and importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+OK, EINVAL, ENOMEM, EUNBOUND, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+D3Q19_MRT_LES, D3Q27_FCLB = 1, 2
+F64, F32, F16 = 1, 2, 3
+DTYPE_F64, DTYPE_F32 = 1, 2
+BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
+PERIODIC, WALL, INLET, OUTFLOW = 0, 1, 2, 3
+RHO_FULL, RHO_DEVIATION = 0, 1
+
+STORAGE = {"f64": F64, "f32": F32, "f16": F16}
+MODEL = {"mrt": D3Q19_MRT_LES, "fclb": D3Q27_FCLB}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, strerror(status), status))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("mrt_basis", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("cs_smag", ctypes.c_double),
+        ("rates", ctypes.c_double * 8),
+        ("use_default_rates", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class Boundaries(ctypes.Structure):
+    _fields_ = [
+        ("face_type", ctypes.c_int32 * 6),
+        ("face_u", (ctypes.c_double * 3) * 6),
+        ("inlet_u", ctypes.c_void_p),
+        ("inlet_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("inlet_mask", ctypes.c_void_p),
+        ("inlet_amp", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+_SIGS = {
+    "lbm_create_lattice": [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)],
+    "lbm_required_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lbm_bind_memory": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "lbm_set_boundaries": [ctypes.c_void_p, ctypes.POINTER(Boundaries)],
+    "lbm_init_equilibrium": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_int, ctypes.c_int64],
+    "lbm_set_populations": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64],
+    "lbm_get_populations": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "lbm_step": [ctypes.c_void_p, ctypes.c_int64],
+    "lbm_get_macroscopic": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                            ctypes.c_int],
+    "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
+    "lbm_state_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lbm_save_state": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)],
+    "lbm_load_state": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64,
+                       ctypes.c_int32],
+    "lbm_get_time": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "lbm_set_stream": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_destroy": [ctypes.c_void_p],
+    "lbm_strerror": [ctypes.c_int],
+    "lbm_stream_copy": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+}
+
+
+def lib():
+    """The loaded ``liblbm.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbm.so is not built: run python -m paper_1206_0389_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "lbm_strerror" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def strerror(status: int) -> str:
+    return lib().lbm_strerror(int(status)).decode()
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise LbmError(rc, where)
+    return rc
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return DTYPE_F64
+    if t.dtype == torch.float32:
+        return DTYPE_F32
+    raise TypeError("fields must be float64 or float32, got %s" % t.dtype)
+
+
+def _dev(t: torch.Tensor):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---- C ABI mirrors -------------------------------------------------------
+
+def create_lattice(cfg: Config):
+    h = ctypes.c_void_p()
+    _check(lib().lbm_create_lattice(ctypes.byref(cfg), ctypes.byref(h)), "lbm_create_lattice")
+    return h
+
+
+def required_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_required_bytes(h, ctypes.byref(n)), "lbm_required_bytes")
+    return n.value
+
+
+def bind_memory(h, block: torch.Tensor):
+    _check(lib().lbm_bind_memory(h, _dev(block), block.numel() * block.element_size()),
+           "lbm_bind_memory")
+
+
+def set_boundaries(h, bc: Boundaries):
+    _check(lib().lbm_set_boundaries(h, ctypes.byref(bc)), "lbm_set_boundaries")
+
+
+def init_equilibrium(h, drho: torch.Tensor, u: torch.Tensor, t0: int = 0):
+    code = _dtype_code(drho)
+    assert u.dtype == drho.dtype
+    _check(lib().lbm_init_equilibrium(h, _dev(drho), _dev(u), code, int(t0)),
+           "lbm_init_equilibrium")
+
+
+def set_populations(h, f: torch.Tensor, t0: int = 0):
+    _check(lib().lbm_set_populations(h, _dev(f), _dtype_code(f), int(t0)), "lbm_set_populations")
+
+
+def get_populations(h, f: torch.Tensor):
+    _check(lib().lbm_get_populations(h, _dev(f), _dtype_code(f)), "lbm_get_populations")
+
+
+def step(h, n: int):
+    _check(lib().lbm_step(h, int(n)), "lbm_step")
+
+
+def get_macroscopic(h, rho, u, rho_mode=RHO_DEVIATION):
+    ref = rho if rho is not None else u
+    code = _dtype_code(ref)
+    _check(lib().lbm_get_macroscopic(h, _dev(rho) if rho is not None else None,
+                                     _dev(u) if u is not None else None, code, int(rho_mode)),
+           "lbm_get_macroscopic")
+
+
+def reduce(h, check: bool = True):
+    out = (ctypes.c_double * 5)()
+    rc = lib().lbm_reduce(h, out)
+    if check:
+        _check(rc, "lbm_reduce")
+    return list(out), rc
+
+
+def state_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_state_bytes(h, ctypes.byref(n)), "lbm_state_bytes")
+    return n.value
+
+
+def save_state(h, buf: torch.Tensor):
+    t = ctypes.c_int64()
+    p = ctypes.c_int32()
+    _check(lib().lbm_save_state(h, _dev(buf), buf.numel() * buf.element_size(),
+                                ctypes.byref(t), ctypes.byref(p)), "lbm_save_state")
+    return t.value, p.value
+
+
+def load_state(h, buf: torch.Tensor, t: int, parity: int):
+    _check(lib().lbm_load_state(h, _dev(buf), buf.numel() * buf.element_size(), int(t),
+                                int(parity)), "lbm_load_state")
+
+
+def get_time(h) -> int:
+    t = ctypes.c_int64()
+    _check(lib().lbm_get_time(h, ctypes.byref(t)), "lbm_get_time")
+    return t.value
+
+
+def set_stream(h, stream=None):
+    _check(lib().lbm_set_stream(h, _stream_handle(stream)), "lbm_set_stream")
+
+
+def destroy(h):
+    lib().lbm_destroy(h)
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
+    _check(lib().lbm_stream_copy(_dev(dst), _dev(src), int(nbytes), _stream_handle(stream)),
+           "lbm_stream_copy")
+
+
+# ---- convenience wrapper ---------------------------------------------------
+
+def make_config(model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01, cs_smag=0.0,
+                mrt_basis=BASIS_TABLE1, rates=None, stream=None) -> Config:
+    c = Config()
+    c.model = MODEL[model] if isinstance(model, str) else int(model)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.nx, c.ny, c.nz = (int(v) for v in shape)
+    c.mrt_basis = int(mrt_basis)
+    c.nu = float(nu)
+    c.cs_smag = float(cs_smag)
+    if rates is None:
+        c.use_default_rates = 1
+    else:
+        c.use_default_rates = 0
+        for k, v in enumerate(rates):
+            c.rates[k] = float(v)
+    c.stream = _stream_handle(stream).value
+    return c
+
+
+class Lattice:
+    """A lattice whose device block is a torch tensor owned by this object.
+
+    shape = (nx, ny, nz); populations are indexed [Q][nz][ny][nx].
+    """
+
+    def __init__(self, model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01,
+                 cs_smag=0.0, mrt_basis=BASIS_TABLE1, rates=None, device="cuda", stream=None):
+        self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
+        self.h = create_lattice(self.cfg)
+        self.Q = 27 if self.cfg.model == D3Q27_FCLB else 19
+        self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
+        self.N = self.nx * self.ny * self.nz
+        self.device = torch.device(device)
+        nbytes = required_bytes(self.h)
+        self.block = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.block.data_ptr()) % 256
+        self._view = self.block[off:off + nbytes]
+        bind_memory(self.h, self._view)
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_destroy(h)
+            self.h = None
+
+    @property
+    def shape3(self):
+        return (self.nz, self.ny, self.nx)
+
+    def set_boundaries(self, faces, face_u=None, inlet_u=None, inlet_mask=None,
+                       inlet_amp=0.0, seed=0):
+        bc = Boundaries()
+        for k in range(6):
+            bc.face_type[k] = int(faces[k])
+        if face_u is not None:
+            for k in range(6):
+                for c in range(3):
+                    bc.face_u[k][c] = float(face_u[k][c])
+        keep = []
+        dims = (self.nx, self.ny, self.nz)
+        if inlet_u is not None:
+            d = [k for k in range(6) if int(faces[k]) == INLET]
+            if d:
+                ax = d[0] // 2
+                na = dims[1] if ax == 0 else dims[0]
+                nb = dims[1] if ax == 2 else dims[2]
+                if tuple(inlet_u.shape) != (3, nb, na):
+                    raise ValueError("inlet_u must have shape (3, %d, %d)" % (nb, na))
+                if inlet_mask is not None and tuple(inlet_mask.shape) != (nb, na):
+                    raise ValueError("inlet_mask must have shape (%d, %d)" % (nb, na))
+            iu = inlet_u.to(self.device).contiguous()
+            keep.append(iu)
+            bc.inlet_u = iu.data_ptr()
+            bc.inlet_dtype = _dtype_code(iu)
+        if inlet_mask is not None:
+            im = inlet_mask.to(device=self.device, dtype=torch.uint8).contiguous()
+            keep.append(im)
+            bc.inlet_mask = im.data_ptr()
+        bc.inlet_amp = float(inlet_amp)
+        bc.seed = int(seed)
+        set_boundaries(self.h, bc)
+        self._keep = keep
+
+    def _expect(self, t, shape, what):
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (what, shape, tuple(t.shape)))
+
+    def init_equilibrium(self, drho, u, t0=0):
+        drho = torch.as_tensor(drho).to(self.device).contiguous()
+        u = torch.as_tensor(u).to(device=self.device, dtype=drho.dtype).contiguous()
+        self._expect(drho, self.shape3, "drho")
+        self._expect(u, (3,) + self.shape3, "u")
+        init_equilibrium(self.h, drho, u, t0)
+
+    def set_populations(self, f, t0=0):
+        f = torch.as_tensor(f).to(self.device).contiguous()
+        self._expect(f, (self.Q,) + self.shape3, "f")
+        set_populations(self.h, f, t0)
+
+    def populations(self, dtype=torch.float64):
+        out = torch.empty((self.Q,) + self.shape3, dtype=dtype, device=self.device)
+        get_populations(self.h, out)
+        return out
+
+    def step(self, n=1):
+        step(self.h, n)
+
+    def macroscopic(self, dtype=torch.float64, rho_mode=RHO_DEVIATION):
+        rho = torch.empty(self.shape3, dtype=dtype, device=self.device)
+        u = torch.empty((3,) + self.shape3, dtype=dtype, device=self.device)
+        get_macroscopic(self.h, rho, u, rho_mode)
+        return rho, u
+
+    def reduce(self, check=True):
+        return reduce(self.h, check)[0]
+
+    def save_state(self):
+        buf = torch.empty(state_bytes(self.h), dtype=torch.uint8, device=self.device)
+        t, p = save_state(self.h, buf)
+        return buf, t, p
+
+    def load_state(self, buf, t, parity):
+        load_state(self.h, buf, t, parity)
+
+    @property
+    def time(self):
+        return get_time(self.h)

@@ -1,0 +1,524 @@
+// gfx950 kernels of the uniform lattice: fused collide-and-stream with
+// in-place AA-pattern streaming, boundary rules, initialisation, readouts
+// and FP64 reductions.
+//
+// Storage: one array per population, f[q][z][y][x] (x fastest), deviations
+// f_i - w_i in S = double, float or _Float16; arithmetic in double for
+// double storage and float otherwise. One thread per node, x-rows mapped
+// to consecutive lanes so every population access is a coalesced row
+// segment.
+//
+// AA pattern (two step kinds, one array):
+//   even step: node x reads slot i of its own node (= f_i(x, t)), collides
+//              and writes f*_i into slot opp(i) of its own node;
+//   odd step:  node x reads f_i(x, t) = f*_i(x - e_i, t-1) from slot opp(i)
+//              of node x - e_i, collides and writes f*_i into slot i of
+//              node x + e_i, which is where that node reads it next.
+// Every node reads and writes the same set of locations within a step, so
+// the update is race-free in place and moves Q values in and Q values out.
+//
+// Boundaries (left side of Eq. (1), pull form f_i(x) = f*_i(x - e_i)):
+// a population whose source lies beyond a non-periodic face is
+//   WALL/INLET: bounced back at the half-way point with the wall or inlet
+//               velocity, f_i(x) = f*_opp(i)(x) + 6 w_i e_i.u;
+//   OUTFLOW:    copied from the boundary plane, f_i(x) = f*_i(s), s = x - e_i
+//               with the face-normal coordinate kept (a ghost layer equal to
+//               the last plane: zero normal gradient).
+// In AA form the bounce-back reads/writes the node's own opposite slot. The
+// outflow copy needs f*_i(s) twice (normal streaming and the ghost), so even
+// steps also store the inward populations of the outflow plane in a small
+// ghost plane buffer that odd steps read; odd steps write the ghost copies
+// straight into the (otherwise unwritten) inward slots of the plane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fclb.h"
+#include "mrt.h"
+#include "stencil.h"
+
+namespace lbm {
+
+struct BcArgs {
+  uint32_t nonper;   // bits of non-periodic faces
+  uint32_t wall;     // bits of WALL faces
+  uint32_t inlet;    // bit of the INLET face (0 if none)
+  uint32_t outflow;  // bit of the OUTFLOW face (0 if none)
+  double face_u[6][3];
+  const void* inlet_u;
+  const uint8_t* inlet_mask;
+  double inlet_amp;
+  uint64_t seed;
+  int inlet_f64;
+  int inlet_axis;
+  int inlet_na, inlet_nb;
+  int out_axis;
+  int ghost_na;      // extent of the outflow face's first tangential axis
+  long long ghost_n; // nodes of the outflow face
+};
+
+struct LatArgs {
+  void* f;      // [Q][N]
+  void* ghost;  // [Q][ghost_n]
+  int nx, ny, nz;
+  long long N;
+  MrtParams mrt;
+  double omega;  // FCLB shear rate
+  BcArgs bc;
+};
+
+// ---------------------------------------------------------------- storage
+template <typename S>
+struct Compute {
+  using type = float;
+};
+template <>
+struct Compute<double> {
+  using type = double;
+};
+
+template <typename R, typename S>
+__device__ __forceinline__ R ld(const S* p) {
+  return R(*p);
+}
+template <typename S, typename R>
+__device__ __forceinline__ void st(S* p, R v) {
+  *p = S(v);
+}
+
+// ------------------------------------------------------------------ models
+template <int KIND>
+struct Model;
+template <>
+struct Model<0> {  // D3Q19 MRT-LES, Table 1 basis
+  static constexpr int Q = 19;
+  template <typename real>
+  __device__ static void collide(real (&f)[19], const LatArgs& a) {
+    mrt_collide<real, 0>(f, a.mrt);
+  }
+};
+template <>
+struct Model<1> {  // D3Q19 MRT-LES, d'Humieres basis
+  static constexpr int Q = 19;
+  template <typename real>
+  __device__ static void collide(real (&f)[19], const LatArgs& a) {
+    mrt_collide<real, 1>(f, a.mrt);
+  }
+};
+template <>
+struct Model<2> {  // D3Q27 FCLB
+  static constexpr int Q = 27;
+  template <typename real>
+  __device__ static void collide(real (&f)[27], const LatArgs& a) {
+    fclb_collide<real>(f, real(a.omega));
+  }
+};
+
+// Compile-time loop: calls fn(integral_constant<int, I>) for I = 0..N-1.
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(fn);
+  }
+}
+
+// --------------------------------------------------------------- geometry
+struct Node {
+  int x, y, z;
+  int self;
+  int xo[3], yo[3], zo[3];  // linear offsets of coordinate c-1, c, c+1
+  uint32_t atface;          // non-periodic faces the node lies on
+  __device__ __forceinline__ int at(int dx, int dy, int dz) const {
+    return zo[dz + 1] + yo[dy + 1] + xo[dx + 1];
+  }
+};
+
+__device__ __forceinline__ int wrap_dn(int c, int n) { return c == 0 ? n - 1 : c - 1; }
+__device__ __forceinline__ int wrap_up(int c, int n) { return c == n - 1 ? 0 : c + 1; }
+
+__device__ __forceinline__ Node make_node(const LatArgs& a, int x, int y, int z) {
+  Node n;
+  n.x = x;
+  n.y = y;
+  n.z = z;
+  const int sy = a.nx, sz = a.nx * a.ny;
+  n.xo[0] = wrap_dn(x, a.nx);
+  n.xo[1] = x;
+  n.xo[2] = wrap_up(x, a.nx);
+  n.yo[0] = wrap_dn(y, a.ny) * sy;
+  n.yo[1] = y * sy;
+  n.yo[2] = wrap_up(y, a.ny) * sy;
+  n.zo[0] = wrap_dn(z, a.nz) * sz;
+  n.zo[1] = z * sz;
+  n.zo[2] = wrap_up(z, a.nz) * sz;
+  n.self = n.zo[1] + n.yo[1] + x;
+  uint32_t m = 0;
+  m |= (x == 0) ? 1u : 0u;
+  m |= (x == a.nx - 1) ? 2u : 0u;
+  m |= (y == 0) ? 4u : 0u;
+  m |= (y == a.ny - 1) ? 8u : 0u;
+  m |= (z == 0) ? 16u : 0u;
+  m |= (z == a.nz - 1) ? 32u : 0u;
+  n.atface = m & a.bc.nonper;
+  return n;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): one output for a given state.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t s) {
+  uint64_t z = s + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Velocity of an inlet-face node at step t (base profile + seeded draw).
+__device__ __forceinline__ void inlet_velocity(const BcArgs& b, const Node& n, long long t,
+                                               double u[3]) {
+  const int coord[3] = {n.x, n.y, n.z};
+  const int A = coord[b.inlet_axis == 0 ? 1 : 0];
+  const int B = coord[b.inlet_axis == 2 ? 1 : 2];
+  const long idx = (long)B * b.inlet_na + A;
+  const long nf = (long)b.inlet_na * b.inlet_nb;
+  const bool pert = b.inlet_mask != nullptr && b.inlet_mask[idx] != 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double v = b.inlet_f64 ? ((const double*)b.inlet_u)[c * nf + idx]
+                           : (double)((const float*)b.inlet_u)[c * nf + idx];
+    if (pert) {
+      const uint64_t key = b.seed ^ (((uint64_t)t << 32) | ((uint64_t)c << 28) |
+                                     ((uint64_t)B << 14) | (uint64_t)A);
+      const double U = (double)(splitmix64(key) >> 11) * (1.0 / 9007199254740992.0);
+      v += b.inlet_amp * (2.0 * U - 1.0);
+    }
+    u[c] = v;
+  }
+}
+
+// Ghost-plane index of the node x - e_I with the outflow-normal coordinate
+// kept (I = 0 gives the node itself).
+template <int I>
+__device__ __forceinline__ long long ghost_index(const LatArgs& a, const Node& n) {
+  const int d = a.bc.out_axis;
+  const int sx = (d == 0 || cx(I) == 0) ? n.x : (cx(I) > 0 ? wrap_dn(n.x, a.nx) : wrap_up(n.x, a.nx));
+  const int sy = (d == 1 || cy(I) == 0) ? n.y : (cy(I) > 0 ? wrap_dn(n.y, a.ny) : wrap_up(n.y, a.ny));
+  const int sz = (d == 2 || cz(I) == 0) ? n.z : (cz(I) > 0 ? wrap_dn(n.z, a.nz) : wrap_up(n.z, a.nz));
+  const int A = d == 0 ? sy : sx;
+  const int B = d == 2 ? sy : sz;
+  return (long long)B * a.bc.ghost_na + A;
+}
+
+template <int I>
+__device__ __forceinline__ double face_dot(const BcArgs& b, uint32_t bits) {
+  const int face = __builtin_ctz(bits);
+  return cx(I) * b.face_u[face][0] + cy(I) * b.face_u[face][1] + cz(I) * b.face_u[face][2];
+}
+
+// f_I(x, t) at odd parity: the pull through the post-collision slots.
+// uin is the inlet velocity of the step whose streaming this completes.
+template <int Q, int I, typename real, typename S, bool BC>
+__device__ __forceinline__ real pull(const LatArgs& a, const S* F, const Node& n,
+                                     const double* uin) {
+  constexpr int IO = opposite<Q>(I);
+  const size_t N = (size_t)a.N;
+  if constexpr (BC) {
+    const uint32_t crossed = n.atface & pull_faces(I);
+    if (crossed) {
+      const real w6 = real(6.0 * weight<Q>(I));
+      if (crossed & a.bc.wall)
+        return ld<real>(F + (size_t)I * N + n.self) +
+               w6 * real(face_dot<I>(a.bc, crossed & a.bc.wall));
+      if (crossed & a.bc.inlet)
+        return ld<real>(F + (size_t)I * N + n.self) +
+               w6 * real(cx(I) * uin[0] + cy(I) * uin[1] + cz(I) * uin[2]);
+      const S* G = (const S*)a.ghost;
+      return ld<real>(G + (size_t)I * (size_t)a.bc.ghost_n + ghost_index<I>(a, n));
+    }
+  }
+  return ld<real>(F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I)));
+}
+
+// Store f*_I(x, t) at the end of an odd step (push to x + e_I), with the
+// bounce-back and outflow ghost rules. uin: inlet velocity of this step.
+template <int Q, int I, typename real, typename S, bool BC>
+__device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real v,
+                                     const double* uin) {
+  constexpr int IO = opposite<Q>(I);
+  const size_t N = (size_t)a.N;
+  if constexpr (BC) {
+    const uint32_t crossed = n.atface & push_faces(I);
+    const real w6 = real(6.0 * weight<Q>(I));
+    if (crossed) {
+      if (crossed & a.bc.wall)
+        st(F + (size_t)IO * N + n.self, v - w6 * real(face_dot<I>(a.bc, crossed & a.bc.wall)));
+      else if (crossed & a.bc.inlet)
+        st(F + (size_t)IO * N + n.self,
+           v - w6 * real(cx(I) * uin[0] + cy(I) * uin[1] + cz(I) * uin[2]));
+      // else: the population leaves through the outflow face
+    } else {
+      st(F + (size_t)I * N + n.at(cx(I), cy(I), cz(I)), v);
+    }
+    // ghost copy: a node on the outflow plane supplies the inward
+    // population I of its in-plane neighbour x + e_I (normal part removed)
+    if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0) {
+      const int d = a.bc.out_axis;
+      const int tx = d == 0 ? 0 : cx(I), ty = d == 1 ? 0 : cy(I), tz = d == 2 ? 0 : cz(I);
+      st(F + (size_t)I * N + n.at(tx, ty, tz), v);
+    }
+    return;
+  }
+  st(F + (size_t)I * N + n.at(cx(I), cy(I), cz(I)), v);
+}
+
+// --------------------------------------------------------------- kernels
+__device__ __forceinline__ bool node_coords(const LatArgs& a, int& x, int& y, int& z) {
+  x = blockIdx.x * blockDim.x + threadIdx.x;
+  y = blockIdx.y * blockDim.y + threadIdx.y;
+  z = blockIdx.z;
+  return x < a.nx && y < a.ny;
+}
+
+// One collide-and-stream step of the uniform lattice at time t.
+template <int KIND, typename S, bool ODD, bool BC>
+__global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t) {
+  using M = Model<KIND>;
+  using real = typename Compute<S>::type;
+  constexpr int Q = M::Q;
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const Node n = make_node(a, x, y, z);
+  S* __restrict__ F = (S*)a.f;
+  const size_t N = (size_t)a.N;
+  double uin_prev[3] = {0, 0, 0}, uin_now[3] = {0, 0, 0};
+  if constexpr (BC && ODD) {
+    if (n.atface & a.bc.inlet) {
+      inlet_velocity(a.bc, n, t - 1, uin_prev);
+      inlet_velocity(a.bc, n, t, uin_now);
+    }
+  }
+  real f[Q];
+  if constexpr (!ODD) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = ld<real>(F + (size_t)I * N + n.self);
+    });
+  } else {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = pull<Q, I, real, S, BC>(a, F, n, uin_prev);
+    });
+  }
+  M::collide(f, a);
+  if constexpr (!ODD) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      st(F + (size_t)opposite<Q>(I) * N + n.self, f[I]);
+    });
+    if constexpr (BC) {
+      if (n.atface & a.bc.outflow) {
+        S* G = (S*)a.ghost;
+        const long long g = ghost_index<0>(a, n);
+        static_for<0, Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          if (n.atface & a.bc.outflow & pull_faces(I))
+            st(G + (size_t)I * (size_t)a.bc.ghost_n + g, f[I]);
+        });
+      }
+    }
+  } else {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      push<Q, I, real, S, BC>(a, F, n, f[I], uin_now);
+    });
+  }
+}
+
+// Natural (pre-collision) populations of a node in double precision.
+template <int Q, typename S, bool BC>
+__device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, int parity,
+                                              long long t, double (&f)[Q]) {
+  const S* F = (const S*)a.f;
+  const size_t N = (size_t)a.N;
+  if (parity == 0) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = ld<double>(F + (size_t)I * N + n.self);
+    });
+  } else {
+    double uin[3] = {0, 0, 0};
+    if constexpr (BC) {
+      if (n.atface & a.bc.inlet) inlet_velocity(a.bc, n, t - 1, uin);
+    }
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = pull<Q, I, double, S, BC>(a, F, n, uin);
+    });
+  }
+}
+
+template <int Q, typename S, bool BC, typename O>
+__global__ __launch_bounds__(256) void get_populations_kernel(const LatArgs a, int parity,
+                                                              long long t, O* out) {
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const Node n = make_node(a, x, y, z);
+  double f[Q];
+  fetch_natural<Q, S, BC>(a, n, parity, t, f);
+  for (int i = 0; i < Q; ++i) out[(size_t)i * a.N + n.self] = O(f[i]);
+}
+
+template <int Q, typename S, typename O>
+__global__ __launch_bounds__(256) void set_populations_kernel(const LatArgs a, const O* in) {
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const int self = (z * a.ny + y) * a.nx + x;
+  S* F = (S*)a.f;
+  for (int i = 0; i < Q; ++i)
+    F[(size_t)i * a.N + self] = S((double)in[(size_t)i * a.N + self]);
+}
+
+// Equilibrium deviations of the model for (drho, u), computed in double:
+// MRT Eq. (2); FCLB the product equilibrium rho prod phi(e_a; u_a), whose
+// central moments are the Table 2 equilibria.
+template <int KIND, typename S, typename I>
+__global__ __launch_bounds__(256) void init_equilibrium_kernel(const LatArgs a, const I* drho,
+                                                               const I* u) {
+  constexpr int Q = Model<KIND>::Q;
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const size_t self = ((size_t)z * a.ny + y) * a.nx + x;
+  const size_t N = (size_t)a.N;
+  const double d = drho[self];
+  const double ux = u[self], uy = u[N + self], uz = u[2 * N + self];
+  S* F = (S*)a.f;
+  if constexpr (Q == 19) {
+    const double uu = ux * ux + uy * uy + uz * uz;
+    static_for<0, 19>([&](auto ic) {
+      constexpr int I2 = decltype(ic)::value;
+      const double eu = cx(I2) * ux + cy(I2) * uy + cz(I2) * uz;
+      F[(size_t)I2 * N + self] = S(weight<19>(I2) * (d + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    });
+  } else {
+    // phi(0) = 2/3 - u^2, phi(+-1) = (1/3 + u^2 +- u)/2; deviation from the
+    // rest factors (2/3, 1/6) expanded so no O(1) terms cancel.
+    const double uv[3] = {ux, uy, uz};
+    double ph[3][3], ph0[3];  // ph[d][e+1] = phi, ph0 = rest factor
+    for (int c = 0; c < 3; ++c) {
+      const double q = uv[c] * uv[c];
+      ph[c][1] = 2.0 / 3.0 - q;
+      ph[c][0] = 0.5 * (1.0 / 3.0 + q - uv[c]);
+      ph[c][2] = 0.5 * (1.0 / 3.0 + q + uv[c]);
+    }
+    ph0[0] = 1.0 / 6.0;
+    ph0[1] = 2.0 / 3.0;
+    ph0[2] = 1.0 / 6.0;
+    static_for<0, 27>([&](auto ic) {
+      constexpr int I2 = decltype(ic)::value;
+      const double a0 = ph0[cx(I2) + 1], b0 = ph0[cy(I2) + 1], c0 = ph0[cz(I2) + 1];
+      const double da = ph[0][cx(I2) + 1] - a0, db = ph[1][cy(I2) + 1] - b0,
+                   dc = ph[2][cz(I2) + 1] - c0;
+      // (a0+da)(b0+db)(c0+dc)(1+d) - a0 b0 c0
+      const double prod_dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 +
+                              da * b0 * dc + a0 * db * dc + da * db * dc;
+      const double full = a0 * b0 * c0 + prod_dev;
+      F[(size_t)I2 * N + self] = S(prod_dev + d * full);
+    });
+  }
+}
+
+template <int KIND, typename S, bool BC, typename O>
+__global__ __launch_bounds__(256) void macroscopic_kernel(const LatArgs a, int parity, long long t,
+                                                          O* rho, O* u, int rho_mode) {
+  constexpr int Q = Model<KIND>::Q;
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const Node n = make_node(a, x, y, z);
+  double f[Q];
+  fetch_natural<Q, S, BC>(a, n, parity, t, f);
+  double d = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    j[0] += cx(i) * f[i];
+    j[1] += cy(i) * f[i];
+    j[2] += cz(i) * f[i];
+  }
+  const double r = (KIND == 2) ? 1.0 + d : 1.0;
+  if (rho) rho[n.self] = O(rho_mode == 0 ? 1.0 + d : d);
+  if (u) {
+    const size_t N = (size_t)a.N;
+    u[n.self] = O(j[0] / r);
+    u[N + n.self] = O(j[1] / r);
+    u[2 * N + n.self] = O(j[2] / r);
+  }
+}
+
+// Per-block FP64 partial sums (mass deviation, momentum, kinetic energy) in
+// a fixed tree order, one row of 5 per block of the launch grid.
+template <int KIND, typename S, bool BC>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const LatArgs a, int parity,
+                                                             long long t, double* partial) {
+  constexpr int Q = Model<KIND>::Q;
+  __shared__ double sh[5][256];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nthreads = blockDim.x * blockDim.y;
+  double v[5] = {0, 0, 0, 0, 0};
+  int x, y, z;
+  if (node_coords(a, x, y, z)) {
+    const Node n = make_node(a, x, y, z);
+    double f[Q];
+    fetch_natural<Q, S, BC>(a, n, parity, t, f);
+    double d = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      d += f[i];
+      j[0] += cx(i) * f[i];
+      j[1] += cy(i) * f[i];
+      j[2] += cz(i) * f[i];
+    }
+    const double r = (KIND == 2) ? 1.0 + d : 1.0;
+    v[0] = d;
+    v[1] = j[0];
+    v[2] = j[1];
+    v[3] = j[2];
+    v[4] = 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / r;
+  }
+  for (int k = 0; k < 5; ++k) sh[k][tid] = v[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s && tid + s < nthreads)
+      for (int k = 0; k < 5; ++k) sh[k][tid] += sh[k][tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    for (int k = 0; k < 5; ++k) partial[b * 5 + k] = sh[k][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial, size_t nb,
+                                                           double* out) {
+  __shared__ double sh[5][256];
+  const int tid = threadIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  for (size_t b = tid; b < nb; b += 256)
+    for (int k = 0; k < 5; ++k) v[k] += partial[b * 5 + k];
+  for (int k = 0; k < 5; ++k) sh[k][tid] = v[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int k = 0; k < 5; ++k) sh[k][tid] += sh[k][tid + s];
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int k = 0; k < 5; ++k) out[k] = sh[k][0];
+}
+
+// Plain vectorised copy: the achievable-bandwidth probe.
+__global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst,
+                                                   const uint4* __restrict__ src, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace lbm

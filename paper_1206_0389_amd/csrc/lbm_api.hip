@@ -1,0 +1,468 @@
+// Host runtime of the C ABI declared in include/lbm.h: validation, memory
+// layout inside the caller's block, launch configuration and dispatch over
+// model x storage x step parity x boundary handling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "kernels.h"
+
+using namespace lbm;
+
+struct lbm_lattice {
+  lbm_config cfg;
+  int kind;  // 0 MRT Table 1, 1 MRT d'Humieres, 2 FCLB
+  int Q;
+  size_t N;
+  size_t elem;  // bytes per stored value
+  hipStream_t stream;
+  // bound memory
+  char* base = nullptr;
+  size_t bytes = 0;
+  size_t off_ghost = 0, off_partial = 0, off_result = 0, req = 0;
+  size_t ghost_n_max = 0;
+  size_t nblocks = 0;
+  // state
+  int64_t t = 0;
+  int parity = 0;
+  bool has_bc = false;
+  LatArgs args;
+  dim3 grid, block;
+};
+
+namespace {
+
+thread_local std::string g_hip_msg;
+
+int hip_fail(hipError_t e) {
+  g_hip_msg = std::string("HIP error: ") + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void launch_shape(lbm_lattice* L) {
+  const int nx = L->cfg.nx, ny = L->cfg.ny, nz = L->cfg.nz;
+  int bx = nx < 256 ? nx : 256;
+  int by = 256 / bx;
+  if (by > ny) by = ny;
+  if (by < 1) by = 1;
+  L->block = dim3(bx, by, 1);
+  L->grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+  L->nblocks = (size_t)L->grid.x * L->grid.y * L->grid.z;
+}
+
+template <typename S>
+int step_dispatch_s(lbm_lattice* L, bool odd, long long t) {
+  const LatArgs& a = L->args;
+#define LBM_STEP(KIND)                                                                        \
+  if (L->kind == KIND) {                                                                      \
+    if (odd) {                                                                                \
+      if (L->has_bc)                                                                          \
+        hipLaunchKernelGGL((step_kernel<KIND, S, true, true>), L->grid, L->block, 0,          \
+                           L->stream, a, t);                                                  \
+      else                                                                                    \
+        hipLaunchKernelGGL((step_kernel<KIND, S, true, false>), L->grid, L->block, 0,         \
+                           L->stream, a, t);                                                  \
+    } else {                                                                                  \
+      if (L->has_bc)                                                                          \
+        hipLaunchKernelGGL((step_kernel<KIND, S, false, true>), L->grid, L->block, 0,         \
+                           L->stream, a, t);                                                  \
+      else                                                                                    \
+        hipLaunchKernelGGL((step_kernel<KIND, S, false, false>), L->grid, L->block, 0,        \
+                           L->stream, a, t);                                                  \
+    }                                                                                         \
+  }
+  LBM_STEP(0)
+  LBM_STEP(1)
+  LBM_STEP(2)
+#undef LBM_STEP
+  return LBM_OK;
+}
+
+int step_dispatch(lbm_lattice* L, bool odd, long long t) {
+  switch (L->cfg.storage) {
+    case LBM_F64: return step_dispatch_s<double>(L, odd, t);
+    case LBM_F32: return step_dispatch_s<float>(L, odd, t);
+    default: return step_dispatch_s<_Float16>(L, odd, t);
+  }
+}
+
+// Runs fn<KIND, S, BC>() for the lattice's configuration.
+template <typename Fn>
+void with_config(const lbm_lattice* L, Fn&& fn) {
+  auto by_s = [&](auto kind_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    auto by_bc = [&](auto s_tag) {
+      using S = typename decltype(s_tag)::type;
+      if (L->has_bc)
+        fn(std::integral_constant<int, KIND>{}, s_tag, std::true_type{});
+      else
+        fn(std::integral_constant<int, KIND>{}, s_tag, std::false_type{});
+    };
+    switch (L->cfg.storage) {
+      case LBM_F64: by_bc(std::type_identity<double>{}); break;
+      case LBM_F32: by_bc(std::type_identity<float>{}); break;
+      default: by_bc(std::type_identity<_Float16>{}); break;
+    }
+  };
+  switch (L->kind) {
+    case 0: by_s(std::integral_constant<int, 0>{}); break;
+    case 1: by_s(std::integral_constant<int, 1>{}); break;
+    default: by_s(std::integral_constant<int, 2>{}); break;
+  }
+}
+
+int check_launch() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
+
+void default_bc(BcArgs& b) {
+  std::memset(&b, 0, sizeof(b));
+  b.inlet_axis = 2;
+  b.out_axis = 2;
+  b.ghost_na = 1;
+  b.ghost_n = 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int status) {
+  switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument or configuration";
+    case LBM_ENOMEM: return "bound device block is smaller than required";
+    case LBM_EUNBOUND: return "no device memory bound";
+    case LBM_EHIP: return g_hip_msg.empty() ? "HIP error" : g_hip_msg.c_str();
+    case LBM_ENONFINITE: return "non-finite global sum";
+    case LBM_ESTATE: return "call not valid in the current lattice state";
+    default: return "unknown status";
+  }
+}
+
+int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
+  if (!cfg || !out) return LBM_EINVAL;
+  const lbm_config& c = *cfg;
+  if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB) return LBM_EINVAL;
+  if (c.storage != LBM_F64 && c.storage != LBM_F32 && c.storage != LBM_F16) return LBM_EINVAL;
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1) return LBM_EINVAL;
+  const double nnodes = (double)c.nx * c.ny * c.nz;
+  if (nnodes >= 2147483648.0) return LBM_EINVAL;
+  if (c.nz > 65535 || c.ny > 65535 * 256) return LBM_EINVAL;  // launch grid limits
+  if (!(c.nu > 0.0) || !std::isfinite(c.nu)) return LBM_EINVAL;
+  if (!(c.cs_smag >= 0.0) || !std::isfinite(c.cs_smag)) return LBM_EINVAL;
+  if (c.model == LBM_D3Q19_MRT_LES &&
+      c.mrt_basis != LBM_BASIS_TABLE1 && c.mrt_basis != LBM_BASIS_DHUMIERES)
+    return LBM_EINVAL;
+  if (c.model == LBM_D3Q19_MRT_LES && !c.use_default_rates) {
+    const int nr = c.mrt_basis == LBM_BASIS_TABLE1 ? 4 : 5;
+    for (int k = 0; k < nr; ++k)
+      if (!(c.rates[k] > 0.0 && c.rates[k] < 2.0)) return LBM_EINVAL;
+  }
+  lbm_lattice* L = new (std::nothrow) lbm_lattice();
+  if (!L) return LBM_EINVAL;
+  L->cfg = c;
+  L->kind = c.model == LBM_D3Q27_FCLB ? 2 : (c.mrt_basis == LBM_BASIS_TABLE1 ? 0 : 1);
+  L->Q = c.model == LBM_D3Q27_FCLB ? 27 : 19;
+  L->N = (size_t)c.nx * c.ny * c.nz;
+  L->elem = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
+  L->stream = (hipStream_t)c.stream;
+  launch_shape(L);
+  // memory layout: populations | outflow ghost plane | partials | result
+  size_t face = (size_t)c.ny * c.nz;
+  if ((size_t)c.nx * c.nz > face) face = (size_t)c.nx * c.nz;
+  if ((size_t)c.nx * c.ny > face) face = (size_t)c.nx * c.ny;
+  L->ghost_n_max = face;
+  L->off_ghost = align256(L->N * L->Q * L->elem);
+  L->off_partial = L->off_ghost + align256(face * L->Q * L->elem);
+  L->off_result = L->off_partial + align256(L->nblocks * 5 * sizeof(double));
+  L->req = L->off_result + 256;
+  // arguments
+  LatArgs& a = L->args;
+  std::memset(&a, 0, sizeof(a));
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.nz = c.nz;
+  a.N = (long long)L->N;
+  const double tau0 = 3.0 * c.nu + 0.5;
+  a.mrt.tau0 = tau0;
+  a.mrt.cs18 = 18.0 * c.cs_smag * c.cs_smag;
+  a.omega = 1.0 / tau0;
+  if (c.model == LBM_D3Q19_MRT_LES) {
+    if (c.use_default_rates) {
+      const double t1[5] = {1.0, 1.0, 1.0, 1.0, 1.0};
+      const double dh[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+      for (int k = 0; k < 5; ++k)
+        a.mrt.rates[k] = c.mrt_basis == LBM_BASIS_TABLE1 ? t1[k] : dh[k];
+    } else {
+      for (int k = 0; k < 5; ++k) a.mrt.rates[k] = c.rates[k];
+    }
+  }
+  default_bc(a.bc);
+  *out = L;
+  return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_lattice* L, size_t* bytes) {
+  if (!L || !bytes) return LBM_EINVAL;
+  *bytes = L->req;
+  return LBM_OK;
+}
+
+int lbm_bind_memory(lbm_lattice* L, void* dev, size_t bytes) {
+  if (!L || !dev) return LBM_EINVAL;
+  if (((uintptr_t)dev & 255) != 0) return LBM_EINVAL;
+  if (bytes < L->req) return LBM_ENOMEM;
+  L->base = (char*)dev;
+  L->bytes = bytes;
+  L->args.f = L->base;
+  L->args.ghost = L->base + L->off_ghost;
+  L->t = 0;
+  L->parity = 0;
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_lattice* L, void* stream) {
+  if (!L) return LBM_EINVAL;
+  L->stream = (hipStream_t)stream;
+  return LBM_OK;
+}
+
+int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
+  if (!L || !bc) return LBM_EINVAL;
+  if (L->parity != 0) return LBM_ESTATE;
+  const int n3[3] = {L->cfg.nx, L->cfg.ny, L->cfg.nz};
+  BcArgs b;
+  default_bc(b);
+  int n_inlet = 0, n_out = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int ty = bc->face_type[f];
+    if (ty < LBM_PERIODIC || ty > LBM_OUTFLOW) return LBM_EINVAL;
+    if (ty != LBM_PERIODIC) {
+      b.nonper |= 1u << f;
+      if (n3[f / 2] < 2) return LBM_EINVAL;
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (!std::isfinite(bc->face_u[f][k])) return LBM_EINVAL;
+      b.face_u[f][k] = bc->face_u[f][k];
+    }
+    if (ty == LBM_WALL) b.wall |= 1u << f;
+    if (ty == LBM_INLET) {
+      b.inlet |= 1u << f;
+      b.inlet_axis = f / 2;
+      ++n_inlet;
+    }
+    if (ty == LBM_OUTFLOW) {
+      b.outflow |= 1u << f;
+      b.out_axis = f / 2;
+      ++n_out;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    const bool lo = (b.nonper >> (2 * d)) & 1u, hi = (b.nonper >> (2 * d + 1)) & 1u;
+    if (lo != hi) return LBM_EINVAL;  // faces of one axis: both periodic or neither
+  }
+  if (n_inlet > 1 || n_out > 1) return LBM_EINVAL;
+  if (n_inlet) {
+    if (!bc->inlet_u || !valid_dtype(bc->inlet_dtype)) return LBM_EINVAL;
+    if (!std::isfinite(bc->inlet_amp)) return LBM_EINVAL;
+    b.inlet_u = bc->inlet_u;
+    b.inlet_f64 = bc->inlet_dtype == LBM_DTYPE_F64;
+    b.inlet_mask = bc->inlet_mask;
+    b.inlet_amp = bc->inlet_amp;
+    b.seed = bc->seed;
+    const int d = b.inlet_axis;
+    b.inlet_na = n3[d == 0 ? 1 : 0];
+    b.inlet_nb = n3[d == 2 ? 1 : 2];
+    if (b.inlet_na >= 16384 || b.inlet_nb >= 16384) return LBM_EINVAL;
+  }
+  if (n_out) {
+    const int d = b.out_axis;
+    b.ghost_na = n3[d == 0 ? 1 : 0];
+    b.ghost_n = (long long)b.ghost_na * n3[d == 2 ? 1 : 2];
+  }
+  L->args.bc = b;
+  L->has_bc = b.nonper != 0;
+  return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_lattice* L, const void* drho, const void* u, int dtype,
+                         int64_t t0) {
+  if (!L || !drho || !u || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  with_config(L, [&](auto kind_c, auto s_tag, auto) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    if (dtype == LBM_DTYPE_F64)
+      hipLaunchKernelGGL((init_equilibrium_kernel<KIND, S, double>), L->grid, L->block, 0,
+                         L->stream, L->args, (const double*)drho, (const double*)u);
+    else
+      hipLaunchKernelGGL((init_equilibrium_kernel<KIND, S, float>), L->grid, L->block, 0,
+                         L->stream, L->args, (const float*)drho, (const float*)u);
+  });
+  const int rc = check_launch();
+  if (rc) return rc;
+  L->t = t0;
+  L->parity = 0;
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_lattice* L, const void* f, int dtype, int64_t t0) {
+  if (!L || !f || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  with_config(L, [&](auto kind_c, auto s_tag, auto) {
+    constexpr int Q = Model<decltype(kind_c)::value>::Q;
+    using S = typename decltype(s_tag)::type;
+    if (dtype == LBM_DTYPE_F64)
+      hipLaunchKernelGGL((set_populations_kernel<Q, S, double>), L->grid, L->block, 0,
+                         L->stream, L->args, (const double*)f);
+    else
+      hipLaunchKernelGGL((set_populations_kernel<Q, S, float>), L->grid, L->block, 0,
+                         L->stream, L->args, (const float*)f);
+  });
+  const int rc = check_launch();
+  if (rc) return rc;
+  L->t = t0;
+  L->parity = 0;
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_lattice* L, void* f, int dtype) {
+  if (!L || !f || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int Q = Model<decltype(kind_c)::value>::Q;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    if (dtype == LBM_DTYPE_F64)
+      hipLaunchKernelGGL((get_populations_kernel<Q, S, BC, double>), L->grid, L->block, 0,
+                         L->stream, L->args, L->parity, (long long)L->t, (double*)f);
+    else
+      hipLaunchKernelGGL((get_populations_kernel<Q, S, BC, float>), L->grid, L->block, 0,
+                         L->stream, L->args, L->parity, (long long)L->t, (float*)f);
+  });
+  return check_launch();
+}
+
+int lbm_step(lbm_lattice* L, int64_t n) {
+  if (!L || n < 0) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  for (int64_t k = 0; k < n; ++k) {
+    step_dispatch(L, L->parity == 1, (long long)L->t);
+    L->t += 1;
+    L->parity ^= 1;
+  }
+  return check_launch();
+}
+
+int lbm_get_macroscopic(lbm_lattice* L, void* rho, void* u, int dtype, int rho_mode) {
+  if (!L || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (rho_mode != LBM_RHO_FULL && rho_mode != LBM_RHO_DEVIATION) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (!rho && !u) return LBM_OK;
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    if (dtype == LBM_DTYPE_F64)
+      hipLaunchKernelGGL((macroscopic_kernel<KIND, S, BC, double>), L->grid, L->block, 0,
+                         L->stream, L->args, L->parity, (long long)L->t, (double*)rho,
+                         (double*)u, rho_mode);
+    else
+      hipLaunchKernelGGL((macroscopic_kernel<KIND, S, BC, float>), L->grid, L->block, 0,
+                         L->stream, L->args, L->parity, (long long)L->t, (float*)rho,
+                         (float*)u, rho_mode);
+  });
+  return check_launch();
+}
+
+int lbm_reduce(lbm_lattice* L, double out[5]) {
+  if (!L || !out) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  double* partial = (double*)(L->base + L->off_partial);
+  double* result = (double*)(L->base + L->off_result);
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
+                       L->args, L->parity, (long long)L->t, partial);
+  });
+  int rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
+                     L->nblocks, result);
+  rc = check_launch();
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(out, result, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                                L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(out[k])) return LBM_ENONFINITE;
+  return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_lattice* L, size_t* bytes) {
+  if (!L || !bytes) return LBM_EINVAL;
+  *bytes = L->off_partial;
+  return LBM_OK;
+}
+
+int lbm_save_state(lbm_lattice* L, void* dev, size_t bytes, int64_t* t, int32_t* parity) {
+  if (!L || !dev) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (bytes < L->off_partial) return LBM_ENOMEM;
+  const hipError_t e =
+      hipMemcpyAsync(dev, L->base, L->off_partial, hipMemcpyDeviceToDevice, L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (t) *t = L->t;
+  if (parity) *parity = L->parity;
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_lattice* L, const void* dev, size_t bytes, int64_t t, int32_t parity) {
+  if (!L || !dev || (parity != 0 && parity != 1)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (bytes < L->off_partial) return LBM_ENOMEM;
+  const hipError_t e =
+      hipMemcpyAsync(L->base, dev, L->off_partial, hipMemcpyDeviceToDevice, L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  L->t = t;
+  L->parity = parity;
+  return LBM_OK;
+}
+
+int lbm_get_time(const lbm_lattice* L, int64_t* t) {
+  if (!L || !t) return LBM_EINVAL;
+  *t = L->t;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_lattice* L) {
+  delete L;
+  return LBM_OK;
+}
+
+int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream) {
+  if (!dst || !src || (((uintptr_t)dst | (uintptr_t)src | n) & 15) != 0) return LBM_EINVAL;
+  const size_t n16 = n / 16;
+  if (n16 == 0) return LBM_OK;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     (uint4*)dst, (const uint4*)src, n16);
+  return check_launch();
+}
+
+}  // extern "C"

@@ -80,9 +80,10 @@ def jet_inlet(na: int, nb: int, diameter: float, u_jet: float, u_coflow: float,
     return u, mask.astype(np.uint8)
 
 
-def uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.0), drho: float = 0.0):
-    f = np.full((nz, ny, nx), float(drho))
-    uu = np.empty((3, nz, ny, nx))
+def uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.0), drho: float = 0.0, dtype=np.float64):
+    """Uniform (drho, u) fields."""
+    f = np.full((nz, ny, nx), float(drho), dtype=dtype)
+    uu = np.empty((3, nz, ny, nx), dtype=dtype)
     for c in range(3):
         uu[c] = u[c]
     return f, uu

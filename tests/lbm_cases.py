@@ -1,0 +1,81 @@
+"""Shared set-up for GPU-vs-oracle parity tests: builds the same lattice on
+both sides from the same seeded inputs (synth) and compares them."""
+import numpy as np
+
+import oracle
+import synth
+
+MODELS = {  # name: (model code, mrt basis)
+    "fclb": (oracle.FCLB27, oracle.BASIS_TABLE1),
+    "mrt_table1": (oracle.MRT19, oracle.BASIS_TABLE1),
+    "mrt_dhumieres": (oracle.MRT19, oracle.BASIS_DHUMIERES),
+}
+W, I, O, P = oracle.WALL, oracle.INLET, oracle.OUTFLOW, oracle.PERIODIC
+JET_FACES = [W, W, W, W, I, O]
+
+
+def face_velocities(coflow=0.002, axis=2):
+    fu = [[0.0, 0.0, 0.0] for _ in range(6)]
+    for k in range(4):
+        fu[k][axis] = coflow
+    return fu
+
+
+def gpu_lattice(name, storage, shape, nu, cs=0.0, rates=None, faces=None, face_u=None,
+                inlet=None, amp=0.0, seed=0):
+    import torch
+    import paper_1206_0389_amd as P
+    model, basis = MODELS[name]
+    lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs,
+                    mrt_basis=basis, rates=rates)
+    if faces is not None:
+        iu = im = None
+        if inlet is not None:
+            iu = torch.from_numpy(np.ascontiguousarray(inlet[0], dtype=np.float64))
+            im = torch.from_numpy(np.ascontiguousarray(inlet[1], dtype=np.uint8))
+        lat.set_boundaries(faces, face_u=face_u, inlet_u=iu, inlet_mask=im, inlet_amp=amp,
+                           seed=seed)
+    return lat
+
+
+def oracle_lattice(name, shape, nu, cs=0.0, rates=None, faces=None, face_u=None, inlet=None,
+                   amp=0.0, seed=0, origin=(0, 0, 0), extent=None):
+    model, basis = MODELS[name]
+    nx, ny, nz = shape
+    kw = {}
+    if faces is not None:
+        kw = dict(faces=faces, face_u=face_u, inlet_amp=amp, seed=seed, origin=origin)
+        if inlet is not None:
+            kw.update(inlet_u=inlet[0], inlet_mask=inlet[1])
+            if extent is not None:
+                kw["inlet_extent"] = extent
+    return oracle.Lattice(model, nx, ny, nz, nu=nu, cs_smag=cs, basis=basis, rates=rates, **kw)
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def window(shape, faces, lo, hi, margin):
+    """Oracle window [lo, hi) (+margin on cut sides) of a global lattice.
+
+    Returns (wlo, whi, wfaces, inner) where inner are the slices of the
+    window that hold exact values after `margin` steps.
+    """
+    wlo, whi, wf, inner = [], [], [], []
+    for d in range(3):
+        n = shape[d]
+        a = max(lo[d] - margin, 0)
+        b = min(hi[d] + margin, n)
+        per = faces[2 * d] == P
+        if per and (lo[d] - margin < 0 or hi[d] + margin > n):
+            a, b = 0, n  # periodic axis: take it whole
+        wlo.append(a)
+        whi.append(b)
+        f_lo = faces[2 * d] if a == 0 else P
+        f_hi = faces[2 * d + 1] if b == n else P
+        if per and (a, b) == (0, n):
+            f_lo = f_hi = P
+        wf += [f_lo, f_hi]
+        inner.append(slice(lo[d] - a, hi[d] - a))
+    return wlo, whi, wf, inner

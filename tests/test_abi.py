@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI (no GPU needed: nothing here launches).
+
+The library must load and export every function declared in include/lbm.h;
+argument validation happens on the host before any launch.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:int|const char\*)\s+(lbm_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1206_0389_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("liblbm.so not built")
+    return P
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["lbm_create_lattice", "lbm_set_boundaries", "lbm_step", "lbm_get_macroscopic"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(P):
+    lib = P.lib()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(P.exported_symbols()) | {"lbm_strerror"}
+
+
+def _cfg(P, **kw):
+    c = P.Config()
+    c.model = {"fclb": P.D3Q27_FCLB, "mrt": P.D3Q19_MRT_LES}[kw.get("model", "fclb")]
+    c.storage = kw.get("storage", P.F32)
+    c.nx, c.ny, c.nz = kw.get("shape", (16, 8, 4))
+    c.nu = kw.get("nu", 0.01)
+    c.cs_smag = kw.get("cs", 0.0)
+    c.mrt_basis = kw.get("basis", 0)
+    c.use_default_rates = 1
+    return c
+
+
+def _create(P, c):
+    h = ctypes.c_void_p()
+    rc = P.lib().lbm_create_lattice(ctypes.byref(c), ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validates_configuration(P):
+    ok, h = _create(P, _cfg(P))
+    assert ok == P.OK
+    P.lib().lbm_destroy(h)
+    bad = [dict(nu=0.0), dict(nu=-1.0), dict(cs=-0.1), dict(shape=(0, 4, 4)),
+           dict(shape=(2048, 2048, 1024)), dict(storage=7)]
+    for kw in bad:
+        rc, _ = _create(P, _cfg(P, **kw))
+        assert rc == P.EINVAL, kw
+    c = _cfg(P, model="mrt")
+    c.mrt_basis = 5
+    assert _create(P, c)[0] == P.EINVAL
+    c = _cfg(P, model="mrt")
+    c.use_default_rates = 0
+    c.rates[0] = 2.5
+    assert _create(P, c)[0] == P.EINVAL
+    assert P.lib().lbm_create_lattice(None, None) == P.EINVAL
+
+
+def test_required_bytes_and_binding_checks(P):
+    _, h = _create(P, _cfg(P, shape=(16, 8, 4), storage=P.F32))
+    n = ctypes.c_size_t()
+    assert P.lib().lbm_required_bytes(h, ctypes.byref(n)) == P.OK
+    assert n.value >= 16 * 8 * 4 * 27 * 4
+    # unbound: every data call refuses before launching
+    assert P.lib().lbm_step(h, 1) == P.EUNBOUND
+    out = (ctypes.c_double * 5)()
+    assert P.lib().lbm_reduce(h, out) == P.EUNBOUND
+    # misaligned or short blocks are refused without touching them
+    assert P.lib().lbm_bind_memory(h, ctypes.c_void_p(0x1001), n.value) == P.EINVAL
+    assert P.lib().lbm_bind_memory(h, ctypes.c_void_p(0x100000), n.value - 1) == P.ENOMEM
+    assert P.lib().lbm_step(h, -1) == P.EINVAL
+    P.lib().lbm_destroy(h)
+
+
+def test_boundary_validation(P):
+    _, h = _create(P, _cfg(P))
+    bc = P.Boundaries()
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK  # all periodic
+    bc.face_type[0] = P.WALL  # x- wall with a periodic x+ is inconsistent
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.face_type[1] = P.WALL
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
+    bc.face_type[4], bc.face_type[5] = P.INLET, P.OUTFLOW  # inlet without data
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.inlet_u = 0x1000
+    bc.inlet_dtype = 9
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.inlet_dtype = P.DTYPE_F64
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
+    bc.face_type[2] = bc.face_type[3] = P.OUTFLOW  # two outflow faces
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.face_type[2] = bc.face_type[3] = 11
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    P.lib().lbm_destroy(h)
+
+
+def test_strerror(P):
+    assert "invalid" in P.strerror(P.EINVAL)
+    assert P.strerror(P.ENONFINITE)
+    assert P.strerror(12345) == "unknown status"

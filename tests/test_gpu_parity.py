@@ -1,0 +1,177 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+FP64 storage: max |f_gpu - f_oracle| / max |f_oracle| <= 1e-12 (the two
+differ only in rounding order: FMA contraction on the GPU, a factorised
+central-moment transform vs the oracle's dense 27x27 solve).
+FP32 / FP16 storage: the per-step error is dominated by rounding the
+stored deviations (2^-24 and 2^-11 relative) plus FP32 arithmetic; the
+bounds below allow a few units of that per step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lbm_cases import (JET_FACES, MODELS, O, P, W, I, face_velocities, gpu_lattice,
+                       oracle_lattice, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+TOL = {"f64": 1e-12, "f32": 4e-6, "f16": 2e-3}
+NAMES = list(MODELS)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run_pair(name, storage, shape, nu, steps, cs=0.1, faces=None, face_u=None, inlet=None,
+              amp=0.0, seed=0, t0=0, f0=None, rates=None):
+    nx, ny, nz = shape
+    Q = 19 if MODELS[name][0] == oracle.MRT19 else 27
+    _say("case", name, storage, shape, "steps", steps, "faces", faces)
+    f = f0 if f0 is not None else synth.random_populations(Q, (nz, ny, nx), amp=1e-2, seed=11)
+    g = gpu_lattice(name, storage, shape, nu, cs=cs, rates=rates, faces=faces, face_u=face_u,
+                    inlet=inlet, amp=amp, seed=seed)
+    o = oracle_lattice(name, shape, nu, cs=cs, rates=rates, faces=faces, face_u=face_u,
+                       inlet=inlet, amp=amp, seed=seed)
+    g.set_populations(torch.from_numpy(f), t0)
+    snaps = []
+    for k in steps:
+        g.step(k - (g.time - t0))
+        snaps.append((k, g.populations().cpu().numpy()))
+    out, ref, done = [], f.copy(), 0
+    for k, gp in snaps:
+        ref = o.run(ref, t0 + done, k - done)
+        done = k
+        out.append(rel_err(gp, ref))
+    return out
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 9), (1, 16, 3)])
+def test_periodic_step_parity_fp64(name, shape):
+    errs = _run_pair(name, "f64", shape, 0.02, [1, 2, 5])
+    assert max(errs) <= TOL["f64"], errs
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("layout", ["jet", "zoutflow_lo", "x_inlet", "y_inlet_walls"])
+def test_boundary_step_parity_fp64(name, layout):
+    fu = face_velocities(0.002)
+    fu[4] = [0.0, 0.0, 0.0]
+    fu[0] = [0.0, 0.001, 0.002]
+    shape = (10, 8, 9)
+    nx, ny, nz = shape
+    if layout == "jet":
+        faces, inlet = JET_FACES, synth.jet_inlet(nx, ny, 4.0, 0.05, 0.002)
+    elif layout == "zoutflow_lo":
+        faces, inlet = [P, P, W, W, O, I], synth.jet_inlet(nx, ny, 4.0, 0.04, 0.001)
+    elif layout == "x_inlet":
+        faces, inlet = [I, O, W, W, P, P], synth.jet_inlet(ny, nz, 3.0, 0.04, 0.001, axis=0)
+    else:
+        faces, inlet = [W, W, O, I, W, W], synth.jet_inlet(nx, nz, 3.0, 0.04, 0.001, axis=1)
+    errs = _run_pair(name, "f64", shape, 0.02, [1, 2, 6], faces=faces, face_u=fu, inlet=inlet,
+                     amp=5e-4, seed=12060389, t0=3)
+    assert max(errs) <= TOL["f64"], errs
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_reduced_storage_within_stated_tolerance(name, storage):
+    errs = _run_pair(name, storage, (16, 12, 10), 0.02, [1, 3], faces=JET_FACES,
+                     face_u=face_velocities(0.002), inlet=synth.jet_inlet(16, 12, 6.0, 0.05, 0.002),
+                     amp=5e-4, seed=3)
+    assert errs[0] <= TOL[storage], errs
+    assert errs[1] <= 3 * TOL[storage], errs
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_equilibrium_macroscopic_and_reductions(name):
+    shape = (16, 8, 6)
+    nx, ny, nz = shape
+    _say("case init/macro/reduce", name)
+    drho, u = synth.smooth_random_fields(nx, ny, nz, 0.05, 0.02, seed=5)
+    g = gpu_lattice(name, "f64", shape, 0.01, cs=0.1)
+    o = oracle_lattice(name, shape, 0.01, cs=0.1)
+    g.init_equilibrium(torch.from_numpy(drho), torch.from_numpy(u))
+    ref = o.init_equilibrium(drho, u)
+    assert rel_err(g.populations().cpu().numpy(), ref) <= 1e-14
+    for k in (3, 1):  # odd and even parity readouts
+        g.step(k)
+        ref = o.run(ref, g.time - k, k)
+        d_g, u_g = g.macroscopic()
+        d_o, u_o = o.macroscopic(ref)
+        assert np.abs(d_g.cpu().numpy() - d_o).max() <= 1e-14
+        assert np.abs(u_g.cpu().numpy() - u_o).max() <= 1e-14
+        rg, ro = np.array(g.reduce()), o.reduce(ref)
+        scale = np.array([np.abs(d_o).sum(), *np.abs(u_o).sum(axis=(1, 2, 3)), ro[4]])
+        assert np.all(np.abs(rg - ro) <= 1e-12 * scale + 1e-300)
+    rho_full, _ = g.macroscopic(rho_mode=0)
+    assert np.allclose(rho_full.cpu().numpy(), 1 + d_g.cpu().numpy(), atol=1e-15)
+
+
+def test_nonfinite_state_is_reported():
+    g = gpu_lattice("fclb", "f32", (8, 8, 8), 0.01)
+    f = np.zeros((27, 8, 8, 8))
+    f[3, 2, 2, 2] = np.nan
+    g.set_populations(torch.from_numpy(f))
+    import paper_1206_0389_amd as Pk
+    _, rc = Pk.reduce(g.h, check=False)
+    assert rc == Pk.ENONFINITE
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_save_load_is_bit_identical(storage):
+    _say("case save/load", storage)
+    shape = (16, 8, 12)
+    g = gpu_lattice("fclb", storage, shape, 0.01, faces=JET_FACES,
+                    face_u=face_velocities(0.002), inlet=synth.jet_inlet(16, 8, 4.0, 0.05, 0.002),
+                    amp=5e-4, seed=9)
+    d, u = synth.smooth_random_fields(*shape, 0.05, 0.01, seed=2)
+    g.init_equilibrium(torch.from_numpy(d), torch.from_numpy(u))
+    g.step(3)  # odd parity snapshot
+    buf, t, p = g.save_state()
+    buf = buf.clone()
+    g.step(5)
+    a = g.populations().cpu().numpy()
+    g.load_state(buf, t, p)
+    g.step(5)
+    b = g.populations().cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_zero_steps_and_time():
+    g = gpu_lattice("mrt_table1", "f32", (8, 4, 4), 0.01)
+    g.set_populations(torch.zeros(19, 4, 4, 8, dtype=torch.float64), 7)
+    g.step(0)
+    assert g.time == 7
+    g.step(3)
+    assert g.time == 10
+
+
+def test_c1_taylor_green_dhumieres_fp64_against_oracle():
+    """32^3 periodic Taylor-Green, u0 = 0.05, nu = 0.005, C_S = 0.1, the
+    d'Humieres rates, FP64, 100 steps: every population vs the oracle, and
+    the energy decay at least the molecular rate -6 nu k0^2."""
+    n, u0, nu, cs, steps = 32, 0.05, 0.005, 0.1, 100
+    _say("case C1 TGV 32^3")
+    drho, u = synth.taylor_green(n, u0)
+    g = gpu_lattice("mrt_dhumieres", "f64", (n, n, n), nu, cs=cs)
+    o = oracle_lattice("mrt_dhumieres", (n, n, n), nu, cs=cs)
+    g.init_equilibrium(torch.from_numpy(drho), torch.from_numpy(u))
+    ref = o.init_equilibrium(drho, u)
+    E = [g.reduce()[4]]
+    for _ in range(steps // 10):
+        g.step(10)
+        E.append(g.reduce()[4])
+    ref = o.run(ref, 0, steps)
+    assert rel_err(g.populations().cpu().numpy(), ref) <= 1e-12
+    assert E[-1] == pytest.approx(o.reduce(ref)[4], rel=1e-12)
+    k0 = 2 * np.pi / n
+    rate = np.log(E[-1] / E[5]) / 50.0
+    assert rate < -6 * nu * k0 * k0 * 0.97
