@@ -111,7 +111,8 @@ typedef struct lbm_config {
  * x-, x+, y-, y+, z-, z+ (the "-" face holds coordinate 0).
  *   face_type  LBM_PERIODIC | LBM_WALL | LBM_INLET | LBM_OUTFLOW. Opposite
  *              faces must both be periodic or both non-periodic.
- *              At most one LBM_INLET face and one LBM_OUTFLOW face.
+ *              At most one LBM_INLET face and one LBM_OUTFLOW face; the
+ *              outflow face must be a z face (z- or z+).
  *   face_u     wall velocity of LBM_WALL faces (lattice units).
  *   inlet_u    device, velocity on the inlet face, [3][nb][na] of
  *              inlet_dtype, where (a, b) are the face's two tangential
@@ -123,7 +124,7 @@ typedef struct lbm_config {
  * The streaming rule at a face (population i arriving from outside at
  * node x, post-collision values f*):
  *   WALL, INLET  f_i(x) = f*_opp(i)(x) + 6 w_i (e_i . u)   (u = wall or inlet)
- *   OUTFLOW      f_i(x) = f*_i(x - e_i with the face-normal coordinate kept)
+ *   OUTFLOW      f_i(x) = f*_i(x - e_i with the z coordinate kept)
  * Where a source lies beyond several faces, WALL wins over INLET over
  * OUTFLOW. The inlet buffers must stay valid while the lattice steps.
  */

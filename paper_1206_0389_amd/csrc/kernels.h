@@ -21,9 +21,9 @@
 // a population whose source lies beyond a non-periodic face is
 //   WALL/INLET: bounced back at the half-way point with the wall or inlet
 //               velocity, f_i(x) = f*_opp(i)(x) + 6 w_i e_i.u;
-//   OUTFLOW:    copied from the boundary plane, f_i(x) = f*_i(s), s = x - e_i
-//               with the face-normal coordinate kept (a ghost layer equal to
-//               the last plane: zero normal gradient).
+//   OUTFLOW:    (a z face) copied from the boundary plane, f_i(x) = f*_i(s),
+//               s = x - e_i with the z coordinate kept (a ghost layer equal
+//               to the last plane: zero normal gradient).
 // In AA form the bounce-back reads/writes the node's own opposite slot. The
 // outflow copy needs f*_i(s) twice (normal streaming and the ghost), so even
 // steps also store the inward populations of the outflow plane in a small
@@ -54,9 +54,7 @@ struct BcArgs {
   int inlet_f64;
   int inlet_axis;
   int inlet_na, inlet_nb;
-  int out_axis;
-  int ghost_na;      // extent of the outflow face's first tangential axis
-  long long ghost_n; // nodes of the outflow face
+  long long ghost_n; // nodes of a z plane (the outflow face is a z face)
 };
 
 struct LatArgs {
@@ -197,79 +195,85 @@ __device__ __forceinline__ void inlet_velocity(const BcArgs& b, const Node& n, l
   }
 }
 
-// Ghost-plane index of the node x - e_I with the outflow-normal coordinate
-// kept (I = 0 gives the node itself).
-template <int I>
-__device__ __forceinline__ long long ghost_index(const LatArgs& a, const Node& n) {
-  const int d = a.bc.out_axis;
-  const int sx = (d == 0 || cx(I) == 0) ? n.x : (cx(I) > 0 ? wrap_dn(n.x, a.nx) : wrap_up(n.x, a.nx));
-  const int sy = (d == 1 || cy(I) == 0) ? n.y : (cy(I) > 0 ? wrap_dn(n.y, a.ny) : wrap_up(n.y, a.ny));
-  const int sz = (d == 2 || cz(I) == 0) ? n.z : (cz(I) > 0 ? wrap_dn(n.z, a.nz) : wrap_up(n.z, a.nz));
-  const int A = d == 0 ? sy : sx;
-  const int B = d == 2 ? sy : sz;
-  return (long long)B * a.bc.ghost_na + A;
+// Bounce-back term 6 w_I e_I.u_w of the first (lowest face index) WALL face
+// that x - e_I crosses, selected without branches; 0 if none.
+template <int Q, int I, typename real>
+__device__ __forceinline__ real wall_term(const BcArgs& b, uint32_t cw) {
+  real term = real(0);
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    const int e = c_axis(I, d);
+    if (e == 0) continue;
+    const int F = e > 0 ? 2 * d : 2 * d + 1;
+    const real dot = real(6.0 * weight<Q>(I) *
+                          (cx(I) * b.face_u[F][0] + cy(I) * b.face_u[F][1] + cz(I) * b.face_u[F][2]));
+    term = ((cw >> F) & 1u) ? dot : term;
+  }
+  return term;
 }
 
-template <int I>
-__device__ __forceinline__ double face_dot(const BcArgs& b, uint32_t bits) {
-  const int face = __builtin_ctz(bits);
-  return cx(I) * b.face_u[face][0] + cy(I) * b.face_u[face][1] + cz(I) * b.face_u[face][2];
-}
-
-// f_I(x, t) at odd parity: the pull through the post-collision slots.
-// uin is the inlet velocity of the step whose streaming this completes.
-template <int Q, int I, typename real, typename S, bool BC>
-__device__ __forceinline__ real pull(const LatArgs& a, const S* F, const Node& n,
-                                     const double* uin) {
+// Where f_I(x, t) lives at odd parity: slot opp(I) of node x - e_I (the
+// pull through the post-collision slots), the node's own slot I (WALL or
+// INLET bounce-back, see pull_term) or the outflow ghost plane (index of
+// x - e_I in the z plane). Selects only, no branches, so the loads of all
+// directions can be issued back to back.
+template <int Q, int I, typename S, bool BC>
+__device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, const Node& n) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
-  if constexpr (BC) {
+  const S* normal = F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I));
+  if constexpr (!BC) {
+    return normal;
+  } else {
     const uint32_t crossed = n.atface & pull_faces(I);
-    if (crossed) {
-      const real w6 = real(6.0 * weight<Q>(I));
-      if (crossed & a.bc.wall)
-        return ld<real>(F + (size_t)I * N + n.self) +
-               w6 * real(face_dot<I>(a.bc, crossed & a.bc.wall));
-      if (crossed & a.bc.inlet)
-        return ld<real>(F + (size_t)I * N + n.self) +
-               w6 * real(cx(I) * uin[0] + cy(I) * uin[1] + cz(I) * uin[2]);
-      const S* G = (const S*)a.ghost;
-      return ld<real>(G + (size_t)I * (size_t)a.bc.ghost_n + ghost_index<I>(a, n));
-    }
+    const bool bb = (crossed & (a.bc.wall | a.bc.inlet)) != 0;
+    const S* own = F + (size_t)I * N + n.self;
+    const S* ghost = (const S*)a.ghost + (size_t)I * (size_t)a.bc.ghost_n +
+                     (n.yo[1 - cy(I)] + n.xo[1 - cx(I)]);
+    return bb ? own : (crossed ? ghost : normal);
   }
-  return ld<real>(F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I)));
+}
+
+// Bounce-back term added to the value read by pull_addr: 6 w_I e_I.u with
+// the wall's velocity (first WALL face crossed) or the inlet velocity.
+template <int Q, int I, typename real>
+__device__ __forceinline__ real pull_term(const LatArgs& a, const Node& n, const real* uin) {
+  const uint32_t crossed = n.atface & pull_faces(I);
+  const uint32_t cw = crossed & a.bc.wall;
+  const uint32_t ci = crossed & a.bc.inlet;
+  const real tw = wall_term<Q, I, real>(a.bc, cw);
+  const real ti = real(6.0 * weight<Q>(I)) *
+                  (real(cx(I)) * uin[0] + real(cy(I)) * uin[1] + real(cz(I)) * uin[2]);
+  return cw ? tw : (ci ? ti : real(0));
 }
 
 // Store f*_I(x, t) at the end of an odd step (push to x + e_I), with the
-// bounce-back and outflow ghost rules. uin: inlet velocity of this step.
+// bounce-back rule (own slot opp(I), minus the term) and the outflow rule
+// (dropped; a node on the outflow plane also writes the inward population
+// I of its in-plane neighbour, the ghost copy of the next pull).
 template <int Q, int I, typename real, typename S, bool BC>
 __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real v,
-                                     const double* uin) {
+                                     const real* uin) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
-  if constexpr (BC) {
+  S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
+  if constexpr (!BC) {
+    st(normal, v);
+  } else {
     const uint32_t crossed = n.atface & push_faces(I);
-    const real w6 = real(6.0 * weight<Q>(I));
-    if (crossed) {
-      if (crossed & a.bc.wall)
-        st(F + (size_t)IO * N + n.self, v - w6 * real(face_dot<I>(a.bc, crossed & a.bc.wall)));
-      else if (crossed & a.bc.inlet)
-        st(F + (size_t)IO * N + n.self,
-           v - w6 * real(cx(I) * uin[0] + cy(I) * uin[1] + cz(I) * uin[2]));
-      // else: the population leaves through the outflow face
-    } else {
-      st(F + (size_t)I * N + n.at(cx(I), cy(I), cz(I)), v);
-    }
-    // ghost copy: a node on the outflow plane supplies the inward
-    // population I of its in-plane neighbour x + e_I (normal part removed)
-    if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0) {
-      const int d = a.bc.out_axis;
-      const int tx = d == 0 ? 0 : cx(I), ty = d == 1 ? 0 : cy(I), tz = d == 2 ? 0 : cz(I);
-      st(F + (size_t)I * N + n.at(tx, ty, tz), v);
-    }
-    return;
+    const uint32_t cw = crossed & a.bc.wall;
+    const uint32_t ci = crossed & a.bc.inlet;
+    // the bounce-back of direction I is the pull of opp(I) seen from here
+    const real tw = wall_term<Q, IO, real>(a.bc, cw);
+    const real ti = real(6.0 * weight<Q>(I)) * (real(cx(IO)) * uin[0] + real(cy(IO)) * uin[1] +
+                                                real(cz(IO)) * uin[2]);
+    const real term = cw ? tw : (ci ? ti : real(0));
+    const bool bb = (cw | ci) != 0;
+    S* own = F + (size_t)IO * N + n.self;
+    if (bb || !crossed) st(bb ? own : normal, bb ? v + term : v);
+    if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0)
+      st(F + (size_t)I * N + n.at(cx(I), cy(I), 0), v);
   }
-  st(F + (size_t)I * N + n.at(cx(I), cy(I), cz(I)), v);
 }
 
 // --------------------------------------------------------------- kernels
@@ -307,8 +311,15 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t)
   } else {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = pull<Q, I, real, S, BC>(a, F, n, uin_prev);
+      f[I] = ld<real>(pull_addr<Q, I, S, BC>(a, F, n));
     });
+    if constexpr (BC) {
+      const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        f[I] += pull_term<Q, I, real>(a, n, up);
+      });
+    }
   }
   M::collide(f, a);
   if constexpr (!ODD) {
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t)
     if constexpr (BC) {
       if (n.atface & a.bc.outflow) {
         S* G = (S*)a.ghost;
-        const long long g = ghost_index<0>(a, n);
+        const long long g = n.yo[1] + n.xo[1];
         static_for<0, Q>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
           if (n.atface & a.bc.outflow & pull_faces(I))
@@ -328,9 +339,10 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t)
       }
     }
   } else {
+    const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      push<Q, I, real, S, BC>(a, F, n, f[I], uin_now);
+      push<Q, I, real, S, BC>(a, F, n, f[I], un);
     });
   }
 }
@@ -353,7 +365,8 @@ __device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, i
     }
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = pull<Q, I, double, S, BC>(a, F, n, uin);
+      f[I] = ld<double>(pull_addr<Q, I, S, BC>(a, F, n));
+      if constexpr (BC) f[I] += pull_term<Q, I, double>(a, n, uin);
     });
   }
 }

@@ -127,8 +127,6 @@ bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
 void default_bc(BcArgs& b) {
   std::memset(&b, 0, sizeof(b));
   b.inlet_axis = 2;
-  b.out_axis = 2;
-  b.ghost_na = 1;
   b.ghost_n = 1;
 }
 
@@ -177,10 +175,9 @@ int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
   L->elem = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
   L->stream = (hipStream_t)c.stream;
   launch_shape(L);
-  // memory layout: populations | outflow ghost plane | partials | result
-  size_t face = (size_t)c.ny * c.nz;
-  if ((size_t)c.nx * c.nz > face) face = (size_t)c.nx * c.nz;
-  if ((size_t)c.nx * c.ny > face) face = (size_t)c.nx * c.ny;
+  // memory layout: populations | outflow ghost plane (one z plane) |
+  // reduction partials | result
+  const size_t face = (size_t)c.nx * c.ny;
   L->ghost_n_max = face;
   L->off_ghost = align256(L->N * L->Q * L->elem);
   L->off_partial = L->off_ghost + align256(face * L->Q * L->elem);
@@ -262,8 +259,8 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
       ++n_inlet;
     }
     if (ty == LBM_OUTFLOW) {
+      if (f / 2 != 2) return LBM_EINVAL;  // outflow faces are z faces
       b.outflow |= 1u << f;
-      b.out_axis = f / 2;
       ++n_out;
     }
   }
@@ -285,11 +282,7 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
     b.inlet_nb = n3[d == 2 ? 1 : 2];
     if (b.inlet_na >= 16384 || b.inlet_nb >= 16384) return LBM_EINVAL;
   }
-  if (n_out) {
-    const int d = b.out_axis;
-    b.ghost_na = n3[d == 0 ? 1 : 0];
-    b.ghost_n = (long long)b.ghost_na * n3[d == 2 ? 1 : 2];
-  }
+  if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
   L->args.bc = b;
   L->has_bc = b.nonper != 0;
   return LBM_OK;
