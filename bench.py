@@ -182,7 +182,8 @@ def main():
     print("bench: main done %.1f MLUPS" % main_res["mlups"], flush=True)
     others = []
     if not args.no_others:
-        for name in ["jet256-fclb-f16", "jet256-fclb-f64", "tgv256-mrt-f32", "tgv256-mrt-f16",
+        for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-mrt-f32", "jet256-mrt-f16",
+                     "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32"]:
             if name == args.workload:
                 continue

@@ -67,6 +67,22 @@ struct LatArgs {
   BcArgs bc;
 };
 
+// Which rows (fixed y, z; all x) a launch covers. BOX: y in [y0, y0+ny_in),
+// z in [z0, z0+nz_in) with blockIdx.z = z - z0. LIST: the rows lying on a
+// non-periodic y or z face, enumerated as the zb planes first, then the yb
+// rows of every other z; blockIdx.y is the row number.
+struct Rows {
+  int y0, ny_in, z0, nz_in;
+  int zb_n, zb[2];
+  int yb_n, yb[2];
+  int zi0;
+};
+enum { ROWS_BOX = 0, ROWS_LIST = 1 };
+// Boundary handling of a step kernel: none (all faces periodic), general
+// (any face type, any node), or x walls only (rows off every non-periodic
+// y/z face, x faces WALL or periodic).
+enum { BC_NONE = 0, BC_GENERAL = 1, BC_XWALL = 2 };
+
 // ---------------------------------------------------------------- storage
 template <typename S>
 struct Compute {
@@ -276,6 +292,54 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
   }
 }
 
+// Rows off the y/z faces: only the x faces can be crossed, and they are
+// walls. Population I (e_Ix = +1) enters through x- at x = 0, (e_Ix = -1)
+// through x+ at x = nx-1; the wall term is a per-direction constant.
+template <int Q, int I, typename S>
+__device__ __forceinline__ const S* pull_addr_xwall(const LatArgs& a, const S* F, const Node& n) {
+  constexpr int IO = opposite<Q>(I);
+  const size_t N = (size_t)a.N;
+  const S* normal = F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I));
+  if constexpr (cx(I) == 0) {
+    return normal;
+  } else {
+    const bool bb = (n.atface & (cx(I) > 0 ? 1u : 2u)) != 0;
+    return bb ? F + (size_t)I * N + n.self : normal;
+  }
+}
+
+template <int Q, int I, typename real>
+__device__ __forceinline__ real pull_term_xwall(const LatArgs& a, const Node& n) {
+  if constexpr (cx(I) == 0) {
+    return real(0);
+  } else {
+    constexpr int F = cx(I) > 0 ? 0 : 1;
+    const real t = real(6.0 * weight<Q>(I) *
+                        (cx(I) * a.bc.face_u[F][0] + cy(I) * a.bc.face_u[F][1] +
+                         cz(I) * a.bc.face_u[F][2]));
+    return (n.atface & (1u << F)) ? t : real(0);
+  }
+}
+
+template <int Q, int I, typename real, typename S>
+__device__ __forceinline__ void push_xwall(const LatArgs& a, S* F, const Node& n, real v) {
+  constexpr int IO = opposite<Q>(I);
+  const size_t N = (size_t)a.N;
+  S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
+  if constexpr (cx(I) == 0) {
+    st(normal, v);
+  } else {
+    // leaving through x+ (e_Ix = +1 at x = nx-1) returns as opp(I), which
+    // enters through x+: its wall term uses face 1, and vice versa
+    constexpr int Fc = cx(I) > 0 ? 1 : 0;
+    const bool bb = (n.atface & (1u << Fc)) != 0;
+    const real t = real(6.0 * weight<Q>(I) *
+                        (cx(IO) * a.bc.face_u[Fc][0] + cy(IO) * a.bc.face_u[Fc][1] +
+                         cz(IO) * a.bc.face_u[Fc][2]));
+    st(bb ? F + (size_t)IO * N + n.self : normal, bb ? v + t : v);
+  }
+}
+
 // --------------------------------------------------------------- kernels
 __device__ __forceinline__ bool node_coords(const LatArgs& a, int& x, int& y, int& z) {
   x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,14 +348,37 @@ __device__ __forceinline__ bool node_coords(const LatArgs& a, int& x, int& y, in
   return x < a.nx && y < a.ny;
 }
 
-// One collide-and-stream step of the uniform lattice at time t.
-template <int KIND, typename S, bool ODD, bool BC>
-__global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t) {
+template <int ROWS>
+__device__ __forceinline__ bool row_coords(const LatArgs& a, const Rows& r, int& x, int& y,
+                                           int& z) {
+  x = blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (ROWS == ROWS_BOX) {
+    y = r.y0 + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    z = r.z0 + (int)blockIdx.z;
+    return x < a.nx && y < r.y0 + r.ny_in;
+  } else {
+    const int row = blockIdx.y;
+    if (row < r.zb_n * a.ny) {
+      z = r.zb[row / a.ny];
+      y = row % a.ny;
+    } else {
+      const int k = row - r.zb_n * a.ny;
+      y = r.yb[k % r.yb_n];
+      z = r.zi0 + k / r.yb_n;
+    }
+    return x < a.nx;
+  }
+}
+
+// One collide-and-stream step at time t over the rows selected by r.
+template <int KIND, typename S, bool ODD, int BCM, int ROWS>
+__global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r, long long t) {
   using M = Model<KIND>;
   using real = typename Compute<S>::type;
   constexpr int Q = M::Q;
+  constexpr bool BC = BCM == BC_GENERAL;
   int x, y, z;
-  if (!node_coords(a, x, y, z)) return;
+  if (!row_coords<ROWS>(a, r, x, y, z)) return;
   const Node n = make_node(a, x, y, z);
   S* __restrict__ F = (S*)a.f;
   const size_t N = (size_t)a.N;
@@ -309,16 +396,27 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t)
       f[I] = ld<real>(F + (size_t)I * N + n.self);
     });
   } else {
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      f[I] = ld<real>(pull_addr<Q, I, S, BC>(a, F, n));
-    });
-    if constexpr (BC) {
-      const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
+    if constexpr (BCM == BC_XWALL) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] += pull_term<Q, I, real>(a, n, up);
+        f[I] = ld<real>(pull_addr_xwall<Q, I, S>(a, F, n));
       });
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        f[I] += pull_term_xwall<Q, I, real>(a, n);
+      });
+    } else {
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        f[I] = ld<real>(pull_addr<Q, I, S, BC>(a, F, n));
+      });
+      if constexpr (BC) {
+        const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
+        static_for<0, Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          f[I] += pull_term<Q, I, real>(a, n, up);
+        });
+      }
     }
   }
   M::collide(f, a);
@@ -339,11 +437,18 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, long long t)
       }
     }
   } else {
-    const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      push<Q, I, real, S, BC>(a, F, n, f[I], un);
-    });
+    if constexpr (BCM == BC_XWALL) {
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        push_xwall<Q, I, real, S>(a, F, n, f[I]);
+      });
+    } else {
+      const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        push<Q, I, real, S, BC>(a, F, n, f[I], un);
+      });
+    }
   }
 }
 

@@ -32,6 +32,11 @@ struct lbm_lattice {
   bool has_bc = false;
   LatArgs args;
   dim3 grid, block;
+  // odd steps with boundaries split into rows off the y/z faces (x walls
+  // only) and the rows on them
+  bool split_odd = false;
+  Rows rows_all, rows_inner, rows_bnd;
+  dim3 grid_inner, grid_bnd, block_bnd;
 };
 
 namespace {
@@ -56,40 +61,94 @@ void launch_shape(lbm_lattice* L) {
   L->nblocks = (size_t)L->grid.x * L->grid.y * L->grid.z;
 }
 
-template <typename S>
-int step_dispatch_s(lbm_lattice* L, bool odd, long long t) {
-  const LatArgs& a = L->args;
-#define LBM_STEP(KIND)                                                                        \
-  if (L->kind == KIND) {                                                                      \
-    if (odd) {                                                                                \
-      if (L->has_bc)                                                                          \
-        hipLaunchKernelGGL((step_kernel<KIND, S, true, true>), L->grid, L->block, 0,          \
-                           L->stream, a, t);                                                  \
-      else                                                                                    \
-        hipLaunchKernelGGL((step_kernel<KIND, S, true, false>), L->grid, L->block, 0,         \
-                           L->stream, a, t);                                                  \
-    } else {                                                                                  \
-      if (L->has_bc)                                                                          \
-        hipLaunchKernelGGL((step_kernel<KIND, S, false, true>), L->grid, L->block, 0,         \
-                           L->stream, a, t);                                                  \
-      else                                                                                    \
-        hipLaunchKernelGGL((step_kernel<KIND, S, false, false>), L->grid, L->block, 0,        \
-                           L->stream, a, t);                                                  \
-    }                                                                                         \
-  }
-  LBM_STEP(0)
-  LBM_STEP(1)
-  LBM_STEP(2)
-#undef LBM_STEP
-  return LBM_OK;
+template <int KIND, typename S, bool ODD, int BCM, int ROWS>
+void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t) {
+  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS>), grid, block, 0, L->stream, L->args,
+                     r, t);
 }
 
-int step_dispatch(lbm_lattice* L, bool odd, long long t) {
-  switch (L->cfg.storage) {
-    case LBM_F64: return step_dispatch_s<double>(L, odd, t);
-    case LBM_F32: return step_dispatch_s<float>(L, odd, t);
-    default: return step_dispatch_s<_Float16>(L, odd, t);
+template <int KIND, typename S>
+void step_model(const lbm_lattice* L, bool odd, long long t) {
+  if (!L->has_bc) {
+    if (odd)
+      launch_step<KIND, S, true, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+    else
+      launch_step<KIND, S, false, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+  } else if (!odd) {
+    launch_step<KIND, S, false, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+  } else if (!L->split_odd) {
+    launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+  } else {
+    if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
+      launch_step<KIND, S, true, BC_XWALL, ROWS_BOX>(L, L->grid_inner, L->block, L->rows_inner,
+                                                     t);
+    if (L->grid_bnd.y > 0)
+      launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST>(L, L->grid_bnd, L->block_bnd,
+                                                        L->rows_bnd, t);
   }
+}
+
+template <typename S>
+void step_dispatch_s(lbm_lattice* L, bool odd, long long t) {
+  switch (L->kind) {
+    case 0: step_model<0, S>(L, odd, t); break;
+    case 1: step_model<1, S>(L, odd, t); break;
+    default: step_model<2, S>(L, odd, t); break;
+  }
+}
+
+void step_dispatch(lbm_lattice* L, bool odd, long long t) {
+  switch (L->cfg.storage) {
+    case LBM_F64: step_dispatch_s<double>(L, odd, t); break;
+    case LBM_F32: step_dispatch_s<float>(L, odd, t); break;
+    default: step_dispatch_s<_Float16>(L, odd, t); break;
+  }
+}
+
+// Row sets of the split odd step for the current boundary description.
+void plan_rows(lbm_lattice* L) {
+  const int nx = L->cfg.nx, ny = L->cfg.ny, nz = L->cfg.nz;
+  const uint32_t np = L->args.bc.nonper;
+  Rows all{};
+  all.y0 = 0;
+  all.ny_in = ny;
+  all.z0 = 0;
+  all.nz_in = nz;
+  L->rows_all = all;
+  const bool ynp = (np & 12u) != 0, znp = (np & 48u) != 0;
+  Rows in = all;
+  if (ynp) {
+    in.y0 = 1;
+    in.ny_in = ny - 2;
+  }
+  if (znp) {
+    in.z0 = 1;
+    in.nz_in = nz - 2;
+  }
+  L->rows_inner = in;
+  Rows b{};
+  if (znp) {
+    b.zb_n = 2;
+    b.zb[0] = 0;
+    b.zb[1] = nz - 1;
+  }
+  if (ynp) {
+    b.yb_n = 2;
+    b.yb[0] = 0;
+    b.yb[1] = ny - 1;
+  }
+  b.zi0 = znp ? 1 : 0;
+  const long long nrows = (long long)b.zb_n * ny + (long long)b.yb_n * (nz - b.zb_n);
+  L->rows_bnd = b;
+  const uint32_t xbits = np & 3u;
+  const bool x_ok = (L->args.bc.inlet & 3u) == 0 && (xbits == 0 || (L->args.bc.wall & 3u) == 3u);
+  L->split_odd = L->has_bc && x_ok && nrows <= 65535;
+  const int bx = L->block.x, by = L->block.y;
+  L->grid_inner = dim3((nx + bx - 1) / bx, in.ny_in > 0 ? (in.ny_in + by - 1) / by : 0,
+                       in.nz_in > 0 ? in.nz_in : 0);
+  const int bbx = nx < 256 ? nx : 256;
+  L->block_bnd = dim3(bbx, 1, 1);
+  L->grid_bnd = dim3((nx + bbx - 1) / bbx, (unsigned)(nrows > 0 ? nrows : 0), 1);
 }
 
 // Runs fn<KIND, S, BC>() for the lattice's configuration.
@@ -205,6 +264,7 @@ int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
     }
   }
   default_bc(a.bc);
+  plan_rows(L);
   *out = L;
   return LBM_OK;
 }
@@ -285,6 +345,7 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
   if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
   L->args.bc = b;
   L->has_bc = b.nonper != 0;
+  plan_rows(L);
   return LBM_OK;
 }
 

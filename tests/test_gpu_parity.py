@@ -60,7 +60,8 @@ def test_periodic_step_parity_fp64(name, shape):
 
 
 @pytest.mark.parametrize("name", NAMES)
-@pytest.mark.parametrize("layout", ["jet", "zoutflow_lo", "x_inlet", "y_inlet_walls"])
+@pytest.mark.parametrize("layout", ["jet", "zoutflow_lo", "x_inlet", "y_inlet_walls",
+                                    "xwalls_only", "channel_thin"])
 def test_boundary_step_parity_fp64(name, layout):
     fu = face_velocities(0.002)
     fu[4] = [0.0, 0.0, 0.0]
@@ -73,8 +74,13 @@ def test_boundary_step_parity_fp64(name, layout):
         faces, inlet = [P, P, W, W, O, I], synth.jet_inlet(nx, ny, 4.0, 0.04, 0.001)
     elif layout == "x_inlet":
         faces, inlet = [I, W, P, P, W, O], synth.jet_inlet(ny, nz, 3.0, 0.04, 0.001, axis=0)
-    else:
+    elif layout == "y_inlet_walls":
         faces, inlet = [W, W, W, I, O, W], synth.jet_inlet(nx, nz, 3.0, 0.04, 0.001, axis=1)
+    elif layout == "xwalls_only":
+        faces, inlet = [W, W, P, P, P, P], None
+    else:  # walls two nodes apart in y: no interior rows at all
+        faces, inlet = [W, W, W, W, I, O], synth.jet_inlet(nx, 2, 2.0, 0.04, 0.001)
+        shape = (nx, 2, nz)
     errs = _run_pair(name, "f64", shape, 0.02, [1, 2, 6], faces=faces, face_u=fu, inlet=inlet,
                      amp=5e-4, seed=12060389, t0=3)
     assert max(errs) <= TOL["f64"], errs
