@@ -31,9 +31,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS and % of HBM roofline, D3Q19-MRT and D3Q27-FCLB, FP32/FP16 vs FP64"
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
-# traffic measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE for the default
-# workload's step kernel, in bytes per launch (None until profiled again).
-MEASURED_TRAFFIC = None
+# HBM bytes per step of the default workload measured with rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (scaled by a copy kernel of known size), valid only
+# for the kernel sources whose hash is recorded with it.
+MEASURED_TRAFFIC = {"bytes_per_step": 7.418e9, "sources_sha256_16": "117cefa8ea91810e",
+                    "workload": "jet256-fclb-f32"}
+
+
+def sources_hash():
+    import glob
+    import hashlib
+    m = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1206_0389_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
 
 
 def parse():
@@ -195,7 +207,10 @@ def main():
     alg_per_launch = main_res["bytes_per_lup"] * shape[0] * shape[1] * shape[2]
     roof = {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": main_res["achieved_GBs"] / HBM_PEAK_GBS,
-            "traffic": MEASURED_TRAFFIC,
+            "traffic": (MEASURED_TRAFFIC["bytes_per_step"]
+                        if (MEASURED_TRAFFIC["sources_sha256_16"] == sources_hash()
+                            and MEASURED_TRAFFIC["workload"] == args.workload) else None),
+            "traffic_unit": "bytes per step (one even launch, or the two odd launches)",
             "kernel": "step_kernel<%s,%s>" % (model, storage),
             "algorithmic_bytes_per_launch": alg_per_launch,
             "copy_probe_GBs": copy_gbs,
