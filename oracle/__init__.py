@@ -99,6 +99,18 @@ def lib():
         L.orc_macroscopic.argtypes = [pp, dp, dp, dp]
         L.orc_init_equilibrium.argtypes = [pp, dp, dp, dp]
         L.orc_reduce.argtypes = [pp, dp, dp]
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        L.orc_refine_create.argtypes = [pp, ctypes.c_int, u8p, dp, u8p]
+        L.orc_refine_create.restype = ctypes.c_void_p
+        L.orc_refine_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_refine_geometry.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int64), dp]
+        L.orc_refine_types.argtypes = [ctypes.c_void_p, u8p, u8p]
+        L.orc_refine_ghosts.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), dp, dp]
+        L.orc_refine_rescale.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
+        L.orc_refine_inject.argtypes = [ctypes.c_void_p, dp, dp]
+        L.orc_refine_run.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int64, ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -259,3 +271,93 @@ class Lattice:
         out = np.zeros(5)
         lib().orc_reduce(ctypes.byref(self.p), _dp(_f64(f)), _dp(out))
         return out
+
+
+class Refined:
+    """Two-level nested refinement in the oracle (post-collision storage).
+
+    coarse: a :class:`Lattice` describing the full coarse domain; block: the
+    block edge in coarse nodes; mask: uint8 [nz/B][ny/B][nx/B]; fine inlet
+    arrays at fine resolution when the coarse lattice has an inlet face.
+    """
+
+    def __init__(self, coarse: Lattice, block: int, mask, fine_inlet_u=None,
+                 fine_inlet_mask=None):
+        self.coarse = coarse
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        self._keep = [self.mask]
+        fu = fm = None
+        if fine_inlet_u is not None:
+            fu = _f64(fine_inlet_u)
+            self._keep.append(fu)
+            fu = _dp(fu)
+        if fine_inlet_mask is not None:
+            fm = np.ascontiguousarray(fine_inlet_mask, dtype=np.uint8)
+            self._keep.append(fm)
+            fm = fm.ctypes.data_as(u8p)
+        self.h = lib().orc_refine_create(ctypes.byref(coarse.p), int(block),
+                                         self.mask.ctypes.data_as(u8p), fu, fm)
+        if not self.h:
+            raise ValueError("invalid refinement configuration")
+        lo = (ctypes.c_int32 * 3)()
+        M = (ctypes.c_int32 * 3)()
+        cnt = (ctypes.c_int64 * 4)()
+        r = ctypes.c_double()
+        lib().orc_refine_geometry(self.h, lo, M, cnt, ctypes.byref(r))
+        self.lo = tuple(lo)
+        self.M = tuple(M)  # (Mx, My, Mz)
+        self.counts = dict(zip(("fluid", "ghost", "covered", "band"), tuple(cnt)))
+        self.r = r.value
+        self.Q = coarse.Q
+        self.fine_shape = (self.M[2], self.M[1], self.M[0])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_refine_destroy(self.h)
+            self.h = None
+
+    def types(self):
+        ct = np.zeros(self.coarse.shape, dtype=np.uint8)
+        ft = np.zeros(self.fine_shape, dtype=np.uint8)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        lib().orc_refine_types(self.h, ct.ctypes.data_as(u8p), ft.ctypes.data_as(u8p))
+        return ct, ft
+
+    def ghosts(self, fc=None):
+        ng = self.counts["ghost"]
+        coords = np.zeros((ng, 3), dtype=np.int32)
+        g = None
+        if fc is not None:
+            g = np.zeros((self.Q, ng))
+            lib().orc_refine_ghosts(self.h, coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    _dp(_f64(fc)), _dp(g))
+        else:
+            lib().orc_refine_ghosts(self.h, coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    None, None)
+        return coords, g
+
+    def rescale(self, f, s):
+        out = np.zeros(self.Q)
+        lib().orc_refine_rescale(self.h, _dp(_f64(f)), float(s), _dp(out))
+        return out
+
+    def inject(self, fc, ff):
+        fc = _f64(fc).copy()
+        lib().orc_refine_inject(self.h, _dp(fc), _dp(_f64(ff)))
+        return fc
+
+    def run(self, fc, ff, t0, n):
+        fc = _f64(fc).copy()
+        ff = _f64(ff).copy()
+        lib().orc_refine_run(self.h, _dp(fc), _dp(ff), int(t0), int(n))
+        return fc, ff
+
+    def fine_lattice(self):
+        """An oracle Lattice describing the fine box (fine viscosity), for
+        equilibria and macroscopic readouts of the fine level."""
+        c = self.coarse
+        lat = Lattice(c.model, self.M[0], self.M[1], self.M[2], nu=2.0 * c.p.nu,
+                      cs_smag=c.p.cs_smag, basis=c.p.mrt_basis,
+                      rates=list(c.p.rates)[:5])
+        return lat

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -606,6 +607,472 @@ void orc_reduce(const orc_params* p, const double* f, double* out) {
     s[4] += 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho;
   }
   for (int k = 0; k < 5; ++k) out[k] = s[k];
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Two-level nested time refinement (Section 1: hierarchical block grid with a
+// nested time step, Yu et al.'s interpolation and rescaling; Section 3:
+// refinement levels, constant CFL). The paper cites the method and prints no
+// formulas; this follows the readings recorded in the design notes:
+//  * 2:1 vertex-centred nesting: fine node j sits at coarse coordinate j/2;
+//    a refined coarse block of B^3 nodes carries (2B)^3 fine nodes;
+//    dt_f = dt_c / 2, so in lattice units nu_f = 2 nu_c (tau_f - 1/2 =
+//    2 (tau_c - 1/2)) and velocities are equal on both levels.
+//  * Both levels store post-collision values and advance by pull + collide.
+//  * Fine ghost nodes (outside the refined region, next to it) hold coarse
+//    post-collision populations interpolated in space (tensor 4-point cubic
+//    Lagrange, one-sided near non-periodic domain faces) and in time (linear
+//    between the coarse states at t and t+1 for the half step), rescaled
+//    f_f = f_eq + r (f_c - f_eq), r = (tau_f - 1) / (2 (tau_c - 1)).
+//  * Covered coarse nodes (refined, outside every ghost stencil) receive
+//    f_c = f_eq + (f_f - f_eq) / r from the coincident fine node after each
+//    coarse step.
+// ===========================================================================
+
+namespace {
+
+struct Refine {
+  orc_params c;      // coarse lattice (full domain)
+  orc_params f;      // fine level: global fine extent 2N, fine viscosity
+  int B;             // block size (coarse nodes)
+  int nb[3];         // blocks per axis
+  std::vector<uint8_t> mask;
+  int lo[3], M[3];   // fine box origin (global fine coords) and extent
+  std::vector<uint8_t> ctype;  // 0 outside R, 1 refined (band), 2 covered
+  std::vector<uint8_t> ftype;  // 0 inactive, 1 fluid, 2 ghost
+  std::vector<long> ghosts;    // fine box indices of ghost nodes
+  double r;
+  int Q;
+  std::vector<double> g0, g1;  // interpolated coarse values at ghosts [Q][ng]
+  bool have_g0 = false;
+};
+
+bool refined_block(const Refine& R, int bx, int by, int bz) {
+  return R.mask[((long)bz * R.nb[1] + by) * R.nb[0] + bx] != 0;
+}
+
+bool coarse_in_R(const Refine& R, int x, int y, int z) {
+  return refined_block(R, x / R.B, y / R.B, z / R.B);
+}
+
+bool fine_in_R(const Refine& R, int jx, int jy, int jz) {
+  const int n2[3] = {2 * R.c.nx, 2 * R.c.ny, 2 * R.c.nz};
+  if (jx < 0 || jy < 0 || jz < 0 || jx >= n2[0] || jy >= n2[1] || jz >= n2[2]) return false;
+  return refined_block(R, jx / (2 * R.B), jy / (2 * R.B), jz / (2 * R.B));
+}
+
+long fidx(const Refine& R, int lx, int ly, int lz) {
+  return ((long)lz * R.M[1] + ly) * R.M[0] + lx;
+}
+
+// 4-point Lagrange weights at position p on nodes s..s+3.
+void lagrange4(double p, int s, double w[4]) {
+  for (int a = 0; a < 4; ++a) {
+    double v = 1.0;
+    for (int b = 0; b < 4; ++b)
+      if (b != a) v *= (p - (s + b)) / (double)(a - b);
+    w[a] = v;
+  }
+}
+
+// Stencil of fine coordinate j along an axis of n coarse nodes: nodes and
+// weights (1 node if j is even, 4 otherwise; indices wrapped if periodic).
+int stencil1d(int j, int n, bool periodic, int idx[4], double w[4]) {
+  if (j % 2 == 0) {
+    int c = j / 2;
+    if (periodic) c = ((c % n) + n) % n;
+    idx[0] = c;
+    w[0] = 1.0;
+    return 1;
+  }
+  const double p = 0.5 * j;
+  int s = (j - 1) / 2 - 1;
+  if (!periodic) {
+    if (s < 0) s = 0;
+    if (s > n - 4) s = n - 4;
+  }
+  lagrange4(p, s, w);
+  for (int a = 0; a < 4; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
+  return 4;
+}
+
+void ghost_global(const Refine& R, long gi, int j[3]) {
+  const long l = R.ghosts[gi];
+  const int lx = (int)(l % R.M[0]), ly = (int)((l / R.M[0]) % R.M[1]),
+            lz = (int)(l / ((long)R.M[0] * R.M[1]));
+  j[0] = lx + R.lo[0];
+  j[1] = ly + R.lo[1];
+  j[2] = lz + R.lo[2];
+}
+
+// Spatial interpolation of coarse post-collision values at every ghost.
+void interp_ghosts(const Refine& R, const double* fc, std::vector<double>& out) {
+  const long ng = (long)R.ghosts.size();
+  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
+  const int n3[3] = {R.c.nx, R.c.ny, R.c.nz};
+  out.assign((size_t)R.Q * ng, 0.0);
+  #pragma omp parallel for schedule(static)
+  for (long gi = 0; gi < ng; ++gi) {
+    int j[3];
+    ghost_global(R, gi, j);
+    int idx[3][4];
+    double w[3][4];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d)
+      cnt[d] = stencil1d(j[d], n3[d], R.c.face_type[2 * d] == ORC_PERIODIC, idx[d], w[d]);
+    for (int q = 0; q < R.Q; ++q) {
+      double s = 0.0;
+      for (int c = 0; c < cnt[2]; ++c)
+        for (int b = 0; b < cnt[1]; ++b)
+          for (int a = 0; a < cnt[0]; ++a) {
+            const long n = ((long)idx[2][c] * R.c.ny + idx[1][b]) * R.c.nx + idx[0][a];
+            s += w[0][a] * w[1][b] * w[2][c] * fc[q * Nc + n];
+          }
+      out[(size_t)q * ng + gi] = s;
+    }
+  }
+}
+
+// The model's equilibrium (deviation form) for the moments of f.
+void equilibrium_of(int model, const double* f, double* feq) {
+  const int Q = nq(model);
+  double d = 0.0, j[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    for (int a = 0; a < 3; ++a) j[a] += f[i] * E[i][a];
+  }
+  if (model == ORC_MRT19) {
+    feq_incomp(19, d, j, feq);
+  } else {
+    const double rho = 1.0 + d;
+    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    for (int i = 0; i < 27; ++i)
+      feq[i] = rho * phi(E[i][0], u[0]) * phi(E[i][1], u[1]) * phi(E[i][2], u[2]) -
+               weight(27, i);
+  }
+}
+
+// f_eq + s (f - f_eq) for one node.
+void rescale_node(int model, const double* f, double s, double* out) {
+  double feq[27];
+  equilibrium_of(model, f, feq);
+  for (int i = 0; i < nq(model); ++i) out[i] = feq[i] + s * (f[i] - feq[i]);
+}
+
+void fill_ghosts(const Refine& R, const std::vector<double>& g, double* ff) {
+  const long ng = (long)R.ghosts.size();
+  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+  #pragma omp parallel for schedule(static)
+  for (long gi = 0; gi < ng; ++gi) {
+    double a[27], b[27];
+    for (int q = 0; q < R.Q; ++q) a[q] = g[(size_t)q * ng + gi];
+    rescale_node(R.c.model, a, R.r, b);
+    for (int q = 0; q < R.Q; ++q) ff[q * Nf + R.ghosts[gi]] = b[q];
+  }
+}
+
+void inject(const Refine& R, double* fc, const double* ff) {
+  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
+  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+  #pragma omp parallel for schedule(static)
+  for (long n = 0; n < Nc; ++n) {
+    if (R.ctype[n] != 2) continue;
+    const int x = (int)(n % R.c.nx), y = (int)((n / R.c.nx) % R.c.ny),
+              z = (int)(n / ((long)R.c.nx * R.c.ny));
+    const long l = fidx(R, 2 * x - R.lo[0], 2 * y - R.lo[1], 2 * z - R.lo[2]);
+    double a[27], b[27];
+    for (int q = 0; q < R.Q; ++q) a[q] = ff[q * Nf + l];
+    rescale_node(R.c.model, a, 1.0 / R.r, b);
+    for (int q = 0; q < R.Q; ++q) fc[q * Nc + n] = b[q];
+  }
+}
+
+// Coarse step in post-collision storage: out = C(pull(in)) on nodes that
+// are not covered (covered nodes are left as they are).
+void coarse_step(const Refine& R, const double* in, double* out, int64_t t) {
+  const orc_params* p = &R.c;
+  const long N = (long)p->nx * p->ny * p->nz;
+  const int Q = R.Q;
+  #pragma omp parallel for schedule(static)
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const long n = node_index(p, x, y, z);
+        if (R.ctype[n] == 2) continue;
+        double a[27], b[27];
+        for (int i = 0; i < Q; ++i) a[i] = pull(p, in, Q, i, x, y, z, t);
+        collide_node(p, a, b);
+        for (int i = 0; i < Q; ++i) out[i * N + n] = b[i];
+      }
+}
+
+// Pull on the fine level: sources inside the box come from the box (fluid
+// or ghost nodes); sources beyond a domain face follow the boundary rules on
+// the fine level (R.f: global fine extent, fine inlet arrays).
+double fine_pull(const Refine& R, const double* in, int i, int lx, int ly, int lz, int64_t t) {
+  const orc_params* p = &R.f;
+  const int j[3] = {lx + R.lo[0], ly + R.lo[1], lz + R.lo[2]};
+  const int n[3] = {p->nx, p->ny, p->nz};
+  int s[3] = {j[0] - E[i][0], j[1] - E[i][1], j[2] - E[i][2]};
+  int crossed[6] = {0, 0, 0, 0, 0, 0};
+  bool any = false;
+  for (int d = 0; d < 3; ++d) {
+    int face = -1;
+    if (s[d] < 0) face = 2 * d;
+    else if (s[d] >= n[d]) face = 2 * d + 1;
+    if (face < 0) continue;
+    if (p->face_type[face] == ORC_PERIODIC) {
+      s[d] = (s[d] + n[d]) % n[d];
+    } else {
+      crossed[face] = 1;
+      any = true;
+    }
+  }
+  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+  const long self = fidx(R, lx, ly, lz);
+  const int Q = R.Q;
+  if (any) {
+    const int io = opposite(Q, i);
+    for (int face = 0; face < 6; ++face)
+      if (crossed[face] && p->face_type[face] == ORC_WALL) {
+        const double* uw = p->face_u[face];
+        return in[io * Nf + self] + 6.0 * weight(Q, i) *
+                                        (E[i][0] * uw[0] + E[i][1] * uw[1] + E[i][2] * uw[2]);
+      }
+    for (int face = 0; face < 6; ++face)
+      if (crossed[face] && p->face_type[face] == ORC_INLET) {
+        double uin[3];
+        inlet_velocity(p, face, j[0], j[1], j[2], t, uin);
+        return in[io * Nf + self] +
+               6.0 * weight(Q, i) * (E[i][0] * uin[0] + E[i][1] * uin[1] + E[i][2] * uin[2]);
+      }
+    for (int d = 0; d < 3; ++d) {
+      if (s[d] < 0) s[d] = 0;
+      if (s[d] >= n[d]) s[d] = n[d] - 1;
+    }
+  }
+  return in[i * Nf + fidx(R, s[0] - R.lo[0], s[1] - R.lo[1], s[2] - R.lo[2])];
+}
+
+void fine_step(const Refine& R, const double* in, double* out, int64_t t) {
+  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+  const int Q = R.Q;
+  #pragma omp parallel for schedule(static)
+  for (int lz = 0; lz < R.M[2]; ++lz)
+    for (int ly = 0; ly < R.M[1]; ++ly)
+      for (int lx = 0; lx < R.M[0]; ++lx) {
+        const long l = fidx(R, lx, ly, lz);
+        if (R.ftype[l] != 1) continue;
+        double a[27], b[27];
+        for (int i = 0; i < Q; ++i) a[i] = fine_pull(R, in, i, lx, ly, lz, t);
+        collide_node(&R.f, a, b);
+        for (int i = 0; i < Q; ++i) out[i * Nf + l] = b[i];
+      }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Build the two-level geometry. coarse: full-domain lattice parameters;
+// block: block edge in coarse nodes (must divide nx, ny, nz); mask:
+// [nz/B][ny/B][nx/B], 1 = refined; fine inlet arrays at fine resolution
+// ([3][2 nb][2 na], may be null if there is no inlet). Returns null on a
+// bad configuration.
+void* orc_refine_create(const orc_params* coarse, int block, const uint8_t* mask,
+                        const double* fine_inlet_u, const uint8_t* fine_inlet_mask) {
+  if (block < 2 || coarse->nx % block || coarse->ny % block || coarse->nz % block) return nullptr;
+  Refine* R = new Refine();
+  R->c = *coarse;
+  R->B = block;
+  R->Q = nq(coarse->model);
+  R->nb[0] = coarse->nx / block;
+  R->nb[1] = coarse->ny / block;
+  R->nb[2] = coarse->nz / block;
+  const long nblk = (long)R->nb[0] * R->nb[1] * R->nb[2];
+  R->mask.assign(mask, mask + nblk);
+  // fine level parameters
+  R->f = *coarse;
+  R->f.nx = 2 * coarse->nx;
+  R->f.ny = 2 * coarse->ny;
+  R->f.nz = 2 * coarse->nz;
+  R->f.nu = 2.0 * coarse->nu;
+  R->f.inlet_u = fine_inlet_u;
+  R->f.inlet_mask = fine_inlet_mask;
+  R->f.inlet_na = 0;
+  R->f.inlet_nb = 0;
+  for (int face = 0; face < 6; ++face)
+    if (coarse->face_type[face] == ORC_INLET) {
+      const int d = face / 2;
+      const int n2[3] = {R->f.nx, R->f.ny, R->f.nz};
+      R->f.inlet_na = n2[d == 0 ? 1 : 0];
+      R->f.inlet_nb = n2[d == 2 ? 1 : 2];
+    }
+  R->f.seed = coarse->seed + 1;
+  for (int k = 0; k < 3; ++k) R->f.origin[k] = 0;
+  const double tc = 3.0 * coarse->nu + 0.5, tf = 3.0 * R->f.nu + 0.5;
+  R->r = (tf - 1.0) / (2.0 * (tc - 1.0));
+  // fine box: bounding box of the refined blocks, one ghost layer beyond
+  // every side that is not a domain face
+  int blo[3] = {1 << 30, 1 << 30, 1 << 30}, bhi[3] = {-1, -1, -1};
+  for (int bz = 0; bz < R->nb[2]; ++bz)
+    for (int by = 0; by < R->nb[1]; ++by)
+      for (int bx = 0; bx < R->nb[0]; ++bx)
+        if (refined_block(*R, bx, by, bz)) {
+          const int b3[3] = {bx, by, bz};
+          for (int d = 0; d < 3; ++d) {
+            blo[d] = std::min(blo[d], b3[d]);
+            bhi[d] = std::max(bhi[d], b3[d] + 1);
+          }
+        }
+  for (int d = 0; d < 3 && bhi[0] >= 0; ++d)
+    if (coarse->face_type[2 * d] == ORC_PERIODIC) {
+      const bool full = blo[d] == 0 && bhi[d] == R->nb[d];
+      const bool inside = blo[d] > 0 && bhi[d] < R->nb[d];
+      if (!full && !inside) {  // a wrapped fine pull would leave the box
+        delete R;
+        return nullptr;
+      }
+    }
+  if (bhi[0] < 0) {  // nothing refined: an empty fine level
+    for (int d = 0; d < 3; ++d) {
+      R->lo[d] = 0;
+      R->M[d] = 0;
+    }
+  } else {
+    const int n2[3] = {R->f.nx, R->f.ny, R->f.nz};
+    for (int d = 0; d < 3; ++d) {
+      int a = 2 * block * blo[d], b = 2 * block * bhi[d];
+      if (a > 0) a -= 1;
+      if (b < n2[d]) b += 1;
+      R->lo[d] = a;
+      R->M[d] = b - a;
+    }
+  }
+  const long Nf = (long)R->M[0] * R->M[1] * R->M[2];
+  R->ftype.assign(Nf, 0);
+  for (int lz = 0; lz < R->M[2]; ++lz)
+    for (int ly = 0; ly < R->M[1]; ++ly)
+      for (int lx = 0; lx < R->M[0]; ++lx) {
+        const int jx = lx + R->lo[0], jy = ly + R->lo[1], jz = lz + R->lo[2];
+        uint8_t t = 0;
+        if (fine_in_R(*R, jx, jy, jz)) {
+          t = 1;
+        } else {
+          for (int dz = -1; dz <= 1 && !t; ++dz)
+            for (int dy = -1; dy <= 1 && !t; ++dy)
+              for (int dx = -1; dx <= 1 && !t; ++dx)
+                if (fine_in_R(*R, jx + dx, jy + dy, jz + dz)) t = 2;
+        }
+        R->ftype[fidx(*R, lx, ly, lz)] = t;
+        if (t == 2) R->ghosts.push_back(fidx(*R, lx, ly, lz));
+      }
+  // coarse types: refined nodes are covered unless a ghost stencil uses them
+  const long Nc = (long)coarse->nx * coarse->ny * coarse->nz;
+  R->ctype.assign(Nc, 0);
+  for (int z = 0; z < coarse->nz; ++z)
+    for (int y = 0; y < coarse->ny; ++y)
+      for (int x = 0; x < coarse->nx; ++x)
+        if (coarse_in_R(*R, x, y, z)) R->ctype[((long)z * coarse->ny + y) * coarse->nx + x] = 2;
+  const int n3[3] = {coarse->nx, coarse->ny, coarse->nz};
+  for (long gi = 0; gi < (long)R->ghosts.size(); ++gi) {
+    int j[3];
+    ghost_global(*R, gi, j);
+    int idx[3][4];
+    double w[3][4];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d)
+      cnt[d] = stencil1d(j[d], n3[d], coarse->face_type[2 * d] == ORC_PERIODIC, idx[d], w[d]);
+    for (int c = 0; c < cnt[2]; ++c)
+      for (int b = 0; b < cnt[1]; ++b)
+        for (int a = 0; a < cnt[0]; ++a) {
+          const long n = ((long)idx[2][c] * coarse->ny + idx[1][b]) * coarse->nx + idx[0][a];
+          if (R->ctype[n] == 2) R->ctype[n] = 1;
+        }
+  }
+  return R;
+}
+
+void orc_refine_destroy(void* h) { delete (Refine*)h; }
+
+// lo[3], M[3]; counts = {fluid, ghost, covered, band}; ratio r.
+void orc_refine_geometry(void* h, int32_t* lo, int32_t* M, int64_t* counts, double* r) {
+  const Refine& R = *(Refine*)h;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = R.lo[d];
+    M[d] = R.M[d];
+  }
+  int64_t nf = 0, ng = 0, nc = 0, nbnd = 0;
+  for (uint8_t t : R.ftype) {
+    nf += t == 1;
+    ng += t == 2;
+  }
+  for (uint8_t t : R.ctype) {
+    nc += t == 2;
+    nbnd += t == 1;
+  }
+  counts[0] = nf;
+  counts[1] = ng;
+  counts[2] = nc;
+  counts[3] = nbnd;
+  *r = R.r;
+}
+
+void orc_refine_types(void* h, uint8_t* ctype, uint8_t* ftype) {
+  const Refine& R = *(Refine*)h;
+  std::memcpy(ctype, R.ctype.data(), R.ctype.size());
+  std::memcpy(ftype, R.ftype.data(), R.ftype.size());
+}
+
+// Ghost fine global coordinates [ng][3] and the raw (not rescaled) spatial
+// interpolation of a coarse field fc ([Q][Nc]) at them, [Q][ng].
+void orc_refine_ghosts(void* h, int32_t* coords, const double* fc, double* g) {
+  const Refine& R = *(Refine*)h;
+  for (long gi = 0; gi < (long)R.ghosts.size(); ++gi) {
+    int j[3];
+    ghost_global(R, gi, j);
+    for (int d = 0; d < 3; ++d) coords[3 * gi + d] = j[d];
+  }
+  if (fc && g) {
+    std::vector<double> out;
+    interp_ghosts(R, fc, out);
+    std::memcpy(g, out.data(), out.size() * sizeof(double));
+  }
+}
+
+// f_eq + s (f - f_eq) on one node of the refined model.
+void orc_refine_rescale(void* h, const double* f, double s, double* out) {
+  const Refine& R = *(Refine*)h;
+  rescale_node(R.c.model, f, s, out);
+}
+
+void orc_refine_inject(void* h, double* fc, const double* ff) {
+  inject(*(Refine*)h, fc, ff);
+}
+
+// Advance n coarse steps from coarse time t0. fc: coarse post-collision
+// state [Q][Nc]; ff: fine box post-collision state [Q][M]; both in place.
+// Fine step indices (inlet perturbation) are 2t and 2t+1.
+void orc_refine_run(void* h, double* fc, double* ff, int64_t t0, int64_t n) {
+  Refine& R = *(Refine*)h;
+  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
+  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+  std::vector<double> bc(fc, fc + (size_t)R.Q * Nc), bf(ff, ff + (size_t)R.Q * Nf);
+  std::vector<double> g0, g1;
+  for (int64_t t = t0; t < t0 + n; ++t) {
+    interp_ghosts(R, fc, g0);
+    fill_ghosts(R, g0, ff);
+    coarse_step(R, fc, bc.data(), t);
+    fine_step(R, ff, bf.data(), 2 * t);
+    interp_ghosts(R, bc.data(), g1);
+    for (size_t k = 0; k < g0.size(); ++k) g0[k] = 0.5 * (g0[k] + g1[k]);
+    fill_ghosts(R, g0, bf.data());
+    fine_step(R, bf.data(), ff, 2 * t + 1);
+    std::memcpy(fc, bc.data(), sizeof(double) * R.Q * Nc);
+    inject(R, fc, ff);
+  }
 }
 
 }  // extern "C"
