@@ -64,14 +64,57 @@ def workload(name):
     """(model, storage, shape, kind) from a name like jet256-fclb-f32."""
     kind, model, storage = name.split("-")
     shapes = {"jet256": (256, 256, 512), "tgv256": (256, 256, 512), "tgv128": (128, 128, 128),
-              "jet128": (128, 128, 256)}
+              "jet128": (128, 128, 256), "ref128": (128, 128, 256)}
     return model, storage, shapes[kind], kind
+
+
+def refined_jet_mask(nx, ny, nz, B=16, layers=8, radius=62.0):
+    """Blocks of the first `layers` streamwise block layers whose centre lies
+    within `radius` coarse nodes of the jet axis."""
+    import numpy as np
+    m = np.zeros((nz // B, ny // B, nx // B), dtype=np.uint8)
+    for bz in range(layers):
+        for by in range(ny // B):
+            for bx in range(nx // B):
+                cx, cy = (bx + 0.5) * B - nx / 2, (by + 0.5) * B - ny / 2
+                if cx * cx + cy * cy <= radius * radius:
+                    m[bz, by, bx] = 1
+    return m
 
 
 def make_lattice(name, P, torch, synth):
     import numpy as np
     model, storage, shape, kind = workload(name)
     nx, ny, nz = shape
+    if kind == "ref128":
+        nu, cs, B = 1e-4, 0.1, 16
+        mask = refined_jet_mask(nx, ny, nz, B)
+        iu, im = synth.jet_inlet(nx, ny, 16.0, 0.05, 0.002)
+        fiu, fim = synth.jet_inlet(2 * nx, 2 * ny, 32.0, 0.05, 0.002)
+        fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
+        lat = P.RefinedLattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs,
+                               block=B, mask=mask,
+                               faces=[P.WALL] * 4 + [P.INLET, P.OUTFLOW], face_u=fu,
+                               inlet_u=torch.from_numpy(iu), inlet_mask=torch.from_numpy(im),
+                               fine_inlet_u=torch.from_numpy(fiu),
+                               fine_inlet_mask=torch.from_numpy(fim), inlet_amp=5e-4,
+                               seed=12060389)
+        for level in (0, 1):
+            d, u = synth.uniform_fields(*lat.shape3(level)[::-1], u=(0.0, 0.0, 0.002),
+                                        dtype=np.float32)
+            lat.init_equilibrium(level, torch.from_numpy(d), torch.from_numpy(u))
+        c = lat.counts
+        desc = {"workload": "two-level refined round jet, coarse %dx%dx%d, 16^3 blocks, %d of %d "
+                            "blocks refined (layers 0-7, centre radius <= 62), D=16 coarse / 32 "
+                            "fine inlet u=0.05 +1%% perturbation, co-flow 0.002, nu_c=1e-4"
+                            % (nx, ny, nz, int(mask.sum()), mask.size),
+                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "fine_nodes": c["fluid"], "ghost_nodes": c["ghost"],
+                "covered_coarse": c["covered"],
+                "updates_per_coarse_step": nx * ny * nz - c["covered"] + 2 * c["fluid"],
+                "cs_smag": cs if model == "mrt" else None}
+        lat.updates_per_step = desc["updates_per_coarse_step"]
+        return lat, desc
     if kind.startswith("jet"):
         nu, cs = 1e-4, 0.1
         lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs)
@@ -119,7 +162,7 @@ def measure(name, P, torch, synth, steps, warmup):
     red = lat.reduce(check=False)
     model, storage, shape, _ = workload(name)
     q = 27 if model == "fclb" else 19
-    n = shape[0] * shape[1] * shape[2]
+    n = getattr(lat, "updates_per_step", shape[0] * shape[1] * shape[2])
     alg_bytes = 2 * q * BYTES[storage] * n
     gbs = alg_bytes / (ms * 1e-3) / 1e9
     out = {"name": name, "mlups": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
@@ -196,7 +239,8 @@ def main():
     if not args.no_others:
         for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-mrt-f32", "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
-                     "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32"]:
+                     "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
+                     "ref128-mrt-f32"]:
             if name == args.workload:
                 continue
             r = measure(name, P, torch, synth, args.other_steps, 10)

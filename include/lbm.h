@@ -218,6 +218,84 @@ const char* lbm_strerror(int status);
  * Both buffers device, 16-byte aligned, non-overlapping. */
 int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
 
+
+/* ======================================================================
+ * Two-level nested time refinement on a block grid (the hierarchical
+ * block grid with nested time steps of Section 1 and of the numerical
+ * set-up in Section 3; interface interpolation and rescaling after Yu et
+ * al., cited there without formulas: the readings are in the design notes).
+ *
+ * Level 0 is the coarse lattice cfg->nx x ny x nz (lattice viscosity
+ * cfg->nu). Level 1 refines by 2 in space and time the union of the blocks
+ * (block^3 coarse nodes each) whose refine_mask entry is 1: fine node j of
+ * an axis sits at coarse coordinate j/2, the fine viscosity in fine lattice
+ * units is 2 nu, velocities are equal on both levels. The fine level is
+ * stored over a box (lbm_refined_geometry: origin lo in fine coordinates,
+ * extent dims) holding the refined nodes plus one layer of ghost nodes.
+ * Both levels hold post-collision populations (deviations, ABI order);
+ * one lbm_refined_step advances one coarse step = two fine steps.
+ * Covered coarse nodes (refined and not read by the interface
+ * interpolation) are overwritten from the fine level after each step.
+ * ====================================================================== */
+typedef struct lbm_refined lbm_refined;
+
+/* refine_mask: host uint8 [nz/block][ny/block][nx/block] (copied); block
+ * >= 2 divides nx, ny, nz; every extent >= 4; tau = 3 nu + 1/2 must differ
+ * from 1 on both levels (the rescale factor (tau_f-1)/(2(tau_c-1)) and its
+ * inverse must exist). */
+int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* refine_mask,
+                       lbm_refined** out);
+
+/* Fine box origin lo (fine coordinates) and extent dims; counts = {fine
+ * nodes, ghost nodes, covered coarse nodes, coarse nodes read by the
+ * interpolation}. */
+int lbm_refined_geometry(const lbm_refined* r, int32_t lo[3], int32_t dims[3],
+                         int64_t counts[4]);
+
+/* Bytes of device memory (two arrays per level, node types, ghost and
+ * covered lists, interpolation buffers, reduction scratch). Valid after
+ * the last lbm_refined_set_boundaries. */
+int lbm_refined_required_bytes(const lbm_refined* r, size_t* bytes);
+
+/* Hand over the device block (256-byte aligned) and upload the geometry;
+ * blocking. LBM_ESTATE if the refined region touches a periodic axis it
+ * does not span (set non-periodic boundaries first). */
+int lbm_refined_bind_memory(lbm_refined* r, void* dev, size_t bytes);
+
+/* Boundary description of the domain (as lbm_set_boundaries, applied on
+ * both levels; outflow may be any face). With an inlet face the fine level
+ * needs its own inlet arrays at fine resolution, [3][2 nb][2 na] and
+ * [2 nb][2 na] (mask may be NULL), same dtype; it draws its perturbation
+ * with seed + 1 and the fine step index. Must precede
+ * lbm_refined_bind_memory (LBM_ESTATE after it). */
+int lbm_refined_set_boundaries(lbm_refined* r, const lbm_boundaries* bc,
+                               const void* fine_inlet_u, const uint8_t* fine_inlet_mask);
+
+/* Equilibrium state of one level (0 coarse: fields over nx*ny*nz; 1 fine:
+ * fields over the fine box), as lbm_init_equilibrium. Sets the time. */
+int lbm_refined_init_equilibrium(lbm_refined* r, int level, const void* drho, const void* u,
+                                 int dtype, int64_t t0);
+
+/* Post-collision populations of one level, [Q][box] (set / get). */
+int lbm_refined_set_populations(lbm_refined* r, int level, const void* f, int dtype,
+                                int64_t t0);
+int lbm_refined_get_populations(lbm_refined* r, int level, void* f, int dtype);
+
+/* Advance n coarse steps (asynchronous). */
+int lbm_refined_step(lbm_refined* r, int64_t n);
+
+/* rho and u of one level's box (as lbm_get_macroscopic). */
+int lbm_refined_get_macroscopic(lbm_refined* r, int level, void* rho, void* u, int dtype,
+                                int rho_mode);
+
+/* Blocking FP64 sums over the domain: coarse nodes outside the refined
+ * region plus fine nodes weighted by 1/8 (their volume in coarse cells). */
+int lbm_refined_reduce(lbm_refined* r, double out[5]);
+
+int lbm_refined_get_time(const lbm_refined* r, int64_t* t);
+int lbm_refined_set_stream(lbm_refined* r, void* stream);
+int lbm_refined_destroy(lbm_refined* r);
+
 #ifdef __cplusplus
 }
 #endif

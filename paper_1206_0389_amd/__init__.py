@@ -85,6 +85,26 @@ _SIGS = {
     "lbm_destroy": [ctypes.c_void_p],
     "lbm_strerror": [ctypes.c_int],
     "lbm_stream_copy": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lbm_refined_create": [ctypes.POINTER(Config), ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_void_p)],
+    "lbm_refined_geometry": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)],
+    "lbm_refined_required_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lbm_refined_bind_memory": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "lbm_refined_set_boundaries": [ctypes.c_void_p, ctypes.POINTER(Boundaries), ctypes.c_void_p,
+                                   ctypes.c_void_p],
+    "lbm_refined_init_equilibrium": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_int64],
+    "lbm_refined_set_populations": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_int64],
+    "lbm_refined_get_populations": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int],
+    "lbm_refined_step": [ctypes.c_void_p, ctypes.c_int64],
+    "lbm_refined_get_macroscopic": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "lbm_refined_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
+    "lbm_refined_get_time": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "lbm_refined_set_stream": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_refined_destroy": [ctypes.c_void_p],
 }
 
 
@@ -362,3 +382,142 @@ class Lattice:
     @property
     def time(self):
         return get_time(self.h)
+
+
+class RefinedLattice:
+    """Two-level nested time refinement (C ABI lbm_refined_*).
+
+    shape = coarse (nx, ny, nz); mask = uint8 [nz/B][ny/B][nx/B]. With
+    boundaries (faces, face_u, inlet arrays at both resolutions) they are
+    set before the device block is bound, as the ABI requires. Both levels
+    hold post-collision populations; level 1 is the fine box of extent
+    ``fine_shape3`` (nz, ny, nx) at origin ``fine_lo`` (fine coordinates).
+    """
+
+    def __init__(self, model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01, cs_smag=0.0,
+                 mrt_basis=BASIS_TABLE1, rates=None, block=16, mask=None, faces=None,
+                 face_u=None, inlet_u=None, inlet_mask=None, fine_inlet_u=None,
+                 fine_inlet_mask=None, inlet_amp=0.0, seed=0, device="cuda", stream=None):
+        import numpy as np
+        self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
+        self.Q = 27 if self.cfg.model == D3Q27_FCLB else 19
+        self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
+        self.device = torch.device(device)
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.shape != (self.nz // block, self.ny // block, self.nx // block):
+            raise ValueError("mask must have shape (nz/B, ny/B, nx/B)")
+        self._mask = m
+        self.h = ctypes.c_void_p()
+        _check(lib().lbm_refined_create(ctypes.byref(self.cfg), int(block),
+                                        m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                        ctypes.byref(self.h)), "lbm_refined_create")
+        self._keep = []
+        if faces is not None:
+            bc = Boundaries()
+            for k in range(6):
+                bc.face_type[k] = int(faces[k])
+            if face_u is not None:
+                for k in range(6):
+                    for c in range(3):
+                        bc.face_u[k][c] = float(face_u[k][c])
+            fiu = fim = None
+            if inlet_u is not None:
+                ax = [k for k in range(6) if int(faces[k]) == INLET][0] // 2
+                dims = (self.nx, self.ny, self.nz)
+                na = dims[1] if ax == 0 else dims[0]
+                nb = dims[1] if ax == 2 else dims[2]
+                if tuple(inlet_u.shape) != (3, nb, na) or \
+                        tuple(fine_inlet_u.shape) != (3, 2 * nb, 2 * na):
+                    raise ValueError("inlet arrays must be (3, nb, na) and (3, 2nb, 2na)")
+                iu = inlet_u.to(self.device).contiguous()
+                fiu = fine_inlet_u.to(device=self.device, dtype=iu.dtype).contiguous()
+                self._keep += [iu, fiu]
+                bc.inlet_u = iu.data_ptr()
+                bc.inlet_dtype = _dtype_code(iu)
+                if inlet_mask is not None:
+                    im = inlet_mask.to(device=self.device, dtype=torch.uint8).contiguous()
+                    fim = fine_inlet_mask.to(device=self.device, dtype=torch.uint8).contiguous()
+                    if tuple(im.shape) != (nb, na) or tuple(fim.shape) != (2 * nb, 2 * na):
+                        raise ValueError("inlet masks must be (nb, na) and (2nb, 2na)")
+                    self._keep += [im, fim]
+                    bc.inlet_mask = im.data_ptr()
+            bc.inlet_amp = float(inlet_amp)
+            bc.seed = int(seed)
+            _check(lib().lbm_refined_set_boundaries(
+                self.h, ctypes.byref(bc),
+                ctypes.c_void_p(fiu.data_ptr()) if fiu is not None else None,
+                ctypes.c_void_p(fim.data_ptr()) if fim is not None else None),
+                "lbm_refined_set_boundaries")
+        lo = (ctypes.c_int32 * 3)()
+        dims = (ctypes.c_int32 * 3)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(lib().lbm_refined_geometry(self.h, lo, dims, cnt), "lbm_refined_geometry")
+        self.fine_lo = tuple(lo)
+        self.fine_dims = tuple(dims)
+        self.counts = dict(zip(("fluid", "ghost", "covered", "band"), tuple(cnt)))
+        n = ctypes.c_size_t()
+        _check(lib().lbm_refined_required_bytes(self.h, ctypes.byref(n)),
+               "lbm_refined_required_bytes")
+        self.block = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.block.data_ptr()) % 256
+        self._view = self.block[off:off + n.value]
+        _check(lib().lbm_refined_bind_memory(self.h, _dev(self._view), n.value),
+               "lbm_refined_bind_memory")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.lbm_refined_destroy(h)
+            self.h = None
+
+    def shape3(self, level):
+        if level == 0:
+            return (self.nz, self.ny, self.nx)
+        return (self.fine_dims[2], self.fine_dims[1], self.fine_dims[0])
+
+    def init_equilibrium(self, level, drho, u, t0=0):
+        drho = torch.as_tensor(drho).to(self.device).contiguous()
+        u = torch.as_tensor(u).to(device=self.device, dtype=drho.dtype).contiguous()
+        if tuple(drho.shape) != self.shape3(level) or tuple(u.shape) != (3,) + self.shape3(level):
+            raise ValueError("field shapes do not match level %d" % level)
+        _check(lib().lbm_refined_init_equilibrium(self.h, int(level), _dev(drho), _dev(u),
+                                                  _dtype_code(drho), int(t0)),
+               "lbm_refined_init_equilibrium")
+
+    def set_populations(self, level, f, t0=0):
+        f = torch.as_tensor(f).to(self.device).contiguous()
+        if tuple(f.shape) != (self.Q,) + self.shape3(level):
+            raise ValueError("population shape does not match level %d" % level)
+        _check(lib().lbm_refined_set_populations(self.h, int(level), _dev(f), _dtype_code(f),
+                                                 int(t0)), "lbm_refined_set_populations")
+
+    def populations(self, level, dtype=torch.float64):
+        out = torch.empty((self.Q,) + self.shape3(level), dtype=dtype, device=self.device)
+        _check(lib().lbm_refined_get_populations(self.h, int(level), _dev(out),
+                                                 _dtype_code(out)),
+               "lbm_refined_get_populations")
+        return out
+
+    def step(self, n=1):
+        _check(lib().lbm_refined_step(self.h, int(n)), "lbm_refined_step")
+
+    def macroscopic(self, level, dtype=torch.float64, rho_mode=RHO_DEVIATION):
+        rho = torch.empty(self.shape3(level), dtype=dtype, device=self.device)
+        u = torch.empty((3,) + self.shape3(level), dtype=dtype, device=self.device)
+        _check(lib().lbm_refined_get_macroscopic(self.h, int(level), _dev(rho), _dev(u),
+                                                 _dtype_code(rho), int(rho_mode)),
+               "lbm_refined_get_macroscopic")
+        return rho, u
+
+    def reduce(self, check=True):
+        out = (ctypes.c_double * 5)()
+        rc = lib().lbm_refined_reduce(self.h, out)
+        if check:
+            _check(rc, "lbm_refined_reduce")
+        return list(out)
+
+    @property
+    def time(self):
+        t = ctypes.c_int64()
+        _check(lib().lbm_refined_get_time(self.h, ctypes.byref(t)), "lbm_refined_get_time")
+        return t.value

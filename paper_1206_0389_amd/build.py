@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbm_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "lbm_api.hip"), os.path.join(HERE, "csrc", "lbm_refine.hip")]
 HEADERS = [os.path.join(HERE, "csrc", n) for n in os.listdir(os.path.join(HERE, "csrc"))
            if n.endswith(".h")] + [os.path.join(ROOT, "include", "lbm.h")]
 

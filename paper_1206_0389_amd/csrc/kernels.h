@@ -105,27 +105,28 @@ __device__ __forceinline__ void st(S* p, R v) {
 // ------------------------------------------------------------------ models
 template <int KIND>
 struct Model;
+// Args: any struct with the level's physics (fields mrt and omega).
 template <>
 struct Model<0> {  // D3Q19 MRT-LES, Table 1 basis
   static constexpr int Q = 19;
-  template <typename real>
-  __device__ static void collide(real (&f)[19], const LatArgs& a) {
+  template <typename real, typename Args>
+  __device__ static void collide(real (&f)[19], const Args& a) {
     mrt_collide<real, 0>(f, a.mrt);
   }
 };
 template <>
 struct Model<1> {  // D3Q19 MRT-LES, d'Humieres basis
   static constexpr int Q = 19;
-  template <typename real>
-  __device__ static void collide(real (&f)[19], const LatArgs& a) {
+  template <typename real, typename Args>
+  __device__ static void collide(real (&f)[19], const Args& a) {
     mrt_collide<real, 1>(f, a.mrt);
   }
 };
 template <>
 struct Model<2> {  // D3Q27 FCLB
   static constexpr int Q = 27;
-  template <typename real>
-  __device__ static void collide(real (&f)[27], const LatArgs& a) {
+  template <typename real, typename Args>
+  __device__ static void collide(real (&f)[27], const Args& a) {
     fclb_collide<real>(f, real(a.omega));
   }
 };
@@ -189,9 +190,9 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t s) {
 }
 
 // Velocity of an inlet-face node at step t (base profile + seeded draw).
-__device__ __forceinline__ void inlet_velocity(const BcArgs& b, const Node& n, long long t,
+__device__ __forceinline__ void inlet_velocity(const BcArgs& b, int x, int y, int z, long long t,
                                                double u[3]) {
-  const int coord[3] = {n.x, n.y, n.z};
+  const int coord[3] = {x, y, z};
   const int A = coord[b.inlet_axis == 0 ? 1 : 0];
   const int B = coord[b.inlet_axis == 2 ? 1 : 2];
   const long idx = (long)B * b.inlet_na + A;
@@ -253,11 +254,11 @@ __device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, cons
 // Bounce-back term added to the value read by pull_addr: 6 w_I e_I.u with
 // the wall's velocity (first WALL face crossed) or the inlet velocity.
 template <int Q, int I, typename real>
-__device__ __forceinline__ real pull_term(const LatArgs& a, const Node& n, const real* uin) {
-  const uint32_t crossed = n.atface & pull_faces(I);
-  const uint32_t cw = crossed & a.bc.wall;
-  const uint32_t ci = crossed & a.bc.inlet;
-  const real tw = wall_term<Q, I, real>(a.bc, cw);
+__device__ __forceinline__ real pull_term(const BcArgs& b, uint32_t atface, const real* uin) {
+  const uint32_t crossed = atface & pull_faces(I);
+  const uint32_t cw = crossed & b.wall;
+  const uint32_t ci = crossed & b.inlet;
+  const real tw = wall_term<Q, I, real>(b, cw);
   const real ti = real(6.0 * weight<Q>(I)) *
                   (real(cx(I)) * uin[0] + real(cy(I)) * uin[1] + real(cz(I)) * uin[2]);
   return cw ? tw : (ci ? ti : real(0));
@@ -385,8 +386,8 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   double uin_prev[3] = {0, 0, 0}, uin_now[3] = {0, 0, 0};
   if constexpr (BC && ODD) {
     if (n.atface & a.bc.inlet) {
-      inlet_velocity(a.bc, n, t - 1, uin_prev);
-      inlet_velocity(a.bc, n, t, uin_now);
+      inlet_velocity(a.bc, n.x, n.y, n.z, t - 1, uin_prev);
+      inlet_velocity(a.bc, n.x, n.y, n.z, t, uin_now);
     }
   }
   real f[Q];
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
         const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
         static_for<0, Q>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
-          f[I] += pull_term<Q, I, real>(a, n, up);
+          f[I] += pull_term<Q, I, real>(a.bc, n.atface, up);
         });
       }
     }
@@ -466,12 +467,12 @@ __device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, i
   } else {
     double uin[3] = {0, 0, 0};
     if constexpr (BC) {
-      if (n.atface & a.bc.inlet) inlet_velocity(a.bc, n, t - 1, uin);
+      if (n.atface & a.bc.inlet) inlet_velocity(a.bc, n.x, n.y, n.z, t - 1, uin);
     }
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       f[I] = ld<double>(pull_addr<Q, I, S, BC>(a, F, n));
-      if constexpr (BC) f[I] += pull_term<Q, I, double>(a, n, uin);
+      if constexpr (BC) f[I] += pull_term<Q, I, double>(a.bc, n.atface, uin);
     });
   }
 }
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const LatArgs a, in
   }
 }
 
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial, size_t nb,
+static __global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial, size_t nb,
                                                            double* out) {
   __shared__ double sh[5][256];
   const int tid = threadIdx.x;
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial
 }
 
 // Plain vectorised copy: the achievable-bandwidth probe.
-__global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst,
+static __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst,
                                                    const uint4* __restrict__ src, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
