@@ -244,12 +244,15 @@ void interp(const lbm_refined* R, const GhostArgs& ga, const void* fc, void* G) 
                      R->stream, ga, (const S*)fc, (Rt*)G);
 }
 
+// Ghosts := rescale(c0 A + c1 B); both buffers must hold finite values
+// (a zero weight does not hide a NaN).
 template <int KIND, typename S>
-void fill(const lbm_refined* R, const GhostArgs& ga, double c0, double c1, void* ff) {
+void fill(const lbm_refined* R, const GhostArgs& ga, const void* A, const void* B, double c0,
+          double c1, void* ff) {
   using Rt = typename Compute<S>::type;
   if (ga.ng == 0) return;
   hipLaunchKernelGGL((fill_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0, R->stream,
-                     ga, (const Rt*)R->g0, (const Rt*)R->g1, c0, c1, R->r, (S*)ff);
+                     ga, (const Rt*)A, (const Rt*)B, c0, c1, R->r, (S*)ff);
 }
 
 template <int KIND, typename S>
@@ -258,14 +261,14 @@ void one_coarse_step(lbm_refined* R, long long t) {
   const bool fine = R->Nf > 0;
   if (fine) {
     if (!R->g0_valid) interp<KIND, S>(R, ga, R->Lc.a, R->g0);
-    fill<KIND, S>(R, ga, 1.0, 0.0, R->Lf.a);
+    fill<KIND, S>(R, ga, R->g0, R->g0, 1.0, 0.0, R->Lf.a);
   }
   hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_c, R->block_c, 0, R->stream, R->Lc, 0, t);
   if (fine) {
     hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_f, R->block_f, 0, R->stream, R->Lf, 1,
                        2 * t);
     interp<KIND, S>(R, ga, R->Lc.b, R->g1);
-    fill<KIND, S>(R, ga, 0.5, 0.5, R->Lf.b);
+    fill<KIND, S>(R, ga, R->g0, R->g1, 0.5, 0.5, R->Lf.b);
     Level L2 = R->Lf;
     std::swap(L2.a, L2.b);
     hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_f, R->block_f, 0, R->stream, L2, 1,
