@@ -41,6 +41,13 @@ struct lbm_refined {
   int64_t t = 0;
   bool has_bc = false;
   bool geometry_ok = false;  // false until a valid boundary set is known
+  // per level (0 coarse, 1 fine): rows off the non-periodic y/z domain faces
+  // (x-wall kernel) and the rows on them (general kernel)
+  struct Plan {
+    int mode;  // 0: no boundary logic, 1: x-wall rows + face rows, 2: general
+    Rows all, inner, face;
+    dim3 grid_all, grid_inner, grid_face, block, block_face;
+  } plan[2];
 };
 
 namespace {
@@ -234,14 +241,77 @@ void with_kind_s(const lbm_refined* R, Fn&& fn) {
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
+// Row sets of one level's box: the box rows whose global y and z lie on no
+// non-periodic domain face, and the rows that do (listed as whole z planes
+// first, then single y rows).
+void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block) {
+  const uint32_t np = L.bc.nonper;
+  const int Mx = L.M[0], My = L.M[1], Mz = L.M[2];
+  Rows all{};
+  all.ny_in = My;
+  all.nz_in = Mz;
+  p.all = all;
+  p.block = block;
+  p.grid_all = dim3((Mx + block.x - 1) / block.x, (My + block.y - 1) / block.y, Mz);
+  Rows in = all, f{};
+  const bool ylo = (np & 4u) && L.lo[1] == 0, yhi = (np & 8u) && L.lo[1] + My == L.n[1];
+  const bool zlo = (np & 16u) && L.lo[2] == 0, zhi = (np & 32u) && L.lo[2] + Mz == L.n[2];
+  if (ylo) f.yb[f.yb_n++] = 0;
+  if (yhi) f.yb[f.yb_n++] = My - 1;
+  if (zlo) f.zb[f.zb_n++] = 0;
+  if (zhi) f.zb[f.zb_n++] = Mz - 1;
+  in.y0 = ylo ? 1 : 0;
+  in.ny_in = My - (ylo ? 1 : 0) - (yhi ? 1 : 0);
+  in.z0 = zlo ? 1 : 0;
+  in.nz_in = Mz - (zlo ? 1 : 0) - (zhi ? 1 : 0);
+  f.zi0 = zlo ? 1 : 0;
+  p.inner = in;
+  p.face = f;
+  const long long nrows = (long long)f.zb_n * My + (long long)f.yb_n * (Mz - f.zb_n);
+  p.grid_inner = dim3((Mx + block.x - 1) / block.x,
+                      in.ny_in > 0 ? (in.ny_in + block.y - 1) / block.y : 0,
+                      in.nz_in > 0 ? in.nz_in : 0);
+  const int bbx = Mx < 256 ? (Mx > 0 ? Mx : 1) : 256;
+  p.block_face = dim3(bbx, 1, 1);
+  p.grid_face = dim3((Mx + bbx - 1) / bbx, (unsigned)(nrows > 0 ? nrows : 0), 1);
+  const bool x_walls = (L.bc.inlet & 3u) == 0 && ((np & 3u) == 0 || (L.bc.wall & 3u) == 3u);
+  if (np == 0)
+    p.mode = 0;
+  else if (x_walls && nrows <= 65535)
+    p.mode = 1;
+  else
+    p.mode = 2;
+}
+
+template <int KIND, typename S>
+void level_step(const lbm_refined* R, const Level& L, const lbm_refined::Plan& p, int mode,
+                long long t) {
+  if (L.Nbox == 0) return;
+  if (p.mode == 0) {
+    hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_NONE, ROWS_BOX>), p.grid_all, p.block, 0,
+                       R->stream, L, p.all, mode, t);
+  } else if (p.mode == 2) {
+    hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_BOX>), p.grid_all, p.block, 0,
+                       R->stream, L, p.all, mode, t);
+  } else {
+    if (p.grid_inner.y > 0 && p.grid_inner.z > 0)
+      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_XWALL, ROWS_BOX>), p.grid_inner, p.block, 0,
+                         R->stream, L, p.inner, mode, t);
+    if (p.grid_face.y > 0)
+      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_LIST>), p.grid_face,
+                         p.block_face, 0, R->stream, L, p.face, mode, t);
+  }
+}
+
 // The interpolation of coarse state fc into G, then ghosts := rescale of
 // c0 G0 + c1 G1 written into the fine array ff.
 template <int KIND, typename S>
 void interp(const lbm_refined* R, const GhostArgs& ga, const void* fc, void* G) {
   using Rt = typename Compute<S>::type;
   if (ga.ng == 0) return;
-  hipLaunchKernelGGL((interp_kernel<Model<KIND>::Q, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
-                     R->stream, ga, (const S*)fc, (Rt*)G);
+  hipLaunchKernelGGL((interp_kernel<Model<KIND>::Q, S, Rt>),
+                     dim3(blocks_for(ga.ng * Model<KIND>::Q)), dim3(256), 0, R->stream, ga,
+                     (const S*)fc, (Rt*)G);
 }
 
 // Ghosts := rescale(c0 A + c1 B); both buffers must hold finite values
@@ -263,16 +333,14 @@ void one_coarse_step(lbm_refined* R, long long t) {
     if (!R->g0_valid) interp<KIND, S>(R, ga, R->Lc.a, R->g0);
     fill<KIND, S>(R, ga, R->g0, R->g0, 1.0, 0.0, R->Lf.a);
   }
-  hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_c, R->block_c, 0, R->stream, R->Lc, 0, t);
+  level_step<KIND, S>(R, R->Lc, R->plan[0], 0, t);
   if (fine) {
-    hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_f, R->block_f, 0, R->stream, R->Lf, 1,
-                       2 * t);
+    level_step<KIND, S>(R, R->Lf, R->plan[1], 1, 2 * t);
     interp<KIND, S>(R, ga, R->Lc.b, R->g1);
     fill<KIND, S>(R, ga, R->g0, R->g1, 0.5, 0.5, R->Lf.b);
     Level L2 = R->Lf;
     std::swap(L2.a, L2.b);
-    hipLaunchKernelGGL((ab_step_kernel<KIND, S>), R->grid_f, R->block_f, 0, R->stream, L2, 1,
-                       2 * t + 1);
+    level_step<KIND, S>(R, L2, R->plan[1], 1, 2 * t + 1);
   }
   std::swap(R->Lc.a, R->Lc.b);
   std::swap(R->g0, R->g1);
@@ -360,6 +428,8 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask
   shape_for(c.nx, c.ny, c.nz, R->grid_c, R->block_c, R->nblocks_c);
   shape_for(R->M[0], R->M[1], R->M[2], R->grid_f, R->block_f, R->nblocks_f);
   layout(R);
+  plan_level(R->plan[0], R->Lc, R->block_c);
+  plan_level(R->plan[1], R->Lf, R->block_f);
   *out = R;
   return LBM_OK;
 }
@@ -501,6 +571,8 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
   R->Lf.bc = bf;
   R->has_bc = b.nonper != 0;
   R->g0_valid = false;
+  plan_level(R->plan[0], R->Lc, R->block_c);
+  plan_level(R->plan[1], R->Lf, R->block_f);
   return LBM_OK;
 }
 

@@ -127,17 +127,55 @@ __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, con
   return bb ? own : (crossed ? outflow : normal);
 }
 
-// One pull-and-collide update of a level at time t. mode 0 updates every
-// node whose type is not 2 (coarse), mode 1 only type-1 nodes (fine).
-template <int KIND, typename S>
-__global__ __launch_bounds__(256) void ab_step_kernel(const Level L, int mode, long long t) {
+// x-wall-only pull for rows off every non-periodic y/z face: population I
+// enters through x- (e_Ix = +1 at global x = 0) or x+ (e_Ix = -1 at x =
+// n_x - 1), where it is the node's own opposite slot plus a per-direction
+// wall term.
+template <int Q, int I, typename S>
+__device__ __forceinline__ const S* ab_pull_addr_xwall(const Level& L, const S* A,
+                                                       const BoxNode& n) {
+  constexpr int IO = opposite<Q>(I);
+  const size_t N = (size_t)L.Nbox;
+  const S* normal = A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I));
+  if constexpr (cx(I) == 0) {
+    return normal;
+  } else {
+    const bool bb = (n.atface & (cx(I) > 0 ? 1u : 2u)) != 0;
+    return bb ? A + (size_t)IO * N + n.self : normal;
+  }
+}
+
+template <int Q, int I, typename real>
+__device__ __forceinline__ real ab_term_xwall(const Level& L, const BoxNode& n) {
+  if constexpr (cx(I) == 0) {
+    return real(0);
+  } else {
+    constexpr int F = cx(I) > 0 ? 0 : 1;
+    const real t = real(6.0 * weight<Q>(I) *
+                        (cx(I) * L.bc.face_u[F][0] + cy(I) * L.bc.face_u[F][1] +
+                         cz(I) * L.bc.face_u[F][2]));
+    return (n.atface & (1u << F)) ? t : real(0);
+  }
+}
+
+// One pull-and-collide update of a level at time t over the rows r (box-
+// local coordinates). mode 0 updates every node whose type is not 2
+// (coarse), mode 1 only type-1 nodes (fine). BCM: BC_NONE (no non-periodic
+// face), BC_XWALL (rows off the y/z faces, x faces walls) or BC_GENERAL.
+template <int KIND, typename S, int BCM, int ROWS>
+__global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows r, int mode,
+                                                      long long t) {
   using M = Model<KIND>;
   using real = typename Compute<S>::type;
   constexpr int Q = M::Q;
-  const int lx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ly = blockIdx.y * blockDim.y + threadIdx.y;
-  const int lz = blockIdx.z;
-  if (lx >= L.M[0] || ly >= L.M[1]) return;
+  int lx, ly, lz;
+  {
+    LatArgs dims;
+    dims.nx = L.M[0];
+    dims.ny = L.M[1];
+    dims.nz = L.M[2];
+    if (!row_coords<ROWS>(dims, r, lx, ly, lz)) return;
+  }
   const int self = (lz * L.M[1] + ly) * L.M[0] + lx;
   const uint8_t ty = L.type[self];
   if (mode == 0 ? ty == 2 : ty != 1) return;
@@ -145,17 +183,34 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, int mode, l
   const S* A = (const S*)L.a;
   S* B = (S*)L.b;
   real f[Q];
-  static_for<0, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    f[I] = ld<real>(ab_pull_addr<Q, I, S>(L, A, n));
-  });
-  if (n.atface) {
-    double uin[3] = {0, 0, 0};
-    if (n.atface & L.bc.inlet) inlet_velocity(L.bc, n.g[0], n.g[1], n.g[2], t, uin);
-    const real up[3] = {real(uin[0]), real(uin[1]), real(uin[2])};
+  if constexpr (BCM == BC_GENERAL) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
+      f[I] = ld<real>(ab_pull_addr<Q, I, S>(L, A, n));
+    });
+    if (n.atface) {
+      double uin[3] = {0, 0, 0};
+      if (n.atface & L.bc.inlet) inlet_velocity(L.bc, n.g[0], n.g[1], n.g[2], t, uin);
+      const real up[3] = {real(uin[0]), real(uin[1]), real(uin[2])};
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
+      });
+    }
+  } else if constexpr (BCM == BC_XWALL) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = ld<real>(ab_pull_addr_xwall<Q, I, S>(L, A, n));
+    });
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] += ab_term_xwall<Q, I, real>(L, n);
+    });
+  } else {
+    const size_t N = (size_t)L.Nbox;
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f[I] = ld<real>(A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I)));
     });
   }
   M::collide(f, L);
@@ -220,11 +275,14 @@ struct GhostArgs {
 };
 
 // G[q][g] = spatial interpolation of the coarse post-collision field at
-// ghost g.
+// ghost g; one thread per (ghost, population), population-major so that a
+// wave reads the stencils of neighbouring ghosts in one population array.
 template <int Q, typename S, typename R>
 __global__ __launch_bounds__(256) void interp_kernel(const GhostArgs ga, const S* fc, R* G) {
-  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ga.ng) return;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ga.ng * Q) return;
+  const int q = (int)(k / ga.ng);
+  const long long gi = k - (long long)q * ga.ng;
   const int l = ga.ghosts[gi];
   const int lx = l % ga.fM[0], ly = (l / ga.fM[0]) % ga.fM[1], lz = l / (ga.fM[0] * ga.fM[1]);
   const int j[3] = {lx + ga.flo[0], ly + ga.flo[1], lz + ga.flo[2]};
@@ -233,17 +291,15 @@ __global__ __launch_bounds__(256) void interp_kernel(const GhostArgs ga, const S
   int cnt[3];
   for (int d = 0; d < 3; ++d)
     cnt[d] = interp_stencil(j[d], ga.cn[d], (ga.cper >> d) & 1u, idx[d], w[d]);
-  for (int q = 0; q < Q; ++q) {
-    const S* fq = fc + (size_t)q * (size_t)ga.Nc;
-    R s = 0;
-    for (int c = 0; c < cnt[2]; ++c)
-      for (int b = 0; b < cnt[1]; ++b) {
-        const R wbc = R(w[1][b] * w[2][c]);
-        const size_t row = ((size_t)idx[2][c] * ga.cn[1] + idx[1][b]) * ga.cn[0];
-        for (int a = 0; a < cnt[0]; ++a) s += R(w[0][a]) * wbc * ld<R>(fq + row + idx[0][a]);
-      }
-    G[(size_t)q * ga.ng + gi] = s;
-  }
+  const S* fq = fc + (size_t)q * (size_t)ga.Nc;
+  R s = 0;
+  for (int c = 0; c < cnt[2]; ++c)
+    for (int b = 0; b < cnt[1]; ++b) {
+      const R wbc = R(w[1][b] * w[2][c]);
+      const size_t row = ((size_t)idx[2][c] * ga.cn[1] + idx[1][b]) * ga.cn[0];
+      for (int a = 0; a < cnt[0]; ++a) s += R(w[0][a]) * wbc * ld<R>(fq + row + idx[0][a]);
+    }
+  G[(size_t)q * ga.ng + gi] = s;
 }
 
 // Ghost populations = rescale(c0 G0 + c1 G1) into the fine state ff.
