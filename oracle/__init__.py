@@ -16,6 +16,15 @@ Parity status of each oracle function (what pins it, see tests/):
   run (streaming + BCs)       exact first-moment transport law, shear-wave
                               and Taylor-Green decay rates, Couette profile
   splitmix64                  published test vector
+  Refined (two-level nesting) polynomial exactness of the interpolant,
+                              Chapman-Enskog rescaling, uniform flow kept,
+                              reduction to the uniform lattice, shear-wave decay
+  collide_jvp (FCLB)          central differences, rest-state relaxation
+                              spectrum (1 - omega shear, trace removed),
+                              conservation, equilibrium tangent fixed
+  tangent_step / adjoint_step central differences of run; dot-product identity;
+                              periodic mass/momentum adjoint invariants
+  probe_ke, inlet_gradient    central differences of J through many steps
 """
 from __future__ import annotations
 
@@ -111,6 +120,12 @@ def lib():
         L.orc_refine_rescale.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.orc_refine_inject.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_refine_run.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int64, ctypes.c_int64]
+        L.orc_collide_jvp.argtypes = [pp, dp, dp, dp]
+        L.orc_tangent_step.argtypes = [pp, dp, dp, dp]
+        L.orc_adjoint_step.argtypes = [pp, dp, dp, dp, dp]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.orc_probe_ke.argtypes = [pp, dp, i32p, i32p, dp]
+        L.orc_probe_ke.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -271,6 +286,65 @@ class Lattice:
         out = np.zeros(5)
         lib().orc_reduce(ctypes.byref(self.p), _dp(_f64(f)), _dp(out))
         return out
+
+    # ---- adjoint of the FCLB model (exact Jacobian-vector products by
+    # dual numbers; the transpose of streaming is the scatter of the pull) ----
+    def _need_fclb(self):
+        if self.model != FCLB27:
+            raise ValueError("the oracle's adjoint covers the FCLB model only")
+
+    def collide_jvp(self, f, v):
+        self._need_fclb()
+        out = np.zeros(self.Q)
+        lib().orc_collide_jvp(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(v)), _dp(out))
+        return out
+
+    def tangent_step(self, f, v):
+        self._need_fclb()
+        out = np.zeros((self.Q,) + self.shape)
+        lib().orc_tangent_step(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(v)), _dp(out))
+        return out
+
+    def adjoint_step(self, f, lam_next, grad):
+        """Adjoint at t from the state f_t and the adjoint at t+1; grad
+        ([3][nb][na], float64) is accumulated in place."""
+        self._need_fclb()
+        lam = np.zeros((self.Q,) + self.shape)
+        assert grad.dtype == np.float64 and grad.flags.c_contiguous
+        lib().orc_adjoint_step(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(lam_next)), _dp(lam),
+                               _dp(grad))
+        return lam
+
+    def probe_ke(self, f, lo, hi, grad=False):
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        hi = np.ascontiguousarray(hi, dtype=np.int32)
+        lam = np.zeros((self.Q,) + self.shape) if grad else None
+        J = lib().orc_probe_ke(ctypes.byref(self.p), _dp(_f64(f)), lo.ctypes.data_as(i32p),
+                               hi.ctypes.data_as(i32p), _dp(lam) if grad else None)
+        return (J, lam) if grad else J
+
+    def inlet_gradient(self, f0, t0, nsteps, lo, hi, every=20):
+        """Probe kinetic energy J after nsteps from the pre-collision state f0
+        at time t0, and dJ/du_in ([3][nb][na]) of a static additive inlet
+        velocity, by the discrete adjoint. States are checkpointed every
+        `every` steps and recomputed segment by segment in reverse."""
+        self._need_fclb()
+        ckpt = {}
+        f = _f64(f0).copy()
+        for t in range(nsteps):
+            if t % every == 0:
+                ckpt[t] = f
+            f = self.run(f, t0 + t, 1)
+        J, lam = self.probe_ke(f, lo, hi, grad=True)
+        grad = np.zeros((3, self.p.inlet_nb, self.p.inlet_na))
+        for s in sorted(ckpt, reverse=True):
+            states = [ckpt[s]]
+            for t in range(s, min(s + every, nsteps) - 1):
+                states.append(self.run(states[-1], t0 + t, 1))
+            for fs in reversed(states):
+                lam = self.adjoint_step(fs, lam, grad)
+        return J, grad, lam
 
 
 class Refined:

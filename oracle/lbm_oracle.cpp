@@ -89,20 +89,43 @@ int opposite(int Q, int i) {
   return -1;
 }
 
-double ipow(double x, int k) {
-  double r = 1.0;
-  for (int j = 0; j < k; ++j) r *= x;
+// Forward-mode dual number (value, derivative along one direction): exact
+// Jacobian-vector products of the oracle's own double-precision code.
+struct Dual {
+  double v, d;
+  Dual(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+inline Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+inline double value_of(double x) { return x; }
+inline double value_of(Dual x) { return x.v; }
+inline bool is_zero(double x) { return x == 0.0; }
+inline bool is_zero(Dual x) { return x.v == 0.0 && x.d == 0.0; }
+
+template <typename T>
+T ipow(T x, int k) {
+  T r = 1.0;
+  for (int j = 0; j < k; ++j) r = r * x;
   return r;
 }
 
 // Gaussian elimination with partial pivoting: solves A x = b in place
-// (A is n x n row-major and is destroyed; b becomes x).
-void dense_solve(int n, double* A, double* b) {
+// (A is n x n row-major and is destroyed; b becomes x). Pivots are chosen
+// on values, so a dual-number solve follows the same elimination.
+template <typename T>
+void dense_solve(int n, T* A, T* b) {
   for (int k = 0; k < n; ++k) {
     int p = k;
-    double best = std::fabs(A[k * n + k]);
+    double best = std::fabs(value_of(A[k * n + k]));
     for (int r = k + 1; r < n; ++r) {
-      double v = std::fabs(A[r * n + k]);
+      double v = std::fabs(value_of(A[r * n + k]));
       if (v > best) { best = v; p = r; }
     }
     if (p != k) {
@@ -110,14 +133,14 @@ void dense_solve(int n, double* A, double* b) {
       std::swap(b[k], b[p]);
     }
     for (int r = k + 1; r < n; ++r) {
-      double l = A[r * n + k] / A[k * n + k];
-      if (l == 0.0) continue;
+      T l = A[r * n + k] / A[k * n + k];
+      if (is_zero(l)) continue;
       for (int c = k; c < n; ++c) A[r * n + c] -= l * A[k * n + c];
       b[r] -= l * b[k];
     }
   }
   for (int r = n - 1; r >= 0; --r) {
-    double s = b[r];
+    T s = b[r];
     for (int c = r + 1; c < n; ++c) s -= A[r * n + c] * b[c];
     b[r] = s / A[r * n + r];
   }
@@ -300,20 +323,21 @@ void mrt_collide(const double* f, double tau0, double cs, int basis,
 
 // Eqs. (14)-(15) per unit mass: kappa_abc = (1/rho) sum_i F_i (e_x-u_x)^a
 // (e_y-u_y)^b (e_z-u_z)^c, a,b,c in {0,1,2}; index 9a + 3b + c.
-void central_moments(const double* F, double* rho_out, double* u, double* kappa) {
-  double rho = 0.0, j[3] = {0, 0, 0};
+template <typename T>
+void central_moments(const T* F, T* rho_out, T* u, T* kappa) {
+  T rho = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 27; ++i) {
     rho += F[i];
-    for (int a = 0; a < 3; ++a) j[a] += F[i] * E[i][a];
+    for (int a = 0; a < 3; ++a) j[a] += F[i] * T(E[i][a]);
   }
   for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 3; ++c) {
-        double s = 0.0;
+        T s = 0.0;
         for (int i = 0; i < 27; ++i)
-          s += F[i] * ipow(E[i][0] - u[0], a) * ipow(E[i][1] - u[1], b) *
-               ipow(E[i][2] - u[2], c);
+          s += F[i] * ipow(T(E[i][0]) - u[0], a) * ipow(T(E[i][1]) - u[1], b) *
+               ipow(T(E[i][2]) - u[2], c);
         kappa[9 * a + 3 * b + c] = s / rho;
       }
   *rho_out = rho;
@@ -321,23 +345,25 @@ void central_moments(const double* F, double* rho_out, double* u, double* kappa)
 
 // FCLB collision (Section 2, Table 1 groups applied to central moments,
 // Table 2 equilibria, all rates except the shear rate equal to 1).
-void fclb_collide(const double* f, double omega, double* fout) {
-  double F[27];
-  for (int i = 0; i < 27; ++i) F[i] = weight(27, i) + f[i];
-  double rho, u[3], k[27];
+template <typename T>
+void fclb_collide(const T* f, double omega, T* fout) {
+  T F[27];
+  for (int i = 0; i < 27; ++i) F[i] = T(weight(27, i)) + f[i];
+  T rho, u[3], k[27];
   central_moments(F, &rho, u, k);
   auto K = [&](int a, int b, int c) { return k[9 * a + 3 * b + c]; };
-  double ks[27];
+  T ks[27];
   for (int m = 0; m < 27; ++m) ks[m] = 0.0;  // orders 1, 3, 5 relax to 0
   ks[0] = 1.0;
-  const double T = K(2, 0, 0) + K(0, 2, 0) + K(0, 0, 2);
+  const T T3 = K(2, 0, 0) + K(0, 2, 0) + K(0, 0, 2);
+  const T third = 1.0 / 3.0, omc = 1.0 - omega;
   // second order: trace to 1 (rate s2 = 1), deviatoric part at omega
-  const double k200 = 1.0 / 3.0 + (1.0 - omega) * (K(2, 0, 0) - T / 3.0);
-  const double k020 = 1.0 / 3.0 + (1.0 - omega) * (K(0, 2, 0) - T / 3.0);
-  const double k002 = 1.0 / 3.0 + (1.0 - omega) * (K(0, 0, 2) - T / 3.0);
-  const double k110 = (1.0 - omega) * K(1, 1, 0);
-  const double k101 = (1.0 - omega) * K(1, 0, 1);
-  const double k011 = (1.0 - omega) * K(0, 1, 1);
+  const T k200 = third + omc * (K(2, 0, 0) - T3 * third);
+  const T k020 = third + omc * (K(0, 2, 0) - T3 * third);
+  const T k002 = third + omc * (K(0, 0, 2) - T3 * third);
+  const T k110 = omc * K(1, 1, 0);
+  const T k101 = omc * K(1, 0, 1);
+  const T k011 = omc * K(0, 1, 1);
   ks[9 * 2 + 0 + 0] = k200;
   ks[0 + 3 * 2 + 0] = k020;
   ks[0 + 0 + 2] = k002;
@@ -354,18 +380,18 @@ void fclb_collide(const double* f, double omega, double* fout) {
   // sixth order
   ks[9 * 2 + 3 * 2 + 2] = k200 * k020 * k002;
   // back to populations: sum_i F*_i prod_a (e_ia - u_a)^{n_a} = rho kappa*
-  double A[27 * 27], b[27];
+  T A[27 * 27], b[27];
   for (int a = 0; a < 3; ++a)
     for (int bb = 0; bb < 3; ++bb)
       for (int c = 0; c < 3; ++c) {
         const int m = 9 * a + 3 * bb + c;
         for (int i = 0; i < 27; ++i)
-          A[m * 27 + i] = ipow(E[i][0] - u[0], a) * ipow(E[i][1] - u[1], bb) *
-                          ipow(E[i][2] - u[2], c);
+          A[m * 27 + i] = ipow(T(E[i][0]) - u[0], a) * ipow(T(E[i][1]) - u[1], bb) *
+                          ipow(T(E[i][2]) - u[2], c);
         b[m] = rho * ks[m];
       }
   dense_solve(27, A, b);
-  for (int i = 0; i < 27; ++i) fout[i] = b[i] - weight(27, i);
+  for (int i = 0; i < 27; ++i) fout[i] = b[i] - T(weight(27, i));
 }
 
 void collide_node(const orc_params* p, const double* f, double* fout) {
@@ -412,17 +438,22 @@ inline long node_index(const orc_params* p, int x, int y, int z) {
   return ((long)z * p->ny + y) * p->nx + x;
 }
 
-// Pull-streamed value of population i at node (x,y,z) at t+1 from the
-// post-collision field fpost of step t, with the boundary rules:
+// Where the pull-streamed population i of node (x,y,z) comes from:
 //  * periodic faces wrap;
 //  * a source beyond a WALL face: halfway bounce-back with the wall's
-//    velocity, f_i = f*_opp(i) + 6 w_i (e_i . u_w);
+//    velocity, f_i = f*_opp(i)(x) + 6 w_i (e_i . u_w);
 //  * beyond an INLET face: the same with the inlet velocity at the node;
 //  * beyond OUTFLOW faces only: the post-collision value of the nearest
 //    boundary node (a ghost layer copying the last plane).
 // When a source lies beyond several faces, WALL wins over INLET over OUTFLOW.
-double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y,
-            int z, int64_t t) {
+enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3 };
+struct Source {
+  int kind;
+  long node;  // source node (NORMAL/OUTFLOW) or the node itself
+  int face;   // crossed WALL/INLET face
+};
+
+Source classify(const orc_params* p, int i, int x, int y, int z) {
   const int n[3] = {p->nx, p->ny, p->nz};
   int s[3] = {x - E[i][0], y - E[i][1], z - E[i][2]};
   int crossed[6] = {0, 0, 0, 0, 0, 0};
@@ -439,28 +470,46 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
       any = true;
     }
   }
-  const long N = (long)p->nx * p->ny * p->nz;
-  if (!any) return fpost[i * N + node_index(p, s[0], s[1], s[2])];
-  const long self = node_index(p, x, y, z);
-  const int io = opposite(Q, i);
+  if (!any) return {SRC_NORMAL, node_index(p, s[0], s[1], s[2]), -1};
   for (int face = 0; face < 6; ++face)
-    if (crossed[face] && p->face_type[face] == ORC_WALL) {
-      const double* uw = p->face_u[face];
-      const double eu = E[i][0] * uw[0] + E[i][1] * uw[1] + E[i][2] * uw[2];
-      return fpost[io * N + self] + 6.0 * weight(Q, i) * eu;
-    }
+    if (crossed[face] && p->face_type[face] == ORC_WALL)
+      return {SRC_WALL, node_index(p, x, y, z), face};
   for (int face = 0; face < 6; ++face)
-    if (crossed[face] && p->face_type[face] == ORC_INLET) {
-      double uin[3];
-      inlet_velocity(p, face, x, y, z, t, uin);
-      const double eu = E[i][0] * uin[0] + E[i][1] * uin[1] + E[i][2] * uin[2];
-      return fpost[io * N + self] + 6.0 * weight(Q, i) * eu;
-    }
+    if (crossed[face] && p->face_type[face] == ORC_INLET)
+      return {SRC_INLET, node_index(p, x, y, z), face};
   for (int d = 0; d < 3; ++d) {
     if (s[d] < 0) s[d] = 0;
     if (s[d] >= n[d]) s[d] = n[d] - 1;
   }
-  return fpost[i * N + node_index(p, s[0], s[1], s[2])];
+  return {SRC_OUTFLOW, node_index(p, s[0], s[1], s[2]), -1};
+}
+
+// Pull-streamed value of population i at node (x,y,z) at t+1 from the
+// post-collision field fpost of step t (rules in classify()).
+double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y, int z,
+            int64_t t) {
+  const long N = (long)p->nx * p->ny * p->nz;
+  const Source src = classify(p, i, x, y, z);
+  if (src.kind == SRC_NORMAL || src.kind == SRC_OUTFLOW) return fpost[i * N + src.node];
+  const int io = opposite(Q, i);
+  double u[3];
+  if (src.kind == SRC_WALL) {
+    for (int c = 0; c < 3; ++c) u[c] = p->face_u[src.face][c];
+  } else {
+    inlet_velocity(p, src.face, x, y, z, t, u);
+  }
+  const double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+  return fpost[io * N + src.node] + 6.0 * weight(Q, i) * eu;
+}
+
+// Exact Jacobian-vector product of the FCLB collision of one node, by
+// forward-mode dual numbers through the same code as the collision.
+void collide_jvp(const orc_params* p, const double* f, const double* v, double* out) {
+  const double tau0 = 3.0 * p->nu + 0.5;
+  Dual a[27], b[27];
+  for (int i = 0; i < 27; ++i) a[i] = Dual(f[i], v[i]);
+  fclb_collide(a, 1.0 / tau0, b);
+  for (int i = 0; i < 27; ++i) out[i] = b[i].d;
 }
 
 }  // namespace
@@ -1073,6 +1122,127 @@ void orc_refine_run(void* h, double* fc, double* ff, int64_t t0, int64_t n) {
     std::memcpy(fc, bc.data(), sizeof(double) * R.Q * Nc);
     inject(R, fc, ff);
   }
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Discrete adjoint of the FCLB collide-and-stream map (used to check the GPU's
+// hand-written adjoint): step t maps the pre-collision state f_t to
+// f_{t+1} = S(C(f_t), u_in); for an objective J(f_T) the adjoint runs
+// lambda_t = J_C(f_t)^T S^T lambda_{t+1}, and the inlet velocity's gradient
+// collects the bounce-back terms 6 w_i e_i lambda_{t+1,i}.
+// ===========================================================================
+extern "C" {
+
+void orc_collide_jvp(const orc_params* p, const double* f, const double* v, double* out) {
+  collide_jvp(p, f, v, out);
+}
+
+// Tangent of one step: out = S(J_C(f_t) v) (the inlet velocity held fixed).
+void orc_tangent_step(const orc_params* p, const double* f, const double* v, double* out) {
+  const int Q = nq(p->model);
+  const long N = (long)p->nx * p->ny * p->nz;
+  std::vector<double> dpost((size_t)Q * N);
+  #pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; ++n) {
+    double a[27], b[27], c[27];
+    for (int i = 0; i < Q; ++i) {
+      a[i] = f[i * N + n];
+      b[i] = v[i * N + n];
+    }
+    collide_jvp(p, a, b, c);
+    for (int i = 0; i < Q; ++i) dpost[i * N + n] = c[i];
+  }
+  #pragma omp parallel for schedule(static)
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const long self = node_index(p, x, y, z);
+        for (int i = 0; i < Q; ++i) {
+          const Source src = classify(p, i, x, y, z);
+          const int k = (src.kind == SRC_WALL || src.kind == SRC_INLET) ? opposite(Q, i) : i;
+          out[i * N + self] = dpost[k * N + src.node];
+        }
+      }
+}
+
+// One adjoint step. f: pre-collision state at t; lam_next: adjoint at t+1;
+// lam: output adjoint at t; grad: [3][nb][na] inlet-velocity gradient,
+// accumulated (the inlet face's tangential layout of the forward inlet).
+void orc_adjoint_step(const orc_params* p, const double* f, const double* lam_next, double* lam,
+                      double* grad) {
+  const int Q = nq(p->model);
+  const long N = (long)p->nx * p->ny * p->nz;
+  std::vector<double> mu((size_t)Q * N, 0.0);
+  // S^T: scatter every pulled population back to where it came from
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const long self = node_index(p, x, y, z);
+        for (int i = 0; i < Q; ++i) {
+          const double v = lam_next[i * N + self];
+          const Source src = classify(p, i, x, y, z);
+          if (src.kind == SRC_NORMAL || src.kind == SRC_OUTFLOW) {
+            mu[i * N + src.node] += v;
+          } else {
+            mu[opposite(Q, i) * N + src.node] += v;
+            if (src.kind == SRC_INLET && grad) {
+              const int g[3] = {x + p->origin[0], y + p->origin[1], z + p->origin[2]};
+              const int axis = src.face / 2;
+              const int a = g[axis == 0 ? 1 : 0], b = g[axis == 2 ? 1 : 2];
+              const long nf = (long)p->inlet_na * p->inlet_nb;
+              for (int c = 0; c < 3; ++c)
+                grad[c * nf + (long)b * p->inlet_na + a] += 6.0 * weight(Q, i) * E[i][c] * v;
+            }
+          }
+        }
+      }
+  // J_C^T per node: column j of J_C is the JVP with the unit vector e_j
+  #pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; ++n) {
+    double a[27], e[27], c[27];
+    for (int i = 0; i < Q; ++i) a[i] = f[i * N + n];
+    for (int j = 0; j < Q; ++j) {
+      for (int i = 0; i < Q; ++i) e[i] = (i == j) ? 1.0 : 0.0;
+      collide_jvp(p, a, e, c);
+      double s = 0.0;
+      for (int i = 0; i < Q; ++i) s += c[i] * mu[i * N + n];
+      lam[j * N + n] = s;
+    }
+  }
+}
+
+// Mean kinetic energy |j|^2 / (2 rho) over the probe box [lo, hi) of the
+// pre-collision state f, and (if lam is not null) its gradient dJ/df.
+double orc_probe_ke(const orc_params* p, const double* f, const int32_t* lo, const int32_t* hi,
+                    double* lam) {
+  const int Q = nq(p->model);
+  const long N = (long)p->nx * p->ny * p->nz;
+  const double np = (double)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+  if (lam)
+    for (long k = 0; k < (long)Q * N; ++k) lam[k] = 0.0;
+  double J = 0.0;
+  for (int z = lo[2]; z < hi[2]; ++z)
+    for (int y = lo[1]; y < hi[1]; ++y)
+      for (int x = lo[0]; x < hi[0]; ++x) {
+        const long n = node_index(p, x, y, z);
+        double d = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+          d += f[i * N + n];
+          for (int a = 0; a < 3; ++a) j[a] += f[i * N + n] * E[i][a];
+        }
+        const bool comp = p->model == ORC_FCLB27;
+        const double rho = comp ? 1.0 + d : 1.0;
+        const double jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+        J += 0.5 * jj / rho / np;
+        if (lam)
+          for (int i = 0; i < Q; ++i) {
+            const double ej = E[i][0] * j[0] + E[i][1] * j[1] + E[i][2] * j[2];
+            lam[i * N + n] = (ej / rho - (comp ? 0.5 * jj / (rho * rho) : 0.0)) / np;
+          }
+      }
+  return J;
 }
 
 }  // extern "C"

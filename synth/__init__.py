@@ -112,3 +112,29 @@ def smooth_random_fields(nx, ny, nz, u_amp: float, rho_amp: float, seed: int,
     drho = field(rho_amp)
     u = np.stack([field(u_amp), field(u_amp), field(u_amp)])
     return drho, u
+
+
+def jet_adjoint_case(n: int = 128, nz: int = 256, diameter: int = 16, u_jet: float = 0.05,
+                     u_coflow: float = 0.002, sigma: float = 0.005, seed: int = 389):
+    """Round jet for the inlet-sensitivity study: a top-hat inlet of the given
+    diameter centred on the z- face of an n x n x nz box, with a static
+    perturbation of u_z on the nozzle's bounding square (diameter x diameter
+    nodes, including the corners outside the disk), drawn from N(0, sigma^2),
+    and a probe box of (2 diameter)^3 nodes centred on the axis, starting 5
+    diameters downstream.
+
+    Returns a dict: ``inlet_u`` [3, n, n] (base + perturbation), ``base_u``,
+    ``square`` = (b0, b1, a0, a1) index bounds of the perturbed square on the
+    face, ``delta`` [diameter, diameter], ``probe_lo`` / ``probe_hi`` (x, y, z).
+    """
+    base, disk = jet_inlet(n, n, float(diameter), u_jet, u_coflow)
+    c0 = n // 2 - diameter // 2
+    square = (c0, c0 + diameter, c0, c0 + diameter)
+    delta = gaussian_field((diameter, diameter), sigma, seed)
+    u = base.copy()
+    u[2, square[0]:square[1], square[2]:square[3]] += delta
+    p0 = n // 2 - diameter
+    lo = (p0, p0, 5 * diameter)
+    hi = (p0 + 2 * diameter, p0 + 2 * diameter, 7 * diameter)
+    return {"inlet_u": u, "base_u": base, "disk": disk, "square": square, "delta": delta,
+            "probe_lo": lo, "probe_hi": hi}
