@@ -220,6 +220,44 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
 
 
 /* ======================================================================
+ * Discrete adjoint of the D3Q27 FCLB collide-and-stream step (the FCLB
+ * collision of Section 2 with the streaming and boundary rules above).
+ * Not an operation of the paper: it differentiates the paper's uniform
+ * FCLB update so that gradients of a flow objective with respect to the
+ * inlet velocity can be taken through many steps.
+ *
+ * One step maps the pre-collision state f_t to f_{t+1} = S(C(f_t); u_in).
+ * For an objective J(f_T), lambda_T = dJ/df_T and
+ *   lambda_t = J_C(f_t)^T S^T lambda_{t+1},
+ * and the gradient of J with respect to the inlet velocity collects, at each
+ * inlet-face node and each step, 6 w_i e_i lambda_{t+1,i} over the
+ * directions i that bounce back through the inlet face.
+ *
+ * Layout of f_t and lambda: natural pre-collision order [27][nz][ny][nx] in
+ * the velocity order of Section 2, as returned by lbm_get_populations (full
+ * deviations f_i - w_i for f_t). dtype is the adjoint's arithmetic and
+ * storage type: LBM_DTYPE_F64 or LBM_DTYPE_F32, the same for f_t and both
+ * lambda arrays. All buffers are caller-owned device memory; work is queued
+ * on the lattice's stream and the lattice's own state is not touched.
+ * ====================================================================== */
+
+/* Probe objective of the current pre-collision state: J = mean over the
+ * box lo <= (x, y, z) < hi of |j|^2 / (2 rho), with rho = 1 + sum f for the
+ * FCLB model and rho = 1 for the incompressible MRT model. If lambda is not
+ * NULL it receives dJ/df (zero outside the box) in dtype. Blocking: J is
+ * returned on the host. LBM_EINVAL for an empty or out-of-range box. */
+int lbm_probe_ke(lbm_lattice* lat, const int32_t lo[3], const int32_t hi[3], void* lambda,
+                 int dtype, double* J);
+
+/* One adjoint step: lambda = J_C(f_t)^T S^T lambda_next for the lattice's
+ * configuration and boundaries (FCLB only, else LBM_EINVAL). grad_inlet,
+ * if not NULL, is a device double array [3][nb][na] laid out like the
+ * inlet velocity field of lbm_boundaries, to which this step's inlet terms
+ * are added. lambda must not alias lambda_next or f_t. Asynchronous. */
+int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next, void* lambda,
+                     int dtype, double* grad_inlet);
+
+/* ======================================================================
  * Two-level nested time refinement on a block grid (the hierarchical
  * block grid with nested time steps of Section 1 and of the numerical
  * set-up in Section 3; interface interpolation and rescaling after Yu et

@@ -85,6 +85,11 @@ _SIGS = {
     "lbm_destroy": [ctypes.c_void_p],
     "lbm_strerror": [ctypes.c_int],
     "lbm_stream_copy": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lbm_probe_ke": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                     ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int,
+                     ctypes.POINTER(ctypes.c_double)],
+    "lbm_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_int, ctypes.c_void_p],
     "lbm_refined_create": [ctypes.POINTER(Config), ctypes.c_int32,
                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_void_p)],
     "lbm_refined_geometry": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -252,6 +257,27 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
            "lbm_stream_copy")
 
 
+def probe_ke(h, lo, hi, lam=None, dtype=DTYPE_F64) -> float:
+    lo3 = (ctypes.c_int32 * 3)(*[int(v) for v in lo])
+    hi3 = (ctypes.c_int32 * 3)(*[int(v) for v in hi])
+    J = ctypes.c_double()
+    code = _dtype_code(lam) if lam is not None else dtype
+    _check(lib().lbm_probe_ke(h, lo3, hi3, _dev(lam) if lam is not None else None, code,
+                              ctypes.byref(J)), "lbm_probe_ke")
+    return J.value
+
+
+def adjoint_step(h, f: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor, grad=None):
+    code = _dtype_code(f)
+    if _dtype_code(lam_next) != code or _dtype_code(lam) != code:
+        raise TypeError("f, lam_next and lam must share one dtype")
+    if grad is not None and grad.dtype != torch.float64:
+        raise TypeError("grad must be float64")
+    _check(lib().lbm_adjoint_step(h, _dev(f), _dev(lam_next), _dev(lam), code,
+                                  _dev(grad) if grad is not None else None),
+           "lbm_adjoint_step")
+
+
 # ---- convenience wrapper ---------------------------------------------------
 
 def make_config(model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01, cs_smag=0.0,
@@ -382,6 +408,23 @@ class Lattice:
     @property
     def time(self):
         return get_time(self.h)
+
+    @property
+    def adjoint_dtype(self):
+        """Arithmetic type of the adjoint: float64 for FP64 storage, else float32."""
+        return torch.float64 if self.cfg.storage == STORAGE["f64"] else torch.float32
+
+    def probe_ke(self, lo, hi, lam=None):
+        """Mean |j|^2 / (2 rho) over the box [lo, hi) (x, y, z order) of the
+        current state; lam, if given ([Q][nz][ny][nx]), receives dJ/df."""
+        if lam is not None:
+            self._expect(lam, (self.Q,) + self.shape3, "lam")
+        return probe_ke(self.h, lo, hi, lam)
+
+    def adjoint_step(self, f, lam_next, lam, grad=None):
+        for t, what in ((f, "f"), (lam_next, "lam_next"), (lam, "lam")):
+            self._expect(t, (self.Q,) + self.shape3, what)
+        adjoint_step(self.h, f, lam_next, lam, grad)
 
 
 class RefinedLattice:

@@ -45,8 +45,18 @@ __device__ __forceinline__ void uncentral3(real& a0, real& a1, real& a2, real u)
   a2 = real(0.5) * (m2 + m1);
 }
 
+// Macroscopic quantities and relaxed second-order central moments of one
+// node: everything the post-collision moment set depends on.
 template <typename real>
-__device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
+struct FclbState {
+  real drho, inv, ux, uy, uz;
+  real ax, ay, az, bxy, bxz, byz;  // relaxed rho (kappa_aa - T/3), rho kappa_ab
+};
+
+// Forward central transform of the deviations (only the second order is
+// used: every other group relaxes with rate 1) and the shear relaxation.
+template <typename real>
+__device__ __forceinline__ FclbState<real> fclb_relax(const real (&f)[27], real omega) {
   real A[3][3][3];
   real drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -57,12 +67,16 @@ __device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
     if (cy(i)) jy += cy(i) > 0 ? f[i] : -f[i];
     if (cz(i)) jz += cz(i) > 0 ? f[i] : -f[i];
   }
+  FclbState<real> s;
+  s.drho = drho;
   const real rho = real(1) + drho;
-  const real inv = real(1) / rho;
-  const real ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  s.inv = real(1) / rho;
+  s.ux = jx * s.inv;
+  s.uy = jy * s.inv;
+  s.uz = jz * s.inv;
+  const real ux = s.ux, uy = s.uy, uz = s.uz;
 
-  // Central moments D_abc of the deviations about u (only the second order
-  // survives dead-code elimination: all other groups relax with rate 1).
+  // Central moments D_abc of the deviations about u.
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -78,19 +92,28 @@ __device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
 
   const real third = real(1.0 / 3.0);
   const real omc = real(1) - omega;
-  const real ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-  const real uu = ux2 + uy2 + uz2;
+  const real uu = ux * ux + uy * uy + uz * uz;
   const real dtr = A[2][0][0] + A[0][2][0] + A[0][0][2];
   // rho (kappa_aa - T/3) relaxed with omega; rho kappa_ab relaxed with omega
-  const real ax = omc * ((ux2 + A[2][0][0]) - third * (uu + dtr));
-  const real ay = omc * ((uy2 + A[0][2][0]) - third * (uu + dtr));
-  const real az = omc * ((uz2 + A[0][0][2]) - third * (uu + dtr));
-  const real bxy = omc * (ux * uy + A[1][1][0]);
-  const real bxz = omc * (ux * uz + A[1][0][1]);
-  const real byz = omc * (uy * uz + A[0][1][1]);
-  const real c2x = third + ux2, c2y = third + uy2, c2z = third + uz2;
+  s.ax = omc * ((ux * ux + A[2][0][0]) - third * (uu + dtr));
+  s.ay = omc * ((uy * uy + A[0][2][0]) - third * (uu + dtr));
+  s.az = omc * ((uz * uz + A[0][0][2]) - third * (uu + dtr));
+  s.bxy = omc * (ux * uy + A[1][1][0]);
+  s.bxz = omc * (ux * uz + A[1][0][1]);
+  s.byz = omc * (uy * uz + A[0][1][1]);
+  return s;
+}
 
-  // G = rho kappa* - (central moments of the rest weights about u)
+// Post-collision central moments G = rho kappa* minus the central moments
+// of the rest weights about u, then the inverse transform to deviations.
+template <typename real>
+__device__ __forceinline__ void fclb_post(const FclbState<real>& s, real (&A)[3][3][3]) {
+  const real drho = s.drho, inv = s.inv, ux = s.ux, uy = s.uy, uz = s.uz;
+  const real ax = s.ax, ay = s.ay, az = s.az, bxy = s.bxy, bxz = s.bxz, byz = s.byz;
+  const real third = real(1.0 / 3.0);
+  const real ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const real uu = ux2 + uy2 + uz2;
+  const real c2x = third + ux2, c2y = third + uy2, c2z = third + uz2;
   A[0][0][0] = drho;
   A[1][0][0] = ux;
   A[0][1][0] = uy;
@@ -134,7 +157,13 @@ __device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) uncentral3(A[a][b][0], A[a][b][1], A[a][b][2], uz);
+}
 
+template <typename real>
+__device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
+  const FclbState<real> s = fclb_relax(f, omega);
+  real A[3][3][3];
+  fclb_post(s, A);
 #pragma unroll
   for (int i = 0; i < 27; ++i) f[i] = A[cx(i) + 1][cy(i) + 1][cz(i) + 1];
 }

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/lbm.h"
+#include "adjoint.h"
 #include "kernels.h"
 
 using namespace lbm;
@@ -506,6 +507,76 @@ int lbm_get_time(const lbm_lattice* L, int64_t* t) {
 int lbm_destroy(lbm_lattice* L) {
   delete L;
   return LBM_OK;
+}
+
+int lbm_probe_ke(lbm_lattice* L, const int32_t lo[3], const int32_t hi[3], void* lambda,
+                 int dtype, double* J) {
+  if (!L || !lo || !hi || !J || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  const int n3[3] = {L->cfg.nx, L->cfg.ny, L->cfg.nz};
+  for (int d = 0; d < 3; ++d)
+    if (lo[d] < 0 || hi[d] > n3[d] || lo[d] >= hi[d]) return LBM_EINVAL;
+  const double scale = 1.0 / ((double)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+  double* partial = (double*)(L->base + L->off_partial);
+  double* result = (double*)(L->base + L->off_result);
+  const int3 l3 = make_int3(lo[0], lo[1], lo[2]), h3 = make_int3(hi[0], hi[1], hi[2]);
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    if (dtype == LBM_DTYPE_F64)
+      hipLaunchKernelGGL((probe_kernel<KIND, S, BC, double>), L->grid, L->block, 0, L->stream,
+                         L->args, L->parity, (long long)L->t, l3, h3, scale, (double*)lambda,
+                         partial);
+    else
+      hipLaunchKernelGGL((probe_kernel<KIND, S, BC, float>), L->grid, L->block, 0, L->stream,
+                         L->args, L->parity, (long long)L->t, l3, h3, scale, (float*)lambda,
+                         partial);
+  });
+  int rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
+                     L->nblocks, result);
+  rc = check_launch();
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(J, result, sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  return std::isfinite(*J) ? LBM_OK : LBM_ENONFINITE;
+}
+
+int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, void* lambda,
+                     int dtype, double* grad_inlet) {
+  if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (L->kind != 2) return LBM_EINVAL;
+  if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
+  auto run = [&](auto real_tag) {
+    using R = typename decltype(real_tag)::type;
+    const R* f = (const R*)f_t;
+    const R* ln = (const R*)lambda_next;
+    R* l = (R*)lambda;
+    if (!L->has_bc) {
+      hipLaunchKernelGGL((adjoint_kernel<R, BC_NONE, ROWS_BOX>), L->grid, L->block, 0,
+                         L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
+    } else if (!L->split_odd) {
+      hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_BOX>), L->grid, L->block, 0,
+                         L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
+    } else {
+      if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
+        hipLaunchKernelGGL((adjoint_kernel<R, BC_XWALL, ROWS_BOX>), L->grid_inner, L->block, 0,
+                           L->stream, L->args, L->rows_inner, f, ln, l, grad_inlet);
+      if (L->grid_bnd.y > 0)
+        hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_LIST>), L->grid_bnd,
+                           L->block_bnd, 0, L->stream, L->args, L->rows_bnd, f, ln, l,
+                           grad_inlet);
+    }
+  };
+  if (dtype == LBM_DTYPE_F64)
+    run(std::type_identity<double>{});
+  else
+    run(std::type_identity<float>{});
+  return check_launch();
 }
 
 int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream) {
