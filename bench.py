@@ -14,8 +14,12 @@ the stream the kernels run on, bracketed by device synchronisation.
 Prints one JSON line. ``roofline`` prices the step kernel's algorithmic
 traffic, 2 Q b bytes per node update (Q populations of b bytes read and
 written once), against the 8 TB/s HBM peak. ``others`` holds the same
-measurement for the other model/storage combinations. ``cpu_baseline`` is
-the FP64 oracle timed on the host cores on a cut-down of the same workload.
+measurement for the other model/storage combinations. ``adjoint`` times the
+inlet-sensitivity gradient (FCLB adjoint, 128 x 128 x 256 jet, 400 steps,
+checkpoints every 20) and the adjoint step kernel alone, priced at 3 Q b
+bytes per node (state and adjoint read, adjoint written). ``cpu_baseline``
+is the FP64 oracle timed on the host cores on a cut-down of the same
+workload.
 """
 from __future__ import annotations
 
@@ -33,17 +37,21 @@ METRIC = "MLUPS and % of HBM roofline, D3Q19-MRT and D3Q27-FCLB, FP32/FP16 vs FP
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 # HBM bytes per step of the default workload measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (scaled by a copy kernel of known size), valid only
-# for the kernel sources whose hash is recorded with it.
-MEASURED_TRAFFIC = {"bytes_per_step": 7.418e9, "sources_sha256_16": "117cefa8ea91810e",
+# for the step kernel's sources whose hash is recorded with it.
+STEP_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "lbm_api.hip")
+MEASURED_TRAFFIC = {"bytes_per_step": 7.418e9, "sources_sha256_16": "0b78d78811a3afb7",
                     "workload": "jet256-fclb-f32"}
+# The same for one adjoint step of the 128 x 128 x 256 jet (FP32).
+ADJOINT_SOURCES = ("stencil.h", "fclb.h", "kernels.h", "adjoint.h", "lbm_api.hip")
+MEASURED_ADJOINT_TRAFFIC = {"bytes_per_step": 1.411e9, "sources_sha256_16": "3c90825872658d90",
+                            "storage": "f32"}
 
 
-def sources_hash():
-    import glob
+def sources_hash(names=STEP_SOURCES):
     import hashlib
     m = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1206_0389_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1206_0389_amd", "csrc", n), "rb") as fh:
             m.update(fh.read())
     return m.hexdigest()[:16]
 
@@ -57,6 +65,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-others", action="store_true")
     p.add_argument("--other-steps", type=int, default=50)
+    p.add_argument("--no-adjoint", action="store_true")
     return p.parse_args()
 
 
@@ -174,6 +183,71 @@ def measure(name, P, torch, synth, steps, warmup):
     return out
 
 
+def measure_adjoint(P, torch, synth, storage="f32", steps=50):
+    """Inlet-sensitivity gradient of the 128 x 128 x 256 FCLB jet (D = 16,
+    u = 0.05, nu = 2e-4, co-flow 0.002), 400 steps from rest with checkpoints
+    every 20, u_z perturbed on the 16 x 16 nozzle square (N(0, 0.005^2), seed
+    389), J = mean kinetic energy of the 32^3 probe at z in [80, 112)."""
+    from paper_1206_0389_amd.adjoint import InletProbeObjective
+    n, nz, d, nsteps = 128, 256, 16, 400
+    c = synth.jet_adjoint_case(n, nz, d, u_jet=0.05, u_coflow=0.002, sigma=0.005, seed=389)
+    fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
+    lat = P.Lattice(model="fclb", storage=storage, shape=(n, n, nz), nu=2e-4)
+    obj = InletProbeObjective(lat, [P.WALL] * 4 + [P.INLET, P.OUTFLOW], fu,
+                              torch.from_numpy(c["base_u"]), c["square"], c["probe_lo"],
+                              c["probe_hi"], nsteps, every=20)
+    delta = torch.from_numpy(c["delta"]).cuda()
+    obj.forward(delta)
+    obj.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = obj.forward(delta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad, _ = obj.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b0, b1, a0, a1 = c["square"]
+    gnorm = float(grad[2, b0:b1, a0:a1].norm())
+    # the adjoint step kernel alone, on recorded states
+    f = obj._rec[0]
+    lam = obj._rec[1].clone()
+    lam2 = torch.empty_like(lam)
+    g = torch.zeros_like(grad)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        lat.adjoint_step(f, lam, lam2, g)
+        lam, lam2 = lam2, lam
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        lat.adjoint_step(f, lam, lam2, g)
+        lam, lam2 = lam2, lam
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = n * n * nz
+    bpn = 3 * 27 * (8 if storage == "f64" else 4)
+    gbs = bpn * nodes / (ms * 1e-3) / 1e9
+    out = {"workload": "inlet-sensitivity jet 128x128x256 FCLB, D=16 u=0.05 nu=2e-4, 400 "
+                       "steps, checkpoints every 20, 16x16 u_z perturbation (sigma 0.005, seed "
+                       "389), probe 32^3 at z in [80,112)",
+           "storage": storage, "J": J, "grad_l2": gnorm, "gradient_s": t2 - t0,
+           "forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_step_ms": ms,
+           "adjoint_mlups": nodes / (ms * 1e-3) / 1e6, "adjoint_bytes_per_node": bpn,
+           "adjoint_GBs": gbs, "adjoint_frac_of_8TBs": gbs / HBM_PEAK_GBS,
+           "kernel": "adjoint_kernel<%s>" % ("double" if storage == "f64" else "float"),
+           "traffic": (MEASURED_ADJOINT_TRAFFIC["bytes_per_step"]
+                       if (MEASURED_ADJOINT_TRAFFIC["storage"] == storage and
+                           MEASURED_ADJOINT_TRAFFIC["sources_sha256_16"] ==
+                           sources_hash(ADJOINT_SOURCES)) else None)}
+    del obj, lat, f, lam, lam2, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(P, torch, nbytes=4 << 30, reps=10):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -246,6 +320,10 @@ def main():
             r = measure(name, P, torch, synth, args.other_steps, 10)
             print("bench: %s %.1f MLUPS" % (name, r["mlups"]), flush=True)
             others.append(r)
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = [measure_adjoint(P, torch, synth, st) for st in ("f32", "f64")]
+        print("bench: adjoint gradient %.2f s (f32)" % adjoint[0]["gradient_s"], flush=True)
     copy_gbs = copy_bandwidth(P, torch)
     model, storage, shape, _ = workload(args.workload)
     alg_per_launch = main_res["bytes_per_lup"] * shape[0] * shape[1] * shape[2]
@@ -263,7 +341,7 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": storage, "data": "synthetic", "config": main_res["config"],
-            "roofline": roof, "others": others}
+            "roofline": roof, "others": others, "adjoint": adjoint}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", flush=True)
         line["cpu_baseline"] = cpu_baseline(model)

@@ -99,6 +99,12 @@ class InletProbeObjective:
         self._final[1], self._final[2] = save_state(lat.h, self._final[0])
         return lat.probe_ke(self.lo, self.hi)
 
+    def value(self, delta) -> float:
+        """J(delta) without keeping checkpoints (for finite differences)."""
+        self._reset(delta)
+        self.lat.step(self.nsteps)
+        return self.lat.probe_ke(self.lo, self.hi)
+
     # -- backward ---------------------------------------------------------
     def backward(self):
         """dJ/du_in on the whole inlet face ([3, nb, na], float64) and

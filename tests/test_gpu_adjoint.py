@@ -136,12 +136,15 @@ def test_adjoint_rejects_mrt_and_aliasing():
 N, NZ, D, NSTEPS, NU, COFLOW = 32, 64, 4, 400, 2e-4, 0.002
 
 
-def _jet_objective(storage, every=20):
+def _jet_objective(storage, every=20, scale=4):
+    """The inlet-sensitivity jet (128 x 128 x 256, D = 16) with every length
+    divided by scale."""
     import paper_1206_0389_amd as Pk
     from paper_1206_0389_amd.adjoint import InletProbeObjective
-    c = synth.jet_adjoint_case(N, NZ, D, u_jet=0.05, u_coflow=COFLOW, sigma=0.005, seed=389)
+    n, nz, d = 4 * N // scale, 4 * NZ // scale, 4 * D // scale
+    c = synth.jet_adjoint_case(n, nz, d, u_jet=0.05, u_coflow=COFLOW, sigma=0.005, seed=389)
     face_u = [[0.0, 0.0, COFLOW] for _ in range(4)] + [[0.0, 0.0, 0.0]] * 2
-    lat = Pk.Lattice(model="fclb", storage=storage, shape=(N, N, NZ), nu=NU)
+    lat = Pk.Lattice(model="fclb", storage=storage, shape=(n, n, nz), nu=NU)
     obj = InletProbeObjective(lat, [W, W, W, W, I, O], face_u, torch.from_numpy(c["base_u"]),
                               c["square"], c["probe_lo"], c["probe_hi"], NSTEPS, every=every)
     return obj, c
@@ -194,7 +197,7 @@ def test_cutdown_gradient_matches_finite_differences():
             dp, dm = delta.clone(), delta.clone()
             dp[b, a] += h
             dm[b, a] -= h
-            fd[b, a] = (obj.forward(dp) - obj.forward(dm)) / (2 * h)
+            fd[b, a] = (obj.value(dp) - obj.value(dm)) / (2 * h)
     rel = float(np.linalg.norm(g - fd) / np.linalg.norm(fd))
     print("adjoint vs FD relative L2", rel, flush=True)
     assert rel <= 1e-4
@@ -223,3 +226,55 @@ def test_checkpoint_spacing_does_not_change_gradient():
     g1, l1 = obj1.backward()
     g2, l2 = obj2.backward()
     assert torch.equal(g1, g2) and torch.equal(l1, l2)
+
+
+# ------------------------------------------------- full-size jet (128^2 x 256)
+_FULL = {}
+
+
+def _full_gradients():
+    """FP64 and FP32 adjoint gradients of the full-size jet, computed once."""
+    if not _FULL:
+        for storage in ("f64", "f32"):
+            obj, c = _jet_objective(storage, scale=1)
+            delta = torch.from_numpy(c["delta"]).cuda()
+            J = obj.forward(delta)
+            grad, _ = obj.backward()
+            b0, b1, a0, a1 = c["square"]
+            _FULL[storage] = (J, grad[2, b0:b1, a0:a1].cpu().numpy())
+            if storage == "f64":
+                _FULL["obj"], _FULL["delta"] = obj, delta
+            del obj
+            torch.cuda.empty_cache()
+    return _FULL
+
+
+def test_full_jet_fp32_gradient_close_to_fp64():
+    r = _full_gradients()
+    (J64, g64), (J32, g32) = r["f64"], r["f32"]
+    rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    print("full jet: J", J64, J32, "FP32 vs FP64 gradient relative L2", rel, flush=True)
+    assert abs(J32 - J64) <= 1e-3 * abs(J64)
+    assert rel <= 1e-3
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_full_jet_gradient_matches_finite_differences(part):
+    """Central differences of J (FP64, h = 1e-6) for all 256 components,
+    a quarter per test."""
+    r = _full_gradients()
+    obj, delta = r["obj"], r["delta"]
+    g = r["f64"][1]
+    h = 1e-6
+    rows = range(4 * part, 4 * part + 4)
+    fd = np.zeros((4, g.shape[1]))
+    for k, b in enumerate(rows):
+        for a in range(g.shape[1]):
+            dp, dm = delta.clone(), delta.clone()
+            dp[b, a] += h
+            dm[b, a] -= h
+            fd[k, a] = (obj.value(dp) - obj.value(dm)) / (2 * h)
+    ga = g[4 * part:4 * part + 4]
+    rel = float(np.linalg.norm(ga - fd) / np.linalg.norm(fd))
+    print("full jet rows", list(rows), "adjoint vs FD relative L2", rel, flush=True)
+    assert rel <= 1e-4
