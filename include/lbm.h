@@ -249,6 +249,15 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
 int lbm_probe_ke(lbm_lattice* lat, const int32_t lo[3], const int32_t hi[3], void* lambda,
                  int dtype, double* J);
 
+/* One FCLB step (as lbm_step with n = 1) that also writes the natural
+ * pre-collision state it collides, i.e. what lbm_get_populations would have
+ * returned before the step, into rec ([27][nz][ny][nx], device). dtype must
+ * be the adjoint's type: LBM_DTYPE_F64 for FP64 storage, LBM_DTYPE_F32 for
+ * FP32 storage; FP16 storage and the MRT model give LBM_EINVAL. At inlet and
+ * wall nodes of FP32 storage the bounce-back term is added in FP32, as the
+ * step computes it (lbm_get_populations adds it in FP64). Asynchronous. */
+int lbm_step_record(lbm_lattice* lat, void* rec, int dtype);
+
 /* One adjoint step: lambda = J_C(f_t)^T S^T lambda_next for the lattice's
  * configuration and boundaries (FCLB only, else LBM_EINVAL). grad_inlet,
  * if not NULL, is a device double array [3][nb][na] laid out like the

@@ -88,6 +88,7 @@ _SIGS = {
     "lbm_probe_ke": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                      ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int,
                      ctypes.POINTER(ctypes.c_double)],
+    "lbm_step_record": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "lbm_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_int, ctypes.c_void_p],
     "lbm_refined_create": [ctypes.POINTER(Config), ctypes.c_int32,
@@ -267,6 +268,10 @@ def probe_ke(h, lo, hi, lam=None, dtype=DTYPE_F64) -> float:
     return J.value
 
 
+def step_record(h, rec: torch.Tensor):
+    _check(lib().lbm_step_record(h, _dev(rec), _dtype_code(rec)), "lbm_step_record")
+
+
 def adjoint_step(h, f: torch.Tensor, lam_next: torch.Tensor, lam: torch.Tensor, grad=None):
     code = _dtype_code(f)
     if _dtype_code(lam_next) != code or _dtype_code(lam) != code:
@@ -420,6 +425,11 @@ class Lattice:
         if lam is not None:
             self._expect(lam, (self.Q,) + self.shape3, "lam")
         return probe_ke(self.h, lo, hi, lam)
+
+    def step_record(self, rec):
+        """One step, writing the pre-collision state it collides into rec."""
+        self._expect(rec, (self.Q,) + self.shape3, "rec")
+        step_record(self.h, rec)
 
     def adjoint_step(self, f, lam_next, lam, grad=None):
         for t, what in ((f, "f"), (lam_next, "lam_next"), (lam, "lam")):

@@ -8,7 +8,7 @@ J = mean |j|^2 / (2 rho) over the probe box after the last step.
 
 The backward pass seeds lambda_T = dJ/df_T (lbm_probe_ke), then walks the
 segments in reverse: restore the segment's checkpoint, recompute its steps
-while recording each pre-collision state (lbm_get_populations), and run
+while recording each pre-collision state (lbm_step_record), and run
 lbm_adjoint_step back through them, which also accumulates dJ/du_in on the
 inlet face. With ``every`` about sqrt(nsteps) the memory is two sets of
 sqrt(nsteps) states and the work one extra forward pass.
@@ -22,7 +22,7 @@ import math
 
 import torch
 
-from . import INLET, Lattice, get_populations, save_state, state_bytes
+from . import INLET, Lattice, save_state, state_bytes
 
 
 class InletProbeObjective:
@@ -125,9 +125,7 @@ class InletProbeObjective:
             lat.load_state(buf, t, parity)
             n = min(self.every, self.nsteps - s * self.every)
             for k in range(n):
-                get_populations(lat.h, self._rec[k])
-                if k < n - 1:
-                    lat.step(1)
+                lat.step_record(self._rec[k])
             for k in reversed(range(n)):
                 lat.adjoint_step(self._rec[k], lam, lam2, grad)
                 lam, lam2 = lam2, lam

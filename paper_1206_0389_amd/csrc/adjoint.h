@@ -180,13 +180,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
   real fv[Q], m[Q];
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    fv[I] = f[(size_t)I * N + n.self];
+    fv[I] = ld<real, true>(f + (size_t)I * N + n.self);
   });
   double gin[3] = {0, 0, 0};
   if constexpr (BCM == BC_NONE) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      m[I] = ln[(size_t)I * N + n.at(cx(I), cy(I), cz(I))];
+      m[I] = ld<real, cx(I) == 0>(ln + (size_t)I * N + n.at(cx(I), cy(I), cz(I)));
     });
   } else if constexpr (BCM == BC_XWALL) {
     static_for<0, Q>([&](auto ic) {
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
       constexpr int IO = opposite<Q>(I);
       const size_t normal = (size_t)I * N + n.at(cx(I), cy(I), cz(I));
       if constexpr (cx(I) == 0) {
-        m[I] = ln[normal];
+        m[I] = ld<real, true>(ln + normal);
       } else {
         const bool bb = (n.atface & (cx(I) > 0 ? 2u : 1u)) != 0;
         m[I] = ln[bb ? (size_t)IO * N + n.self : normal];
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
   fclb_vjp<real>(fv, m, real(a.omega));
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    l[(size_t)I * N + n.self] = m[I];
+    st<BCM != BC_GENERAL>(l + (size_t)I * N + n.self, m[I]);
   });
   if constexpr (BCM == BC_GENERAL) {
     if (grad && (n.atface & a.bc.inlet)) {

@@ -93,13 +93,24 @@ struct Compute<double> {
   using type = double;
 };
 
-template <typename R, typename S>
+// NT: non-temporal (streaming) hint. The step kernels touch every population
+// once per step, so nothing they load or store is reused from cache except
+// the partial lines at the ends of one-element x shifts; the hint is applied
+// where accesses are aligned to the row (measured: +8 % on the even step,
+// +3 % on the odd step's x-aligned directions, nothing on shifted ones).
+template <typename R, bool NT = false, typename S>
 __device__ __forceinline__ R ld(const S* p) {
-  return R(*p);
+  if constexpr (NT)
+    return R(__builtin_nontemporal_load(p));
+  else
+    return R(*p);
 }
-template <typename S, typename R>
+template <bool NT = false, typename S, typename R>
 __device__ __forceinline__ void st(S* p, R v) {
-  *p = S(v);
+  if constexpr (NT)
+    __builtin_nontemporal_store(S(v), p);
+  else
+    *p = S(v);
 }
 
 // ------------------------------------------------------------------ models
@@ -275,7 +286,7 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
   const size_t N = (size_t)a.N;
   S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
   if constexpr (!BC) {
-    st(normal, v);
+    st<cx(I) == 0>(normal, v);
   } else {
     const uint32_t crossed = n.atface & push_faces(I);
     const uint32_t cw = crossed & a.bc.wall;
@@ -328,7 +339,7 @@ __device__ __forceinline__ void push_xwall(const LatArgs& a, S* F, const Node& n
   const size_t N = (size_t)a.N;
   S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
   if constexpr (cx(I) == 0) {
-    st(normal, v);
+    st<true>(normal, v);
   } else {
     // leaving through x+ (e_Ix = +1 at x = nx-1) returns as opp(I), which
     // enters through x+: its wall term uses face 1, and vice versa
@@ -371,9 +382,13 @@ __device__ __forceinline__ bool row_coords(const LatArgs& a, const Rows& r, int&
   }
 }
 
-// One collide-and-stream step at time t over the rows selected by r.
+// One collide-and-stream step at time t over the rows selected by r. If rec
+// is not null, the natural pre-collision state the step collides is also
+// written to rec ([Q][N] in the compute type). The record is a runtime
+// switch, so recording and plain steps run the same code and round alike.
 template <int KIND, typename S, bool ODD, int BCM, int ROWS>
-__global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r, long long t) {
+__global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r, long long t,
+                                                   typename Compute<S>::type* rec) {
   using M = Model<KIND>;
   using real = typename Compute<S>::type;
   constexpr int Q = M::Q;
@@ -394,13 +409,13 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   if constexpr (!ODD) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real>(F + (size_t)I * N + n.self);
+      f[I] = ld<real, true>(F + (size_t)I * N + n.self);
     });
   } else {
     if constexpr (BCM == BC_XWALL) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = ld<real>(pull_addr_xwall<Q, I, S>(a, F, n));
+        f[I] = ld<real, cx(I) == 0>(pull_addr_xwall<Q, I, S>(a, F, n));
       });
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     } else {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = ld<real>(pull_addr<Q, I, S, BC>(a, F, n));
+        f[I] = ld<real, !BC && cx(I) == 0>(pull_addr<Q, I, S, BC>(a, F, n));
       });
       if constexpr (BC) {
         const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
@@ -420,11 +435,17 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       }
     }
   }
+  if (rec != nullptr) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      st<true>(rec + (size_t)I * N + n.self, f[I]);
+    });
+  }
   M::collide(f, a);
   if constexpr (!ODD) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      st(F + (size_t)opposite<Q>(I) * N + n.self, f[I]);
+      st<true>(F + (size_t)opposite<Q>(I) * N + n.self, f[I]);
     });
     if constexpr (BC) {
       if (n.atface & a.bc.outflow) {
@@ -633,11 +654,13 @@ static __global__ __launch_bounds__(256) void reduce_final_kernel(const double* 
     for (int k = 0; k < 5; ++k) out[k] = sh[k][0];
 }
 
-// Plain vectorised copy: the achievable-bandwidth probe.
-static __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst,
-                                                   const uint4* __restrict__ src, size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+// Plain vectorised copy, one 16-byte element per thread with the streaming
+// hint: the achievable-bandwidth probe.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+static __global__ __launch_bounds__(256) void copy_kernel(u32x4* __restrict__ dst,
+                                                   const u32x4* __restrict__ src, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace lbm

@@ -63,38 +63,39 @@ void launch_shape(lbm_lattice* L) {
 }
 
 template <int KIND, typename S, bool ODD, int BCM, int ROWS>
-void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t) {
-  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS>), grid, block, 0, L->stream, L->args,
-                     r, t);
+void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t,
+                 void* rec) {
+  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS>), grid, block, 0, L->stream,
+                     L->args, r, t, (typename Compute<S>::type*)rec);
 }
 
 template <int KIND, typename S>
-void step_model(const lbm_lattice* L, bool odd, long long t) {
+void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
   if (!L->has_bc) {
     if (odd)
-      launch_step<KIND, S, true, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+      launch_step<KIND, S, true, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
     else
-      launch_step<KIND, S, false, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+      launch_step<KIND, S, false, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else if (!odd) {
-    launch_step<KIND, S, false, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+    launch_step<KIND, S, false, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else if (!L->split_odd) {
-    launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t);
+    launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else {
     if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
       launch_step<KIND, S, true, BC_XWALL, ROWS_BOX>(L, L->grid_inner, L->block, L->rows_inner,
-                                                     t);
+                                                     t, rec);
     if (L->grid_bnd.y > 0)
       launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST>(L, L->grid_bnd, L->block_bnd,
-                                                        L->rows_bnd, t);
+                                                        L->rows_bnd, t, rec);
   }
 }
 
 template <typename S>
 void step_dispatch_s(lbm_lattice* L, bool odd, long long t) {
   switch (L->kind) {
-    case 0: step_model<0, S>(L, odd, t); break;
-    case 1: step_model<1, S>(L, odd, t); break;
-    default: step_model<2, S>(L, odd, t); break;
+    case 0: step_model<0, S>(L, odd, t, nullptr); break;
+    case 1: step_model<1, S>(L, odd, t, nullptr); break;
+    default: step_model<2, S>(L, odd, t, nullptr); break;
   }
 }
 
@@ -104,6 +105,15 @@ void step_dispatch(lbm_lattice* L, bool odd, long long t) {
     case LBM_F32: step_dispatch_s<float>(L, odd, t); break;
     default: step_dispatch_s<_Float16>(L, odd, t); break;
   }
+}
+
+// One FCLB step that also records the pre-collision state (FP64 and FP32
+// storage: the adjoint's recomputation).
+void step_record_dispatch(lbm_lattice* L, bool odd, long long t, void* rec) {
+  if (L->cfg.storage == LBM_F64)
+    step_model<2, double>(L, odd, t, rec);
+  else
+    step_model<2, float>(L, odd, t, rec);
 }
 
 // Row sets of the split odd step for the current boundary description.
@@ -419,6 +429,17 @@ int lbm_step(lbm_lattice* L, int64_t n) {
   return check_launch();
 }
 
+int lbm_step_record(lbm_lattice* L, void* rec, int dtype) {
+  if (!L || !rec || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (L->kind != 2 || L->cfg.storage == LBM_F16) return LBM_EINVAL;
+  if (dtype != (L->cfg.storage == LBM_F64 ? LBM_DTYPE_F64 : LBM_DTYPE_F32)) return LBM_EINVAL;
+  step_record_dispatch(L, L->parity == 1, (long long)L->t, rec);
+  L->t += 1;
+  L->parity ^= 1;
+  return check_launch();
+}
+
 int lbm_get_macroscopic(lbm_lattice* L, void* rho, void* u, int dtype, int rho_mode) {
   if (!L || !valid_dtype(dtype)) return LBM_EINVAL;
   if (rho_mode != LBM_RHO_FULL && rho_mode != LBM_RHO_DEVIATION) return LBM_EINVAL;
@@ -583,10 +604,10 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream) {
   if (!dst || !src || (((uintptr_t)dst | (uintptr_t)src | n) & 15) != 0) return LBM_EINVAL;
   const size_t n16 = n / 16;
   if (n16 == 0) return LBM_OK;
-  size_t blocks = (n16 + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const size_t blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffffu) return LBM_EINVAL;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                     (uint4*)dst, (const uint4*)src, n16);
+                     (u32x4*)dst, (const u32x4*)src, n16);
   return check_launch();
 }
 

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
   } else if constexpr (BCM == BC_XWALL) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real>(ab_pull_addr_xwall<Q, I, S>(L, A, n));
+      f[I] = ld<real, cx(I) == 0>(ab_pull_addr_xwall<Q, I, S>(L, A, n));
     });
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
@@ -210,14 +210,14 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
     const size_t N = (size_t)L.Nbox;
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real>(A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I)));
+      f[I] = ld<real, cx(I) == 0>(A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I)));
     });
   }
   M::collide(f, L);
   const size_t N = (size_t)L.Nbox;
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    st(B + (size_t)I * N + self, f[I]);
+    st<BCM != BC_GENERAL>(B + (size_t)I * N + self, f[I]);
   });
 }
 

@@ -278,3 +278,32 @@ def test_full_jet_gradient_matches_finite_differences(part):
     rel = float(np.linalg.norm(ga - fd) / np.linalg.norm(fd))
     print("full jet rows", list(rows), "adjoint vs FD relative L2", rel, flush=True)
     assert rel <= 1e-4
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("faces", ["jet", "periodic"])
+def test_step_record_matches_get_populations(storage, faces):
+    """lbm_step_record writes the state lbm_get_populations returns before the
+    step (FP64: exactly; FP32: the bounce-back term is added in FP32) and
+    advances the lattice exactly like lbm_step."""
+    shape = (37, 9, 11)
+    nx, ny, nz = shape
+    g1, _, _ = _pair(FACE_SETS[faces], shape, storage=storage)
+    g2, _, _ = _pair(FACE_SETS[faces], shape, storage=storage)
+    f = synth.random_populations(27, (nz, ny, nx), 1e-2, seed=14)
+    for g in (g1, g2):
+        g.set_populations(torch.from_numpy(f))
+    dt = g1.adjoint_dtype
+    rec = torch.empty((27, nz, ny, nx), dtype=dt, device="cuda")
+    for k in range(3):  # even and odd parities
+        want = g1.populations(dt)
+        g1.step_record(rec)
+        g2.step(1)
+        if storage == "f64":
+            assert torch.equal(rec, want), k
+        else:
+            assert float((rec - want).abs().max()) <= 1e-7 * float(want.abs().max()), k
+        assert torch.equal(g1.populations(), g2.populations()), k
+    import paper_1206_0389_amd as Pk
+    with pytest.raises(Pk.LbmError):
+        g1.step_record(rec.to(torch.float32 if dt == torch.float64 else torch.float64))
