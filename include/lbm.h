@@ -140,7 +140,10 @@ typedef struct lbm_boundaries {
 } lbm_boundaries;
 
 /* Validate cfg and create a handle (host memory only). On error *out is
- * left untouched. */
+ * left untouched. Limits: fewer than 2^31 nodes, nz <= 65535, and one
+ * population's storage (nodes x element size) below 4 GiB: 537 M nodes in
+ * FP64, 1.07 G in FP32 (the kernels address a population with 32-bit byte
+ * offsets). */
 int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out);
 
 /* Bytes of device memory the lattice needs (populations, the outflow ghost
@@ -262,7 +265,9 @@ int lbm_step_record(lbm_lattice* lat, void* rec, int dtype);
  * configuration and boundaries (FCLB only, else LBM_EINVAL). grad_inlet,
  * if not NULL, is a device double array [3][nb][na] laid out like the
  * inlet velocity field of lbm_boundaries, to which this step's inlet terms
- * are added. lambda must not alias lambda_next or f_t. Asynchronous. */
+ * are added. lambda must not alias lambda_next or f_t; two populations of
+ * an adjoint array (2 x nodes x element size) must stay below 4 GiB, else
+ * LBM_EINVAL. Asynchronous. */
 int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next, void* lambda,
                      int dtype, double* grad_inlet);
 

@@ -177,27 +177,35 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
   if (!row_coords<ROWS>(a, r, x, y, z)) return;
   const Node n = make_node(a, x, y, z);
   const size_t N = (size_t)a.N;
+  // 32-bit byte offsets from per-population bases (see ldo); the x-wall rows
+  // select between a population and its opposite from the lower slab
+  const uint32_t sz = sizeof(real);
+  const uint32_t self_off = (uint32_t)n.self * sz;
   real fv[Q], m[Q];
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    fv[I] = ld<real, true>(f + (size_t)I * N + n.self);
+    fv[I] = ldo<real, true>(f + (size_t)I * N, self_off);
   });
   double gin[3] = {0, 0, 0};
   if constexpr (BCM == BC_NONE) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      m[I] = ld<real, cx(I) == 0>(ln + (size_t)I * N + n.at(cx(I), cy(I), cz(I)));
+      m[I] = ldo<real, cx(I) == 0>(ln + (size_t)I * N,
+                                   (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz);
     });
   } else if constexpr (BCM == BC_XWALL) {
+    const uint32_t slab = (uint32_t)N * sz;
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       constexpr int IO = opposite<Q>(I);
-      const size_t normal = (size_t)I * N + n.at(cx(I), cy(I), cz(I));
+      const uint32_t nb = (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz;
       if constexpr (cx(I) == 0) {
-        m[I] = ld<real, true>(ln + normal);
+        m[I] = ldo<real, true>(ln + (size_t)I * N, nb);
       } else {
+        constexpr int LO = I < IO ? I : IO;
         const bool bb = (n.atface & (cx(I) > 0 ? 2u : 1u)) != 0;
-        m[I] = ln[bb ? (size_t)IO * N + n.self : normal];
+        const uint32_t off = bb ? (IO - LO) * slab + self_off : (I - LO) * slab + nb;
+        m[I] = ldo<real>(ln + (size_t)LO * N, off);
       }
     });
   } else {
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
   fclb_vjp<real>(fv, m, real(a.omega));
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    st<BCM != BC_GENERAL>(l + (size_t)I * N + n.self, m[I]);
+    sto<BCM != BC_GENERAL>(l + (size_t)I * N, self_off, m[I]);
   });
   if constexpr (BCM == BC_GENERAL) {
     if (grad && (n.atface & a.bc.inlet)) {

@@ -55,6 +55,10 @@ struct BcArgs {
   int inlet_axis;
   int inlet_na, inlet_nb;
   long long ghost_n; // nodes of a z plane (the outflow face is a z face)
+  // 6 w_J (e_J . u_F) for population J entering through x face F (0: x-,
+  // 1: x+), set on the host with the face velocities
+  double xterm[2][27];
+  float xterm_f[2][27];
 };
 
 struct LatArgs {
@@ -111,6 +115,42 @@ __device__ __forceinline__ void st(S* p, R v) {
     __builtin_nontemporal_store(S(v), p);
   else
     *p = S(v);
+}
+
+// Population slabs are addressed as a uniform base pointer (SGPRs) plus a
+// 32-bit byte offset of the node: the loads and stores then take the
+// scalar-base form and need no 64-bit address arithmetic per lane. A slab
+// (one population, all nodes) is below 4 GiB (checked at creation); offsets
+// that span two adjacent slabs (a population and its opposite) are used
+// only while two slabs stay below 4 GiB.
+template <typename R, bool NT = false, typename S>
+__device__ __forceinline__ R ldo(const S* base, uint32_t off) {
+  return ld<R, NT>((const S*)((const char*)base + off));
+}
+template <bool NT = false, typename S, typename R>
+__device__ __forceinline__ void sto(S* base, uint32_t off, R v) {
+  st<NT>((S*)((char*)base + off), v);
+}
+// Host: 6 w_J (e_J . u_F) for the x faces, per model (the weights differ).
+inline void fill_xterms(BcArgs& b, int Q) {
+  for (int F = 0; F < 2; ++F)
+    for (int j = 0; j < 27; ++j) {
+      double v = 0.0;
+      if (j < Q) {
+        const double w = Q == 27 ? weight<27>(j) : weight<19>(j);
+        v = 6.0 * w * (cx(j) * b.face_u[F][0] + cy(j) * b.face_u[F][1] + cz(j) * b.face_u[F][2]);
+      }
+      b.xterm[F][j] = v;
+      b.xterm_f[F][j] = (float)v;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T xterm(const BcArgs& b, int face, int i) {
+  if constexpr (sizeof(T) == sizeof(double))
+    return b.xterm[face][i];
+  else
+    return T(b.xterm_f[face][i]);
 }
 
 // ------------------------------------------------------------------ models
@@ -284,10 +324,11 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
                                      const real* uin) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
-  S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
   if constexpr (!BC) {
-    st<cx(I) == 0>(normal, v);
+    sto<cx(I) == 0>(F + (size_t)I * N, (uint32_t)n.at(cx(I), cy(I), cz(I)) * (uint32_t)sizeof(S),
+                    v);
   } else {
+    S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
     const uint32_t crossed = n.atface & push_faces(I);
     const uint32_t cw = crossed & a.bc.wall;
     const uint32_t ci = crossed & a.bc.inlet;
@@ -306,49 +347,44 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
 
 // Rows off the y/z faces: only the x faces can be crossed, and they are
 // walls. Population I (e_Ix = +1) enters through x- at x = 0, (e_Ix = -1)
-// through x+ at x = nx-1; the wall term is a per-direction constant.
-template <int Q, int I, typename S>
-__device__ __forceinline__ const S* pull_addr_xwall(const LatArgs& a, const S* F, const Node& n) {
+// through x+ at x = nx-1; the wall term is a per-direction constant. The
+// bounce-back source (slot I of the node itself) and the normal source (slot
+// opp(I) of x - e_I) are selected as offsets from the lower of the two
+// slabs, so one scalar-base load serves both.
+template <int Q, int I, typename real, bool NT, typename S>
+__device__ __forceinline__ real pull_xwall(const LatArgs& a, const S* F, const Node& n) {
   constexpr int IO = opposite<Q>(I);
-  const size_t N = (size_t)a.N;
-  const S* normal = F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I));
+  const uint32_t sz = sizeof(S);
+  const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
   if constexpr (cx(I) == 0) {
-    return normal;
+    return ldo<real, NT>(F + (size_t)IO * a.N, nb);
   } else {
-    const bool bb = (n.atface & (cx(I) > 0 ? 1u : 2u)) != 0;
-    return bb ? F + (size_t)I * N + n.self : normal;
+    constexpr int LO = I < IO ? I : IO;
+    const uint32_t slab = (uint32_t)a.N * sz;
+    constexpr int F_ = cx(I) > 0 ? 0 : 1;
+    const bool bb = (n.atface & (1u << F_)) != 0;
+    const uint32_t off = bb ? (I - LO) * slab + (uint32_t)n.self * sz : (IO - LO) * slab + nb;
+    const real v = ldo<real, NT>(F + (size_t)LO * a.N, off);
+    return bb ? v + xterm<real>(a.bc, F_, I) : v;
   }
 }
 
-template <int Q, int I, typename real>
-__device__ __forceinline__ real pull_term_xwall(const LatArgs& a, const Node& n) {
-  if constexpr (cx(I) == 0) {
-    return real(0);
-  } else {
-    constexpr int F = cx(I) > 0 ? 0 : 1;
-    const real t = real(6.0 * weight<Q>(I) *
-                        (cx(I) * a.bc.face_u[F][0] + cy(I) * a.bc.face_u[F][1] +
-                         cz(I) * a.bc.face_u[F][2]));
-    return (n.atface & (1u << F)) ? t : real(0);
-  }
-}
-
-template <int Q, int I, typename real, typename S>
+template <int Q, int I, typename real, bool NT, typename S>
 __device__ __forceinline__ void push_xwall(const LatArgs& a, S* F, const Node& n, real v) {
   constexpr int IO = opposite<Q>(I);
-  const size_t N = (size_t)a.N;
-  S* normal = F + (size_t)I * N + n.at(cx(I), cy(I), cz(I));
+  const uint32_t sz = sizeof(S);
+  const uint32_t nb = (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz;
   if constexpr (cx(I) == 0) {
-    st<true>(normal, v);
+    sto<NT>(F + (size_t)I * a.N, nb, v);
   } else {
     // leaving through x+ (e_Ix = +1 at x = nx-1) returns as opp(I), which
     // enters through x+: its wall term uses face 1, and vice versa
+    constexpr int LO = I < IO ? I : IO;
+    const uint32_t slab = (uint32_t)a.N * sz;
     constexpr int Fc = cx(I) > 0 ? 1 : 0;
     const bool bb = (n.atface & (1u << Fc)) != 0;
-    const real t = real(6.0 * weight<Q>(I) *
-                        (cx(IO) * a.bc.face_u[Fc][0] + cy(IO) * a.bc.face_u[Fc][1] +
-                         cz(IO) * a.bc.face_u[Fc][2]));
-    st(bb ? F + (size_t)IO * N + n.self : normal, bb ? v + t : v);
+    const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
+    sto<NT>(F + (size_t)LO * a.N, off, bb ? v + xterm<real>(a.bc, Fc, IO) : v);
   }
 }
 
@@ -405,21 +441,24 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       inlet_velocity(a.bc, n.x, n.y, n.z, t, uin_now);
     }
   }
+  const uint32_t self_off = (uint32_t)n.self * (uint32_t)sizeof(S);
   real f[Q];
   if constexpr (!ODD) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real, true>(F + (size_t)I * N + n.self);
+      f[I] = ldo<real, true>(F + (size_t)I * N, self_off);
     });
   } else {
     if constexpr (BCM == BC_XWALL) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = ld<real, cx(I) == 0>(pull_addr_xwall<Q, I, S>(a, F, n));
+        f[I] = pull_xwall<Q, I, real, cx(I) == 0>(a, F, n);
       });
+    } else if constexpr (BCM == BC_NONE) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] += pull_term_xwall<Q, I, real>(a, n);
+        f[I] = ldo<real, cx(I) == 0>(F + (size_t)opposite<Q>(I) * N,
+                                     (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * (uint32_t)sizeof(S));
       });
     } else {
       static_for<0, Q>([&](auto ic) {
@@ -436,16 +475,17 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     }
   }
   if (rec != nullptr) {
+    const uint32_t roff = (uint32_t)n.self * (uint32_t)sizeof(real);
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      st<true>(rec + (size_t)I * N + n.self, f[I]);
+      sto<true>(rec + (size_t)I * N, roff, f[I]);
     });
   }
   M::collide(f, a);
   if constexpr (!ODD) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      st<true>(F + (size_t)opposite<Q>(I) * N + n.self, f[I]);
+      sto<true>(F + (size_t)opposite<Q>(I) * N, self_off, f[I]);
     });
     if constexpr (BC) {
       if (n.atface & a.bc.outflow) {
@@ -462,7 +502,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     if constexpr (BCM == BC_XWALL) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push_xwall<Q, I, real, S>(a, F, n, f[I]);
+        push_xwall<Q, I, real, cx(I) == 0>(a, F, n, f[I]);
       });
     } else {
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};

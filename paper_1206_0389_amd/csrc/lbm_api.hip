@@ -153,7 +153,10 @@ void plan_rows(lbm_lattice* L) {
   L->rows_bnd = b;
   const uint32_t xbits = np & 3u;
   const bool x_ok = (L->args.bc.inlet & 3u) == 0 && (xbits == 0 || (L->args.bc.wall & 3u) == 3u);
-  L->split_odd = L->has_bc && x_ok && nrows <= 65535;
+  // the x-wall rows address a population and its opposite from one base:
+  // two slabs must stay below 4 GiB
+  const bool two_slabs = 2.0 * (double)L->N * (double)L->elem < 4294967296.0;
+  L->split_odd = L->has_bc && x_ok && nrows <= 65535 && two_slabs;
   const int bx = L->block.x, by = L->block.y;
   L->grid_inner = dim3((nx + bx - 1) / bx, in.ny_in > 0 ? (in.ny_in + by - 1) / by : 0,
                        in.nz_in > 0 ? in.nz_in : 0);
@@ -226,6 +229,10 @@ int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
   const double nnodes = (double)c.nx * c.ny * c.nz;
   if (nnodes >= 2147483648.0) return LBM_EINVAL;
   if (c.nz > 65535 || c.ny > 65535 * 256) return LBM_EINVAL;  // launch grid limits
+  // one population slab (all nodes) below 4 GiB: the kernels address it with
+  // 32-bit byte offsets
+  const size_t elem_bytes = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
+  if (nnodes * (double)elem_bytes >= 4294967296.0) return LBM_EINVAL;
   if (!(c.nu > 0.0) || !std::isfinite(c.nu)) return LBM_EINVAL;
   if (!(c.cs_smag >= 0.0) || !std::isfinite(c.cs_smag)) return LBM_EINVAL;
   if (c.model == LBM_D3Q19_MRT_LES &&
@@ -354,6 +361,7 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
     if (b.inlet_na >= 16384 || b.inlet_nb >= 16384) return LBM_EINVAL;
   }
   if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
+  fill_xterms(b, L->Q);
   L->args.bc = b;
   L->has_bc = b.nonper != 0;
   plan_rows(L);
@@ -572,6 +580,10 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
   if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
   if (L->kind != 2) return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
+  // the kernel addresses two adjacent slabs of the adjoint arrays with 32-bit
+  // byte offsets
+  const double rsz = dtype == LBM_DTYPE_F64 ? 8.0 : 4.0;
+  if (2.0 * (double)L->N * rsz >= 4294967296.0) return LBM_EINVAL;
   auto run = [&](auto real_tag) {
     using R = typename decltype(real_tag)::type;
     const R* f = (const R*)f_t;

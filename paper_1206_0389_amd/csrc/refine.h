@@ -130,31 +130,23 @@ __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, con
 // x-wall-only pull for rows off every non-periodic y/z face: population I
 // enters through x- (e_Ix = +1 at global x = 0) or x+ (e_Ix = -1 at x =
 // n_x - 1), where it is the node's own opposite slot plus a per-direction
-// wall term.
-template <int Q, int I, typename S>
-__device__ __forceinline__ const S* ab_pull_addr_xwall(const Level& L, const S* A,
-                                                       const BoxNode& n) {
+// wall term. Both sources are offsets from the lower of the two slabs (one
+// scalar-base load).
+template <int Q, int I, typename real, bool NT, typename S>
+__device__ __forceinline__ real ab_pull_xwall(const Level& L, const S* A, const BoxNode& n) {
   constexpr int IO = opposite<Q>(I);
-  const size_t N = (size_t)L.Nbox;
-  const S* normal = A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I));
+  const uint32_t sz = sizeof(S);
+  const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
   if constexpr (cx(I) == 0) {
-    return normal;
+    return ldo<real, NT>(A + (size_t)I * L.Nbox, nb);
   } else {
-    const bool bb = (n.atface & (cx(I) > 0 ? 1u : 2u)) != 0;
-    return bb ? A + (size_t)IO * N + n.self : normal;
-  }
-}
-
-template <int Q, int I, typename real>
-__device__ __forceinline__ real ab_term_xwall(const Level& L, const BoxNode& n) {
-  if constexpr (cx(I) == 0) {
-    return real(0);
-  } else {
-    constexpr int F = cx(I) > 0 ? 0 : 1;
-    const real t = real(6.0 * weight<Q>(I) *
-                        (cx(I) * L.bc.face_u[F][0] + cy(I) * L.bc.face_u[F][1] +
-                         cz(I) * L.bc.face_u[F][2]));
-    return (n.atface & (1u << F)) ? t : real(0);
+    constexpr int LO = I < IO ? I : IO;
+    const uint32_t slab = (uint32_t)L.Nbox * sz;
+    constexpr int F_ = cx(I) > 0 ? 0 : 1;
+    const bool bb = (n.atface & (1u << F_)) != 0;
+    const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
+    const real v = ldo<real, NT>(A + (size_t)LO * L.Nbox, off);
+    return bb ? v + xterm<real>(L.bc, F_, I) : v;
   }
 }
 
@@ -200,25 +192,30 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
   } else if constexpr (BCM == BC_XWALL) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real, cx(I) == 0>(ab_pull_addr_xwall<Q, I, S>(L, A, n));
-    });
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      f[I] += ab_term_xwall<Q, I, real>(L, n);
+      f[I] = ab_pull_xwall<Q, I, real, cx(I) == 0>(L, A, n);
     });
   } else {
     const size_t N = (size_t)L.Nbox;
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<real, cx(I) == 0>(A + (size_t)I * N + n.at(-cx(I), -cy(I), -cz(I)));
+      f[I] = ldo<real, cx(I) == 0>(A + (size_t)I * N,
+                                   (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * (uint32_t)sizeof(S));
     });
   }
   M::collide(f, L);
   const size_t N = (size_t)L.Nbox;
-  static_for<0, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    st<BCM != BC_GENERAL>(B + (size_t)I * N + self, f[I]);
-  });
+  if constexpr (BCM == BC_GENERAL) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      st(B + (size_t)I * N + self, f[I]);
+    });
+  } else {
+    const uint32_t self_off = (uint32_t)self * (uint32_t)sizeof(S);
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      sto<true>(B + (size_t)I * N, self_off, f[I]);
+    });
+  }
 }
 
 // Equilibrium of the model (deviation form) for the moments of f.
