@@ -343,17 +343,22 @@ void one_coarse_step(lbm_refined* R, long long t) {
     level_step<KIND, S>(R, R->Lf, R->plan[1], 1, 2 * t);
     interp<KIND, S>(R, ga, R->Lc.b, R->g1);
     fill<KIND, S>(R, ga, R->g0, R->g1, 0.5, 0.5, R->Lf.b);
+    // the last fine substep also injects into the covered nodes of the
+    // coarse state at t + 1 (read by no ghost stencil)
     Level L2 = R->Lf;
     std::swap(L2.a, L2.b);
+    if (!R->covered.empty()) {
+      L2.cinj = R->Lc.b;
+      L2.ctype = R->Lc.type;
+      for (int d = 0; d < 3; ++d) L2.cn[d] = R->Lc.n[d];
+      L2.Nc = (long long)R->Nc;
+      L2.rinv = 1.0 / R->r;
+    }
     level_step<KIND, S>(R, L2, R->plan[1], 1, 2 * t + 1);
   }
   std::swap(R->Lc.a, R->Lc.b);
   std::swap(R->g0, R->g1);
   R->g0_valid = fine;
-  if (fine && !R->covered.empty())
-    hipLaunchKernelGGL((inject_kernel<KIND, S>), dim3(blocks_for((long long)R->covered.size())),
-                       dim3(256), 0, R->stream, ga, (const int*)(R->base + R->off[7]),
-                       (long long)R->covered.size(), 1.0 / R->r, (const S*)R->Lf.a, (S*)R->Lc.a);
 }
 
 bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }

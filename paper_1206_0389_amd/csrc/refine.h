@@ -43,6 +43,15 @@ struct Level {
   MrtParams mrt;
   double omega;
   BcArgs bc;
+  // Injection into the covered coarse nodes, done by the last fine substep
+  // of a coarse step (cinj null otherwise): the fine node coincident with a
+  // covered coarse node (all global fine coordinates even, coarse type 2)
+  // writes f_eq + rinv (f - f_eq) of its post-collision state into cinj.
+  void* cinj;
+  const uint8_t* ctype;
+  int cn[3];
+  long long Nc;
+  double rinv;
 };
 
 // 1-D interpolation stencil for fine coordinate j on an axis of n coarse
@@ -150,6 +159,50 @@ __device__ __forceinline__ real ab_pull_xwall(const Level& L, const S* A, const 
   }
 }
 
+// Equilibrium of the model (deviation form) for the moments of f.
+template <int KIND, typename R>
+__device__ __forceinline__ void equilibrium_dev(const R (&f)[Model<KIND>::Q],
+                                                R (&feq)[Model<KIND>::Q]) {
+  constexpr int Q = Model<KIND>::Q;
+  R d = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    j[0] += R(cx(i)) * f[i];
+    j[1] += R(cy(i)) * f[i];
+    j[2] += R(cz(i)) * f[i];
+  }
+  if constexpr (Q == 19) {
+    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const R eu = R(cx(i)) * j[0] + R(cy(i)) * j[1] + R(cz(i)) * j[2];
+      feq[i] = R(weight<19>(i)) * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+    }
+  } else {
+    // rho prod_a phi(e_a; u_a) - w with phi(0) = 2/3 - u^2,
+    // phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors
+    const R rho = R(1) + d;
+    R dp[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R u = j[c] / rho, q = u * u;
+      dp[c][0] = R(0.5) * (q - u);
+      dp[c][1] = -q;
+      dp[c][2] = R(0.5) * (q + u);
+    }
+    const R p0[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const R a0 = p0[cx(i) + 1], b0 = p0[cy(i) + 1], c0 = p0[cz(i) + 1];
+      const R da = dp[0][cx(i) + 1], db = dp[1][cy(i) + 1], dc = dp[2][cz(i) + 1];
+      const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
+                    a0 * db * dc + da * db * dc;
+      feq[i] = dev + d * (a0 * b0 * c0 + dev);
+    }
+  }
+}
+
 // One pull-and-collide update of a level at time t over the rows r (box-
 // local coordinates). mode 0 updates every node whose type is not 2
 // (coarse), mode 1 only type-1 nodes (fine). BCM: BC_NONE (no non-periodic
@@ -216,48 +269,17 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
       sto<true>(B + (size_t)I * N, self_off, f[I]);
     });
   }
-}
-
-// Equilibrium of the model (deviation form) for the moments of f.
-template <int KIND, typename R>
-__device__ __forceinline__ void equilibrium_dev(const R (&f)[Model<KIND>::Q],
-                                                R (&feq)[Model<KIND>::Q]) {
-  constexpr int Q = Model<KIND>::Q;
-  R d = 0, j[3] = {0, 0, 0};
+  if (L.cinj != nullptr && ((n.g[0] | n.g[1] | n.g[2]) & 1) == 0) {
+    const size_t ci = ((size_t)(n.g[2] >> 1) * L.cn[1] + (n.g[1] >> 1)) * L.cn[0] + (n.g[0] >> 1);
+    if (L.ctype[ci] == 2) {
+      real g[Q], feq[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    d += f[i];
-    j[0] += R(cx(i)) * f[i];
-    j[1] += R(cy(i)) * f[i];
-    j[2] += R(cz(i)) * f[i];
-  }
-  if constexpr (Q == 19) {
-    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+      for (int q = 0; q < Q; ++q) g[q] = real(S(f[q]));  // the stored value
+      equilibrium_dev<KIND, real>(g, feq);
+      S* C = (S*)L.cinj;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const R eu = R(cx(i)) * j[0] + R(cy(i)) * j[1] + R(cz(i)) * j[2];
-      feq[i] = R(weight<19>(i)) * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-    }
-  } else {
-    // rho prod_a phi(e_a; u_a) - w with phi(0) = 2/3 - u^2,
-    // phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors
-    const R rho = R(1) + d;
-    R dp[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const R u = j[c] / rho, q = u * u;
-      dp[c][0] = R(0.5) * (q - u);
-      dp[c][1] = -q;
-      dp[c][2] = R(0.5) * (q + u);
-    }
-    const R p0[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const R a0 = p0[cx(i) + 1], b0 = p0[cy(i) + 1], c0 = p0[cz(i) + 1];
-      const R da = dp[0][cx(i) + 1], db = dp[1][cy(i) + 1], dc = dp[2][cz(i) + 1];
-      const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
-                    a0 * db * dc + da * db * dc;
-      feq[i] = dev + d * (a0 * b0 * c0 + dev);
+      for (int q = 0; q < Q; ++q)
+        st(C + (size_t)q * (size_t)L.Nc + ci, feq[q] + real(L.rinv) * (g[q] - feq[q]));
     }
   }
 }
@@ -315,28 +337,6 @@ __global__ __launch_bounds__(256) void fill_kernel(const GhostArgs ga, const R* 
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     st(ff + (size_t)q * (size_t)ga.Nf + l, feq[q] + R(r) * (g[q] - feq[q]));
-}
-
-// Covered coarse nodes = inverse rescale of the coincident fine node.
-template <int KIND, typename S>
-__global__ __launch_bounds__(256) void inject_kernel(const GhostArgs ga, const int* covered,
-                                                     long long ncov, double rinv, const S* ff,
-                                                     S* fc) {
-  using R = typename Compute<S>::type;
-  constexpr int Q = Model<KIND>::Q;
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ncov) return;
-  const int nidx = covered[k];
-  const int x = nidx % ga.cn[0], y = (nidx / ga.cn[0]) % ga.cn[1], z = nidx / (ga.cn[0] * ga.cn[1]);
-  const size_t l = ((size_t)(2 * z - ga.flo[2]) * ga.fM[1] + (2 * y - ga.flo[1])) * ga.fM[0] +
-                   (2 * x - ga.flo[0]);
-  R g[Q], feq[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) g[q] = ld<R>(ff + (size_t)q * (size_t)ga.Nf + l);
-  equilibrium_dev<KIND, R>(g, feq);
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-    st(fc + (size_t)q * (size_t)ga.Nc + nidx, feq[q] + R(rinv) * (g[q] - feq[q]));
 }
 
 // FP64 partial sums over the nodes of a level box whose type equals want,

@@ -79,6 +79,20 @@ def test_create_validates_configuration(P):
     assert P.lib().lbm_create_lattice(None, None) == P.EINVAL
 
 
+def test_create_enforces_the_population_slab_limit(P):
+    """One population (nodes x element size) must stay below 4 GiB: the
+    kernels address it with 32-bit byte offsets."""
+    # 1024 x 1024 x 512 nodes: 4 GiB per population in FP64, 2 GiB in FP32
+    big = (1024, 1024, 512)
+    assert _create(P, _cfg(P, shape=big, storage=P.F64))[0] == P.EINVAL
+    rc, h = _create(P, _cfg(P, shape=big, storage=P.F32))
+    assert rc == P.OK
+    P.lib().lbm_destroy(h)
+    rc, h = _create(P, _cfg(P, shape=(1024, 1024, 511), storage=P.F64))
+    assert rc == P.OK
+    P.lib().lbm_destroy(h)
+
+
 def test_required_bytes_and_binding_checks(P):
     _, h = _create(P, _cfg(P, shape=(16, 8, 4), storage=P.F32))
     n = ctypes.c_size_t()
