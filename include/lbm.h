@@ -328,7 +328,11 @@ int lbm_refined_set_boundaries(lbm_refined* r, const lbm_boundaries* bc,
 int lbm_refined_init_equilibrium(lbm_refined* r, int level, const void* drho, const void* u,
                                  int dtype, int64_t t0);
 
-/* Post-collision populations of one level, [Q][box] (set / get). */
+/* Post-collision populations of one level, [Q][box] (set / get). On level
+ * 1 the ghost nodes (the layer around the refined region) hold interface
+ * values already prepared for the next fine substep, not state: get returns
+ * them as they are, and after a set or init they are rebuilt from the coarse
+ * level at the next step. */
 int lbm_refined_set_populations(lbm_refined* r, int level, const void* f, int dtype,
                                 int64_t t0);
 int lbm_refined_get_populations(lbm_refined* r, int level, void* f, int dtype);

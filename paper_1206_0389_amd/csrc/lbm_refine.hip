@@ -331,18 +331,30 @@ void fill(const lbm_refined* R, const GhostArgs& ga, const void* A, const void* 
 }
 
 template <int KIND, typename S>
+void interp_fill(const lbm_refined* R, const GhostArgs& ga, const void* fc, void* G1,
+                 const void* G0, void* ff_half, void* ff_next) {
+  using Rt = typename Compute<S>::type;
+  if (ga.ng == 0) return;
+  constexpr int GT = 1024 / Model<KIND>::Q;
+  hipLaunchKernelGGL((interp_fill_kernel<KIND, S, Rt>), dim3((unsigned)((ga.ng + GT - 1) / GT)),
+                     dim3(1024), 0, R->stream, ga, (const S*)fc, (Rt*)G1, (const Rt*)G0, R->r,
+                     (S*)ff_half, (S*)ff_next);
+}
+
+template <int KIND, typename S>
 void one_coarse_step(lbm_refined* R, long long t) {
   const GhostArgs ga = ghost_args(R);
   const bool fine = R->Nf > 0;
-  if (fine) {
-    if (!R->g0_valid) interp<KIND, S>(R, ga, R->Lc.a, R->g0);
+  // The ghosts of the first fine substep come from the previous coarse
+  // step's half-step update; after a change of state they are rebuilt.
+  if (fine && !R->g0_valid) {
+    interp<KIND, S>(R, ga, R->Lc.a, R->g0);
     fill<KIND, S>(R, ga, R->g0, R->g0, 1.0, 0.0, R->Lf.a);
   }
   level_step<KIND, S>(R, R->Lc, R->plan[0], 0, t);
   if (fine) {
     level_step<KIND, S>(R, R->Lf, R->plan[1], 1, 2 * t);
-    interp<KIND, S>(R, ga, R->Lc.b, R->g1);
-    fill<KIND, S>(R, ga, R->g0, R->g1, 0.5, 0.5, R->Lf.b);
+    interp_fill<KIND, S>(R, ga, R->Lc.b, R->g1, R->g0, R->Lf.b, R->Lf.a);
     // the last fine substep also injects into the covered nodes of the
     // coarse state at t + 1 (read by no ghost stencil)
     Level L2 = R->Lf;

@@ -67,16 +67,31 @@ __host__ __device__ inline int interp_stencil(int j, int n, bool periodic, int i
     w[0] = 1.0;
     return 1;
   }
-  const double p = 0.5 * j;
+  // The target j/2 lies at t = j/2 - s from the first node: 3/2 inside,
+  // 1/2, 5/2 or 7/2 where the window is moved inside a non-periodic face.
+  // The cubic Lagrange weights at these t are dyadic (written out exactly);
+  // any other t falls back to the product formula.
   int s = (j - 1) / 2 - 1;
   if (!periodic) s = s < 0 ? 0 : (s > n - 4 ? n - 4 : s);
-  for (int a = 0; a < 4; ++a) {
-    double v = 1.0;
-    for (int b = 0; b < 4; ++b)
-      if (b != a) v *= (p - (double)(s + b)) / (double)(a - b);
-    w[a] = v;
-    idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
+  const int k2 = j - 2 * s;  // 2t
+  if (k2 == 3) {
+    w[0] = -1.0 / 16; w[1] = 9.0 / 16; w[2] = 9.0 / 16; w[3] = -1.0 / 16;
+  } else if (k2 == 1) {
+    w[0] = 5.0 / 16; w[1] = 15.0 / 16; w[2] = -5.0 / 16; w[3] = 1.0 / 16;
+  } else if (k2 == 5) {
+    w[0] = 1.0 / 16; w[1] = -5.0 / 16; w[2] = 15.0 / 16; w[3] = 5.0 / 16;
+  } else if (k2 == 7) {
+    w[0] = -5.0 / 16; w[1] = 21.0 / 16; w[2] = -35.0 / 16; w[3] = 35.0 / 16;
+  } else {
+    const double p = 0.5 * j;
+    for (int a = 0; a < 4; ++a) {
+      double v = 1.0;
+      for (int b = 0; b < 4; ++b)
+        if (b != a) v *= (p - (double)(s + b)) / (double)(a - b);
+      w[a] = v;
+    }
   }
+  for (int a = 0; a < 4; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
   return 4;
 }
 
@@ -296,29 +311,49 @@ struct GhostArgs {
 // G[q][g] = spatial interpolation of the coarse post-collision field at
 // ghost g; one thread per (ghost, population), population-major so that a
 // wave reads the stencils of neighbouring ghosts in one population array.
+// Tensor interpolation stencil of one ghost (per axis: 1 or 4 coarse nodes).
+struct GhostStencil {
+  int cnt[3];
+  int idx[3][4];
+  double w[3][4];
+};
+
+__device__ __forceinline__ void ghost_stencil(const GhostArgs& ga, long long gi, GhostStencil& st) {
+  const int l = ga.ghosts[gi];
+  const int lx = l % ga.fM[0], ly = (l / ga.fM[0]) % ga.fM[1], lz = l / (ga.fM[0] * ga.fM[1]);
+  const int j[3] = {lx + ga.flo[0], ly + ga.flo[1], lz + ga.flo[2]};
+  for (int d = 0; d < 3; ++d)
+    st.cnt[d] = interp_stencil(j[d], ga.cn[d], (ga.cper >> d) & 1u, st.idx[d], st.w[d]);
+}
+
+template <typename S, typename R, typename ST>
+__device__ __forceinline__ R interp_apply(const GhostArgs& ga, const S* fc, int q, const ST& st) {
+  const S* fq = fc + (size_t)q * (size_t)ga.Nc;
+  R s = 0;
+  for (int c = 0; c < st.cnt[2]; ++c)
+    for (int b = 0; b < st.cnt[1]; ++b) {
+      const R wbc = R(st.w[1][b] * st.w[2][c]);
+      const size_t row = ((size_t)st.idx[2][c] * ga.cn[1] + st.idx[1][b]) * ga.cn[0];
+      for (int a = 0; a < st.cnt[0]; ++a)
+        s += R(st.w[0][a]) * wbc * ld<R>(fq + row + st.idx[0][a]);
+    }
+  return s;
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ R interp_value(const GhostArgs& ga, const S* fc, int q, long long gi) {
+  GhostStencil st;
+  ghost_stencil(ga, gi, st);
+  return interp_apply<S, R>(ga, fc, q, st);
+}
+
 template <int Q, typename S, typename R>
 __global__ __launch_bounds__(256) void interp_kernel(const GhostArgs ga, const S* fc, R* G) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ga.ng * Q) return;
   const int q = (int)(k / ga.ng);
   const long long gi = k - (long long)q * ga.ng;
-  const int l = ga.ghosts[gi];
-  const int lx = l % ga.fM[0], ly = (l / ga.fM[0]) % ga.fM[1], lz = l / (ga.fM[0] * ga.fM[1]);
-  const int j[3] = {lx + ga.flo[0], ly + ga.flo[1], lz + ga.flo[2]};
-  int idx[3][4];
-  double w[3][4];
-  int cnt[3];
-  for (int d = 0; d < 3; ++d)
-    cnt[d] = interp_stencil(j[d], ga.cn[d], (ga.cper >> d) & 1u, idx[d], w[d]);
-  const S* fq = fc + (size_t)q * (size_t)ga.Nc;
-  R s = 0;
-  for (int c = 0; c < cnt[2]; ++c)
-    for (int b = 0; b < cnt[1]; ++b) {
-      const R wbc = R(w[1][b] * w[2][c]);
-      const size_t row = ((size_t)idx[2][c] * ga.cn[1] + idx[1][b]) * ga.cn[0];
-      for (int a = 0; a < cnt[0]; ++a) s += R(w[0][a]) * wbc * ld<R>(fq + row + idx[0][a]);
-    }
-  G[(size_t)q * ga.ng + gi] = s;
+  G[(size_t)q * ga.ng + gi] = interp_value<S, R>(ga, fc, q, gi);
 }
 
 // Ghost populations = rescale(c0 G0 + c1 G1) into the fine state ff.
@@ -337,6 +372,57 @@ __global__ __launch_bounds__(256) void fill_kernel(const GhostArgs ga, const R* 
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     st(ff + (size_t)q * (size_t)ga.Nf + l, feq[q] + R(r) * (g[q] - feq[q]));
+}
+
+// Half-step interface update in one launch: G1 = interpolation of the
+// coarse state at t+1 (kept for the next coarse step), the ghosts of the
+// second fine substep = rescale(G0/2 + G1/2) into ff_half, and the ghosts
+// of the next coarse step's first substep = rescale(G1) into ff_next (that
+// array's ghost slots are not written by the second substep). A workgroup
+// takes GT ghosts x Q populations, population-major; the rescaling needs
+// each ghost's moments, shared through LDS. Same arithmetic as
+// interp_kernel followed by fill_kernel.
+template <int KIND, typename S, typename R>
+__global__ __launch_bounds__(1024) void interp_fill_kernel(const GhostArgs ga, const S* fc,
+                                                           R* G1, const R* G0, double r,
+                                                           S* ff_half, S* ff_next) {
+  constexpr int Q = Model<KIND>::Q;
+  constexpr int GT = 1024 / Q;
+  __shared__ R sv[2][Q][GT];
+  __shared__ R se[2][Q][GT];
+  __shared__ GhostStencil sst[GT];
+  const int t = threadIdx.x;
+  const int q = t / GT, gl = t - q * GT;
+  const long long g0 = (long long)blockIdx.x * GT;
+  const long long gi = g0 + gl;
+  const bool act = q < Q && gi < ga.ng;
+  if (t < GT && g0 + t < ga.ng) ghost_stencil(ga, g0 + t, sst[t]);
+  __syncthreads();
+  if (act) {
+    const R g1 = interp_apply<S, R>(ga, fc, q, sst[gl]);
+    G1[(size_t)q * ga.ng + gi] = g1;
+    sv[0][q][gl] = R(0.5) * G0[(size_t)q * ga.ng + gi] + R(0.5) * g1;
+    sv[1][q][gl] = g1;
+  }
+  __syncthreads();
+  if (t < 2 * GT) {
+    const int w = t / GT, g = t - w * GT;
+    if (g0 + g < ga.ng) {
+      R v[Q], feq[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = sv[w][i][g];
+      equilibrium_dev<KIND, R>(v, feq);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) se[w][i][g] = feq[i];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const int l = ga.ghosts[gi];
+    const R e0 = se[0][q][gl], e1 = se[1][q][gl];
+    st(ff_half + (size_t)q * (size_t)ga.Nf + l, e0 + R(r) * (sv[0][q][gl] - e0));
+    st(ff_next + (size_t)q * (size_t)ga.Nf + l, e1 + R(r) * (sv[1][q][gl] - e1));
+  }
 }
 
 // FP64 partial sums over the nodes of a level box whose type equals want,

@@ -1,7 +1,11 @@
 """Two-level refined lattice on the GPU vs the FP64 oracle, through the C ABI.
 
 FP64 storage: both levels element by element to 1e-12 relative (rounding
-order only). FP32 storage: a few units of FP32 rounding per step.
+order only). FP32 storage: a few units of FP32 rounding per step. On the
+fine level the ghost nodes are interface scratch (the library prepares the
+next substep's ghosts ahead of time), so they are left out of the
+comparison; every fluid node next to a ghost pulls from it, so a wrong ghost
+value shows up in the fluid nodes one substep later.
 """
 import numpy as np
 import pytest
@@ -81,11 +85,12 @@ def test_refined_step_parity_fp64(name, jet):
     g.set_populations(0, torch.from_numpy(fc), 4)
     g.set_populations(1, torch.from_numpy(ff), 4)
     oc, of = fc, ff
+    keep = R.types()[1] != 2
     for k in range(3):
         g.step(1)
         oc, of = R.run(oc, of, 4 + k, 1)
         ec = rel_err(g.populations(0).cpu().numpy(), oc)
-        ef = rel_err(g.populations(1).cpu().numpy(), of)
+        ef = rel_err(g.populations(1).cpu().numpy()[:, keep], of[:, keep])
         assert ec <= 1e-12 and ef <= 1e-12, (k, ec, ef)
     rg = np.array(g.reduce())
     ro = _oracle_reduce(R, c, oc, of)
@@ -102,8 +107,9 @@ def test_refined_fp32_within_tolerance(name):
     g.set_populations(1, torch.from_numpy(ff))
     g.step(2)
     oc, of = R.run(fc, ff, 0, 2)
+    keep = R.types()[1] != 2
     ec = rel_err(g.populations(0).cpu().numpy(), oc)
-    ef = rel_err(g.populations(1).cpu().numpy(), of)
+    ef = rel_err(g.populations(1).cpu().numpy()[:, keep], of[:, keep])
     assert ec <= 1e-5 and ef <= 1e-5, (ec, ef)
 
 
