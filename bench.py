@@ -91,6 +91,16 @@ def refined_jet_mask(nx, ny, nz, B=16, layers=8, radius=62.0):
     return m
 
 
+def jet_setup(nx, ny, synth):
+    """Boundary data of the round-jet workloads (side walls moving with the
+    co-flow, velocity inlet at z-, zero-gradient outflow at z+)."""
+    diam = 32.0 if nx >= 256 else 16.0
+    iu, im = synth.jet_inlet(nx, ny, diam, 0.05, 0.002)
+    return {"nu": 1e-4, "cs": 0.1, "diameter": diam, "inlet_u": iu, "inlet_mask": im,
+            "face_u": [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2,
+            "inlet_amp": 0.01 * 0.05, "seed": 12060389}
+
+
 def make_lattice(name, P, torch, synth):
     import numpy as np
     model, storage, shape, kind = workload(name)
@@ -125,14 +135,13 @@ def make_lattice(name, P, torch, synth):
         lat.updates_per_step = desc["updates_per_coarse_step"]
         return lat, desc
     if kind.startswith("jet"):
-        nu, cs = 1e-4, 0.1
+        js = jet_setup(nx, ny, synth)
+        nu, cs, diam = js["nu"], js["cs"], js["diameter"]
         lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs)
-        diam = 32.0 if nx >= 256 else 16.0
-        iu, im = synth.jet_inlet(nx, ny, diam, 0.05, 0.002)
-        fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
         faces = [P.WALL, P.WALL, P.WALL, P.WALL, P.INLET, P.OUTFLOW]
-        lat.set_boundaries(faces, face_u=fu, inlet_u=torch.from_numpy(iu),
-                           inlet_mask=torch.from_numpy(im), inlet_amp=0.01 * 0.05, seed=12060389)
+        lat.set_boundaries(faces, face_u=js["face_u"], inlet_u=torch.from_numpy(js["inlet_u"]),
+                           inlet_mask=torch.from_numpy(js["inlet_mask"]),
+                           inlet_amp=js["inlet_amp"], seed=js["seed"])
         d, u = synth.uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.002), dtype=np.float32)
         desc = {"workload": "round jet %dx%dx%d, D=%d inlet u=0.05 +1%% seeded perturbation, "
                             "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4"

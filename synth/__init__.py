@@ -138,3 +138,22 @@ def jet_adjoint_case(n: int = 128, nz: int = 256, diameter: int = 16, u_jet: flo
     hi = (p0 + 2 * diameter, p0 + 2 * diameter, 7 * diameter)
     return {"inlet_u": u, "base_u": base, "disk": disk, "square": square, "delta": delta,
             "probe_lo": lo, "probe_hi": hi}
+
+
+def tiled_populations(q: int, shape, amp: float = 1e-2, seed: int = 0, period=(31, 29, 37),
+                      lo=(0, 0, 0), hi=None, qs=None):
+    """Seeded uniform-noise populations on a large lattice, cheap to evaluate
+    on any sub-box: a random block of `period` = (pz, py, px) nodes repeated
+    periodically. shape = (nz, ny, nx) of the whole lattice; lo, hi = (x, y,
+    z) bounds of the sub-box returned ([q][z][y][x]); qs selects populations
+    (default all). The odd periods make row ends, walls and corners see
+    different values."""
+    nz, ny, nx = shape
+    if hi is None:
+        hi = (nx, ny, nz)
+    base = random_populations(q, period, amp, seed)
+    zs = np.arange(lo[2], hi[2]) % period[0]
+    ys = np.arange(lo[1], hi[1]) % period[1]
+    xs = np.arange(lo[0], hi[0]) % period[2]
+    qsel = range(q) if qs is None else qs
+    return np.stack([base[k][np.ix_(zs, ys, xs)] for k in qsel])

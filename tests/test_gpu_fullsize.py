@@ -1,0 +1,138 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+The 256 x 256 x 512 round jet is built exactly as bench.py builds it (same
+lattice, boundaries, inlet field and perturbation seed), loaded with a seeded
+noise state from synth (far from equilibrium, so every collision term is
+exercised) and stepped three times (even, odd, even parity: both row splits
+of the odd step run). Sampled 8^3 boxes are then compared element by element
+with the FP64 oracle run on the same box padded by the light cone (three
+nodes per side; cut sides are made periodic in the oracle, which only
+corrupts the padding). The boxes cover the interior, both row ends (x walls),
+a y wall, the inlet disk with its perturbation, the inlet-wall corner, the
+outflow plane and the outflow-wall corner.
+
+Tolerances per step, as in the small-lattice parity tests: FP64 1e-12, FP32
+4e-6, FP16 2e-3 of the largest population; the oracle starts from the state
+rounded to the storage precision, exactly as the GPU stored it.
+
+The two-level refined workload is checked at full size through properties
+that hold at any size (uniform flow preserved exactly; FP32 against FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from lbm_cases import MODELS, oracle_lattice, rel_err, window
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+W, I, O = oracle.WALL, oracle.INLET, oracle.OUTFLOW
+JET = [W, W, W, W, I, O]
+STEPS, T0, SEED, AMP = 3, 0, 20120389, 1e-2
+BOXES = [  # (lo, hi) in (x, y, z)
+    ((124, 124, 250), (132, 132, 258)),  # interior
+    ((0, 100, 100), (8, 108, 108)),      # row starts at the x- wall
+    ((248, 100, 100), (256, 108, 108)),  # row ends at the x+ wall
+    ((100, 0, 300), (108, 8, 308)),      # y- wall (face rows of the odd step)
+    ((124, 124, 0), (132, 132, 8)),      # inlet disk, perturbed
+    ((0, 248, 0), (8, 256, 8)),          # x- wall, y+ wall, inlet corner
+    ((120, 0, 504), (128, 8, 512)),      # outflow plane, y- wall
+    ((248, 248, 504), (256, 256, 512)),  # x+, y+, outflow corner
+]
+TOL = {"f64": 1e-12, "f32": 4e-6, "f16": 2e-3}
+ROUND = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+
+
+@pytest.mark.parametrize("workload", ["jet256-fclb-f32", "jet256-mrt-f32", "jet256-fclb-f16",
+                                      "jet256-fclb-f64"])
+def test_jet256_boxes_against_oracle(workload):
+    import bench
+    import paper_1206_0389_amd as P
+    print("case full size", workload, flush=True)
+    model, storage, shape, _ = bench.workload(workload)
+    nx, ny, nz = shape
+    name = "fclb" if model == "fclb" else "mrt_table1"
+    Q = 27 if model == "fclb" else 19
+    lat, _ = bench.make_lattice(workload, P, torch, synth)
+    js = bench.jet_setup(nx, ny, synth)
+    f = torch.empty((Q, nz, ny, nx), dtype=torch.float64, device="cuda")
+    for q in range(Q):
+        f[q] = torch.from_numpy(synth.tiled_populations(Q, (nz, ny, nx), AMP, SEED,
+                                                        qs=[q])[0]).cuda()
+    lat.set_populations(f, t0=T0)
+    del f
+    lat.step(STEPS)
+    torch.cuda.synchronize()
+    got = lat.populations()
+    worst = 0.0
+    for lo, hi in BOXES:
+        wlo, whi, wf, inner = window((nx, ny, nz), JET, lo, hi, STEPS)
+        f0 = synth.tiled_populations(Q, (nz, ny, nx), AMP, SEED, lo=wlo, hi=whi)
+        f0 = f0.astype(ROUND[storage]).astype(np.float64)
+        o = oracle_lattice(name, tuple(b - a for a, b in zip(wlo, whi)), js["nu"],
+                           cs=js["cs"] if model == "mrt" else 0.0, faces=wf,
+                           face_u=js["face_u"], inlet=(js["inlet_u"], js["inlet_mask"]),
+                           amp=js["inlet_amp"], seed=js["seed"], origin=tuple(wlo),
+                           extent=(nx, ny))
+        ref = o.run(f0, T0, STEPS)[:, inner[2], inner[1], inner[0]]
+        g = got[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        err = rel_err(g, ref)
+        worst = max(worst, err)
+        assert err <= STEPS * TOL[storage], (lo, hi, err)
+    print(workload, "worst box error", worst, flush=True)
+
+
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_refined_jet_full_size_properties(model):
+    """The 128 x 128 x 256 two-level jet of the benchmark: a uniform co-flow
+    through the whole configuration (inlet at the co-flow speed everywhere,
+    walls moving with it) stays exactly uniform on both levels in FP64; with
+    the benchmark's inlet and state, FP32 storage tracks FP64 storage within
+    the FP32 per-step tolerance over 3 coarse steps."""
+    import bench
+    import paper_1206_0389_amd as P
+    print("case refined full size", model, flush=True)
+    nx, ny, nz, B = 128, 128, 256, 16
+    mask = bench.refined_jet_mask(nx, ny, nz, B)
+    u0 = 0.002
+    iu = np.zeros((3, ny, nx))
+    iu[2] = u0
+    fiu = np.zeros((3, 2 * ny, 2 * nx))
+    fiu[2] = u0
+    fu = [[0.0, 0.0, u0]] * 4 + [[0.0, 0.0, 0.0]] * 2
+    lat = P.RefinedLattice(model=model, storage="f64", shape=(nx, ny, nz), nu=1e-4,
+                           cs_smag=0.1, block=B, mask=mask,
+                           faces=[P.WALL] * 4 + [P.INLET, P.OUTFLOW], face_u=fu,
+                           inlet_u=torch.from_numpy(iu), fine_inlet_u=torch.from_numpy(fiu))
+    for level in (0, 1):
+        d, u = synth.uniform_fields(*lat.shape3(level)[::-1], u=(0.0, 0.0, u0))
+        lat.init_equilibrium(level, torch.from_numpy(d), torch.from_numpy(u))
+    f0 = [lat.populations(level) for level in (0, 1)]
+    lat.step(3)
+    for level in (0, 1):
+        d, u = lat.macroscopic(level)
+        f1 = lat.populations(level)
+        # every updated node is unchanged; ghosts and covered nodes hold the
+        # same uniform values
+        assert float((f1 - f0[level]).abs().max()) < 1e-15, level
+        assert float((u[2] - u0).abs().max()) < 1e-15 and float(d.abs().max()) < 1e-15
+    del lat, f0
+    torch.cuda.empty_cache()
+    # benchmark inlet and state: FP32 against FP64
+    out = {}
+    for storage in ("f64", "f32"):
+        lat, _ = bench.make_lattice("ref128-%s-%s" % (model, storage), P, torch, synth)
+        lat.step(3)
+        out[storage] = [lat.populations(level) for level in (0, 1)]
+        del lat
+        torch.cuda.empty_cache()
+    for level in (0, 1):
+        a, b = out["f32"][level], out["f64"][level]
+        err = float((a - b).abs().max() / b.abs().max())
+        print("refined", model, "level", level, "FP32 vs FP64", err, flush=True)
+        assert err <= 3 * 2 * TOL["f32"]  # two fine substeps per coarse step
