@@ -53,7 +53,7 @@ def _run_pair(name, storage, shape, nu, steps, cs=0.1, faces=None, face_u=None, 
 
 
 @pytest.mark.parametrize("name", NAMES)
-@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 9), (1, 16, 3)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 9), (1, 16, 3), (16, 12, 1), (7, 1, 1)])
 def test_periodic_step_parity_fp64(name, shape):
     errs = _run_pair(name, "f64", shape, 0.02, [1, 2, 5])
     assert max(errs) <= TOL["f64"], errs
