@@ -27,6 +27,11 @@ struct lbm_refined {
   std::vector<int32_t> ghosts, covered;
   double r;
   hipStream_t stream;
+  // second stream (default priority, non-blocking) on which the coarse step
+  // runs concurrently with the first fine substep, joined by events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool side_tried = false;
   // device layout
   char* base = nullptr;
   size_t off[12] = {0};
@@ -289,22 +294,23 @@ void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem) {
 }
 
 template <int KIND, typename S>
-void level_step(const lbm_refined* R, const Level& L, const lbm_refined::Plan& p, int mode,
+void level_step(const lbm_refined* R, hipStream_t stream, const Level& L,
+                const lbm_refined::Plan& p, int mode,
                 long long t) {
   if (L.Nbox == 0) return;
   if (p.mode == 0) {
     hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_NONE, ROWS_BOX>), p.grid_all, p.block, 0,
-                       R->stream, L, p.all, mode, t);
+                       stream, L, p.all, mode, t);
   } else if (p.mode == 2) {
     hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_BOX>), p.grid_all, p.block, 0,
-                       R->stream, L, p.all, mode, t);
+                       stream, L, p.all, mode, t);
   } else {
     if (p.grid_inner.y > 0 && p.grid_inner.z > 0)
       hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_XWALL, ROWS_BOX>), p.grid_inner, p.block, 0,
-                         R->stream, L, p.inner, mode, t);
+                         stream, L, p.inner, mode, t);
     if (p.grid_face.y > 0)
       hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_LIST>), p.grid_face,
-                         p.block_face, 0, R->stream, L, p.face, mode, t);
+                         p.block_face, 0, stream, L, p.face, mode, t);
   }
 }
 
@@ -351,9 +357,18 @@ void one_coarse_step(lbm_refined* R, long long t) {
     interp<KIND, S>(R, ga, R->Lc.a, R->g0);
     fill<KIND, S>(R, ga, R->g0, R->g0, 1.0, 0.0, R->Lf.a);
   }
-  level_step<KIND, S>(R, R->Lc, R->plan[0], 0, t);
+  // the coarse step (Lc.a -> Lc.b) and the first fine substep (Lf.a -> Lf.b)
+  // touch disjoint memory: fork the coarse step onto the side stream
+  const bool fork = fine && R->side != nullptr;
+  if (fork) {
+    (void)hipEventRecord(R->fork_ev, R->stream);
+    (void)hipStreamWaitEvent(R->side, R->fork_ev, 0);
+  }
+  level_step<KIND, S>(R, fork ? R->side : R->stream, R->Lc, R->plan[0], 0, t);
+  if (fork) (void)hipEventRecord(R->join_ev, R->side);
   if (fine) {
-    level_step<KIND, S>(R, R->Lf, R->plan[1], 1, 2 * t);
+    level_step<KIND, S>(R, R->stream, R->Lf, R->plan[1], 1, 2 * t);
+    if (fork) (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
     interp_fill<KIND, S>(R, ga, R->Lc.b, R->g1, R->g0, R->Lf.b, R->Lf.a);
     // the last fine substep also injects into the covered nodes of the
     // coarse state at t + 1 (read by no ghost stencil)
@@ -366,7 +381,7 @@ void one_coarse_step(lbm_refined* R, long long t) {
       L2.Nc = (long long)R->Nc;
       L2.rinv = 1.0 / R->r;
     }
-    level_step<KIND, S>(R, L2, R->plan[1], 1, 2 * t + 1);
+    level_step<KIND, S>(R, R->stream, L2, R->plan[1], 1, 2 * t + 1);
   }
   std::swap(R->Lc.a, R->Lc.b);
   std::swap(R->g0, R->g1);
@@ -686,6 +701,19 @@ int lbm_refined_get_macroscopic(lbm_refined* R, int level, void* rho, void* u, i
 int lbm_refined_step(lbm_refined* R, int64_t n) {
   if (!R || n < 0) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
+  if (!R->side_tried) {
+    // without the side stream the coarse step simply runs in order
+    R->side_tried = true;
+    if (hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&R->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&R->join_ev, hipEventDisableTiming) != hipSuccess) {
+      if (R->side) (void)hipStreamDestroy(R->side);
+      if (R->fork_ev) (void)hipEventDestroy(R->fork_ev);
+      R->side = nullptr;
+      R->fork_ev = R->join_ev = nullptr;
+      (void)hipGetLastError();
+    }
+  }
   for (int64_t k = 0; k < n; ++k) {
     with_kind_s(R, [&](auto kc, auto st_) {
       one_coarse_step<decltype(kc)::value, typename decltype(st_)::type>(R, (long long)R->t);
@@ -743,6 +771,14 @@ int lbm_refined_set_stream(lbm_refined* R, void* stream) {
 }
 
 int lbm_refined_destroy(lbm_refined* R) {
+  if (R) {
+    if (R->side) {
+      (void)hipStreamSynchronize(R->side);
+      (void)hipStreamDestroy(R->side);
+    }
+    if (R->fork_ev) (void)hipEventDestroy(R->fork_ev);
+    if (R->join_ev) (void)hipEventDestroy(R->join_ev);
+  }
   delete R;
   return LBM_OK;
 }
