@@ -265,8 +265,8 @@ int lbm_step_record(lbm_lattice* lat, void* rec, int dtype);
  * configuration and boundaries (FCLB only, else LBM_EINVAL). grad_inlet,
  * if not NULL, is a device double array [3][nb][na] laid out like the
  * inlet velocity field of lbm_boundaries, to which this step's inlet terms
- * are added. lambda must not alias lambda_next or f_t; two populations of
- * an adjoint array (2 x nodes x element size) must stay below 4 GiB, else
+ * are added. lambda must not alias lambda_next or f_t; one population of an
+ * adjoint array (nodes x element size) must stay below 4 GiB, else
  * LBM_EINVAL. Asynchronous. */
 int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next, void* lambda,
                      int dtype, double* grad_inlet);

@@ -121,8 +121,8 @@ __device__ __forceinline__ void st(S* p, R v) {
 // 32-bit byte offset of the node: the loads and stores then take the
 // scalar-base form and need no 64-bit address arithmetic per lane. A slab
 // (one population, all nodes) is below 4 GiB (checked at creation); offsets
-// that span two adjacent slabs (a population and its opposite) are used
-// only while two slabs stay below 4 GiB.
+// from the lower slab of a population and its opposite (up to 7 slabs apart
+// in the paper's order) are used only while that span stays below 4 GiB.
 template <typename R, bool NT = false, typename S>
 __device__ __forceinline__ R ldo(const S* base, uint32_t off) {
   return ld<R, NT>((const S*)((const char*)base + off));

@@ -116,6 +116,11 @@ void step_record_dispatch(lbm_lattice* L, bool odd, long long t, void* rec) {
     step_model<2, float>(L, odd, t, rec);
 }
 
+// Slabs spanned by a population and its opposite (see max_opposite_distance).
+double slab_span(int Q) {
+  return 1.0 + (Q == 27 ? max_opposite_distance<27>() : max_opposite_distance<19>());
+}
+
 // Row sets of the split odd step for the current boundary description.
 void plan_rows(lbm_lattice* L) {
   const int nx = L->cfg.nx, ny = L->cfg.ny, nz = L->cfg.nz;
@@ -153,10 +158,10 @@ void plan_rows(lbm_lattice* L) {
   L->rows_bnd = b;
   const uint32_t xbits = np & 3u;
   const bool x_ok = (L->args.bc.inlet & 3u) == 0 && (xbits == 0 || (L->args.bc.wall & 3u) == 3u);
-  // the x-wall rows address a population and its opposite from one base:
-  // two slabs must stay below 4 GiB
-  const bool two_slabs = 2.0 * (double)L->N * (double)L->elem < 4294967296.0;
-  L->split_odd = L->has_bc && x_ok && nrows <= 65535 && two_slabs;
+  // the x-wall rows address a population and its opposite from the lower
+  // slab with 32-bit offsets: the span of slabs must stay below 4 GiB
+  const bool span_ok = slab_span(L->Q) * (double)L->N * (double)L->elem < 4294967296.0;
+  L->split_odd = L->has_bc && x_ok && nrows <= 65535 && span_ok;
   const int bx = L->block.x, by = L->block.y;
   L->grid_inner = dim3((nx + bx - 1) / bx, in.ny_in > 0 ? (in.ny_in + by - 1) / by : 0,
                        in.nz_in > 0 ? in.nz_in : 0);
@@ -580,10 +585,13 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
   if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
   if (L->kind != 2) return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
-  // the kernel addresses two adjacent slabs of the adjoint arrays with 32-bit
-  // byte offsets
+  // the kernels address the adjoint arrays with 32-bit byte offsets: one
+  // slab must stay below 4 GiB, and the x-wall rows (a population and its
+  // opposite from the lower slab) need the whole span below 4 GiB, else the
+  // general kernel takes every row
   const double rsz = dtype == LBM_DTYPE_F64 ? 8.0 : 4.0;
-  if (2.0 * (double)L->N * rsz >= 4294967296.0) return LBM_EINVAL;
+  if ((double)L->N * rsz >= 4294967296.0) return LBM_EINVAL;
+  const bool split = L->split_odd && slab_span(27) * (double)L->N * rsz < 4294967296.0;
   auto run = [&](auto real_tag) {
     using R = typename decltype(real_tag)::type;
     const R* f = (const R*)f_t;
@@ -592,7 +600,7 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
     if (!L->has_bc) {
       hipLaunchKernelGGL((adjoint_kernel<R, BC_NONE, ROWS_BOX>), L->grid, L->block, 0,
                          L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
-    } else if (!L->split_odd) {
+    } else if (!split) {
       hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_BOX>), L->grid, L->block, 0,
                          L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
     } else {

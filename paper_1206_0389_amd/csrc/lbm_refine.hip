@@ -249,7 +249,7 @@ unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 // Row sets of one level's box: the box rows whose global y and z lie on no
 // non-periodic domain face, and the rows that do (listed as whole z planes
 // first, then single y rows).
-void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem) {
+void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem, int Q) {
   const uint32_t np = L.bc.nonper;
   const int Mx = L.M[0], My = L.M[1], Mz = L.M[2];
   Rows all{};
@@ -280,9 +280,11 @@ void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem) {
   p.block_face = dim3(bbx, 1, 1);
   p.grid_face = dim3((Mx + bbx - 1) / bbx, (unsigned)(nrows > 0 ? nrows : 0), 1);
   const bool x_walls = (L.bc.inlet & 3u) == 0 && ((np & 3u) == 0 || (L.bc.wall & 3u) == 3u);
-  // the box and x-wall kernels address two adjacent slabs with 32-bit byte
-  // offsets; larger boxes take the general kernel
-  const bool o32 = 2.0 * (double)L.Nbox * (double)elem < 4294967296.0;
+  // the box and x-wall kernels address a population and its opposite from
+  // the lower slab with 32-bit byte offsets; larger boxes take the general
+  // kernel
+  const double span = 1.0 + (Q == 27 ? max_opposite_distance<27>() : max_opposite_distance<19>());
+  const bool o32 = span * (double)L.Nbox * (double)elem < 4294967296.0;
   if (!o32)
     p.mode = 2;
   else if (np == 0)
@@ -465,8 +467,8 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask
   shape_for(c.nx, c.ny, c.nz, R->grid_c, R->block_c, R->nblocks_c);
   shape_for(R->M[0], R->M[1], R->M[2], R->grid_f, R->block_f, R->nblocks_f);
   layout(R);
-  plan_level(R->plan[0], R->Lc, R->block_c, R->elem);
-  plan_level(R->plan[1], R->Lf, R->block_f, R->elem);
+  plan_level(R->plan[0], R->Lc, R->block_c, R->elem, R->Q);
+  plan_level(R->plan[1], R->Lf, R->block_f, R->elem, R->Q);
   *out = R;
   return LBM_OK;
 }
@@ -610,8 +612,8 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
   R->Lf.bc = bf;
   R->has_bc = b.nonper != 0;
   R->g0_valid = false;
-  plan_level(R->plan[0], R->Lc, R->block_c, R->elem);
-  plan_level(R->plan[1], R->Lf, R->block_f, R->elem);
+  plan_level(R->plan[0], R->Lc, R->block_c, R->elem, R->Q);
+  plan_level(R->plan[1], R->Lf, R->block_f, R->elem, R->Q);
   return LBM_OK;
 }
 

@@ -46,6 +46,20 @@ constexpr int opposite(int i) {
   return -1;
 }
 
+// Largest index distance between a population and its opposite in the
+// paper's order (D3Q27: 7, for the corner pairs 19-26; D3Q19: 1). Kernels
+// that address a population and its opposite from the lower of the two
+// slabs span this many slabs plus one.
+template <int Q>
+constexpr int max_opposite_distance() {
+  int d = 0;
+  for (int i = 0; i < Q; ++i) {
+    const int k = i - opposite<Q>(i);
+    d = k > d ? k : (-k > d ? -k : d);
+  }
+  return d;
+}
+
 // Index of velocity (ex, ey, ez) in the D3Q27 order (-1 if absent).
 constexpr int index_of(int x, int y, int z) {
   for (int j = 0; j < 27; ++j)

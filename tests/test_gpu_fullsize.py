@@ -17,6 +17,8 @@ rounded to the storage precision, exactly as the GPU stored it.
 
 The two-level refined workload is checked at full size through properties
 that hold at any size (uniform flow preserved exactly; FP32 against FP64).
+A 512 x 512 x 256 FP64 lattice checks the path taken when 32-bit offsets
+cannot span a population and its opposite.
 """
 import numpy as np
 import pytest
@@ -136,3 +138,45 @@ def test_refined_jet_full_size_properties(model):
         err = float((a - b).abs().max() / b.abs().max())
         print("refined", model, "level", level, "FP32 vs FP64", err, flush=True)
         assert err <= 3 * 2 * TOL["f32"]  # two fine substeps per coarse step
+
+
+def test_lattice_beyond_the_offset_span_takes_the_general_path():
+    """512 x 512 x 256 nodes in FP64: eight population slabs are exactly
+    4 GiB, so the x-wall rows of the odd step (which address a corner
+    population and its opposite, 7 slabs apart, with 32-bit offsets) must run
+    through the general kernel. Boxes at the x walls and the interior against
+    the oracle after 3 steps."""
+    import bench
+    import paper_1206_0389_amd as P
+    nx, ny, nz = 512, 512, 256
+    print("case beyond offset span", (nx, ny, nz), flush=True)
+    js = bench.jet_setup(nx, ny, synth)
+    lat = P.Lattice(model="fclb", storage="f64", shape=(nx, ny, nz), nu=js["nu"])
+    faces = [P.WALL] * 4 + [P.INLET, P.OUTFLOW]
+    lat.set_boundaries(faces, face_u=js["face_u"], inlet_u=torch.from_numpy(js["inlet_u"]),
+                       inlet_mask=torch.from_numpy(js["inlet_mask"]),
+                       inlet_amp=js["inlet_amp"], seed=js["seed"])
+    f = torch.empty((27, nz, ny, nx), dtype=torch.float64, device="cuda")
+    for q in range(27):
+        f[q] = torch.from_numpy(synth.tiled_populations(27, (nz, ny, nx), AMP, SEED,
+                                                        qs=[q])[0]).cuda()
+    lat.set_populations(f, t0=T0)
+    del f
+    lat.step(STEPS)
+    boxes = [((0, 200, 100), (8, 208, 108)), ((504, 300, 120), (512, 308, 128)),
+             ((250, 250, 60), (258, 258, 68)), ((0, 0, 0), (8, 8, 8))]
+    full = lat.populations()
+    worst = 0.0
+    for lo, hi in boxes:
+        wlo, whi, wf, inner = window((nx, ny, nz), JET, lo, hi, STEPS)
+        f0 = synth.tiled_populations(27, (nz, ny, nx), AMP, SEED, lo=wlo, hi=whi)
+        o = oracle_lattice("fclb", tuple(b - a for a, b in zip(wlo, whi)), js["nu"], faces=wf,
+                           face_u=js["face_u"], inlet=(js["inlet_u"], js["inlet_mask"]),
+                           amp=js["inlet_amp"], seed=js["seed"], origin=tuple(wlo),
+                           extent=(nx, ny))
+        ref = o.run(f0, T0, STEPS)[:, inner[2], inner[1], inner[0]]
+        g = full[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        err = rel_err(g, ref)
+        worst = max(worst, err)
+        assert err <= STEPS * TOL["f64"], (lo, hi, err)
+    print("beyond offset span: worst box error", worst, flush=True)
