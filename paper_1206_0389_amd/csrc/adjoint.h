@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
   if (!row_coords<ROWS>(a, r, x, y, z)) return;
   const Node n = make_node(a, x, y, z);
   const size_t N = (size_t)a.N;
-  // 32-bit byte offsets from per-population bases (see ldo); the x-wall rows
+  // 32-bit byte offsets from per-population bases (see ldo); the wall rows
   // select between a population and its opposite from the lower slab
   const uint32_t sz = sizeof(real);
   const uint32_t self_off = (uint32_t)n.self * sz;
@@ -193,19 +193,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
       m[I] = ldo<real, cx(I) == 0>(ln + (size_t)I * N,
                                    (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz);
     });
-  } else if constexpr (BCM == BC_XWALL) {
+  } else if constexpr (BCM == BC_WALLS) {
+    // wall rows: a population pushed through an x or y wall returns as
+    // opp(I) at the node itself (the wall term is a constant)
     const uint32_t slab = (uint32_t)N * sz;
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       constexpr int IO = opposite<Q>(I);
+      constexpr uint32_t WB = push_faces(I) & 15u;
       const uint32_t nb = (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz;
-      if constexpr (cx(I) == 0) {
+      if constexpr (WB == 0) {
         m[I] = ldo<real, true>(ln + (size_t)I * N, nb);
       } else {
         constexpr int LO = I < IO ? I : IO;
-        const bool bb = (n.atface & (cx(I) > 0 ? 2u : 1u)) != 0;
+        const bool bb = (n.atface & WB) != 0;
         const uint32_t off = bb ? (IO - LO) * slab + self_off : (I - LO) * slab + nb;
-        m[I] = ldo<real>(ln + (size_t)LO * N, off);
+        m[I] = ldo<real, cx(I) == 0>(ln + (size_t)LO * N, off);
       }
     });
   } else {

@@ -55,10 +55,10 @@ struct BcArgs {
   int inlet_axis;
   int inlet_na, inlet_nb;
   long long ghost_n; // nodes of a z plane (the outflow face is a z face)
-  // 6 w_J (e_J . u_F) for population J entering through x face F (0: x-,
-  // 1: x+), set on the host with the face velocities
-  double xterm[2][27];
-  float xterm_f[2][27];
+  // 6 w_J (e_J . u_F) for population J entering through x or y face F (0:
+  // x-, 1: x+, 2: y-, 3: y+), set on the host with the face velocities
+  double wterm[4][27];
+  float wterm_f[4][27];
 };
 
 struct LatArgs {
@@ -83,9 +83,9 @@ struct Rows {
 };
 enum { ROWS_BOX = 0, ROWS_LIST = 1 };
 // Boundary handling of a step kernel: none (all faces periodic), general
-// (any face type, any node), or x walls only (rows off every non-periodic
-// y/z face, x faces WALL or periodic).
-enum { BC_NONE = 0, BC_GENERAL = 1, BC_XWALL = 2 };
+// (any face type, any node), or walls only (rows off every non-periodic z
+// face and off y faces that are not walls; x and y faces WALL or periodic).
+enum { BC_NONE = 0, BC_GENERAL = 1, BC_WALLS = 2 };
 
 // ---------------------------------------------------------------- storage
 template <typename S>
@@ -131,26 +131,39 @@ template <bool NT = false, typename S, typename R>
 __device__ __forceinline__ void sto(S* base, uint32_t off, R v) {
   st<NT>((S*)((char*)base + off), v);
 }
-// Host: 6 w_J (e_J . u_F) for the x faces, per model (the weights differ).
-inline void fill_xterms(BcArgs& b, int Q) {
-  for (int F = 0; F < 2; ++F)
+// Host: 6 w_J (e_J . u_F) for the x and y faces, per model (the weights
+// differ).
+inline void fill_wall_terms(BcArgs& b, int Q) {
+  for (int F = 0; F < 4; ++F)
     for (int j = 0; j < 27; ++j) {
       double v = 0.0;
       if (j < Q) {
         const double w = Q == 27 ? weight<27>(j) : weight<19>(j);
         v = 6.0 * w * (cx(j) * b.face_u[F][0] + cy(j) * b.face_u[F][1] + cz(j) * b.face_u[F][2]);
       }
-      b.xterm[F][j] = v;
-      b.xterm_f[F][j] = (float)v;
+      b.wterm[F][j] = v;
+      b.wterm_f[F][j] = (float)v;
     }
 }
 
 template <typename T>
-__device__ __forceinline__ T xterm(const BcArgs& b, int face, int i) {
+__device__ __forceinline__ T wterm(const BcArgs& b, int face, int i) {
   if constexpr (sizeof(T) == sizeof(double))
-    return b.xterm[face][i];
+    return b.wterm[face][i];
   else
-    return T(b.xterm_f[face][i]);
+    return T(b.wterm_f[face][i]);
+}
+
+// Wall term of direction I at a wall-row node whose crossed x face is
+// FX (if bx) and y face FY (if by): the x face comes first, as in wall_term.
+template <int I, typename real, uint32_t XB, uint32_t YB>
+__device__ __forceinline__ real wall_row_term(const BcArgs& b, bool bx, int FX, int FY) {
+  if constexpr (XB == 0)
+    return wterm<real>(b, FY, I);
+  else if constexpr (YB == 0)
+    return wterm<real>(b, FX, I);
+  else
+    return bx ? wterm<real>(b, FX, I) : wterm<real>(b, FY, I);
 }
 
 // ------------------------------------------------------------------ models
@@ -345,46 +358,54 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
   }
 }
 
-// Rows off the y/z faces: only the x faces can be crossed, and they are
-// walls. Population I (e_Ix = +1) enters through x- at x = 0, (e_Ix = -1)
-// through x+ at x = nx-1; the wall term is a per-direction constant. The
-// bounce-back source (slot I of the node itself) and the normal source (slot
-// opp(I) of x - e_I) are selected as offsets from the lower of the two
-// slabs, so one scalar-base load serves both.
+// Wall rows: rows off every non-periodic z face (and off y faces that are
+// not walls), whose x and y faces are WALL or periodic. Population I enters
+// through x- (e_Ix = +1 at x = 0), x+ (e_Ix = -1 at x = nx-1), y- or y+ in
+// the same way, where it is the node's own slot I plus a per-direction wall
+// term (the x face first where a node lies on both). The bounce-back source
+// (slot I of the node itself) and the normal source (slot opp(I) of x - e_I)
+// are selected as offsets from the lower of the two slabs, so one
+// scalar-base load serves both.
 template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ real pull_xwall(const LatArgs& a, const S* F, const Node& n) {
+__device__ __forceinline__ real pull_walls(const LatArgs& a, const S* F, const Node& n) {
   constexpr int IO = opposite<Q>(I);
+  constexpr uint32_t XB = pull_faces(I) & 3u, YB = pull_faces(I) & 12u;
   const uint32_t sz = sizeof(S);
   const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
-  if constexpr (cx(I) == 0) {
+  if constexpr ((XB | YB) == 0) {
     return ldo<real, NT>(F + (size_t)IO * a.N, nb);
   } else {
     constexpr int LO = I < IO ? I : IO;
     const uint32_t slab = (uint32_t)a.N * sz;
-    constexpr int F_ = cx(I) > 0 ? 0 : 1;
-    const bool bb = (n.atface & (1u << F_)) != 0;
+    const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
+    const bool bb = bx || by;
     const uint32_t off = bb ? (I - LO) * slab + (uint32_t)n.self * sz : (IO - LO) * slab + nb;
     const real v = ldo<real, NT>(F + (size_t)LO * a.N, off);
-    return bb ? v + xterm<real>(a.bc, F_, I) : v;
+    const real term =
+        wall_row_term<I, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
+    return bb ? v + term : v;
   }
 }
 
 template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ void push_xwall(const LatArgs& a, S* F, const Node& n, real v) {
+__device__ __forceinline__ void push_walls(const LatArgs& a, S* F, const Node& n, real v) {
   constexpr int IO = opposite<Q>(I);
+  constexpr uint32_t XB = push_faces(I) & 3u, YB = push_faces(I) & 12u;
   const uint32_t sz = sizeof(S);
   const uint32_t nb = (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz;
-  if constexpr (cx(I) == 0) {
+  if constexpr ((XB | YB) == 0) {
     sto<NT>(F + (size_t)I * a.N, nb, v);
   } else {
-    // leaving through x+ (e_Ix = +1 at x = nx-1) returns as opp(I), which
-    // enters through x+: its wall term uses face 1, and vice versa
+    // leaving through a wall, I returns as opp(I), entering through the
+    // same face: the term is that of opp(I) at that face
     constexpr int LO = I < IO ? I : IO;
     const uint32_t slab = (uint32_t)a.N * sz;
-    constexpr int Fc = cx(I) > 0 ? 1 : 0;
-    const bool bb = (n.atface & (1u << Fc)) != 0;
+    const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
+    const bool bb = bx || by;
     const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
-    sto<NT>(F + (size_t)LO * a.N, off, bb ? v + xterm<real>(a.bc, Fc, IO) : v);
+    const real term =
+        wall_row_term<IO, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 1 : 0, cy(I) > 0 ? 3 : 2);
+    sto<NT>(F + (size_t)LO * a.N, off, bb ? v + term : v);
   }
 }
 
@@ -449,10 +470,10 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       f[I] = ldo<real, true>(F + (size_t)I * N, self_off);
     });
   } else {
-    if constexpr (BCM == BC_XWALL) {
+    if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = pull_xwall<Q, I, real, cx(I) == 0>(a, F, n);
+        f[I] = pull_walls<Q, I, real, cx(I) == 0>(a, F, n);
       });
     } else if constexpr (BCM == BC_NONE) {
       static_for<0, Q>([&](auto ic) {
@@ -499,10 +520,10 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       }
     }
   } else {
-    if constexpr (BCM == BC_XWALL) {
+    if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push_xwall<Q, I, real, cx(I) == 0>(a, F, n, f[I]);
+        push_walls<Q, I, real, cx(I) == 0>(a, F, n, f[I]);
       });
     } else {
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};

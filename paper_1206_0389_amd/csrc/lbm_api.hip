@@ -33,8 +33,8 @@ struct lbm_lattice {
   bool has_bc = false;
   LatArgs args;
   dim3 grid, block;
-  // odd steps with boundaries split into rows off the y/z faces (x walls
-  // only) and the rows on them
+  // odd steps with boundaries split into wall rows (x and y faces walls or
+  // periodic, see pull_walls) and the rows on the other non-periodic faces
   bool split_odd = false;
   Rows rows_all, rows_inner, rows_bnd;
   dim3 grid_inner, grid_bnd, block_bnd;
@@ -82,7 +82,7 @@ void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
     launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else {
     if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
-      launch_step<KIND, S, true, BC_XWALL, ROWS_BOX>(L, L->grid_inner, L->block, L->rows_inner,
+      launch_step<KIND, S, true, BC_WALLS, ROWS_BOX>(L, L->grid_inner, L->block, L->rows_inner,
                                                      t, rec);
     if (L->grid_bnd.y > 0)
       launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST>(L, L->grid_bnd, L->block_bnd,
@@ -131,7 +131,10 @@ void plan_rows(lbm_lattice* L) {
   all.z0 = 0;
   all.nz_in = nz;
   L->rows_all = all;
-  const bool ynp = (np & 12u) != 0, znp = (np & 48u) != 0;
+  const bool znp = (np & 48u) != 0;
+  // y faces that are walls stay in the wall rows; other non-periodic y
+  // faces go to the row list
+  const bool ynp = (np & 12u) != 0 && (L->args.bc.wall & 12u) != 12u;
   Rows in = all;
   if (ynp) {
     in.y0 = 1;
@@ -158,7 +161,7 @@ void plan_rows(lbm_lattice* L) {
   L->rows_bnd = b;
   const uint32_t xbits = np & 3u;
   const bool x_ok = (L->args.bc.inlet & 3u) == 0 && (xbits == 0 || (L->args.bc.wall & 3u) == 3u);
-  // the x-wall rows address a population and its opposite from the lower
+  // the wall rows address a population and its opposite from the lower
   // slab with 32-bit offsets: the span of slabs must stay below 4 GiB
   const bool span_ok = slab_span(L->Q) * (double)L->N * (double)L->elem < 4294967296.0;
   L->split_odd = L->has_bc && x_ok && nrows <= 65535 && span_ok;
@@ -366,7 +369,7 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
     if (b.inlet_na >= 16384 || b.inlet_nb >= 16384) return LBM_EINVAL;
   }
   if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
-  fill_xterms(b, L->Q);
+  fill_wall_terms(b, L->Q);
   L->args.bc = b;
   L->has_bc = b.nonper != 0;
   plan_rows(L);
@@ -586,7 +589,7 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
   if (L->kind != 2) return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
   // the kernels address the adjoint arrays with 32-bit byte offsets: one
-  // slab must stay below 4 GiB, and the x-wall rows (a population and its
+  // slab must stay below 4 GiB, and the wall rows (a population and its
   // opposite from the lower slab) need the whole span below 4 GiB, else the
   // general kernel takes every row
   const double rsz = dtype == LBM_DTYPE_F64 ? 8.0 : 4.0;
@@ -605,7 +608,7 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
                          L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
     } else {
       if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
-        hipLaunchKernelGGL((adjoint_kernel<R, BC_XWALL, ROWS_BOX>), L->grid_inner, L->block, 0,
+        hipLaunchKernelGGL((adjoint_kernel<R, BC_WALLS, ROWS_BOX>), L->grid_inner, L->block, 0,
                            L->stream, L->args, L->rows_inner, f, ln, l, grad_inlet);
       if (L->grid_bnd.y > 0)
         hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_LIST>), L->grid_bnd,

@@ -25,16 +25,18 @@ struct lbm_refined {
   size_t Nc, Nf;
   std::vector<uint8_t> ctype, ftype;
   std::vector<int32_t> ghosts, covered;
+  std::vector<int32_t> gcode;       // per ghost: stencil code (GhostGroup)
+  std::vector<GhostGroup> groups;   // ghost groups staged by one workgroup
   double r;
   hipStream_t stream;
   // second stream (default priority, non-blocking) on which the coarse step
   // runs concurrently with the first fine substep, joined by events
   hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, sub1_ev = nullptr;
   bool side_tried = false;
   // device layout
   char* base = nullptr;
-  size_t off[12] = {0};
+  size_t off[14] = {0};
   size_t req = 0;
   Level Lc, Lf;
   void *g0 = nullptr, *g1 = nullptr;
@@ -46,10 +48,11 @@ struct lbm_refined {
   int64_t t = 0;
   bool has_bc = false;
   bool geometry_ok = false;  // false until a valid boundary set is known
-  // per level (0 coarse, 1 fine): rows off the non-periodic y/z domain faces
-  // (x-wall kernel) and the rows on them (general kernel)
+  // per level (0 coarse, 1 fine): wall rows (off the non-periodic z domain
+  // faces and off y faces that are not walls; wall kernel) and the rows on
+  // those faces (general kernel)
   struct Plan {
-    int mode;  // 0: no boundary logic, 1: x-wall rows + face rows, 2: general
+    int mode;  // 0: no boundary logic, 1: wall rows + face rows, 2: general
     Rows all, inner, face;
     dim3 grid_all, grid_inner, grid_face, block, block_face;
   } plan[2];
@@ -95,6 +98,76 @@ bool fine_refined(const lbm_refined* R, const int j[3]) {
     b[d] = j[d] / (2 * R->B);
   }
   return block_refined(R, b[0], b[1], b[2]);
+}
+
+// Orders the ghost list by group (coarse cube of kGhostCube^3 cells, then
+// stencil shape, then box index: the lanes of a wave mostly share one
+// shape), splits each cube into groups of at most kGhostMax ghosts, and sets
+// each group's coarse patch and each ghost's stencil code relative to it. A
+// group whose patch would exceed kPatchEdge on an axis is split into single
+// ghosts (patches of at most 4 nodes per axis).
+void group_ghosts(lbm_refined* R, uint32_t nonper) {
+  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
+  const size_t ng = R->ghosts.size();
+  struct Item {
+    long long key;
+    int32_t l;
+    int start[3], code[3];
+  };
+  std::vector<Item> it(ng);
+  int ncube[3];
+  for (int d = 0; d < 3; ++d) ncube[d] = (n3[d] + kGhostCube - 1) / kGhostCube;
+  for (size_t g = 0; g < ng; ++g) {
+    const int32_t l = R->ghosts[g];
+    const int lx = l % R->M[0], ly = (l / R->M[0]) % R->M[1], lz = l / (R->M[0] * R->M[1]);
+    const int j[3] = {lx + R->lo[0], ly + R->lo[1], lz + R->lo[2]};
+    Item& e = it[g];
+    e.l = l;
+    int cube[3], shape = 0;
+    for (int d = 0; d < 3; ++d) {
+      e.code[d] = stencil_code(j[d], n3[d], ((nonper >> (2 * d)) & 1u) == 0, e.start[d]);
+      cube[d] = (j[d] >> 1) / kGhostCube;
+      shape |= e.code[d] != 0 ? 1 << d : 0;
+    }
+    const long long c = ((long long)cube[2] * ncube[1] + cube[1]) * ncube[0] + cube[0];
+    e.key = (c * 8 + shape) * (1ll << 32) + l;
+  }
+  std::sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
+  R->gcode.assign(ng, 0);
+  R->groups.clear();
+  auto add_group = [&](size_t b, size_t e) {
+    GhostGroup gr;
+    gr.gbeg = (int)b;
+    gr.gend = (int)e;
+    for (int d = 0; d < 3; ++d) {
+      int lo = it[b].start[d], hi = lo;
+      for (size_t k = b; k < e; ++k) {
+        lo = std::min(lo, it[k].start[d]);
+        hi = std::max(hi, it[k].start[d] + (it[k].code[d] ? 3 : 0));
+      }
+      gr.lo[d] = lo;
+      gr.m[d] = hi - lo + 1;
+    }
+    for (size_t k = b; k < e; ++k) {
+      int code = 0;
+      for (int d = 0; d < 3; ++d) code |= ((it[k].start[d] - gr.lo[d]) | (it[k].code[d] << 3)) << (6 * d);
+      R->gcode[k] = code;
+    }
+    R->groups.push_back(gr);
+    return gr.m[0] <= kPatchEdge && gr.m[1] <= kPatchEdge && gr.m[2] <= kPatchEdge;
+  };
+  size_t b = 0;
+  while (b < ng) {
+    const long long cube = it[b].key >> 35;
+    size_t e = b;
+    while (e < ng && (it[e].key >> 35) == cube && e - b < (size_t)kGhostMax) ++e;
+    if (!add_group(b, e)) {
+      R->groups.pop_back();
+      for (size_t k = b; k < e; ++k) add_group(k, k + 1);
+    }
+    b = e;
+  }
+  for (size_t g = 0; g < ng; ++g) R->ghosts[g] = it[g].l;
 }
 
 // Box, node types, ghost and covered lists. Returns false if a refined
@@ -151,6 +224,7 @@ bool build_geometry(lbm_refined* R, const uint32_t nonper) {
           R->ghosts.push_back((int32_t)l);
         }
       }
+  group_ghosts(R, nonper);
   R->ctype.assign(R->Nc, 0);
   for (int z = 0; z < n3[2]; ++z)
     for (int y = 0; y < n3[1]; ++y)
@@ -192,6 +266,8 @@ void layout(lbm_refined* R) {
   R->off[7] = o; o += align256(R->covered.size() * 4);       // covered
   R->off[8] = o; o += align256(ng * R->Q * R->relem);        // G0
   R->off[9] = o; o += align256(ng * R->Q * R->relem);        // G1
+  R->off[12] = o; o += align256(ng * 4);                     // stencil codes
+  R->off[13] = o; o += align256(R->groups.size() * sizeof(GhostGroup));  // groups
   const size_t nbmax = std::max(R->nblocks_c, R->nblocks_f);
   R->off[10] = o; o += align256(nbmax * 5 * sizeof(double));  // partials
   R->off[11] = o; o += 256;                                  // result
@@ -213,16 +289,12 @@ GhostArgs ghost_args(const lbm_refined* R) {
   GhostArgs g;
   g.ghosts = (const int*)(R->base + R->off[6]);
   g.ng = (long long)R->ghosts.size();
-  for (int d = 0; d < 3; ++d) {
-    g.fM[d] = R->M[d];
-    g.flo[d] = R->lo[d];
-  }
+  g.gcode = (const int*)(R->base + R->off[12]);
+  g.groups = (const int*)(R->base + R->off[13]);
+  g.ngroups = (long long)R->groups.size();
   g.cn[0] = R->cfg.nx;
   g.cn[1] = R->cfg.ny;
   g.cn[2] = R->cfg.nz;
-  g.cper = 0;
-  for (int d = 0; d < 3; ++d)
-    if (((R->Lc.bc.nonper >> (2 * d)) & 1u) == 0) g.cper |= 1u << d;
   g.Nc = (long long)R->Nc;
   g.Nf = (long long)R->Nf;
   return g;
@@ -246,9 +318,9 @@ void with_kind_s(const lbm_refined* R, Fn&& fn) {
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
-// Row sets of one level's box: the box rows whose global y and z lie on no
-// non-periodic domain face, and the rows that do (listed as whole z planes
-// first, then single y rows).
+// Row sets of one level's box: the wall rows (global z on no non-periodic
+// domain face, global y on no non-periodic y face other than a wall), and
+// the other rows (listed as whole z planes first, then single y rows).
 void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem, int Q) {
   const uint32_t np = L.bc.nonper;
   const int Mx = L.M[0], My = L.M[1], Mz = L.M[2];
@@ -259,7 +331,10 @@ void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem, i
   p.block = block;
   p.grid_all = dim3((Mx + block.x - 1) / block.x, (My + block.y - 1) / block.y, Mz);
   Rows in = all, f{};
-  const bool ylo = (np & 4u) && L.lo[1] == 0, yhi = (np & 8u) && L.lo[1] + My == L.n[1];
+  // y faces that are walls stay in the wall rows
+  const bool ywall = (L.bc.wall & 12u) == 12u;
+  const bool ylo = !ywall && (np & 4u) && L.lo[1] == 0;
+  const bool yhi = !ywall && (np & 8u) && L.lo[1] + My == L.n[1];
   const bool zlo = (np & 16u) && L.lo[2] == 0, zhi = (np & 32u) && L.lo[2] + Mz == L.n[2];
   if (ylo) f.yb[f.yb_n++] = 0;
   if (yhi) f.yb[f.yb_n++] = My - 1;
@@ -280,7 +355,7 @@ void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem, i
   p.block_face = dim3(bbx, 1, 1);
   p.grid_face = dim3((Mx + bbx - 1) / bbx, (unsigned)(nrows > 0 ? nrows : 0), 1);
   const bool x_walls = (L.bc.inlet & 3u) == 0 && ((np & 3u) == 0 || (L.bc.wall & 3u) == 3u);
-  // the box and x-wall kernels address a population and its opposite from
+  // the box and wall-row kernels address a population and its opposite from
   // the lower slab with 32-bit byte offsets; larger boxes take the general
   // kernel
   const double span = 1.0 + (Q == 27 ? max_opposite_distance<27>() : max_opposite_distance<19>());
@@ -308,7 +383,7 @@ void level_step(const lbm_refined* R, hipStream_t stream, const Level& L,
                        stream, L, p.all, mode, t);
   } else {
     if (p.grid_inner.y > 0 && p.grid_inner.z > 0)
-      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_XWALL, ROWS_BOX>), p.grid_inner, p.block, 0,
+      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_WALLS, ROWS_BOX>), p.grid_inner, p.block, 0,
                          stream, L, p.inner, mode, t);
     if (p.grid_face.y > 0)
       hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_LIST>), p.grid_face,
@@ -316,78 +391,87 @@ void level_step(const lbm_refined* R, hipStream_t stream, const Level& L,
   }
 }
 
-// The interpolation of coarse state fc into G, then ghosts := rescale of
-// c0 G0 + c1 G1 written into the fine array ff.
+// Ghosts of the fine array ff := rescale(c0 G0 + c1 G), G = the
+// interpolation of the coarse state fc (stored into G); G0 may be null
+// (then c0 is unused).
 template <int KIND, typename S>
-void interp(const lbm_refined* R, const GhostArgs& ga, const void* fc, void* G) {
+void ghost_patch(const lbm_refined* R, hipStream_t stream, const GhostArgs& ga, const void* fc,
+                 void* G, const void* G0, double c0, double c1, void* ff) {
   using Rt = typename Compute<S>::type;
-  if (ga.ng == 0) return;
-  hipLaunchKernelGGL((interp_kernel<Model<KIND>::Q, S, Rt>),
-                     dim3(blocks_for(ga.ng * Model<KIND>::Q)), dim3(256), 0, R->stream, ga,
-                     (const S*)fc, (Rt*)G);
+  if (ga.ngroups == 0) return;
+  hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)ga.ngroups), dim3(256), 0,
+                     stream, ga, (const S*)fc, (Rt*)G, (const Rt*)G0, c0, c1, R->r, (S*)ff);
 }
 
-// Ghosts := rescale(c0 A + c1 B); both buffers must hold finite values
-// (a zero weight does not hide a NaN).
+// Ghosts of ff := rescale(G) from the stored interpolation G.
 template <int KIND, typename S>
-void fill(const lbm_refined* R, const GhostArgs& ga, const void* A, const void* B, double c0,
-          double c1, void* ff) {
+void ghost_rescale(const lbm_refined* R, hipStream_t stream, const GhostArgs& ga, const void* G,
+                   void* ff) {
   using Rt = typename Compute<S>::type;
-  if (ga.ng == 0) return;
-  hipLaunchKernelGGL((fill_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0, R->stream,
-                     ga, (const Rt*)A, (const Rt*)B, c0, c1, R->r, (S*)ff);
+  if (ga.ngroups == 0) return;
+  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3((unsigned)ga.ngroups), dim3(256),
+                     0, stream, ga, (const Rt*)G, 1.0, R->r, (S*)ff);
 }
 
-template <int KIND, typename S>
-void interp_fill(const lbm_refined* R, const GhostArgs& ga, const void* fc, void* G1,
-                 const void* G0, void* ff_half, void* ff_next) {
-  using Rt = typename Compute<S>::type;
-  if (ga.ng == 0) return;
-  constexpr int GT = 1024 / Model<KIND>::Q;
-  hipLaunchKernelGGL((interp_fill_kernel<KIND, S, Rt>), dim3((unsigned)((ga.ng + GT - 1) / GT)),
-                     dim3(1024), 0, R->stream, ga, (const S*)fc, (Rt*)G1, (const Rt*)G0, R->r,
-                     (S*)ff_half, (S*)ff_next);
-}
-
+// One coarse step: the coarse update (Lc.a -> Lc.b), two fine substeps
+// (Lf.a -> Lf.b -> Lf.a) and the interface. Ghost slots are written only by
+// the interface kernels and fluid slots only by the fine updates, so with
+// the side stream the work runs as two chains:
+//   main: fine substep 1 ............ [wait interp] fine substep 2 + injection
+//   side: coarse step -> G1, half-step ghosts of Lf.b -> [wait substep 1]
+//         next-step ghosts of Lf.a
+// (the half-step ghosts rescale(G0/2 + G1/2) are read only by substep 2; the
+// next-step ghosts rescale(G1) go into Lf.a, which substep 1 reads, so they
+// wait for it). The main stream joins the side stream at the end.
 template <int KIND, typename S>
 void one_coarse_step(lbm_refined* R, long long t) {
   const GhostArgs ga = ghost_args(R);
   const bool fine = R->Nf > 0;
   // The ghosts of the first fine substep come from the previous coarse
-  // step's half-step update; after a change of state they are rebuilt.
-  if (fine && !R->g0_valid) {
-    interp<KIND, S>(R, ga, R->Lc.a, R->g0);
-    fill<KIND, S>(R, ga, R->g0, R->g0, 1.0, 0.0, R->Lf.a);
-  }
-  // the coarse step (Lc.a -> Lc.b) and the first fine substep (Lf.a -> Lf.b)
-  // touch disjoint memory: fork the coarse step onto the side stream
+  // step; after a change of state they are rebuilt.
+  if (fine && !R->g0_valid)
+    ghost_patch<KIND, S>(R, R->stream, ga, R->Lc.a, R->g0, nullptr, 0.0, 1.0, R->Lf.a);
   const bool fork = fine && R->side != nullptr;
+  hipStream_t side = fork ? R->side : R->stream;
   if (fork) {
     (void)hipEventRecord(R->fork_ev, R->stream);
     (void)hipStreamWaitEvent(R->side, R->fork_ev, 0);
   }
-  level_step<KIND, S>(R, fork ? R->side : R->stream, R->Lc, R->plan[0], 0, t);
+  level_step<KIND, S>(R, side, R->Lc, R->plan[0], 0, t);
+  if (!fine) {
+    std::swap(R->Lc.a, R->Lc.b);
+    R->g0_valid = false;
+    return;
+  }
+  ghost_patch<KIND, S>(R, side, ga, R->Lc.b, R->g1, R->g0, 0.5, 0.5, R->Lf.b);
   if (fork) (void)hipEventRecord(R->join_ev, R->side);
-  if (fine) {
-    level_step<KIND, S>(R, R->stream, R->Lf, R->plan[1], 1, 2 * t);
-    if (fork) (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
-    interp_fill<KIND, S>(R, ga, R->Lc.b, R->g1, R->g0, R->Lf.b, R->Lf.a);
-    // the last fine substep also injects into the covered nodes of the
-    // coarse state at t + 1 (read by no ghost stencil)
-    Level L2 = R->Lf;
-    std::swap(L2.a, L2.b);
-    if (!R->covered.empty()) {
-      L2.cinj = R->Lc.b;
-      L2.ctype = R->Lc.type;
-      for (int d = 0; d < 3; ++d) L2.cn[d] = R->Lc.n[d];
-      L2.Nc = (long long)R->Nc;
-      L2.rinv = 1.0 / R->r;
-    }
+  level_step<KIND, S>(R, R->stream, R->Lf, R->plan[1], 1, 2 * t);
+  // the last fine substep also injects into the covered nodes of the
+  // coarse state at t + 1 (read by no ghost stencil)
+  Level L2 = R->Lf;
+  std::swap(L2.a, L2.b);
+  if (!R->covered.empty()) {
+    L2.cinj = R->Lc.b;
+    L2.ctype = R->Lc.type;
+    for (int d = 0; d < 3; ++d) L2.cn[d] = R->Lc.n[d];
+    L2.Nc = (long long)R->Nc;
+    L2.rinv = 1.0 / R->r;
+  }
+  if (fork) {
+    (void)hipEventRecord(R->sub1_ev, R->stream);
+    (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
+    level_step<KIND, S>(R, R->stream, L2, R->plan[1], 1, 2 * t + 1);
+    (void)hipStreamWaitEvent(R->side, R->sub1_ev, 0);
+    ghost_rescale<KIND, S>(R, R->side, ga, R->g1, R->Lf.a);
+    (void)hipEventRecord(R->join_ev, R->side);
+    (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
+  } else {
+    ghost_rescale<KIND, S>(R, R->stream, ga, R->g1, R->Lf.a);
     level_step<KIND, S>(R, R->stream, L2, R->plan[1], 1, 2 * t + 1);
   }
   std::swap(R->Lc.a, R->Lc.b);
   std::swap(R->g0, R->g1);
-  R->g0_valid = fine;
+  R->g0_valid = true;
 }
 
 bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
@@ -515,6 +599,14 @@ static int upload_geometry(lbm_refined* R) {
                        hipMemcpyHostToDevice, R->stream);
     if (e != hipSuccess) return hip_fail(e);
   }
+  if (!R->ghosts.empty()) {
+    e = hipMemcpyAsync(R->base + R->off[12], R->gcode.data(), R->gcode.size() * 4,
+                       hipMemcpyHostToDevice, R->stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipMemcpyAsync(R->base + R->off[13], R->groups.data(),
+                       R->groups.size() * sizeof(GhostGroup), hipMemcpyHostToDevice, R->stream);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   e = hipStreamSynchronize(R->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e);
 }
@@ -606,8 +698,8 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
   R->Lf.Nbox = (long long)R->Nf;
   shape_for(R->M[0], R->M[1], R->M[2], R->grid_f, R->block_f, R->nblocks_f);
   layout(R);
-  fill_xterms(b, R->Q);
-  fill_xterms(bf, R->Q);
+  fill_wall_terms(b, R->Q);
+  fill_wall_terms(bf, R->Q);
   R->Lc.bc = b;
   R->Lf.bc = bf;
   R->has_bc = b.nonper != 0;
@@ -708,11 +800,14 @@ int lbm_refined_step(lbm_refined* R, int64_t n) {
     R->side_tried = true;
     if (hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&R->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&R->join_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&R->join_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&R->sub1_ev, hipEventDisableTiming) != hipSuccess) {
       if (R->side) (void)hipStreamDestroy(R->side);
       if (R->fork_ev) (void)hipEventDestroy(R->fork_ev);
+      if (R->join_ev) (void)hipEventDestroy(R->join_ev);
+    if (R->sub1_ev) (void)hipEventDestroy(R->sub1_ev);
       R->side = nullptr;
-      R->fork_ev = R->join_ev = nullptr;
+      R->fork_ev = R->join_ev = R->sub1_ev = nullptr;
       (void)hipGetLastError();
     }
   }

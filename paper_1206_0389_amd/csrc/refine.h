@@ -54,45 +54,43 @@ struct Level {
   double rinv;
 };
 
-// 1-D interpolation stencil for fine coordinate j on an axis of n coarse
-// nodes: one node (weight 1) if j is even, else 4-point Lagrange weights at
-// j/2 on nodes s..s+3, s = (j-1)/2 - 1, wrapped on periodic axes and moved
-// inside [0, n) otherwise.
-__host__ __device__ inline int interp_stencil(int j, int n, bool periodic, int idx[4],
-                                              double w[4]) {
+// 1-D interpolation stencil for fine coordinate j on an axis of n >= 4
+// coarse nodes. Code 0: one node, j/2 (j even, weight 1). Codes 1-4: the
+// four nodes s..s+3, s = (j-1)/2 - 1 (moved inside [0, n) on a non-periodic
+// axis), with the cubic Lagrange weights at t = j/2 - s = 1/2, 3/2, 5/2,
+// 7/2 (3/2 inside, the others next to a face). start is the first node
+// before wrapping on a periodic axis.
+__host__ __device__ inline int stencil_code(int j, int n, bool periodic, int& start) {
   if ((j & 1) == 0) {
-    int c = j / 2;
-    if (periodic) c = ((c % n) + n) % n;
-    idx[0] = c;
-    w[0] = 1.0;
-    return 1;
+    start = j / 2;
+    return 0;
   }
-  // The target j/2 lies at t = j/2 - s from the first node: 3/2 inside,
-  // 1/2, 5/2 or 7/2 where the window is moved inside a non-periodic face.
-  // The cubic Lagrange weights at these t are dyadic (written out exactly);
-  // any other t falls back to the product formula.
   int s = (j - 1) / 2 - 1;
   if (!periodic) s = s < 0 ? 0 : (s > n - 4 ? n - 4 : s);
-  const int k2 = j - 2 * s;  // 2t
-  if (k2 == 3) {
-    w[0] = -1.0 / 16; w[1] = 9.0 / 16; w[2] = 9.0 / 16; w[3] = -1.0 / 16;
-  } else if (k2 == 1) {
-    w[0] = 5.0 / 16; w[1] = 15.0 / 16; w[2] = -5.0 / 16; w[3] = 1.0 / 16;
-  } else if (k2 == 5) {
-    w[0] = 1.0 / 16; w[1] = -5.0 / 16; w[2] = 15.0 / 16; w[3] = 5.0 / 16;
-  } else if (k2 == 7) {
-    w[0] = -5.0 / 16; w[1] = 21.0 / 16; w[2] = -35.0 / 16; w[3] = 35.0 / 16;
-  } else {
-    const double p = 0.5 * j;
-    for (int a = 0; a < 4; ++a) {
-      double v = 1.0;
-      for (int b = 0; b < 4; ++b)
-        if (b != a) v *= (p - (double)(s + b)) / (double)(a - b);
-      w[a] = v;
-    }
+  start = s;
+  return (j - 2 * s + 1) / 2;  // 2t = 1, 3, 5, 7
+}
+
+// Weights of a stencil code (dyadic, exact in every precision used).
+__host__ __device__ inline void stencil_weights(int code, double w[4]) {
+  switch (code) {
+    case 0: w[0] = 1.0; w[1] = 0.0; w[2] = 0.0; w[3] = 0.0; break;
+    case 1: w[0] = 5.0 / 16; w[1] = 15.0 / 16; w[2] = -5.0 / 16; w[3] = 1.0 / 16; break;
+    case 2: w[0] = -1.0 / 16; w[1] = 9.0 / 16; w[2] = 9.0 / 16; w[3] = -1.0 / 16; break;
+    case 3: w[0] = 1.0 / 16; w[1] = -5.0 / 16; w[2] = 15.0 / 16; w[3] = 5.0 / 16; break;
+    default: w[0] = -5.0 / 16; w[1] = 21.0 / 16; w[2] = -35.0 / 16; w[3] = 35.0 / 16; break;
   }
-  for (int a = 0; a < 4; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
-  return 4;
+}
+
+// Nodes (wrapped) and weights of the stencil; returns the node count.
+__host__ __device__ inline int interp_stencil(int j, int n, bool periodic, int idx[4],
+                                              double w[4]) {
+  int s;
+  const int code = stencil_code(j, n, periodic, s);
+  stencil_weights(code, w);
+  const int cnt = code == 0 ? 1 : 4;
+  for (int a = 0; a < cnt; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
+  return cnt;
 }
 
 struct BoxNode {
@@ -151,26 +149,59 @@ __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, con
   return bb ? own : (crossed ? outflow : normal);
 }
 
-// x-wall-only pull for rows off every non-periodic y/z face: population I
-// enters through x- (e_Ix = +1 at global x = 0) or x+ (e_Ix = -1 at x =
-// n_x - 1), where it is the node's own opposite slot plus a per-direction
-// wall term. Both sources are offsets from the lower of the two slabs (one
-// scalar-base load).
+// Wall-row pull (rows off every non-periodic z face and off y faces that are
+// not walls; x and y faces WALL or periodic): population I entering through
+// an x or y wall is the node's own opposite slot plus a per-direction wall
+// term (the x face first where a node lies on both). Both sources are
+// offsets from the lower of the two slabs (one scalar-base load).
 template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ real ab_pull_xwall(const Level& L, const S* A, const BoxNode& n) {
+__device__ __forceinline__ real ab_pull_walls(const Level& L, const S* A, const BoxNode& n) {
   constexpr int IO = opposite<Q>(I);
+  constexpr uint32_t XB = pull_faces(I) & 3u, YB = pull_faces(I) & 12u;
   const uint32_t sz = sizeof(S);
   const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
-  if constexpr (cx(I) == 0) {
+  if constexpr ((XB | YB) == 0) {
     return ldo<real, NT>(A + (size_t)I * L.Nbox, nb);
   } else {
     constexpr int LO = I < IO ? I : IO;
     const uint32_t slab = (uint32_t)L.Nbox * sz;
-    constexpr int F_ = cx(I) > 0 ? 0 : 1;
-    const bool bb = (n.atface & (1u << F_)) != 0;
+    const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
+    const bool bb = bx || by;
     const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
     const real v = ldo<real, NT>(A + (size_t)LO * L.Nbox, off);
-    return bb ? v + xterm<real>(L.bc, F_, I) : v;
+    const real term =
+        wall_row_term<I, real, XB, YB>(L.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
+    return bb ? v + term : v;
+  }
+}
+
+// Equilibrium (deviation form) of the population with velocity (ex, ey,
+// ez) for the moments d = sum f, j = sum e f: the incompressible
+// polynomial of Eq. (2) for D3Q19 MRT, the product form rho prod_a
+// phi(e_a; u_a) - w of the factorized model for D3Q27 (phi(0) = 2/3 - u^2,
+// phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors).
+template <int KIND, typename R>
+__device__ __forceinline__ R equilibrium_one(R d, const R (&j)[3], int ex, int ey, int ez) {
+  if constexpr (Model<KIND>::Q == 19) {
+    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+    const R eu = R(ex) * j[0] + R(ey) * j[1] + R(ez) * j[2];
+    const int e2 = ex * ex + ey * ey + ez * ez;
+    const R w = e2 == 0 ? R(1.0 / 3.0) : (e2 == 1 ? R(1.0 / 18.0) : R(1.0 / 36.0));
+    return w * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+  } else {
+    const R rho = R(1) + d;
+    const int e[3] = {ex, ey, ez};
+    R p[3], dp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R u = j[c] / rho, q = u * u;
+      p[c] = e[c] == 0 ? R(2.0 / 3.0) : R(1.0 / 6.0);
+      dp[c] = e[c] == 0 ? -q : (e[c] < 0 ? R(0.5) * (q - u) : R(0.5) * (q + u));
+    }
+    const R a0 = p[0], b0 = p[1], c0 = p[2], da = dp[0], db = dp[1], dc = dp[2];
+    const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
+                  a0 * db * dc + da * db * dc;
+    return dev + d * (a0 * b0 * c0 + dev);
   }
 }
 
@@ -187,41 +218,14 @@ __device__ __forceinline__ void equilibrium_dev(const R (&f)[Model<KIND>::Q],
     j[1] += R(cy(i)) * f[i];
     j[2] += R(cz(i)) * f[i];
   }
-  if constexpr (Q == 19) {
-    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const R eu = R(cx(i)) * j[0] + R(cy(i)) * j[1] + R(cz(i)) * j[2];
-      feq[i] = R(weight<19>(i)) * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-    }
-  } else {
-    // rho prod_a phi(e_a; u_a) - w with phi(0) = 2/3 - u^2,
-    // phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors
-    const R rho = R(1) + d;
-    R dp[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const R u = j[c] / rho, q = u * u;
-      dp[c][0] = R(0.5) * (q - u);
-      dp[c][1] = -q;
-      dp[c][2] = R(0.5) * (q + u);
-    }
-    const R p0[3] = {R(1.0 / 6.0), R(2.0 / 3.0), R(1.0 / 6.0)};
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-      const R a0 = p0[cx(i) + 1], b0 = p0[cy(i) + 1], c0 = p0[cz(i) + 1];
-      const R da = dp[0][cx(i) + 1], db = dp[1][cy(i) + 1], dc = dp[2][cz(i) + 1];
-      const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
-                    a0 * db * dc + da * db * dc;
-      feq[i] = dev + d * (a0 * b0 * c0 + dev);
-    }
-  }
+  for (int i = 0; i < Q; ++i) feq[i] = equilibrium_one<KIND, R>(d, j, cx(i), cy(i), cz(i));
 }
 
 // One pull-and-collide update of a level at time t over the rows r (box-
 // local coordinates). mode 0 updates every node whose type is not 2
 // (coarse), mode 1 only type-1 nodes (fine). BCM: BC_NONE (no non-periodic
-// face), BC_XWALL (rows off the y/z faces, x faces walls) or BC_GENERAL.
+// face), BC_WALLS (wall rows, see ab_pull_walls) or BC_GENERAL.
 template <int KIND, typename S, int BCM, int ROWS>
 __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows r, int mode,
                                                       long long t) {
@@ -257,10 +261,10 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
         f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
       });
     }
-  } else if constexpr (BCM == BC_XWALL) {
+  } else if constexpr (BCM == BC_WALLS) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ab_pull_xwall<Q, I, real, cx(I) == 0>(L, A, n);
+      f[I] = ab_pull_walls<Q, I, real, cx(I) == 0>(L, A, n);
     });
   } else {
     const size_t N = (size_t)L.Nbox;
@@ -302,127 +306,179 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
 struct GhostArgs {
   const int* ghosts;  // fine box indices of the ghost nodes
   long long ng;
-  int fM[3], flo[3];  // fine box extent and origin
-  int cn[3];          // coarse domain extent
-  uint32_t cper;      // periodic axes (bit d)
+  // ghost groups (see GhostGroup) and per-ghost stencil codes
+  const int* groups;
+  const int* gcode;
+  long long ngroups;
   long long Nc, Nf;
+  int cn[3];          // coarse domain extent
 };
 
-// G[q][g] = spatial interpolation of the coarse post-collision field at
-// ghost g; one thread per (ghost, population), population-major so that a
-// wave reads the stencils of neighbouring ghosts in one population array.
-// Tensor interpolation stencil of one ghost (per axis: 1 or 4 coarse nodes).
-struct GhostStencil {
-  int cnt[3];
-  int idx[3][4];
-  double w[3][4];
+// The ghosts are grouped by the coarse cube of kGhostCube^3 cells that holds
+// them (at most kGhostMax ghosts per group; ghosts [gbeg, gend) of the
+// list). A group's stencils read the coarse patch [lo, lo + m) (unwrapped
+// coordinates, wrapped on periodic axes; m <= kGhostCube + 3 per axis),
+// which one workgroup stages in LDS. A ghost's code holds, per axis d in
+// bits 6d..6d+5, its stencil's first node relative to lo (3 bits) and its
+// stencil code (3 bits).
+constexpr int kGhostCube = 4;
+constexpr int kGhostMax = 64;
+constexpr int kPatchEdge = kGhostCube + 3;
+constexpr int kPatchMax = kPatchEdge * kPatchEdge * kPatchEdge;
+struct GhostGroup {
+  int gbeg, gend;
+  int lo[3], m[3];
 };
 
-__device__ __forceinline__ void ghost_stencil(const GhostArgs& ga, long long gi, GhostStencil& st) {
-  const int l = ga.ghosts[gi];
-  const int lx = l % ga.fM[0], ly = (l / ga.fM[0]) % ga.fM[1], lz = l / (ga.fM[0] * ga.fM[1]);
-  const int j[3] = {lx + ga.flo[0], ly + ga.flo[1], lz + ga.flo[2]};
-  for (int d = 0; d < 3; ++d)
-    st.cnt[d] = interp_stencil(j[d], ga.cn[d], (ga.cper >> d) & 1u, st.idx[d], st.w[d]);
-}
-
-template <typename S, typename R, typename ST>
-__device__ __forceinline__ R interp_apply(const GhostArgs& ga, const S* fc, int q, const ST& st) {
-  const S* fq = fc + (size_t)q * (size_t)ga.Nc;
+// Tensor interpolation from a staged patch (x fastest, rows of m0 nodes,
+// planes of m01). The stencil shape is a compile-time count per axis so
+// the LDS reads are unrolled; summation order z, then y, then x.
+template <int C0, int C1, int C2, typename S, typename R>
+__device__ __forceinline__ R patch_interp_fixed(const S* sp, const int (&a)[3],
+                                                const double (&w)[3][4], int m0, int m01) {
   R s = 0;
-  for (int c = 0; c < st.cnt[2]; ++c)
-    for (int b = 0; b < st.cnt[1]; ++b) {
-      const R wbc = R(st.w[1][b] * st.w[2][c]);
-      const size_t row = ((size_t)st.idx[2][c] * ga.cn[1] + st.idx[1][b]) * ga.cn[0];
-      for (int a = 0; a < st.cnt[0]; ++a)
-        s += R(st.w[0][a]) * wbc * ld<R>(fq + row + st.idx[0][a]);
+#pragma unroll
+  for (int c = 0; c < C2; ++c)
+#pragma unroll
+    for (int b = 0; b < C1; ++b) {
+      const R wbc = R(w[1][b] * w[2][c]);
+      const S* row = sp + (a[2] + c) * m01 + (a[1] + b) * m0 + a[0];
+#pragma unroll
+      for (int x = 0; x < C0; ++x) s += R(w[0][x]) * wbc * R(row[x]);
     }
   return s;
 }
 
 template <typename S, typename R>
-__device__ __forceinline__ R interp_value(const GhostArgs& ga, const S* fc, int q, long long gi) {
-  GhostStencil st;
-  ghost_stencil(ga, gi, st);
-  return interp_apply<S, R>(ga, fc, q, st);
-}
-
-template <int Q, typename S, typename R>
-__global__ __launch_bounds__(256) void interp_kernel(const GhostArgs ga, const S* fc, R* G) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ga.ng * Q) return;
-  const int q = (int)(k / ga.ng);
-  const long long gi = k - (long long)q * ga.ng;
-  G[(size_t)q * ga.ng + gi] = interp_value<S, R>(ga, fc, q, gi);
-}
-
-// Ghost populations = rescale(c0 G0 + c1 G1) into the fine state ff.
-template <int KIND, typename S, typename R>
-__global__ __launch_bounds__(256) void fill_kernel(const GhostArgs ga, const R* G0, const R* G1,
-                                                   double c0, double c1, double r, S* ff) {
-  constexpr int Q = Model<KIND>::Q;
-  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ga.ng) return;
-  R g[Q], feq[Q];
+__device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01) {
+  int a[3], shape = 0;
+  double w[3][4];
 #pragma unroll
-  for (int q = 0; q < Q; ++q)
-    g[q] = R(c0) * G0[(size_t)q * ga.ng + gi] + R(c1) * G1[(size_t)q * ga.ng + gi];
-  equilibrium_dev<KIND, R>(g, feq);
-  const int l = ga.ghosts[gi];
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-    st(ff + (size_t)q * (size_t)ga.Nf + l, feq[q] + R(r) * (g[q] - feq[q]));
+  for (int d = 0; d < 3; ++d) {
+    const int cd = (code >> (6 * d)) & 63;
+    a[d] = cd & 7;
+    stencil_weights(cd >> 3, w[d]);
+    shape |= (cd >> 3) != 0 ? 1 << d : 0;
+  }
+  switch (shape) {
+    case 0: return patch_interp_fixed<1, 1, 1, S, R>(sp, a, w, m0, m01);
+    case 1: return patch_interp_fixed<4, 1, 1, S, R>(sp, a, w, m0, m01);
+    case 2: return patch_interp_fixed<1, 4, 1, S, R>(sp, a, w, m0, m01);
+    case 3: return patch_interp_fixed<4, 4, 1, S, R>(sp, a, w, m0, m01);
+    case 4: return patch_interp_fixed<1, 1, 4, S, R>(sp, a, w, m0, m01);
+    case 5: return patch_interp_fixed<4, 1, 4, S, R>(sp, a, w, m0, m01);
+    case 6: return patch_interp_fixed<1, 4, 4, S, R>(sp, a, w, m0, m01);
+    default: return patch_interp_fixed<4, 4, 4, S, R>(sp, a, w, m0, m01);
+  }
 }
 
-// Half-step interface update in one launch: G1 = interpolation of the
-// coarse state at t+1 (kept for the next coarse step), the ghosts of the
-// second fine substep = rescale(G0/2 + G1/2) into ff_half, and the ghosts
-// of the next coarse step's first substep = rescale(G1) into ff_next (that
-// array's ghost slots are not written by the second substep). A workgroup
-// takes GT ghosts x Q populations, population-major; the rescaling needs
-// each ghost's moments, shared through LDS. Same arithmetic as
-// interp_kernel followed by fill_kernel.
+// Rescaled ghost populations of one group: lanes take (ghost, population)
+// pairs population-major, v = c0 G0 + c1 G (G0 may be null), with the
+// moments of each ghost shared through LDS; every lane evaluates the
+// equilibrium of its own population and writes feq + r (v - feq) to ff
+// (Yu's rescaling of the non-equilibrium part).
 template <int KIND, typename S, typename R>
-__global__ __launch_bounds__(1024) void interp_fill_kernel(const GhostArgs ga, const S* fc,
-                                                           R* G1, const R* G0, double r,
-                                                           S* ff_half, S* ff_next) {
+__device__ __forceinline__ void rescale_group(const GhostArgs& ga, long long gbeg, int ngg,
+                                              R (&sv)[Model<KIND>::Q][kGhostMax],
+                                              const int (&se)[Model<KIND>::Q][3], double r,
+                                              S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  constexpr int GT = 1024 / Q;
-  __shared__ R sv[2][Q][GT];
-  __shared__ R se[2][Q][GT];
-  __shared__ GhostStencil sst[GT];
+  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
+    const int q = k / kGhostMax, gl = k % kGhostMax;
+    if (gl >= ngg) continue;
+    R d = 0, j[3] = {0, 0, 0};
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      const R f = sv[I][gl];
+      d += f;
+      j[0] += R(cx(I)) * f;
+      j[1] += R(cy(I)) * f;
+      j[2] += R(cz(I)) * f;
+    });
+    const R feq = equilibrium_one<KIND, R>(d, j, se[q][0], se[q][1], se[q][2]);
+    const int l = ga.ghosts[gbeg + gl];
+    st(ff + (size_t)q * (size_t)ga.Nf + l, feq + R(r) * (sv[q][gl] - feq));
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void velocity_table(int (&se)[Q][3]) {
   const int t = threadIdx.x;
-  const int q = t / GT, gl = t - q * GT;
-  const long long g0 = (long long)blockIdx.x * GT;
-  const long long gi = g0 + gl;
-  const bool act = q < Q && gi < ga.ng;
-  if (t < GT && g0 + t < ga.ng) ghost_stencil(ga, g0 + t, sst[t]);
-  __syncthreads();
-  if (act) {
-    const R g1 = interp_apply<S, R>(ga, fc, q, sst[gl]);
-    G1[(size_t)q * ga.ng + gi] = g1;
-    sv[0][q][gl] = R(0.5) * G0[(size_t)q * ga.ng + gi] + R(0.5) * g1;
-    sv[1][q][gl] = g1;
+  if (t < Q) {
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      if (t == I) {
+        se[I][0] = cx(I);
+        se[I][1] = cy(I);
+        se[I][2] = cz(I);
+      }
+    });
   }
-  __syncthreads();
-  if (t < 2 * GT) {
-    const int w = t / GT, g = t - w * GT;
-    if (g0 + g < ga.ng) {
-      R v[Q], feq[Q];
+}
+
+// Interface update of one ghost group per workgroup: the coarse patch
+// (all populations of the coarse state fc) is staged in LDS, each ghost
+// population is interpolated from it (G, kept for the next coarse step),
+// and the ghosts of ff receive the rescaled c0 G0 + c1 G.
+template <int KIND, typename S, typename R>
+__global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* fc, R* G,
+                                                          const R* G0, double c0, double c1,
+                                                          double r, S* ff) {
+  constexpr int Q = Model<KIND>::Q;
+  __shared__ S sp[Q][kPatchMax];
+  __shared__ R sv[Q][kGhostMax];
+  __shared__ int se[Q][3];
+  const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
+  const long long gbeg = grp->gbeg;
+  const int ngg = grp->gend - grp->gbeg;
+  const int lo[3] = {grp->lo[0], grp->lo[1], grp->lo[2]};
+  const int m0 = grp->m[0], m1 = grp->m[1], m01 = m0 * m1;
+  const int P = m01 * grp->m[2];
+  velocity_table<Q>(se);
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const int pz = p / m01, rem = p - pz * m01, py = rem / m0, px = rem - py * m0;
+    const int g3[3] = {lo[0] + px, lo[1] + py, lo[2] + pz};
+    int c[3];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = sv[w][i][g];
-      equilibrium_dev<KIND, R>(v, feq);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) se[w][i][g] = feq[i];
-    }
+    for (int d = 0; d < 3; ++d)
+      c[d] = g3[d] < 0 ? g3[d] + ga.cn[d] : (g3[d] >= ga.cn[d] ? g3[d] - ga.cn[d] : g3[d]);
+    const size_t idx = ((size_t)c[2] * ga.cn[1] + c[1]) * ga.cn[0] + c[0];
+    static_for<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      sp[I][p] = fc[(size_t)I * (size_t)ga.Nc + idx];
+    });
   }
   __syncthreads();
-  if (act) {
-    const int l = ga.ghosts[gi];
-    const R e0 = se[0][q][gl], e1 = se[1][q][gl];
-    st(ff_half + (size_t)q * (size_t)ga.Nf + l, e0 + R(r) * (sv[0][q][gl] - e0));
-    st(ff_next + (size_t)q * (size_t)ga.Nf + l, e1 + R(r) * (sv[1][q][gl] - e1));
+  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
+    const int q = k / kGhostMax, gl = k % kGhostMax;
+    if (gl >= ngg) continue;
+    const long long gi = gbeg + gl;
+    const R g = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
+    const size_t kk = (size_t)q * ga.ng + gi;
+    G[kk] = g;
+    sv[q][gl] = G0 ? R(c0) * G0[kk] + R(c1) * g : R(c1) * g;
   }
+  __syncthreads();
+  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, se, r, ff);
+}
+
+// Ghosts of ff := rescale(c1 G) from stored interpolated values, by group.
+template <int KIND, typename S, typename R>
+__global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
+                                                            double c1, double r, S* ff) {
+  constexpr int Q = Model<KIND>::Q;
+  __shared__ R sv[Q][kGhostMax];
+  __shared__ int se[Q][3];
+  const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
+  const long long gbeg = grp->gbeg;
+  const int ngg = grp->gend - grp->gbeg;
+  velocity_table<Q>(se);
+  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
+    const int q = k / kGhostMax, gl = k % kGhostMax;
+    if (gl < ngg) sv[q][gl] = R(c1) * G[(size_t)q * ga.ng + gbeg + gl];
+  }
+  __syncthreads();
+  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, se, r, ff);
 }
 
 // FP64 partial sums over the nodes of a level box whose type equals want,
