@@ -338,10 +338,12 @@ int lbm_refined_set_populations(lbm_refined* r, int level, const void* f, int dt
 int lbm_refined_get_populations(lbm_refined* r, int level, void* f, int dtype);
 
 /* Advance n coarse steps (asynchronous, ordered on the lattice's stream).
- * Within a step the coarse update runs on a second, library-owned stream
- * (created at the first call, default priority) concurrently with the first
- * fine substep; events fork it from and join it back to the lattice's
- * stream, so callers see ordinary single-stream semantics. */
+ * Within a step the coarse update and the interface interpolation run on a
+ * second, library-owned stream (created at the first call, default
+ * priority) concurrently with the first fine substep, and the next step's
+ * interface values are rescaled there during the second; events fork it
+ * from and join it back to the lattice's stream, so callers see ordinary
+ * single-stream semantics. */
 int lbm_refined_step(lbm_refined* r, int64_t n);
 
 /* rho and u of one level's box (as lbm_get_macroscopic). */
