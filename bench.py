@@ -17,7 +17,9 @@ written once), against the 8 TB/s HBM peak. ``others`` holds the same
 measurement for the other model/storage combinations. ``adjoint`` times the
 inlet-sensitivity gradient (FCLB adjoint, 128 x 128 x 256 jet, 400 steps,
 checkpoints every 20) and the adjoint step kernel alone, priced at 3 Q b
-bytes per node (state and adjoint read, adjoint written). ``cpu_baseline``
+bytes per node (state and adjoint read, adjoint written). ``statistics``
+times the velocity time-average accumulation on the default workload.
+``cpu_baseline``
 is the FP64 oracle timed on the host cores on a cut-down of the same
 workload.
 """
@@ -257,6 +259,32 @@ def measure_adjoint(P, torch, synth, storage="f32", steps=50):
     return out
 
 
+def measure_stats(P, torch, synth, name="jet256-fclb-f32", reps=50):
+    """Velocity time-average accumulation on the default workload: per call
+    Q b bytes of populations read and 6 FP64 running sums read and written."""
+    lat, desc = make_lattice(name, P, torch, synth)
+    sums = lat.stats_buffer()
+    lat.stats_accumulate(sums)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lat.stats_accumulate(sums)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    model, storage, shape, _ = workload(name)
+    n = shape[0] * shape[1] * shape[2]
+    per_node = (27 if model == "fclb" else 19) * BYTES[storage] + 2 * 6 * 8
+    gbs = per_node * n / (ms * 1e-3) / 1e9
+    del lat, sums
+    torch.cuda.empty_cache()
+    return {"name": name + "-stats", "kernel": "stats_accumulate_kernel", "ms_per_call": ms,
+            "bytes_per_node": per_node, "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+
+
 def copy_bandwidth(P, torch, nbytes=4 << 30, reps=10):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -333,6 +361,7 @@ def main():
     if not args.no_adjoint:
         adjoint = [measure_adjoint(P, torch, synth, st) for st in ("f32", "f64")]
         print("bench: adjoint gradient %.2f s (f32)" % adjoint[0]["gradient_s"], flush=True)
+    stats = measure_stats(P, torch, synth) if not args.no_others else None
     copy_gbs = copy_bandwidth(P, torch)
     model, storage, shape, _ = workload(args.workload)
     alg_per_launch = main_res["bytes_per_lup"] * shape[0] * shape[1] * shape[2]
@@ -350,7 +379,7 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": storage, "data": "synthetic", "config": main_res["config"],
-            "roofline": roof, "others": others, "adjoint": adjoint}
+            "roofline": roof, "others": others, "adjoint": adjoint, "statistics": stats}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", flush=True)
         line["cpu_baseline"] = cpu_baseline(model)

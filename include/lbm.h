@@ -192,6 +192,28 @@ int lbm_get_macroscopic(lbm_lattice* lat, void* rho, void* u, int dtype,
  * (out is still written). */
 int lbm_reduce(lbm_lattice* lat, double out[5]);
 
+/* Time averages of the velocity: the jet statistics of Section 3 (mean
+ * velocity; turbulent intensity, Eq. (25)). The caller owns an FP64 device
+ * buffer sums of 6 x N values ([6][N]: running sums of u_x, u_y, u_z and of
+ * u_x^2, u_y^2, u_z^2), zeroes it to start and counts the calls.
+ * lbm_stats_accumulate adds the velocity of the current state (u as in
+ * lbm_get_macroscopic). Asynchronous on the lattice's stream.
+ * Errors: LBM_EINVAL (null pointer), LBM_EUNBOUND. */
+int lbm_stats_accumulate(lbm_lattice* lat, double* sums);
+
+/* Averages of count >= 1 accumulated states, in dtype (LBM_DTYPE_F64/F32):
+ * mean ([3][N]) = sums / count; rms ([3][N]) = sqrt(<u_a^2> - <u_a>^2), the
+ * root-mean-square fluctuation (0 where rounding makes the difference
+ * negative); ti (N values, may be NULL) = the turbulent intensity of
+ * Eq. (25): the rms of the streamwise component over the mean streamwise
+ * velocity at the jet-axis point of the node's cross-section. axis: the
+ * streamwise direction (0 x, 1 y, 2 z); (p0, p1): the jet-axis point in the
+ * two other coordinates in increasing order (checked only if ti is given).
+ * Asynchronous. Errors: LBM_EINVAL (null sums/mean/rms, count < 1, bad dtype,
+ * axis or axis point). */
+int lbm_stats_finalize(const lbm_lattice* lat, const double* sums, int64_t count, void* mean,
+                       void* rms, void* ti, int dtype, int axis, int p0, int p1);
+
 /* Size in bytes of a state snapshot (populations + outflow ghost plane). */
 int lbm_state_bytes(const lbm_lattice* lat, size_t* bytes);
 

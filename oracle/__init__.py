@@ -25,6 +25,9 @@ Parity status of each oracle function (what pins it, see tests/):
   tangent_step / adjoint_step central differences of run; dot-product identity;
                               periodic mass/momentum adjoint invariants
   probe_ke, inlet_gradient    central differences of J through many steps
+  velocity_statistics         constant and two-level sequences, the variance
+                              (K^2 - 1)/12 of a ramp, Eq. (25) on fields
+                              with known values
 """
 from __future__ import annotations
 
@@ -207,6 +210,32 @@ def splitmix64(state):
 
 def inlet_uniform(seed, t, a, b, c):
     return float(lib().orc_inlet_uniform(seed, t, a, b, c))
+
+
+def velocity_statistics(us, axis=2, point=None):
+    """Time averages of a sequence of velocity fields (the jet statistics of
+    Section 3). us: iterable of K arrays [3][nz][ny][nx]. Returns mean, rms
+    and, if point is given, the turbulent intensity of Eq. (25).
+
+    mean = (1/K) sum_k u_k; rms = sqrt((1/K) sum_k (u_k - mean)^2) (the
+    fluctuation about the mean, population normalisation); ti = rms of the
+    streamwise component (axis) over the mean streamwise velocity at the jet
+    axis point of the same cross-section (point: the two other coordinates in
+    increasing order)."""
+    us = [np.asarray(u, dtype=np.float64) for u in us]
+    K = len(us)
+    mean = sum(us) / K
+    var = sum((u - mean) ** 2 for u in us) / K
+    rms = np.sqrt(var)
+    if point is None:
+        return mean, rms, None
+    m = np.moveaxis(mean[axis], 2 - axis, 0)  # streamwise index first
+    # [stream][a][b] with (a, b) the other coordinates, slowest first
+    axis_mean = m[:, point[1], point[0]]
+    shape = [1, 1, 1]
+    shape[2 - axis] = -1
+    ti = rms[axis] / axis_mean.reshape(shape)
+    return mean, rms, ti
 
 
 class Lattice:

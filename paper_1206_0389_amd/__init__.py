@@ -75,6 +75,10 @@ _SIGS = {
     "lbm_get_macroscopic": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                             ctypes.c_int],
     "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
+    "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_stats_finalize": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                           ctypes.c_int, ctypes.c_int],
     "lbm_state_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "lbm_save_state": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)],
@@ -218,6 +222,23 @@ def reduce(h, check: bool = True):
     if check:
         _check(rc, "lbm_reduce")
     return list(out), rc
+
+
+def stats_accumulate(h, sums: torch.Tensor):
+    if sums.dtype != torch.float64:
+        raise TypeError("sums must be float64")
+    _check(lib().lbm_stats_accumulate(h, _dev(sums)), "lbm_stats_accumulate")
+
+
+def stats_finalize(h, sums, count, mean, rms, ti=None, axis=2, point=(0, 0)):
+    if sums.dtype != torch.float64:
+        raise TypeError("sums must be float64")
+    code = _dtype_code(mean)
+    if rms.dtype != mean.dtype or (ti is not None and ti.dtype != mean.dtype):
+        raise TypeError("mean, rms and ti must share one dtype")
+    _check(lib().lbm_stats_finalize(h, _dev(sums), int(count), _dev(mean), _dev(rms),
+                                    _dev(ti) if ti is not None else None, code, int(axis),
+                                    int(point[0]), int(point[1])), "lbm_stats_finalize")
 
 
 def state_bytes(h) -> int:
@@ -401,6 +422,28 @@ class Lattice:
 
     def reduce(self, check=True):
         return reduce(self.h, check)[0]
+
+    def stats_buffer(self):
+        """Zeroed FP64 running sums for stats_accumulate ([6][nz][ny][nx])."""
+        return torch.zeros((6,) + self.shape3, dtype=torch.float64, device=self.device)
+
+    def stats_accumulate(self, sums):
+        """Add the current velocity (and its squares) to the running sums."""
+        self._expect(sums, (6,) + self.shape3, "sums")
+        stats_accumulate(self.h, sums)
+
+    def stats_finalize(self, sums, count, axis=2, point=None, dtype=torch.float64):
+        """Mean velocity, rms fluctuation ([3][nz][ny][nx] each) and, if the
+        jet-axis point (the two coordinates other than axis, increasing
+        order) is given, the turbulent intensity of Eq. (25) ([nz][ny][nx])."""
+        self._expect(sums, (6,) + self.shape3, "sums")
+        mean = torch.empty((3,) + self.shape3, dtype=dtype, device=self.device)
+        rms = torch.empty_like(mean)
+        ti = torch.empty(self.shape3, dtype=dtype, device=self.device) if point is not None \
+            else None
+        stats_finalize(self.h, sums, count, mean, rms, ti, axis,
+                       point if point is not None else (0, 0))
+        return mean, rms, ti
 
     def save_state(self):
         buf = torch.empty(state_bytes(self.h), dtype=torch.uint8, device=self.device)

@@ -655,6 +655,69 @@ __global__ __launch_bounds__(256) void macroscopic_kernel(const LatArgs a, int p
   }
 }
 
+// Running sums for time averages of the velocity (the jet statistics of
+// Section 3: mean velocity and the turbulent intensity of Eq. (25)): adds u
+// and the squares u_a^2 of the current natural state (u as in
+// macroscopic_kernel) to sums [6][N] in FP64; each node owns its entries.
+template <int KIND, typename S, bool BC>
+__global__ __launch_bounds__(256) void stats_accumulate_kernel(const LatArgs a, int parity,
+                                                               long long t, double* sums) {
+  constexpr int Q = Model<KIND>::Q;
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const Node n = make_node(a, x, y, z);
+  double f[Q];
+  fetch_natural<Q, S, BC>(a, n, parity, t, f);
+  double d = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    j[0] += cx(i) * f[i];
+    j[1] += cy(i) * f[i];
+    j[2] += cz(i) * f[i];
+  }
+  const double r = (KIND == 2) ? 1.0 + d : 1.0;
+  const size_t N = (size_t)a.N;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double u = j[c] / r;
+    sums[c * N + n.self] += u;
+    sums[(3 + c) * N + n.self] += u * u;
+  }
+}
+
+// Time averages from count accumulated states: mean = sums / count, rms =
+// sqrt(<u_a^2> - <u_a>^2) (0 where rounding makes it negative) and, if ti
+// is not null, the turbulent intensity of Eq. (25): the rms of the
+// streamwise component (axis ax) over the mean streamwise velocity at the
+// jet-axis point (p0, p1) of the node's cross-section (the two other
+// coordinates in increasing order).
+template <typename O>
+__global__ __launch_bounds__(256) void stats_finalize_kernel(const LatArgs a, const double* sums,
+                                                             double inv_count, O* mean, O* rms,
+                                                             O* ti, int ax, int p0, int p1) {
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const size_t N = (size_t)a.N;
+  const size_t self = ((size_t)z * a.ny + y) * a.nx + x;
+  double m[3], v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    m[c] = sums[c * N + self] * inv_count;
+    const double var = sums[(3 + c) * N + self] * inv_count - m[c] * m[c];
+    v[c] = var > 0.0 ? sqrt(var) : 0.0;
+    mean[c * N + self] = O(m[c]);
+    rms[c * N + self] = O(v[c]);
+  }
+  if (ti) {
+    int g[3] = {x, y, z};
+    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    g[o0] = p0;
+    g[o1] = p1;
+    const size_t axis_node = ((size_t)g[2] * a.ny + g[1]) * a.nx + g[0];
+    ti[self] = O(v[ax] / (sums[ax * N + axis_node] * inv_count));
+  }
+}
+
 // Per-block FP64 partial sums (mass deviation, momentum, kinetic energy) in
 // a fixed tree order, one row of 5 per block of the launch grid.
 template <int KIND, typename S, bool BC>

@@ -477,6 +477,36 @@ int lbm_get_macroscopic(lbm_lattice* L, void* rho, void* u, int dtype, int rho_m
   return check_launch();
 }
 
+int lbm_stats_accumulate(lbm_lattice* L, double* sums) {
+  if (!L || !sums) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    hipLaunchKernelGGL((stats_accumulate_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
+                       L->args, L->parity, (long long)L->t, sums);
+  });
+  return check_launch();
+}
+
+int lbm_stats_finalize(const lbm_lattice* L, const double* sums, int64_t count, void* mean,
+                       void* rms, void* ti, int dtype, int axis, int p0, int p1) {
+  if (!L || !sums || !mean || !rms || !valid_dtype(dtype) || count < 1) return LBM_EINVAL;
+  if (axis < 0 || axis > 2) return LBM_EINVAL;
+  const int n3[3] = {L->cfg.nx, L->cfg.ny, L->cfg.nz};
+  const int o0 = axis == 0 ? 1 : 0, o1 = axis == 2 ? 1 : 2;
+  if (ti && (p0 < 0 || p0 >= n3[o0] || p1 < 0 || p1 >= n3[o1])) return LBM_EINVAL;
+  const double inv = 1.0 / (double)count;
+  if (dtype == LBM_DTYPE_F64)
+    hipLaunchKernelGGL((stats_finalize_kernel<double>), L->grid, L->block, 0, L->stream, L->args,
+                       sums, inv, (double*)mean, (double*)rms, (double*)ti, axis, p0, p1);
+  else
+    hipLaunchKernelGGL((stats_finalize_kernel<float>), L->grid, L->block, 0, L->stream, L->args,
+                       sums, inv, (float*)mean, (float*)rms, (float*)ti, axis, p0, p1);
+  return check_launch();
+}
+
 int lbm_reduce(lbm_lattice* L, double out[5]) {
   if (!L || !out) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;

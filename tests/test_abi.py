@@ -106,6 +106,17 @@ def test_required_bytes_and_binding_checks(P):
     assert P.lib().lbm_bind_memory(h, ctypes.c_void_p(0x1001), n.value) == P.EINVAL
     assert P.lib().lbm_bind_memory(h, ctypes.c_void_p(0x100000), n.value - 1) == P.ENOMEM
     assert P.lib().lbm_step(h, -1) == P.EINVAL
+    # statistics: refused before any launch
+    fake = ctypes.c_void_p(0x100000)
+    assert P.lib().lbm_stats_accumulate(h, fake) == P.EUNBOUND
+    assert P.lib().lbm_stats_accumulate(h, None) == P.EINVAL
+    fin = P.lib().lbm_stats_finalize
+    assert fin(h, fake, 0, fake, fake, None, P.DTYPE_F64, 2, 0, 0) == P.EINVAL  # count < 1
+    assert fin(h, fake, 1, fake, fake, None, P.DTYPE_F64, 3, 0, 0) == P.EINVAL  # axis
+    assert fin(h, fake, 1, None, fake, None, P.DTYPE_F64, 2, 0, 0) == P.EINVAL  # no mean
+    assert fin(h, fake, 1, fake, fake, fake, P.DTYPE_F64, 2, 16, 0) == P.EINVAL  # x0 >= nx
+    assert fin(h, fake, 1, fake, fake, fake, P.DTYPE_F64, 0, 0, 4) == P.EINVAL  # z0 >= nz
+    assert fin(h, fake, 1, fake, fake, fake, 7, 2, 0, 0) == P.EINVAL  # dtype
     P.lib().lbm_destroy(h)
 
 

@@ -18,7 +18,8 @@ rounded to the storage precision, exactly as the GPU stored it.
 The two-level refined workload is checked at full size through properties
 that hold at any size (uniform flow preserved exactly; FP32 against FP64).
 A 512 x 512 x 256 FP64 lattice checks the path taken when 32-bit offsets
-cannot span a population and its opposite.
+cannot span a population and its opposite. The velocity time averages of
+the FCLB FP32 jet are checked in four of the boxes.
 """
 import numpy as np
 import pytest
@@ -87,6 +88,55 @@ def test_jet256_boxes_against_oracle(workload):
         worst = max(worst, err)
         assert err <= STEPS * TOL[storage], (lo, hi, err)
     print(workload, "worst box error", worst, flush=True)
+
+
+def test_jet256_statistics_boxes():
+    """Time averages (lbm_stats_accumulate after each of the 3 steps of the
+    full-size FCLB FP32 jet, bench launch configuration) in the sampled boxes
+    against the oracle's two-pass statistics of its own states, with the
+    bounds of test_gpu_stats.py (per-step state error 4e-6 relative)."""
+    import bench
+    import paper_1206_0389_amd as P
+    workload = "jet256-fclb-f32"
+    print("case full size statistics", workload, flush=True)
+    model, storage, shape, _ = bench.workload(workload)
+    nx, ny, nz = shape
+    lat, _ = bench.make_lattice(workload, P, torch, synth)
+    js = bench.jet_setup(nx, ny, synth)
+    f = torch.empty((27, nz, ny, nx), dtype=torch.float64, device="cuda")
+    for q in range(27):
+        f[q] = torch.from_numpy(synth.tiled_populations(27, (nz, ny, nx), AMP, SEED,
+                                                        qs=[q])[0]).cuda()
+    lat.set_populations(f, t0=T0)
+    del f
+    sums = lat.stats_buffer()
+    for _ in range(STEPS):
+        lat.step(1)
+        lat.stats_accumulate(sums)
+    mean, rms, _ = lat.stats_finalize(sums, STEPS)
+    del sums
+    e = TOL["f32"]
+    for lo, hi in BOXES[:4]:
+        wlo, whi, wf, inner = window((nx, ny, nz), JET, lo, hi, STEPS)
+        f0 = synth.tiled_populations(27, (nz, ny, nx), AMP, SEED, lo=wlo, hi=whi)
+        f0 = f0.astype(np.float32).astype(np.float64)
+        o = oracle_lattice("fclb", tuple(b - a for a, b in zip(wlo, whi)), js["nu"], faces=wf,
+                           face_u=js["face_u"], inlet=(js["inlet_u"], js["inlet_mask"]),
+                           amp=js["inlet_amp"], seed=js["seed"], origin=tuple(wlo),
+                           extent=(nx, ny))
+        us, fo = [], f0
+        for k in range(STEPS):
+            fo = o.run(fo, T0 + k, 1)
+            us.append(o.macroscopic(fo)[1][:, inner[2], inner[1], inner[0]])
+        m_o, r_o, _ = oracle.velocity_statistics(us)
+        sl = (slice(None), slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        m_g, r_g = mean[sl].cpu().numpy(), rms[sl].cpu().numpy()
+        u2max = float((m_o ** 2 + r_o ** 2).max())
+        dm = float(np.abs(m_g - m_o).max())
+        dv = float(np.abs(r_g ** 2 - r_o ** 2).max())
+        print("statistics box", lo, "mean", dm / np.abs(m_o).max(), "var", dv / u2max, flush=True)
+        assert dm <= STEPS * e * float(np.abs(m_o).max()), (lo, dm)
+        assert dv <= 4 * STEPS * e * u2max, (lo, dv)
 
 
 @pytest.mark.parametrize("model", ["fclb", "mrt"])
