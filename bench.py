@@ -75,7 +75,8 @@ def workload(name):
     """(model, storage, shape, kind) from a name like jet256-fclb-f32."""
     kind, model, storage = name.split("-")
     shapes = {"jet256": (256, 256, 512), "tgv256": (256, 256, 512), "tgv128": (128, 128, 128),
-              "jet128": (128, 128, 256), "ref128": (128, 128, 256)}
+              "jet128": (128, 128, 256), "ref128": (128, 128, 256),
+              "nozzle256": (256, 256, 512)}
     return model, storage, shapes[kind], kind
 
 
@@ -101,6 +102,18 @@ def jet_setup(nx, ny, synth):
     return {"nu": 1e-4, "cs": 0.1, "diameter": diam, "inlet_u": iu, "inlet_mask": im,
             "face_u": [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2,
             "inlet_amp": 0.01 * 0.05, "seed": 12060389}
+
+
+def nozzle_mask(nx, ny, nz, diameter, wall=2, length=16):
+    """Solid tube around the inlet disk: nodes whose distance from the jet
+    axis lies in [D/2, D/2 + wall) on the first `length` planes."""
+    import numpy as np
+    y, x = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(x + 0.5 - nx / 2.0, y + 0.5 - ny / 2.0)
+    ring = (r >= diameter / 2.0) & (r < diameter / 2.0 + wall)
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    m[:length] = ring
+    return m
 
 
 def make_lattice(name, P, torch, synth):
@@ -136,7 +149,7 @@ def make_lattice(name, P, torch, synth):
                 "cs_smag": cs if model == "mrt" else None}
         lat.updates_per_step = desc["updates_per_coarse_step"]
         return lat, desc
-    if kind.startswith("jet"):
+    if kind.startswith("jet") or kind.startswith("nozzle"):
         js = jet_setup(nx, ny, synth)
         nu, cs, diam = js["nu"], js["cs"], js["diameter"]
         lat = P.Lattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs)
@@ -145,9 +158,14 @@ def make_lattice(name, P, torch, synth):
                            inlet_mask=torch.from_numpy(js["inlet_mask"]),
                            inlet_amp=js["inlet_amp"], seed=js["seed"])
         d, u = synth.uniform_fields(nx, ny, nz, u=(0.0, 0.0, 0.002), dtype=np.float32)
+        extra = ""
+        if kind.startswith("nozzle"):
+            sm = nozzle_mask(nx, ny, nz, diam)
+            lat.set_solids(torch.from_numpy(sm))
+            extra = ", solid nozzle tube (wall 2, length 16, %d solid nodes)" % int(sm.sum())
         desc = {"workload": "round jet %dx%dx%d, D=%d inlet u=0.05 +1%% seeded perturbation, "
-                            "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4"
-                            % (nx, ny, nz, int(diam)),
+                            "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4%s"
+                            % (nx, ny, nz, int(diam), extra),
                 "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
                 "cs_smag": cs if model == "mrt" else None}
     else:
@@ -351,7 +369,7 @@ def main():
         for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-mrt-f32", "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
-                     "ref128-mrt-f32"]:
+                     "ref128-mrt-f32", "nozzle256-fclb-f32"]:
             if name == args.workload:
                 continue
             r = measure(name, P, torch, synth, args.other_steps, 10)

@@ -176,6 +176,24 @@ int lbm_set_populations(lbm_lattice* lat, const void* f, int dtype, int64_t t0);
  * order), whatever the in-place streaming parity. */
 int lbm_get_populations(lbm_lattice* lat, void* f, int dtype);
 
+/* Interior solid nodes (a node-type field). solid: device, N bytes
+ * ([nz][ny][nx]), nonzero = solid. masks: device work buffer of N uint32
+ * owned by the caller, filled here with each node's solid-neighbour mask and
+ * read by every later step: it must stay allocated and unchanged until the
+ * solids are cleared (solid = NULL), lbm_set_boundaries is called (which
+ * clears them) or the lattice is destroyed. A population whose pull source
+ * is a solid node bounces back off a wall at rest halfway between the nodes
+ * (the rule of a WALL face with zero velocity). Solid nodes are not updated;
+ * their populations are unspecified, lbm_get_populations returns zeros and
+ * lbm_get_macroscopic the rest state (rho = 1, u = 0) there, and the
+ * reductions, statistics and probe count them as rest. Steps then run the
+ * general boundary kernel on every row. Blocking (validation).
+ * Errors: LBM_EINVAL (masks NULL while solid is given; a solid node on an
+ * OUTFLOW face, whose zero-gradient copy would read it: the solids are then
+ * left cleared), LBM_EUNBOUND, LBM_ESTATE (odd in-place parity). The adjoint
+ * calls (lbm_step_record, lbm_adjoint_step) refuse a lattice with solids. */
+int lbm_set_solids(lbm_lattice* lat, const uint8_t* solid, uint32_t* masks);
+
 /* Advance n >= 0 collide-and-stream steps (asynchronous). */
 int lbm_step(lbm_lattice* lat, int64_t n);
 

@@ -28,6 +28,9 @@ Parity status of each oracle function (what pins it, see tests/):
   velocity_statistics         constant and two-level sequences, the variance
                               (K^2 - 1)/12 of a ramp, Eq. (25) on fields
                               with known values
+  solid nodes (run)           a channel bounded by solid layers equals the
+                              channel bounded by WALL faces; a solid slab
+                              across a periodic box blocks all transport
 """
 from __future__ import annotations
 
@@ -76,6 +79,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("origin", ctypes.c_int32 * 3),
         ("inlet_na", ctypes.c_int32), ("inlet_nb", ctypes.c_int32),
+        ("solid", ctypes.POINTER(ctypes.c_uint8)),
     ]
 
 
@@ -242,12 +246,15 @@ class Lattice:
     """Configuration of an oracle lattice (or window of one).
 
     faces: six of PERIODIC/WALL/INLET/OUTFLOW for x-, x+, y-, y+, z-, z+.
+    solid: optional [nz][ny][nx] mask of interior solid nodes; a population
+    whose source is solid bounces back off a wall at rest, and solid nodes
+    keep their (meaningless) populations unchanged.
     """
 
     def __init__(self, model, nx, ny, nz, nu, cs_smag=0.0, basis=BASIS_TABLE1,
                  rates=None, faces=(PERIODIC,) * 6, face_u=None, inlet_u=None,
                  inlet_mask=None, inlet_amp=0.0, seed=0, origin=(0, 0, 0),
-                 inlet_extent=None):
+                 inlet_extent=None, solid=None):
         p = Params()
         p.model = model
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -280,6 +287,13 @@ class Lattice:
         p.seed = seed
         for k in range(3):
             p.origin[k] = origin[k]
+        self.solid = None
+        if solid is not None:
+            sm = np.ascontiguousarray(solid, dtype=np.uint8)
+            assert sm.shape == (nz, ny, nx)
+            self._keep.append(sm)
+            self.solid = sm
+            p.solid = sm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         self.p = p
         self.model = model
         self.Q = q_of(model)
@@ -321,6 +335,8 @@ class Lattice:
     def _need_fclb(self):
         if self.model != FCLB27:
             raise ValueError("the oracle's adjoint covers the FCLB model only")
+        if self.solid is not None:
+            raise ValueError("the oracle's adjoint has no interior solids")
 
     def collide_jvp(self, f, v):
         self._need_fclb()

@@ -52,6 +52,7 @@ typedef struct orc_params {
   uint64_t seed;              // perturbation seed
   int32_t origin[3];          // global coordinate of local node (0,0,0)
   int32_t inlet_na, inlet_nb; // global extent of the inlet face arrays
+  const uint8_t* solid;       // [N] nonzero = solid node (may be null)
 } orc_params;
 
 }  // extern "C"
@@ -444,9 +445,11 @@ inline long node_index(const orc_params* p, int x, int y, int z) {
 //    velocity, f_i = f*_opp(i)(x) + 6 w_i (e_i . u_w);
 //  * beyond an INLET face: the same with the inlet velocity at the node;
 //  * beyond OUTFLOW faces only: the post-collision value of the nearest
-//    boundary node (a ghost layer copying the last plane).
+//    boundary node (a ghost layer copying the last plane);
+//  * a solid node inside the domain: halfway bounce-back off a wall at
+//    rest, f_i = f*_opp(i)(x) (the same rule as a WALL face with u_w = 0).
 // When a source lies beyond several faces, WALL wins over INLET over OUTFLOW.
-enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3 };
+enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3, SRC_SOLID = 4 };
 struct Source {
   int kind;
   long node;  // source node (NORMAL/OUTFLOW) or the node itself
@@ -470,7 +473,11 @@ Source classify(const orc_params* p, int i, int x, int y, int z) {
       any = true;
     }
   }
-  if (!any) return {SRC_NORMAL, node_index(p, s[0], s[1], s[2]), -1};
+  if (!any) {
+    const long src = node_index(p, s[0], s[1], s[2]);
+    if (p->solid && p->solid[src]) return {SRC_SOLID, node_index(p, x, y, z), -1};
+    return {SRC_NORMAL, src, -1};
+  }
   for (int face = 0; face < 6; ++face)
     if (crossed[face] && p->face_type[face] == ORC_WALL)
       return {SRC_WALL, node_index(p, x, y, z), face};
@@ -492,6 +499,7 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
   const Source src = classify(p, i, x, y, z);
   if (src.kind == SRC_NORMAL || src.kind == SRC_OUTFLOW) return fpost[i * N + src.node];
   const int io = opposite(Q, i);
+  if (src.kind == SRC_SOLID) return fpost[io * N + src.node];
   double u[3];
   if (src.kind == SRC_WALL) {
     for (int c = 0; c < 3; ++c) u[c] = p->face_u[src.face][c];
@@ -590,6 +598,7 @@ int orc_run(const orc_params* p, double* f, int64_t t0, int64_t nsteps) {
       for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
           const long self = node_index(p, x, y, z);
+          if (p->solid && p->solid[self]) continue;  // solid nodes are not updated
           for (int i = 0; i < Q; ++i)
             f[i * N + self] = pull(p, post.data(), Q, i, x, y, z, t);
         }
@@ -935,6 +944,7 @@ void* orc_refine_create(const orc_params* coarse, int block, const uint8_t* mask
   if (block < 2 || coarse->nx % block || coarse->ny % block || coarse->nz % block) return nullptr;
   Refine* R = new Refine();
   R->c = *coarse;
+  R->c.solid = nullptr;  // the refined lattice has no interior solids
   R->B = block;
   R->Q = nq(coarse->model);
   R->nb[0] = coarse->nx / block;

@@ -76,6 +76,7 @@ _SIGS = {
                             ctypes.c_int],
     "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_stats_finalize": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                            ctypes.c_int, ctypes.c_int],
@@ -222,6 +223,15 @@ def reduce(h, check: bool = True):
     if check:
         _check(rc, "lbm_reduce")
     return list(out), rc
+
+
+def set_solids(h, solid, masks):
+    if solid is None:
+        _check(lib().lbm_set_solids(h, None, None), "lbm_set_solids")
+        return
+    if solid.dtype != torch.uint8 or masks.dtype != torch.int32 or masks.numel() != solid.numel():
+        raise TypeError("solid must be uint8 and masks int32 of the same size")
+    _check(lib().lbm_set_solids(h, _dev(solid), _dev(masks)), "lbm_set_solids")
 
 
 def stats_accumulate(h, sums: torch.Tensor):
@@ -389,6 +399,7 @@ class Lattice:
         bc.seed = int(seed)
         set_boundaries(self.h, bc)
         self._keep = keep
+        self._solid_bufs = None  # new boundaries clear the solids
 
     def _expect(self, t, shape, what):
         if tuple(t.shape) != tuple(shape):
@@ -422,6 +433,21 @@ class Lattice:
 
     def reduce(self, check=True):
         return reduce(self.h, check)[0]
+
+    def set_solids(self, solid):
+        """Interior solid nodes from a [nz][ny][nx] mask (nonzero = solid;
+        None clears them). The library keeps a per-node mask buffer owned by
+        this object until the solids are cleared or the boundaries reset."""
+        if solid is None:
+            set_solids(self.h, None, None)
+            self._solid_bufs = None
+            return
+        solid = torch.as_tensor(solid).to(device=self.device, dtype=torch.uint8).contiguous()
+        self._expect(solid, self.shape3, "solid")
+        masks = torch.empty(self.shape3, dtype=torch.int32, device=self.device)
+        self._solid_bufs = None
+        set_solids(self.h, solid, masks)
+        self._solid_bufs = (solid, masks)
 
     def stats_buffer(self):
         """Zeroed FP64 running sums for stats_accumulate ([6][nz][ny][nx])."""

@@ -64,6 +64,10 @@ struct BcArgs {
 struct LatArgs {
   void* f;      // [Q][N]
   void* ghost;  // [Q][ghost_n]
+  // interior solid nodes (null if none): per node, bit i set if the pull
+  // source x - e_i is a solid node inside the domain, bit 31 if the node
+  // itself is solid (see solid_mask_kernel)
+  const uint32_t* solid_nb;
   int nx, ny, nz;
   long long N;
   MrtParams mrt;
@@ -299,15 +303,18 @@ __device__ __forceinline__ real wall_term(const BcArgs& b, uint32_t cw) {
 // x - e_I in the z plane). Selects only, no branches, so the loads of all
 // directions can be issued back to back.
 template <int Q, int I, typename S, bool BC>
-__device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, const Node& n) {
+__device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, const Node& n,
+                                              uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
   const S* normal = F + (size_t)IO * N + n.at(-cx(I), -cy(I), -cz(I));
   if constexpr (!BC) {
     return normal;
   } else {
+    // a solid source bounces back like a WALL face at rest (pull_term adds
+    // nothing: no face is crossed)
     const uint32_t crossed = n.atface & pull_faces(I);
-    const bool bb = (crossed & (a.bc.wall | a.bc.inlet)) != 0;
+    const bool bb = (crossed & (a.bc.wall | a.bc.inlet)) != 0 || ((sb >> I) & 1u) != 0;
     const S* own = F + (size_t)I * N + n.self;
     const S* ghost = (const S*)a.ghost + (size_t)I * (size_t)a.bc.ghost_n +
                      (n.yo[1 - cy(I)] + n.xo[1 - cx(I)]);
@@ -334,7 +341,7 @@ __device__ __forceinline__ real pull_term(const BcArgs& b, uint32_t atface, cons
 // I of its in-plane neighbour, the ghost copy of the next pull).
 template <int Q, int I, typename real, typename S, bool BC>
 __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real v,
-                                     const real* uin) {
+                                     const real* uin, uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
   if constexpr (!BC) {
@@ -350,7 +357,8 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
     const real ti = real(6.0 * weight<Q>(I)) * (real(cx(IO)) * uin[0] + real(cy(IO)) * uin[1] +
                                                 real(cz(IO)) * uin[2]);
     const real term = cw ? tw : (ci ? ti : real(0));
-    const bool bb = (cw | ci) != 0;
+    // x + e_I solid (the pull source of opp(I)): bounce back, no term
+    const bool bb = (cw | ci) != 0 || ((sb >> IO) & 1u) != 0;
     S* own = F + (size_t)IO * N + n.self;
     if (bb || !crossed) st(bb ? own : normal, bb ? v + term : v);
     if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0)
@@ -455,6 +463,14 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   const Node n = make_node(a, x, y, z);
   S* __restrict__ F = (S*)a.f;
   const size_t N = (size_t)a.N;
+  // interior solids (general kernel only): solid nodes are not updated
+  uint32_t sb = 0;
+  if constexpr (BC) {
+    if (a.solid_nb) {
+      sb = a.solid_nb[n.self];
+      if (sb >> 31) return;
+    }
+  }
   double uin_prev[3] = {0, 0, 0}, uin_now[3] = {0, 0, 0};
   if constexpr (BC && ODD) {
     if (n.atface & a.bc.inlet) {
@@ -484,7 +500,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     } else {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = ld<real, !BC && cx(I) == 0>(pull_addr<Q, I, S, BC>(a, F, n));
+        f[I] = ld<real, !BC && cx(I) == 0>(pull_addr<Q, I, S, BC>(a, F, n, sb));
       });
       if constexpr (BC) {
         const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
@@ -529,18 +545,29 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push<Q, I, real, S, BC>(a, F, n, f[I], un);
+        push<Q, I, real, S, BC>(a, F, n, f[I], un, sb);
       });
     }
   }
 }
 
-// Natural (pre-collision) populations of a node in double precision.
+// Natural (pre-collision) populations of a node in double precision; zero
+// (the rest state) at a solid node, whose populations are not updated.
 template <int Q, typename S, bool BC>
 __device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, int parity,
                                               long long t, double (&f)[Q]) {
   const S* F = (const S*)a.f;
   const size_t N = (size_t)a.N;
+  uint32_t sb = 0;
+  if constexpr (BC) {
+    if (a.solid_nb) {
+      sb = a.solid_nb[n.self];
+      if (sb >> 31) {
+        for (int i = 0; i < Q; ++i) f[i] = 0.0;
+        return;
+      }
+    }
+  }
   if (parity == 0) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
@@ -553,10 +580,28 @@ __device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, i
     }
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<double>(pull_addr<Q, I, S, BC>(a, F, n));
+      f[I] = ld<double>(pull_addr<Q, I, S, BC>(a, F, n, sb));
       if constexpr (BC) f[I] += pull_term<Q, I, double>(a.bc, n.atface, uin);
     });
   }
+}
+
+// Solid-neighbour masks of the nodes (LatArgs::solid_nb) from a solid flag
+// per node; flag[0] := 1 if a solid node lies on an OUTFLOW face (the
+// outflow copy would read it).
+template <int Q>
+__global__ __launch_bounds__(256) void solid_mask_kernel(const LatArgs a, const uint8_t* solid,
+                                                         uint32_t* out, int* flag) {
+  int x, y, z;
+  if (!node_coords(a, x, y, z)) return;
+  const Node n = make_node(a, x, y, z);
+  uint32_t m = solid[n.self] ? (1u << 31) : 0u;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    if ((n.atface & pull_faces(I)) == 0 && solid[n.at(-cx(I), -cy(I), -cz(I))]) m |= 1u << I;
+  });
+  out[n.self] = m;
+  if ((m >> 31) && (n.atface & a.bc.outflow)) flag[0] = 1;
 }
 
 template <int Q, typename S, bool BC, typename O>

@@ -31,6 +31,7 @@ struct lbm_lattice {
   int64_t t = 0;
   int parity = 0;
   bool has_bc = false;
+  bool solids = false;  // interior solid nodes set (general kernel only)
   LatArgs args;
   dim3 grid, block;
   // odd steps with boundaries split into wall rows (x and y faces walls or
@@ -164,7 +165,7 @@ void plan_rows(lbm_lattice* L) {
   // the wall rows address a population and its opposite from the lower
   // slab with 32-bit offsets: the span of slabs must stay below 4 GiB
   const bool span_ok = slab_span(L->Q) * (double)L->N * (double)L->elem < 4294967296.0;
-  L->split_odd = L->has_bc && x_ok && nrows <= 65535 && span_ok;
+  L->split_odd = L->has_bc && !L->solids && x_ok && nrows <= 65535 && span_ok;
   const int bx = L->block.x, by = L->block.y;
   L->grid_inner = dim3((nx + bx - 1) / bx, in.ny_in > 0 ? (in.ny_in + by - 1) / by : 0,
                        in.nz_in > 0 ? in.nz_in : 0);
@@ -371,6 +372,8 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
   if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
   fill_wall_terms(b, L->Q);
   L->args.bc = b;
+  L->args.solid_nb = nullptr;  // new boundaries clear the solids
+  L->solids = false;
   L->has_bc = b.nonper != 0;
   plan_rows(L);
   return LBM_OK;
@@ -448,7 +451,7 @@ int lbm_step(lbm_lattice* L, int64_t n) {
 int lbm_step_record(lbm_lattice* L, void* rec, int dtype) {
   if (!L || !rec || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;
-  if (L->kind != 2 || L->cfg.storage == LBM_F16) return LBM_EINVAL;
+  if (L->kind != 2 || L->cfg.storage == LBM_F16 || L->solids) return LBM_EINVAL;
   if (dtype != (L->cfg.storage == LBM_F64 ? LBM_DTYPE_F64 : LBM_DTYPE_F32)) return LBM_EINVAL;
   step_record_dispatch(L, L->parity == 1, (long long)L->t, rec);
   L->t += 1;
@@ -475,6 +478,43 @@ int lbm_get_macroscopic(lbm_lattice* L, void* rho, void* u, int dtype, int rho_m
                          (float*)u, rho_mode);
   });
   return check_launch();
+}
+
+int lbm_set_solids(lbm_lattice* L, const uint8_t* solid, uint32_t* masks) {
+  if (!L) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (L->parity != 0) return LBM_ESTATE;
+  L->args.solid_nb = nullptr;
+  L->solids = false;
+  L->has_bc = L->args.bc.nonper != 0;
+  if (solid) {
+    if (!masks) return LBM_EINVAL;
+    int* flag = (int*)(L->base + L->off_result);
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), L->stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (L->Q == 27)
+      hipLaunchKernelGGL((solid_mask_kernel<27>), L->grid, L->block, 0, L->stream, L->args, solid,
+                         masks, flag);
+    else
+      hipLaunchKernelGGL((solid_mask_kernel<19>), L->grid, L->block, 0, L->stream, L->args, solid,
+                         masks, flag);
+    const int rc = check_launch();
+    if (rc) return rc;
+    int bad = 0;
+    e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, L->stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (bad) {
+      plan_rows(L);
+      return LBM_EINVAL;
+    }
+    L->args.solid_nb = masks;
+    L->solids = true;
+    L->has_bc = true;
+  }
+  plan_rows(L);
+  return LBM_OK;
 }
 
 int lbm_stats_accumulate(lbm_lattice* L, double* sums) {
@@ -616,7 +656,7 @@ int lbm_probe_ke(lbm_lattice* L, const int32_t lo[3], const int32_t hi[3], void*
 int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, void* lambda,
                      int dtype, double* grad_inlet) {
   if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
-  if (L->kind != 2) return LBM_EINVAL;
+  if (L->kind != 2 || L->solids) return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
   // the kernels address the adjoint arrays with 32-bit byte offsets: one
   // slab must stay below 4 GiB, and the wall rows (a population and its
