@@ -374,46 +374,61 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
 // (slot I of the node itself) and the normal source (slot opp(I) of x - e_I)
 // are selected as offsets from the lower of the two slabs, so one
 // scalar-base load serves both.
-template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ real pull_walls(const LatArgs& a, const S* F, const Node& n) {
+// SOLID: interior solid nodes present (sb: the node's solid-neighbour
+// mask); a solid source bounces back like a wall at rest, without a term.
+template <int Q, int I, typename real, bool NT, bool SOLID, typename S>
+__device__ __forceinline__ real pull_walls(const LatArgs& a, const S* F, const Node& n,
+                                           uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
   constexpr uint32_t XB = pull_faces(I) & 3u, YB = pull_faces(I) & 12u;
   const uint32_t sz = sizeof(S);
   const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
-  if constexpr ((XB | YB) == 0) {
+  if constexpr ((XB | YB) == 0 && (!SOLID || I == 0)) {
     return ldo<real, NT>(F + (size_t)IO * a.N, nb);
   } else {
     constexpr int LO = I < IO ? I : IO;
     const uint32_t slab = (uint32_t)a.N * sz;
     const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
-    const bool bb = bx || by;
+    const bool bs = SOLID && ((sb >> I) & 1u) != 0;
+    const bool bb = bx || by || bs;
     const uint32_t off = bb ? (I - LO) * slab + (uint32_t)n.self * sz : (IO - LO) * slab + nb;
     const real v = ldo<real, NT>(F + (size_t)LO * a.N, off);
-    const real term =
-        wall_row_term<I, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
-    return bb ? v + term : v;
+    if constexpr ((XB | YB) == 0) {
+      return v;
+    } else {
+      const real term =
+          wall_row_term<I, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
+      return (bx || by) ? v + term : v;
+    }
   }
 }
 
-template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ void push_walls(const LatArgs& a, S* F, const Node& n, real v) {
+template <int Q, int I, typename real, bool NT, bool SOLID, typename S>
+__device__ __forceinline__ void push_walls(const LatArgs& a, S* F, const Node& n, real v,
+                                           uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
   constexpr uint32_t XB = push_faces(I) & 3u, YB = push_faces(I) & 12u;
   const uint32_t sz = sizeof(S);
   const uint32_t nb = (uint32_t)n.at(cx(I), cy(I), cz(I)) * sz;
-  if constexpr ((XB | YB) == 0) {
+  if constexpr ((XB | YB) == 0 && (!SOLID || I == 0)) {
     sto<NT>(F + (size_t)I * a.N, nb, v);
   } else {
     // leaving through a wall, I returns as opp(I), entering through the
-    // same face: the term is that of opp(I) at that face
+    // same face: the term is that of opp(I) at that face; a solid target
+    // (the pull source of opp(I)) returns it without a term
     constexpr int LO = I < IO ? I : IO;
     const uint32_t slab = (uint32_t)a.N * sz;
     const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
-    const bool bb = bx || by;
+    const bool bs = SOLID && ((sb >> IO) & 1u) != 0;
+    const bool bb = bx || by || bs;
     const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
-    const real term =
-        wall_row_term<IO, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 1 : 0, cy(I) > 0 ? 3 : 2);
-    sto<NT>(F + (size_t)LO * a.N, off, bb ? v + term : v);
+    if constexpr ((XB | YB) == 0) {
+      sto<NT>(F + (size_t)LO * a.N, off, v);
+    } else {
+      const real term =
+          wall_row_term<IO, real, XB, YB>(a.bc, bx, cx(I) > 0 ? 1 : 0, cy(I) > 0 ? 3 : 2);
+      sto<NT>(F + (size_t)LO * a.N, off, (bx || by) ? v + term : v);
+    }
   }
 }
 
@@ -451,7 +466,7 @@ __device__ __forceinline__ bool row_coords(const LatArgs& a, const Rows& r, int&
 // is not null, the natural pre-collision state the step collides is also
 // written to rec ([Q][N] in the compute type). The record is a runtime
 // switch, so recording and plain steps run the same code and round alike.
-template <int KIND, typename S, bool ODD, int BCM, int ROWS>
+template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool SOLID = false>
 __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r, long long t,
                                                    typename Compute<S>::type* rec) {
   using M = Model<KIND>;
@@ -463,13 +478,17 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   const Node n = make_node(a, x, y, z);
   S* __restrict__ F = (S*)a.f;
   const size_t N = (size_t)a.N;
-  // interior solids (general kernel only): solid nodes are not updated
+  // interior solids (general kernel, or the wall rows with SOLID): solid
+  // nodes are not updated
   uint32_t sb = 0;
   if constexpr (BC) {
     if (a.solid_nb) {
       sb = a.solid_nb[n.self];
       if (sb >> 31) return;
     }
+  } else if constexpr (SOLID) {
+    sb = a.solid_nb[n.self];
+    if (sb >> 31) return;
   }
   double uin_prev[3] = {0, 0, 0}, uin_now[3] = {0, 0, 0};
   if constexpr (BC && ODD) {
@@ -489,7 +508,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = pull_walls<Q, I, real, cx(I) == 0>(a, F, n);
+        f[I] = pull_walls<Q, I, real, cx(I) == 0, SOLID>(a, F, n, sb);
       });
     } else if constexpr (BCM == BC_NONE) {
       static_for<0, Q>([&](auto ic) {
@@ -539,7 +558,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push_walls<Q, I, real, cx(I) == 0>(a, F, n, f[I]);
+        push_walls<Q, I, real, cx(I) == 0, SOLID>(a, F, n, f[I], sb);
       });
     } else {
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};

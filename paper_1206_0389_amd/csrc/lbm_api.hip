@@ -63,10 +63,10 @@ void launch_shape(lbm_lattice* L) {
   L->nblocks = (size_t)L->grid.x * L->grid.y * L->grid.z;
 }
 
-template <int KIND, typename S, bool ODD, int BCM, int ROWS>
+template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool SOLID = false>
 void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t,
                  void* rec) {
-  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS>), grid, block, 0, L->stream,
+  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS, SOLID>), grid, block, 0, L->stream,
                      L->args, r, t, (typename Compute<S>::type*)rec);
 }
 
@@ -82,9 +82,14 @@ void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
   } else if (!L->split_odd) {
     launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else {
-    if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
-      launch_step<KIND, S, true, BC_WALLS, ROWS_BOX>(L, L->grid_inner, L->block, L->rows_inner,
-                                                     t, rec);
+    if (L->grid_inner.y > 0 && L->grid_inner.z > 0) {
+      if (L->solids)
+        launch_step<KIND, S, true, BC_WALLS, ROWS_BOX, true>(L, L->grid_inner, L->block,
+                                                             L->rows_inner, t, rec);
+      else
+        launch_step<KIND, S, true, BC_WALLS, ROWS_BOX>(L, L->grid_inner, L->block,
+                                                       L->rows_inner, t, rec);
+    }
     if (L->grid_bnd.y > 0)
       launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST>(L, L->grid_bnd, L->block_bnd,
                                                         L->rows_bnd, t, rec);
@@ -165,7 +170,7 @@ void plan_rows(lbm_lattice* L) {
   // the wall rows address a population and its opposite from the lower
   // slab with 32-bit offsets: the span of slabs must stay below 4 GiB
   const bool span_ok = slab_span(L->Q) * (double)L->N * (double)L->elem < 4294967296.0;
-  L->split_odd = L->has_bc && !L->solids && x_ok && nrows <= 65535 && span_ok;
+  L->split_odd = L->has_bc && x_ok && nrows <= 65535 && span_ok;
   const int bx = L->block.x, by = L->block.y;
   L->grid_inner = dim3((nx + bx - 1) / bx, in.ny_in > 0 ? (in.ny_in + by - 1) / by : 0,
                        in.nz_in > 0 ? in.nz_in : 0);
