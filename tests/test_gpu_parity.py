@@ -184,3 +184,32 @@ def test_c1_taylor_green_dhumieres_fp64_against_oracle():
     k0 = 2 * np.pi / n
     rate = np.log(E[-1] / E[5]) / 50.0
     assert rate < -6 * nu * k0 * k0 * 0.97
+
+
+def test_bgk_as_mrt_with_equal_rates():
+    """The BGK collision of Eq. (1) is the Table-1 MRT with every non-shear
+    rate equal to the shear rate omega = 1/tau and C_S = 0 (the oracle's
+    reduction is pinned in test_oracle_pins.py). Through the explicit rate
+    override: against the oracle on the jet layout (FP64, 1-2-5 steps), and
+    one periodic step against a direct numpy evaluation of Eq. (1) with
+    Eq. (2) and pull streaming by array rolls."""
+    nu = 0.02
+    omega = 1.0 / (3.0 * nu + 0.5)
+    errs = _run_pair("mrt_table1", "f64", (12, 10, 9), nu, [1, 2, 5], cs=0.0,
+                     rates=[omega] * 4, faces=JET_FACES, face_u=face_velocities(0.002),
+                     inlet=synth.jet_inlet(12, 10, 4.0, 0.05, 0.002), amp=5e-4, seed=3)
+    assert max(errs) <= TOL["f64"], errs
+    nx, ny, nz = 8, 6, 5
+    f = synth.random_populations(19, (nz, ny, nx), amp=1e-2, seed=31)
+    g = gpu_lattice("mrt_table1", "f64", (nx, ny, nz), nu, rates=[omega] * 4)
+    g.set_populations(torch.from_numpy(f), 0)
+    g.step(1)
+    e, w, _ = oracle.stencil(19)
+    d = f.sum(axis=0)
+    j = np.einsum("ia,izyx->azyx", e.astype(np.float64), f)
+    eu = np.einsum("ia,azyx->izyx", e.astype(np.float64), j)
+    feq = w[:, None, None, None] * (d + 3 * eu + 4.5 * eu ** 2 - 1.5 * (j ** 2).sum(axis=0))
+    post = f - omega * (f - feq)
+    ref = np.stack([np.roll(post[i], shift=(e[i][2], e[i][1], e[i][0]), axis=(0, 1, 2))
+                    for i in range(19)])
+    assert rel_err(g.populations().cpu().numpy(), ref) <= 1e-13
