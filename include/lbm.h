@@ -68,6 +68,7 @@ extern "C" {
 #define LBM_WALL 1           /* halfway bounce-back, optional velocity    */
 #define LBM_INLET 2          /* halfway bounce-back with inlet velocity   */
 #define LBM_OUTFLOW 3        /* zero-gradient: ghost copy of last plane   */
+#define LBM_FREESLIP 4       /* halfway specular reflection (free slip)   */
 
 #define LBM_RHO_FULL 0       /* lbm_get_macroscopic: write rho            */
 #define LBM_RHO_DEVIATION 1  /* ... write rho - 1                         */
@@ -109,7 +110,8 @@ typedef struct lbm_config {
 /*
  * Boundary description, one entry per face in the order
  * x-, x+, y-, y+, z-, z+ (the "-" face holds coordinate 0).
- *   face_type  LBM_PERIODIC | LBM_WALL | LBM_INLET | LBM_OUTFLOW. Opposite
+ *   face_type  LBM_PERIODIC | LBM_WALL | LBM_INLET | LBM_OUTFLOW |
+ *              LBM_FREESLIP (uniform lattices only). Opposite
  *              faces must both be periodic or both non-periodic.
  *              At most one LBM_INLET face and one LBM_OUTFLOW face; the
  *              outflow face must be a z face (z- or z+).
@@ -119,14 +121,21 @@ typedef struct lbm_config {
  *              coordinates in increasing axis order (z face: a = x, b = y).
  *   inlet_mask device uint8 [nb][na] or NULL; where 1, each component gets
  *              a seeded uniform perturbation inlet_amp * (2U - 1) drawn
- *              per time step from SplitMix64 (see DESIGN notes).
+ *              per time step from SplitMix64 of the seed xor the packed
+ *              (t, component, b, a).
  *   seed       perturbation seed.
  * The streaming rule at a face (population i arriving from outside at
  * node x, post-collision values f*):
  *   WALL, INLET  f_i(x) = f*_opp(i)(x) + 6 w_i (e_i . u)   (u = wall or inlet)
+ *   FREESLIP     f_i(x) = f*_k(x - e_i with the crossed coordinates kept),
+ *                k = i with the components normal to the crossed FREESLIP
+ *                faces reversed (specular reflection half-way, the
+ *                free-slip top of the paper's tank, Section 3)
  *   OUTFLOW      f_i(x) = f*_i(x - e_i with the z coordinate kept)
  * Where a source lies beyond several faces, WALL wins over INLET over
- * OUTFLOW. The inlet buffers must stay valid while the lattice steps.
+ * FREESLIP over OUTFLOW. The inlet buffers must stay valid while the
+ * lattice steps. Lattices with FREESLIP faces have no adjoint
+ * (lbm_step_record and lbm_adjoint_step refuse them).
  */
 typedef struct lbm_boundaries {
   int32_t face_type[6];

@@ -31,6 +31,9 @@ Parity status of each oracle function (what pins it, see tests/):
   solid nodes (run)           a channel bounded by solid layers equals the
                               channel bounded by WALL faces; a solid slab
                               across a periodic box blocks all transport
+  FREESLIP faces (run)        free-slip y faces equal the mirror-symmetric
+                              half of a periodic lattice twice as high;
+                              uniform tangential flow is kept exactly
 """
 from __future__ import annotations
 
@@ -46,7 +49,7 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 MRT19, FCLB27 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
-PERIODIC, WALL, INLET, OUTFLOW = 0, 1, 2, 3
+PERIODIC, WALL, INLET, OUTFLOW, FREESLIP = 0, 1, 2, 3, 4
 
 DHUMIERES_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 TABLE1_RATES = (1.0, 1.0, 1.0, 1.0)
@@ -337,6 +340,8 @@ class Lattice:
             raise ValueError("the oracle's adjoint covers the FCLB model only")
         if self.solid is not None:
             raise ValueError("the oracle's adjoint has no interior solids")
+        if FREESLIP in tuple(self.p.face_type):
+            raise ValueError("the oracle's adjoint has no free-slip faces")
 
     def collide_jvp(self, f, v):
         self._need_fclb()

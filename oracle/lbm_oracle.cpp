@@ -33,7 +33,7 @@ extern "C" {
 
 enum { ORC_MRT19 = 1, ORC_FCLB27 = 2 };
 enum { ORC_BASIS_TABLE1 = 0, ORC_BASIS_DHUMIERES = 1 };
-enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_INLET = 2, ORC_OUTFLOW = 3 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_INLET = 2, ORC_OUTFLOW = 3, ORC_FREESLIP = 4 };
 
 // Must match the ctypes structure in oracle/__init__.py.
 typedef struct orc_params {
@@ -447,14 +447,27 @@ inline long node_index(const orc_params* p, int x, int y, int z) {
 //  * beyond OUTFLOW faces only: the post-collision value of the nearest
 //    boundary node (a ghost layer copying the last plane);
 //  * a solid node inside the domain: halfway bounce-back off a wall at
-//    rest, f_i = f*_opp(i)(x) (the same rule as a WALL face with u_w = 0).
-// When a source lies beyond several faces, WALL wins over INLET over OUTFLOW.
-enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3, SRC_SOLID = 4 };
+//    rest, f_i = f*_opp(i)(x) (the same rule as a WALL face with u_w = 0);
+//  * beyond FREESLIP faces (and possibly OUTFLOW faces): halfway specular
+//    reflection, f_i = f*_k(s) with k = i mirrored across every crossed
+//    FREESLIP face (its normal component reversed) and s = x - e_i with
+//    every crossed coordinate kept (the node the mirrored population left).
+// When a source lies beyond several faces, WALL wins over INLET over
+// FREESLIP over OUTFLOW.
+enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3, SRC_SOLID = 4,
+       SRC_FREESLIP = 5 };
 struct Source {
   int kind;
-  long node;  // source node (NORMAL/OUTFLOW) or the node itself
-  int face;   // crossed WALL/INLET face
+  long node;  // source node (NORMAL/OUTFLOW/FREESLIP) or the node itself
+  int face;   // crossed WALL/INLET face; the mirrored direction (FREESLIP)
 };
+
+// Index of the velocity (ex, ey, ez) in the table (-1 if absent).
+int velocity_index(int Q, int ex, int ey, int ez) {
+  for (int k = 0; k < Q; ++k)
+    if (E[k][0] == ex && E[k][1] == ey && E[k][2] == ez) return k;
+  return -1;
+}
 
 Source classify(const orc_params* p, int i, int x, int y, int z) {
   const int n[3] = {p->nx, p->ny, p->nz};
@@ -488,6 +501,16 @@ Source classify(const orc_params* p, int i, int x, int y, int z) {
     if (s[d] < 0) s[d] = 0;
     if (s[d] >= n[d]) s[d] = n[d] - 1;
   }
+  int e[3] = {E[i][0], E[i][1], E[i][2]};
+  bool mirrored = false;
+  for (int face = 0; face < 6; ++face)
+    if (crossed[face] && p->face_type[face] == ORC_FREESLIP) {
+      e[face / 2] = -e[face / 2];
+      mirrored = true;
+    }
+  if (mirrored)
+    return {SRC_FREESLIP, node_index(p, s[0], s[1], s[2]),
+            velocity_index(nq(p->model), e[0], e[1], e[2])};
   return {SRC_OUTFLOW, node_index(p, s[0], s[1], s[2]), -1};
 }
 
@@ -498,6 +521,7 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
   const long N = (long)p->nx * p->ny * p->nz;
   const Source src = classify(p, i, x, y, z);
   if (src.kind == SRC_NORMAL || src.kind == SRC_OUTFLOW) return fpost[i * N + src.node];
+  if (src.kind == SRC_FREESLIP) return fpost[src.face * N + src.node];
   const int io = opposite(Q, i);
   if (src.kind == SRC_SOLID) return fpost[io * N + src.node];
   double u[3];

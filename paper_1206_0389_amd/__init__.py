@@ -24,7 +24,7 @@ D3Q19_MRT_LES, D3Q27_FCLB = 1, 2
 F64, F32, F16 = 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
-PERIODIC, WALL, INLET, OUTFLOW = 0, 1, 2, 3
+PERIODIC, WALL, INLET, OUTFLOW, FREESLIP = 0, 1, 2, 3, 4
 RHO_FULL, RHO_DEVIATION = 0, 1
 
 STORAGE = {"f64": F64, "f32": F32, "f16": F16}

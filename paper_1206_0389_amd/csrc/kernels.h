@@ -21,9 +21,13 @@
 // a population whose source lies beyond a non-periodic face is
 //   WALL/INLET: bounced back at the half-way point with the wall or inlet
 //               velocity, f_i(x) = f*_opp(i)(x) + 6 w_i e_i.u;
+//   FREESLIP:   reflected specularly at the half-way point, f_i(x) =
+//               f*_k(s), k = i with the normal component reversed, s = x -
+//               e_i with the crossed coordinates kept;
 //   OUTFLOW:    (a z face) copied from the boundary plane, f_i(x) = f*_i(s),
 //               s = x - e_i with the z coordinate kept (a ghost layer equal
 //               to the last plane: zero normal gradient).
+// (WALL before INLET before FREESLIP before OUTFLOW where faces meet.)
 // In AA form the bounce-back reads/writes the node's own opposite slot. The
 // outflow copy needs f*_i(s) twice (normal streaming and the ghost), so even
 // steps also store the inward populations of the outflow plane in a small
@@ -46,6 +50,7 @@ struct BcArgs {
   uint32_t wall;     // bits of WALL faces
   uint32_t inlet;    // bit of the INLET face (0 if none)
   uint32_t outflow;  // bit of the OUTFLOW face (0 if none)
+  uint32_t freeslip; // bits of FREESLIP faces
   double face_u[6][3];
   const void* inlet_u;
   const uint8_t* inlet_mask;
@@ -297,6 +302,25 @@ __device__ __forceinline__ real wall_term(const BcArgs& b, uint32_t cw) {
   return term;
 }
 
+// Compile-time table of the images of I across the axes of mask m (bit d:
+// axis d), selected at run time without an indexed array.
+template <int Q, int I, bool OPP>
+__device__ __forceinline__ int mirror_slot(int m) {
+  int k = OPP ? opposite<Q>(I) : I;
+  static_for<1, 8>([&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    constexpr int J = mirror_index(I, M);
+    constexpr int V = J < 0 ? 0 : (OPP ? opposite<Q>(J) : J);
+    k = m == M ? V : k;
+  });
+  return k;
+}
+
+// Axes (bit d) of the FREESLIP faces in a crossed-face set.
+__device__ __forceinline__ int slip_axes(uint32_t fs) {
+  return ((fs & 3u) ? 1 : 0) | ((fs & 12u) ? 2 : 0) | ((fs & 48u) ? 4 : 0);
+}
+
 // Where f_I(x, t) lives at odd parity: slot opp(I) of node x - e_I (the
 // pull through the post-collision slots), the node's own slot I (WALL or
 // INLET bounce-back, see pull_term) or the outflow ghost plane (index of
@@ -318,7 +342,21 @@ __device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, cons
     const S* own = F + (size_t)I * N + n.self;
     const S* ghost = (const S*)a.ghost + (size_t)I * (size_t)a.bc.ghost_n +
                      (n.yo[1 - cy(I)] + n.xo[1 - cx(I)]);
-    return bb ? own : (crossed ? ghost : normal);
+    // specular: f*_k(s) sits in slot opp(k) of s since the even step; where
+    // the OUTFLOW face is crossed too (s on the outflow plane, k inward),
+    // that slot has a second reader that rewrites it within the odd step,
+    // so the value comes from the ghost plane the even step filled
+    const uint32_t fs = crossed & a.bc.freeslip;
+    const int axes = slip_axes(fs);
+    const S* slip = F + (size_t)mirror_slot<Q, I, true>(axes) * N +
+                    n.at((crossed & 3u) ? 0 : -cx(I), (crossed & 12u) ? 0 : -cy(I),
+                         (crossed & 48u) ? 0 : -cz(I));
+    const S* slip_ghost = (const S*)a.ghost +
+                          (size_t)mirror_slot<Q, I, false>(axes) * (size_t)a.bc.ghost_n +
+                          (n.yo[(crossed & 12u) ? 1 : 1 - cy(I)] +
+                           n.xo[(crossed & 3u) ? 1 : 1 - cx(I)]);
+    const bool edge = (crossed & a.bc.outflow) != 0;
+    return bb ? own : (fs ? (edge ? slip_ghost : slip) : (crossed ? ghost : normal));
   }
 }
 
@@ -360,7 +398,22 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
     // x + e_I solid (the pull source of opp(I)): bounce back, no term
     const bool bb = (cw | ci) != 0 || ((sb >> IO) & 1u) != 0;
     S* own = F + (size_t)IO * N + n.self;
-    if (bb || !crossed) st(bb ? own : normal, bb ? v + term : v);
+    // leaving through FREESLIP faces only (no OUTFLOW): the image k of I
+    // arrives at x + e_I with the crossed coordinates kept, slot k
+    const uint32_t fs = crossed & a.bc.freeslip;
+    const bool slip = !bb && fs != 0 && (crossed & a.bc.outflow) == 0;
+    S* mirrored = F + (size_t)mirror_slot<Q, I, false>(slip_axes(fs)) * N +
+                  n.at((crossed & 3u) ? 0 : cx(I), (crossed & 12u) ? 0 : cy(I),
+                       (crossed & 48u) ? 0 : cz(I));
+    if (bb || !crossed || slip) st(bb ? own : (slip ? mirrored : normal), bb ? v + term : v);
+    // on the outflow plane, a population entering through the outflow face
+    // and leaving through FREESLIP faces is also the image arriving at the
+    // in-plane node (z kept): the source of the edge rule (free slip, then
+    // the outflow's kept coordinate), a second copy as for the ghost plane
+    if (slip && (n.atface & a.bc.outflow & pull_faces(I)))
+      st(F + (size_t)mirror_slot<Q, I, false>(slip_axes(fs)) * N +
+             n.at((crossed & 3u) ? 0 : cx(I), (crossed & 12u) ? 0 : cy(I), 0),
+         v);
     if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0)
       st(F + (size_t)I * N + n.at(cx(I), cy(I), 0), v);
   }

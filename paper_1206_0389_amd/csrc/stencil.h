@@ -67,6 +67,12 @@ constexpr int index_of(int x, int y, int z) {
   return -1;
 }
 
+// Direction i with the components of the axes in mask m (bit d: axis d)
+// reversed: the specular image of i across faces normal to those axes.
+constexpr int mirror_index(int i, int m) {
+  return index_of((m & 1) ? -cx(i) : cx(i), (m & 2) ? -cy(i) : cy(i), (m & 4) ? -cz(i) : cz(i));
+}
+
 // Face bits: bit 2d is the "-" face of axis d (coordinate 0), bit 2d+1 the
 // "+" face (coordinate n-1). pull_faces(i): faces crossed by x - e_i when x
 // lies on them, i.e. the faces through which population i enters.

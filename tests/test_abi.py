@@ -135,6 +135,10 @@ def test_boundary_validation(P):
     assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
     bc.inlet_dtype = P.DTYPE_F64
     assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
+    bc.face_type[2], bc.face_type[3] = P.FREESLIP, P.WALL  # free-slip top, wall bottom
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
+    bc.face_type[3] = 5  # no such face type
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
     bc.face_type[2] = bc.face_type[3] = P.WALL
     bc.face_type[4], bc.face_type[5] = P.WALL, P.WALL
     bc.face_type[0], bc.face_type[1] = P.INLET, P.OUTFLOW  # outflow only on z faces

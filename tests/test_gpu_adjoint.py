@@ -130,6 +130,12 @@ def test_adjoint_rejects_mrt_and_aliasing():
         h.adjoint_step(f, lam, lam)
     with pytest.raises(Pk.LbmError):
         h.probe_ke((0, 0, 0), (5, 4, 4))
+    # no adjoint through free-slip faces
+    h.set_boundaries([Pk.FREESLIP] * 2 + [Pk.PERIODIC] * 4)
+    with pytest.raises(Pk.LbmError):
+        h.adjoint_step(f, lam, torch.empty_like(f))
+    with pytest.raises(Pk.LbmError):
+        h.step_record(torch.empty_like(f))
 
 
 # ------------------------------------------------------------ cut-down jet

@@ -22,6 +22,7 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 TOL = {"f64": 1e-12, "f32": 4e-6, "f16": 2e-3}
+F = oracle.FREESLIP
 NAMES = list(MODELS)
 
 
@@ -61,7 +62,8 @@ def test_periodic_step_parity_fp64(name, shape):
 
 @pytest.mark.parametrize("name", NAMES)
 @pytest.mark.parametrize("layout", ["jet", "zoutflow_lo", "x_inlet", "y_inlet_walls",
-                                    "xwalls_only", "channel_thin"])
+                                    "xwalls_only", "channel_thin", "freeslip_y", "jet_slip_top",
+                                    "slip_x_edges", "slip_box"])
 def test_boundary_step_parity_fp64(name, layout):
     fu = face_velocities(0.002)
     fu[4] = [0.0, 0.0, 0.0]
@@ -78,6 +80,14 @@ def test_boundary_step_parity_fp64(name, layout):
         faces, inlet = [W, W, W, I, O, W], synth.jet_inlet(nx, nz, 3.0, 0.04, 0.001, axis=1)
     elif layout == "xwalls_only":
         faces, inlet = [W, W, P, P, P, P], None
+    elif layout == "freeslip_y":
+        faces, inlet = [P, P, F, F, P, P], None
+    elif layout == "jet_slip_top":  # free slip meets walls, the inlet and the outflow
+        faces, inlet = [W, W, W, F, I, O], synth.jet_inlet(nx, ny, 4.0, 0.05, 0.002)
+    elif layout == "slip_x_edges":  # free-slip / free-slip and free-slip / outflow edges
+        faces, inlet = [F, F, F, W, I, O], synth.jet_inlet(nx, ny, 4.0, 0.05, 0.002)
+    elif layout == "slip_box":
+        faces, inlet = [F] * 6, None
     else:  # walls two nodes apart in y: no interior rows at all
         faces, inlet = [W, W, W, W, I, O], synth.jet_inlet(nx, 2, 2.0, 0.04, 0.001)
         shape = (nx, 2, nz)
