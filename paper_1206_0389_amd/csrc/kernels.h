@@ -326,7 +326,9 @@ __device__ __forceinline__ int slip_axes(uint32_t fs) {
 // INLET bounce-back, see pull_term) or the outflow ghost plane (index of
 // x - e_I in the z plane). Selects only, no branches, so the loads of all
 // directions can be issued back to back.
-template <int Q, int I, typename S, bool BC>
+// EXT: interior solids or FREESLIP faces may be present (the rules for
+// them are compiled only then: they cost registers in the general kernel).
+template <int Q, int I, typename S, bool BC, bool EXT = true>
 __device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, const Node& n,
                                               uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
@@ -338,10 +340,11 @@ __device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, cons
     // a solid source bounces back like a WALL face at rest (pull_term adds
     // nothing: no face is crossed)
     const uint32_t crossed = n.atface & pull_faces(I);
-    const bool bb = (crossed & (a.bc.wall | a.bc.inlet)) != 0 || ((sb >> I) & 1u) != 0;
+    const bool bb = (crossed & (a.bc.wall | a.bc.inlet)) != 0 || (EXT && ((sb >> I) & 1u) != 0);
     const S* own = F + (size_t)I * N + n.self;
     const S* ghost = (const S*)a.ghost + (size_t)I * (size_t)a.bc.ghost_n +
                      (n.yo[1 - cy(I)] + n.xo[1 - cx(I)]);
+    if constexpr (!EXT) return bb ? own : (crossed ? ghost : normal);
     // specular: f*_k(s) sits in slot opp(k) of s since the even step; where
     // the OUTFLOW face is crossed too (s on the outflow plane, k inward),
     // that slot has a second reader that rewrites it within the odd step,
@@ -377,7 +380,7 @@ __device__ __forceinline__ real pull_term(const BcArgs& b, uint32_t atface, cons
 // bounce-back rule (own slot opp(I), minus the term) and the outflow rule
 // (dropped; a node on the outflow plane also writes the inward population
 // I of its in-plane neighbour, the ghost copy of the next pull).
-template <int Q, int I, typename real, typename S, bool BC>
+template <int Q, int I, typename real, typename S, bool BC, bool EXT = true>
 __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real v,
                                      const real* uin, uint32_t sb) {
   constexpr int IO = opposite<Q>(I);
@@ -396,8 +399,14 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
                                                 real(cz(IO)) * uin[2]);
     const real term = cw ? tw : (ci ? ti : real(0));
     // x + e_I solid (the pull source of opp(I)): bounce back, no term
-    const bool bb = (cw | ci) != 0 || ((sb >> IO) & 1u) != 0;
+    const bool bb = (cw | ci) != 0 || (EXT && ((sb >> IO) & 1u) != 0);
     S* own = F + (size_t)IO * N + n.self;
+    if constexpr (!EXT) {
+      if (bb || !crossed) st(bb ? own : normal, bb ? v + term : v);
+      if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0)
+        st(F + (size_t)I * N + n.at(cx(I), cy(I), 0), v);
+      return;
+    }
     // leaving through FREESLIP faces only (no OUTFLOW): the image k of I
     // arrives at x + e_I with the crossed coordinates kept, slot k
     const uint32_t fs = crossed & a.bc.freeslip;
@@ -519,7 +528,9 @@ __device__ __forceinline__ bool row_coords(const LatArgs& a, const Rows& r, int&
 // is not null, the natural pre-collision state the step collides is also
 // written to rec ([Q][N] in the compute type). The record is a runtime
 // switch, so recording and plain steps run the same code and round alike.
-template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool SOLID = false>
+// EXT: interior solids (wall rows and general kernel) or FREESLIP faces
+// (general kernel) present.
+template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool EXT = false>
 __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r, long long t,
                                                    typename Compute<S>::type* rec) {
   using M = Model<KIND>;
@@ -531,15 +542,14 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   const Node n = make_node(a, x, y, z);
   S* __restrict__ F = (S*)a.f;
   const size_t N = (size_t)a.N;
-  // interior solids (general kernel, or the wall rows with SOLID): solid
-  // nodes are not updated
+  // interior solids: solid nodes are not updated
   uint32_t sb = 0;
-  if constexpr (BC) {
+  if constexpr (BC && EXT) {
     if (a.solid_nb) {
       sb = a.solid_nb[n.self];
       if (sb >> 31) return;
     }
-  } else if constexpr (SOLID) {
+  } else if constexpr (BCM == BC_WALLS && EXT) {
     sb = a.solid_nb[n.self];
     if (sb >> 31) return;
   }
@@ -561,7 +571,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = pull_walls<Q, I, real, cx(I) == 0, SOLID>(a, F, n, sb);
+        f[I] = pull_walls<Q, I, real, cx(I) == 0, EXT>(a, F, n, sb);
       });
     } else if constexpr (BCM == BC_NONE) {
       static_for<0, Q>([&](auto ic) {
@@ -572,7 +582,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     } else {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] = ld<real, !BC && cx(I) == 0>(pull_addr<Q, I, S, BC>(a, F, n, sb));
+        f[I] = ld<real, !BC && cx(I) == 0>(pull_addr<Q, I, S, BC, EXT>(a, F, n, sb));
       });
       if constexpr (BC) {
         const real up[3] = {real(uin_prev[0]), real(uin_prev[1]), real(uin_prev[2])};
@@ -611,13 +621,13 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
     if constexpr (BCM == BC_WALLS) {
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push_walls<Q, I, real, cx(I) == 0, SOLID>(a, F, n, f[I], sb);
+        push_walls<Q, I, real, cx(I) == 0, EXT>(a, F, n, f[I], sb);
       });
     } else {
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push<Q, I, real, S, BC>(a, F, n, f[I], un, sb);
+        push<Q, I, real, S, BC, EXT>(a, F, n, f[I], un, sb);
       });
     }
   }

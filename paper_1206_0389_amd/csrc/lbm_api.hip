@@ -63,25 +63,29 @@ void launch_shape(lbm_lattice* L) {
   L->nblocks = (size_t)L->grid.x * L->grid.y * L->grid.z;
 }
 
-template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool SOLID = false>
+template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool EXT = false>
 void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t,
                  void* rec) {
-  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS, SOLID>), grid, block, 0, L->stream,
+  hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS, EXT>), grid, block, 0, L->stream,
                      L->args, r, t, (typename Compute<S>::type*)rec);
 }
 
-template <int KIND, typename S>
-void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
+template <int KIND, typename S, bool EXT>
+void step_model_ext(const lbm_lattice* L, bool odd, long long t, void* rec) {
   if (!L->has_bc) {
     if (odd)
       launch_step<KIND, S, true, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
     else
       launch_step<KIND, S, false, BC_NONE, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
   } else if (!odd) {
-    launch_step<KIND, S, false, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
+    launch_step<KIND, S, false, BC_GENERAL, ROWS_BOX, EXT>(L, L->grid, L->block, L->rows_all, t,
+                                                           rec);
   } else if (!L->split_odd) {
-    launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX>(L, L->grid, L->block, L->rows_all, t, rec);
+    launch_step<KIND, S, true, BC_GENERAL, ROWS_BOX, EXT>(L, L->grid, L->block, L->rows_all, t,
+                                                          rec);
   } else {
+    // wall rows: the solid variant only with solids (free slip never
+    // reaches them)
     if (L->grid_inner.y > 0 && L->grid_inner.z > 0) {
       if (L->solids)
         launch_step<KIND, S, true, BC_WALLS, ROWS_BOX, true>(L, L->grid_inner, L->block,
@@ -91,9 +95,19 @@ void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
                                                        L->rows_inner, t, rec);
     }
     if (L->grid_bnd.y > 0)
-      launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST>(L, L->grid_bnd, L->block_bnd,
-                                                        L->rows_bnd, t, rec);
+      launch_step<KIND, S, true, BC_GENERAL, ROWS_LIST, EXT>(L, L->grid_bnd, L->block_bnd,
+                                                             L->rows_bnd, t, rec);
   }
+}
+
+// Lattices without interior solids or FREESLIP faces run the general
+// kernel compiled without their rules.
+template <int KIND, typename S>
+void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
+  if (L->solids || L->args.bc.freeslip)
+    step_model_ext<KIND, S, true>(L, odd, t, rec);
+  else
+    step_model_ext<KIND, S, false>(L, odd, t, rec);
 }
 
 template <typename S>
