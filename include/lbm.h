@@ -69,6 +69,7 @@ extern "C" {
 #define LBM_INLET 2          /* halfway bounce-back with inlet velocity   */
 #define LBM_OUTFLOW 3        /* zero-gradient: ghost copy of last plane   */
 #define LBM_FREESLIP 4       /* halfway specular reflection (free slip)   */
+#define LBM_PRESSURE 5       /* fixed pressure: anti-bounce-back          */
 
 #define LBM_RHO_FULL 0       /* lbm_get_macroscopic: write rho            */
 #define LBM_RHO_DEVIATION 1  /* ... write rho - 1                         */
@@ -111,7 +112,8 @@ typedef struct lbm_config {
  * Boundary description, one entry per face in the order
  * x-, x+, y-, y+, z-, z+ (the "-" face holds coordinate 0).
  *   face_type  LBM_PERIODIC | LBM_WALL | LBM_INLET | LBM_OUTFLOW |
- *              LBM_FREESLIP (uniform lattices only). Opposite
+ *              LBM_FREESLIP | LBM_PRESSURE (the last two on uniform
+ *              lattices only). Opposite
  *              faces must both be periodic or both non-periodic.
  *              At most one LBM_INLET face and one LBM_OUTFLOW face; the
  *              outflow face must be a z face (z- or z+).
@@ -127,15 +129,21 @@ typedef struct lbm_config {
  * The streaming rule at a face (population i arriving from outside at
  * node x, post-collision values f*):
  *   WALL, INLET  f_i(x) = f*_opp(i)(x) + 6 w_i (e_i . u)   (u = wall or inlet)
+ *   PRESSURE     f_i(x) = -f*_opp(i)(x) + feq_i + feq_opp(i), the model's
+ *                equilibrium at density 1 + face_drho and the node's own
+ *                velocity (of its state before the step): the fixed-pressure
+ *                outflow of the paper's set-up (Section 3), anti-bounce-back
  *   FREESLIP     f_i(x) = f*_k(x - e_i with the crossed coordinates kept),
  *                k = i with the components normal to the crossed FREESLIP
  *                faces reversed (specular reflection half-way, the
  *                free-slip top of the paper's tank, Section 3)
  *   OUTFLOW      f_i(x) = f*_i(x - e_i with the z coordinate kept)
+ *   face_drho  density deviation rho - 1 of LBM_PRESSURE faces (finite and
+ *              above -1, else LBM_EINVAL; ignored for other faces).
  * Where a source lies beyond several faces, WALL wins over INLET over
- * FREESLIP over OUTFLOW. The inlet buffers must stay valid while the
- * lattice steps. Lattices with FREESLIP faces have no adjoint
- * (lbm_step_record and lbm_adjoint_step refuse them).
+ * PRESSURE over FREESLIP over OUTFLOW. The inlet buffers must stay valid
+ * while the lattice steps. Lattices with FREESLIP or PRESSURE faces have no
+ * adjoint (lbm_step_record and lbm_adjoint_step refuse them).
  */
 typedef struct lbm_boundaries {
   int32_t face_type[6];
@@ -146,6 +154,7 @@ typedef struct lbm_boundaries {
   const uint8_t* inlet_mask;
   double inlet_amp;
   uint64_t seed;
+  double face_drho[6];
 } lbm_boundaries;
 
 /* Validate cfg and create a handle (host memory only). On error *out is

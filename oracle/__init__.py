@@ -34,6 +34,9 @@ Parity status of each oracle function (what pins it, see tests/):
   FREESLIP faces (run)        free-slip y faces equal the mirror-symmetric
                               half of a periodic lattice twice as high;
                               uniform tangential flow is kept exactly
+  PRESSURE faces (run)        plug flow from a velocity inlet to a pressure
+                              outlet is a fixed point; a closed box with a
+                              pressure face relaxes to the face's density
 """
 from __future__ import annotations
 
@@ -49,7 +52,7 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 MRT19, FCLB27 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
-PERIODIC, WALL, INLET, OUTFLOW, FREESLIP = 0, 1, 2, 3, 4
+PERIODIC, WALL, INLET, OUTFLOW, FREESLIP, PRESSURE = 0, 1, 2, 3, 4, 5
 
 DHUMIERES_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 TABLE1_RATES = (1.0, 1.0, 1.0, 1.0)
@@ -83,6 +86,7 @@ class Params(ctypes.Structure):
         ("origin", ctypes.c_int32 * 3),
         ("inlet_na", ctypes.c_int32), ("inlet_nb", ctypes.c_int32),
         ("solid", ctypes.POINTER(ctypes.c_uint8)),
+        ("face_drho", ctypes.c_double * 6),
     ]
 
 
@@ -249,6 +253,7 @@ class Lattice:
     """Configuration of an oracle lattice (or window of one).
 
     faces: six of PERIODIC/WALL/INLET/OUTFLOW for x-, x+, y-, y+, z-, z+.
+    face_drho: density deviation of PRESSURE faces (six values).
     solid: optional [nz][ny][nx] mask of interior solid nodes; a population
     whose source is solid bounces back off a wall at rest, and solid nodes
     keep their (meaningless) populations unchanged.
@@ -257,7 +262,7 @@ class Lattice:
     def __init__(self, model, nx, ny, nz, nu, cs_smag=0.0, basis=BASIS_TABLE1,
                  rates=None, faces=(PERIODIC,) * 6, face_u=None, inlet_u=None,
                  inlet_mask=None, inlet_amp=0.0, seed=0, origin=(0, 0, 0),
-                 inlet_extent=None, solid=None):
+                 inlet_extent=None, solid=None, face_drho=None):
         p = Params()
         p.model = model
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -290,6 +295,9 @@ class Lattice:
         p.seed = seed
         for k in range(3):
             p.origin[k] = origin[k]
+        if face_drho is not None:
+            for k in range(6):
+                p.face_drho[k] = face_drho[k]
         self.solid = None
         if solid is not None:
             sm = np.ascontiguousarray(solid, dtype=np.uint8)
@@ -340,8 +348,8 @@ class Lattice:
             raise ValueError("the oracle's adjoint covers the FCLB model only")
         if self.solid is not None:
             raise ValueError("the oracle's adjoint has no interior solids")
-        if FREESLIP in tuple(self.p.face_type):
-            raise ValueError("the oracle's adjoint has no free-slip faces")
+        if FREESLIP in tuple(self.p.face_type) or PRESSURE in tuple(self.p.face_type):
+            raise ValueError("the oracle's adjoint has no free-slip or pressure faces")
 
     def collide_jvp(self, f, v):
         self._need_fclb()

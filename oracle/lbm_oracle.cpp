@@ -33,7 +33,8 @@ extern "C" {
 
 enum { ORC_MRT19 = 1, ORC_FCLB27 = 2 };
 enum { ORC_BASIS_TABLE1 = 0, ORC_BASIS_DHUMIERES = 1 };
-enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_INLET = 2, ORC_OUTFLOW = 3, ORC_FREESLIP = 4 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_INLET = 2, ORC_OUTFLOW = 3, ORC_FREESLIP = 4,
+       ORC_PRESSURE = 5 };
 
 // Must match the ctypes structure in oracle/__init__.py.
 typedef struct orc_params {
@@ -53,6 +54,7 @@ typedef struct orc_params {
   int32_t origin[3];          // global coordinate of local node (0,0,0)
   int32_t inlet_na, inlet_nb; // global extent of the inlet face arrays
   const uint8_t* solid;       // [N] nonzero = solid node (may be null)
+  double face_drho[6];        // density deviation of PRESSURE faces
 } orc_params;
 
 }  // extern "C"
@@ -451,11 +453,14 @@ inline long node_index(const orc_params* p, int x, int y, int z) {
 //  * beyond FREESLIP faces (and possibly OUTFLOW faces): halfway specular
 //    reflection, f_i = f*_k(s) with k = i mirrored across every crossed
 //    FREESLIP face (its normal component reversed) and s = x - e_i with
-//    every crossed coordinate kept (the node the mirrored population left).
+//    every crossed coordinate kept (the node the mirrored population left);
+//  * beyond a PRESSURE face (fixed pressure): anti-bounce-back, f_i =
+//    -f*_opp(i)(x) + feq_i + feq_opp(i), the model's equilibrium at the
+//    face's density and the node's own velocity (of its state at t).
 // When a source lies beyond several faces, WALL wins over INLET over
-// FREESLIP over OUTFLOW.
+// PRESSURE over FREESLIP over OUTFLOW.
 enum { SRC_NORMAL = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTFLOW = 3, SRC_SOLID = 4,
-       SRC_FREESLIP = 5 };
+       SRC_FREESLIP = 5, SRC_PRESSURE = 6 };
 struct Source {
   int kind;
   long node;  // source node (NORMAL/OUTFLOW/FREESLIP) or the node itself
@@ -497,6 +502,9 @@ Source classify(const orc_params* p, int i, int x, int y, int z) {
   for (int face = 0; face < 6; ++face)
     if (crossed[face] && p->face_type[face] == ORC_INLET)
       return {SRC_INLET, node_index(p, x, y, z), face};
+  for (int face = 0; face < 6; ++face)
+    if (crossed[face] && p->face_type[face] == ORC_PRESSURE)
+      return {SRC_PRESSURE, node_index(p, x, y, z), face};
   for (int d = 0; d < 3; ++d) {
     if (s[d] < 0) s[d] = 0;
     if (s[d] >= n[d]) s[d] = n[d] - 1;
@@ -524,6 +532,27 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
   if (src.kind == SRC_FREESLIP) return fpost[src.face * N + src.node];
   const int io = opposite(Q, i);
   if (src.kind == SRC_SOLID) return fpost[io * N + src.node];
+  if (src.kind == SRC_PRESSURE) {
+    // the node's velocity: momentum and mass are those of its state at t
+    double d = 0.0, j[3] = {0, 0, 0};
+    for (int k = 0; k < Q; ++k) {
+      const double v = fpost[k * N + src.node];
+      d += v;
+      for (int a = 0; a < 3; ++a) j[a] += v * E[k][a];
+    }
+    const double rho = (p->model == ORC_MRT19) ? 1.0 : 1.0 + d;
+    const double ub[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    const double drho = p->face_drho[src.face];
+    double feq[27];
+    if (p->model == ORC_MRT19) {
+      feq_incomp(19, drho, ub, feq);
+    } else {
+      for (int k = 0; k < 27; ++k)
+        feq[k] = (1.0 + drho) * phi(E[k][0], ub[0]) * phi(E[k][1], ub[1]) * phi(E[k][2], ub[2]) -
+                 weight(27, k);
+    }
+    return -fpost[io * N + src.node] + feq[i] + feq[io];
+  }
   double u[3];
   if (src.kind == SRC_WALL) {
     for (int c = 0; c < 3; ++c) u[c] = p->face_u[src.face][c];

@@ -24,7 +24,7 @@ D3Q19_MRT_LES, D3Q27_FCLB = 1, 2
 F64, F32, F16 = 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
-PERIODIC, WALL, INLET, OUTFLOW, FREESLIP = 0, 1, 2, 3, 4
+PERIODIC, WALL, INLET, OUTFLOW, FREESLIP, PRESSURE = 0, 1, 2, 3, 4, 5
 RHO_FULL, RHO_DEVIATION = 0, 1
 
 STORAGE = {"f64": F64, "f32": F32, "f16": F16}
@@ -58,6 +58,7 @@ class Boundaries(ctypes.Structure):
         ("inlet_mask", ctypes.c_void_p),
         ("inlet_amp", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("face_drho", ctypes.c_double * 6),
     ]
 
 
@@ -367,7 +368,9 @@ class Lattice:
         return (self.nz, self.ny, self.nx)
 
     def set_boundaries(self, faces, face_u=None, inlet_u=None, inlet_mask=None,
-                       inlet_amp=0.0, seed=0):
+                       inlet_amp=0.0, seed=0, face_drho=None):
+        """faces: six face types (x-, x+, y-, y+, z-, z+); face_u: WALL
+        velocities; face_drho: density deviations of PRESSURE faces."""
         bc = Boundaries()
         for k in range(6):
             bc.face_type[k] = int(faces[k])
@@ -375,6 +378,9 @@ class Lattice:
             for k in range(6):
                 for c in range(3):
                     bc.face_u[k][c] = float(face_u[k][c])
+        if face_drho is not None:
+            for k in range(6):
+                bc.face_drho[k] = float(face_drho[k])
         keep = []
         dims = (self.nx, self.ny, self.nz)
         if inlet_u is not None:

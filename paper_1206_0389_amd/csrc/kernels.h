@@ -21,13 +21,17 @@
 // a population whose source lies beyond a non-periodic face is
 //   WALL/INLET: bounced back at the half-way point with the wall or inlet
 //               velocity, f_i(x) = f*_opp(i)(x) + 6 w_i e_i.u;
+//   PRESSURE:   anti-bounce-back, f_i(x) = -f*_opp(i)(x) + feq_i + feq_opp(i)
+//               with the model's equilibrium at the face's density and the
+//               node's velocity (of its state at t): fixed pressure;
 //   FREESLIP:   reflected specularly at the half-way point, f_i(x) =
 //               f*_k(s), k = i with the normal component reversed, s = x -
 //               e_i with the crossed coordinates kept;
 //   OUTFLOW:    (a z face) copied from the boundary plane, f_i(x) = f*_i(s),
 //               s = x - e_i with the z coordinate kept (a ghost layer equal
 //               to the last plane: zero normal gradient).
-// (WALL before INLET before FREESLIP before OUTFLOW where faces meet.)
+// (WALL before INLET before PRESSURE before FREESLIP before OUTFLOW where
+// faces meet.)
 // In AA form the bounce-back reads/writes the node's own opposite slot. The
 // outflow copy needs f*_i(s) twice (normal streaming and the ghost), so even
 // steps also store the inward populations of the outflow plane in a small
@@ -51,6 +55,8 @@ struct BcArgs {
   uint32_t inlet;    // bit of the INLET face (0 if none)
   uint32_t outflow;  // bit of the OUTFLOW face (0 if none)
   uint32_t freeslip; // bits of FREESLIP faces
+  uint32_t pressure; // bits of PRESSURE faces
+  double face_drho[6];  // density deviation of PRESSURE faces
   double face_u[6][3];
   const void* inlet_u;
   const uint8_t* inlet_mask;
@@ -302,6 +308,55 @@ __device__ __forceinline__ real wall_term(const BcArgs& b, uint32_t cw) {
   return term;
 }
 
+// Equilibrium (deviation form) of the population with velocity (ex, ey,
+// ez) for the moments d = sum f, j = sum e f: the incompressible
+// polynomial of Eq. (2) for D3Q19 MRT, the product form rho prod_a
+// phi(e_a; u_a) - w of the factorized model for D3Q27 (phi(0) = 2/3 - u^2,
+// phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors).
+template <int KIND, typename R>
+__device__ __forceinline__ R equilibrium_one(R d, const R (&j)[3], int ex, int ey, int ez) {
+  if constexpr (Model<KIND>::Q == 19) {
+    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+    const R eu = R(ex) * j[0] + R(ey) * j[1] + R(ez) * j[2];
+    const int e2 = ex * ex + ey * ey + ez * ez;
+    const R w = e2 == 0 ? R(1.0 / 3.0) : (e2 == 1 ? R(1.0 / 18.0) : R(1.0 / 36.0));
+    return w * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+  } else {
+    const R rho = R(1) + d;
+    const int e[3] = {ex, ey, ez};
+    R p[3], dp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R u = j[c] / rho, q = u * u;
+      p[c] = e[c] == 0 ? R(2.0 / 3.0) : R(1.0 / 6.0);
+      dp[c] = e[c] == 0 ? -q : (e[c] < 0 ? R(0.5) * (q - u) : R(0.5) * (q + u));
+    }
+    const R a0 = p[0], b0 = p[1], c0 = p[2], da = dp[0], db = dp[1], dc = dp[2];
+    const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
+                  a0 * db * dc + da * db * dc;
+    return dev + d * (a0 * b0 * c0 + dev);
+  }
+}
+
+// The fixed-pressure (anti-bounce-back) part of direction I at a PRESSURE
+// face: feq_I + feq_opp(I) at density deviation dout and velocity u.
+template <int KIND, int I, typename real>
+__device__ __forceinline__ real pressure_pair(real dout, const real (&u)[3]) {
+  constexpr int IO = opposite<Model<KIND>::Q>(I);
+  const real s = (Model<KIND>::Q == 19) ? real(1) : real(1) + dout;
+  const real j[3] = {s * u[0], s * u[1], s * u[2]};
+  return equilibrium_one<KIND, real>(dout, j, cx(I), cy(I), cz(I)) +
+         equilibrium_one<KIND, real>(dout, j, cx(IO), cy(IO), cz(IO));
+}
+
+// Density deviation of the lowest face in the mask of crossed PRESSURE faces.
+__device__ __forceinline__ double pressure_drho(const BcArgs& b, uint32_t crossed) {
+  double d = 0.0;
+#pragma unroll
+  for (int F = 5; F >= 0; --F) d = ((crossed >> F) & 1u) ? b.face_drho[F] : d;
+  return d;
+}
+
 // Compile-time table of the images of I across the axes of mask m (bit d:
 // axis d), selected at run time without an indexed array.
 template <int Q, int I, bool OPP>
@@ -359,7 +414,10 @@ __device__ __forceinline__ const S* pull_addr(const LatArgs& a, const S* F, cons
                           (n.yo[(crossed & 12u) ? 1 : 1 - cy(I)] +
                            n.xo[(crossed & 3u) ? 1 : 1 - cx(I)]);
     const bool edge = (crossed & a.bc.outflow) != 0;
-    return bb ? own : (fs ? (edge ? slip_ghost : slip) : (crossed ? ghost : normal));
+    // PRESSURE: anti-bounce-back from the own slot, where the store that
+    // filled it (either parity) left the completed value
+    const bool pr = (crossed & a.bc.pressure) != 0;
+    return (bb || pr) ? own : (fs ? (edge ? slip_ghost : slip) : (crossed ? ghost : normal));
   }
 }
 
@@ -382,7 +440,7 @@ __device__ __forceinline__ real pull_term(const BcArgs& b, uint32_t atface, cons
 // I of its in-plane neighbour, the ghost copy of the next pull).
 template <int Q, int I, typename real, typename S, bool BC, bool EXT = true>
 __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real v,
-                                     const real* uin, uint32_t sb) {
+                                     const real* uin, uint32_t sb, const real* unode) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)a.N;
   if constexpr (!BC) {
@@ -405,6 +463,15 @@ __device__ __forceinline__ void push(const LatArgs& a, S* F, const Node& n, real
       if (bb || !crossed) st(bb ? own : normal, bb ? v + term : v);
       if ((n.atface & a.bc.outflow & pull_faces(I)) && (n.atface & push_faces(I)) == 0)
         st(F + (size_t)I * N + n.at(cx(I), cy(I), 0), v);
+      return;
+    }
+    // leaving through a PRESSURE face: returns as opp(I) into the own slot,
+    // -f*_I + feq_I + feq_opp(I) at the node's velocity
+    if ((crossed & a.bc.pressure) && !bb) {
+      constexpr int KQ = Q == 27 ? 2 : 0;
+      const real u[3] = {unode[0], unode[1], unode[2]};
+      const real dp = real(pressure_drho(a.bc, crossed & a.bc.pressure));
+      st(own, -v + pressure_pair<KQ, I, real>(dp, u));
       return;
     }
     // leaving through FREESLIP faces only (no OUTFLOW): the image k of I
@@ -600,11 +667,39 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       sto<true>(rec + (size_t)I * N, roff, f[I]);
     });
   }
+  // the node's velocity (kept by the collision) for PRESSURE faces
+  real unode[3] = {0, 0, 0};
+  if constexpr (BC && EXT) {
+    if (n.atface & a.bc.pressure) {
+      real d = 0, j[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        d += f[i];
+        j[0] += real(cx(i)) * f[i];
+        j[1] += real(cy(i)) * f[i];
+        j[2] += real(cz(i)) * f[i];
+      }
+      const real rho = Q == 27 ? real(1) + d : real(1);
+      unode[0] = j[0] / rho;
+      unode[1] = j[1] / rho;
+      unode[2] = j[2] / rho;
+    }
+  }
   M::collide(f, a);
   if constexpr (!ODD) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      sto<true>(F + (size_t)opposite<Q>(I) * N, self_off, f[I]);
+      real v = f[I];
+      // leaving through a PRESSURE face: the own slot opp(I) takes the
+      // anti-bounce-back value the next pull reads as it is
+      if constexpr (BC && EXT) {
+        constexpr int KQ = Q == 27 ? 2 : 0;
+        const uint32_t crossed = n.atface & push_faces(I);
+        if ((crossed & a.bc.pressure) && !(crossed & (a.bc.wall | a.bc.inlet)))
+          v = -v + pressure_pair<KQ, I, real>(
+                       real(pressure_drho(a.bc, crossed & a.bc.pressure)), unode);
+      }
+      sto<true>(F + (size_t)opposite<Q>(I) * N, self_off, v);
     });
     if constexpr (BC) {
       if (n.atface & a.bc.outflow) {
@@ -627,7 +722,7 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
       const real un[3] = {real(uin_now[0]), real(uin_now[1]), real(uin_now[2])};
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        push<Q, I, real, S, BC, EXT>(a, F, n, f[I], un, sb);
+        push<Q, I, real, S, BC, EXT>(a, F, n, f[I], un, sb, unode);
       });
     }
   }

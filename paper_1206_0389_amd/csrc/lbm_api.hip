@@ -100,11 +100,11 @@ void step_model_ext(const lbm_lattice* L, bool odd, long long t, void* rec) {
   }
 }
 
-// Lattices without interior solids or FREESLIP faces run the general
-// kernel compiled without their rules.
+// Lattices without interior solids, FREESLIP or PRESSURE faces run the
+// general kernel compiled without their rules.
 template <int KIND, typename S>
 void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
-  if (L->solids || L->args.bc.freeslip)
+  if (L->solids || L->args.bc.freeslip || L->args.bc.pressure)
     step_model_ext<KIND, S, true>(L, odd, t, rec);
   else
     step_model_ext<KIND, S, false>(L, odd, t, rec);
@@ -349,7 +349,7 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
   int n_inlet = 0, n_out = 0;
   for (int f = 0; f < 6; ++f) {
     const int ty = bc->face_type[f];
-    if (ty < LBM_PERIODIC || ty > LBM_FREESLIP) return LBM_EINVAL;
+    if (ty < LBM_PERIODIC || ty > LBM_PRESSURE) return LBM_EINVAL;
     if (ty != LBM_PERIODIC) {
       b.nonper |= 1u << f;
       if (n3[f / 2] < 2) return LBM_EINVAL;
@@ -360,6 +360,11 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
     }
     if (ty == LBM_WALL) b.wall |= 1u << f;
     if (ty == LBM_FREESLIP) b.freeslip |= 1u << f;
+    if (ty == LBM_PRESSURE) {
+      if (!std::isfinite(bc->face_drho[f]) || !(bc->face_drho[f] > -1.0)) return LBM_EINVAL;
+      b.pressure |= 1u << f;
+      b.face_drho[f] = bc->face_drho[f];
+    }
     if (ty == LBM_INLET) {
       b.inlet |= 1u << f;
       b.inlet_axis = f / 2;
@@ -471,7 +476,8 @@ int lbm_step(lbm_lattice* L, int64_t n) {
 int lbm_step_record(lbm_lattice* L, void* rec, int dtype) {
   if (!L || !rec || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;
-  if (L->kind != 2 || L->cfg.storage == LBM_F16 || L->solids || L->args.bc.freeslip)
+  if (L->kind != 2 || L->cfg.storage == LBM_F16 || L->solids || L->args.bc.freeslip ||
+      L->args.bc.pressure)
     return LBM_EINVAL;
   if (dtype != (L->cfg.storage == LBM_F64 ? LBM_DTYPE_F64 : LBM_DTYPE_F32)) return LBM_EINVAL;
   step_record_dispatch(L, L->parity == 1, (long long)L->t, rec);
@@ -677,7 +683,8 @@ int lbm_probe_ke(lbm_lattice* L, const int32_t lo[3], const int32_t hi[3], void*
 int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, void* lambda,
                      int dtype, double* grad_inlet) {
   if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
-  if (L->kind != 2 || L->solids || L->args.bc.freeslip) return LBM_EINVAL;
+  if (L->kind != 2 || L->solids || L->args.bc.freeslip || L->args.bc.pressure)
+    return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
   // the kernels address the adjoint arrays with 32-bit byte offsets: one
   // slab must stay below 4 GiB, and the wall rows (a population and its

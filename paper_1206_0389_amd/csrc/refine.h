@@ -175,36 +175,6 @@ __device__ __forceinline__ real ab_pull_walls(const Level& L, const S* A, const 
   }
 }
 
-// Equilibrium (deviation form) of the population with velocity (ex, ey,
-// ez) for the moments d = sum f, j = sum e f: the incompressible
-// polynomial of Eq. (2) for D3Q19 MRT, the product form rho prod_a
-// phi(e_a; u_a) - w of the factorized model for D3Q27 (phi(0) = 2/3 - u^2,
-// phi(+-1) = (1/3 + u^2 +- u)/2, expanded about the rest factors).
-template <int KIND, typename R>
-__device__ __forceinline__ R equilibrium_one(R d, const R (&j)[3], int ex, int ey, int ez) {
-  if constexpr (Model<KIND>::Q == 19) {
-    const R uu = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
-    const R eu = R(ex) * j[0] + R(ey) * j[1] + R(ez) * j[2];
-    const int e2 = ex * ex + ey * ey + ez * ez;
-    const R w = e2 == 0 ? R(1.0 / 3.0) : (e2 == 1 ? R(1.0 / 18.0) : R(1.0 / 36.0));
-    return w * (d + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-  } else {
-    const R rho = R(1) + d;
-    const int e[3] = {ex, ey, ez};
-    R p[3], dp[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const R u = j[c] / rho, q = u * u;
-      p[c] = e[c] == 0 ? R(2.0 / 3.0) : R(1.0 / 6.0);
-      dp[c] = e[c] == 0 ? -q : (e[c] < 0 ? R(0.5) * (q - u) : R(0.5) * (q + u));
-    }
-    const R a0 = p[0], b0 = p[1], c0 = p[2], da = dp[0], db = dp[1], dc = dp[2];
-    const R dev = da * b0 * c0 + a0 * db * c0 + a0 * b0 * dc + da * db * c0 + da * b0 * dc +
-                  a0 * db * dc + da * db * dc;
-    return dev + d * (a0 * b0 * c0 + dev);
-  }
-}
-
 // Equilibrium of the model (deviation form) for the moments of f.
 template <int KIND, typename R>
 __device__ __forceinline__ void equilibrium_dev(const R (&f)[Model<KIND>::Q],

@@ -22,7 +22,7 @@ def face_velocities(coflow=0.002, axis=2):
 
 
 def gpu_lattice(name, storage, shape, nu, cs=0.0, rates=None, faces=None, face_u=None,
-                inlet=None, amp=0.0, seed=0):
+                inlet=None, amp=0.0, seed=0, face_drho=None):
     import torch
     import paper_1206_0389_amd as P
     model, basis = MODELS[name]
@@ -34,17 +34,19 @@ def gpu_lattice(name, storage, shape, nu, cs=0.0, rates=None, faces=None, face_u
             iu = torch.from_numpy(np.ascontiguousarray(inlet[0], dtype=np.float64))
             im = torch.from_numpy(np.ascontiguousarray(inlet[1], dtype=np.uint8))
         lat.set_boundaries(faces, face_u=face_u, inlet_u=iu, inlet_mask=im, inlet_amp=amp,
-                           seed=seed)
+                           seed=seed, face_drho=face_drho)
     return lat
 
 
 def oracle_lattice(name, shape, nu, cs=0.0, rates=None, faces=None, face_u=None, inlet=None,
-                   amp=0.0, seed=0, origin=(0, 0, 0), extent=None):
+                   amp=0.0, seed=0, origin=(0, 0, 0), extent=None, face_drho=None):
     model, basis = MODELS[name]
     nx, ny, nz = shape
     kw = {}
     if faces is not None:
         kw = dict(faces=faces, face_u=face_u, inlet_amp=amp, seed=seed, origin=origin)
+        if face_drho is not None:
+            kw["face_drho"] = face_drho
         if inlet is not None:
             kw.update(inlet_u=inlet[0], inlet_mask=inlet[1])
             if extent is not None:

@@ -137,7 +137,15 @@ def test_boundary_validation(P):
     assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
     bc.face_type[2], bc.face_type[3] = P.FREESLIP, P.WALL  # free-slip top, wall bottom
     assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
-    bc.face_type[3] = 5  # no such face type
+    bc.face_type[3] = P.PRESSURE  # fixed-pressure face at density deviation 0.01
+    bc.face_drho[3] = 0.01
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.OK
+    bc.face_drho[3] = -1.0  # non-positive density
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.face_drho[3] = float("nan")
+    assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
+    bc.face_drho[3] = 0.0
+    bc.face_type[3] = 6  # no such face type
     assert P.lib().lbm_set_boundaries(h, ctypes.byref(bc)) == P.EINVAL
     bc.face_type[2] = bc.face_type[3] = P.WALL
     bc.face_type[4], bc.face_type[5] = P.WALL, P.WALL

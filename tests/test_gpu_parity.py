@@ -23,6 +23,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 TOL = {"f64": 1e-12, "f32": 4e-6, "f16": 2e-3}
 F = oracle.FREESLIP
+PR = oracle.PRESSURE
 NAMES = list(MODELS)
 
 
@@ -31,15 +32,15 @@ def _say(*a):
 
 
 def _run_pair(name, storage, shape, nu, steps, cs=0.1, faces=None, face_u=None, inlet=None,
-              amp=0.0, seed=0, t0=0, f0=None, rates=None):
+              amp=0.0, seed=0, t0=0, f0=None, rates=None, face_drho=None):
     nx, ny, nz = shape
     Q = 19 if MODELS[name][0] == oracle.MRT19 else 27
     _say("case", name, storage, shape, "steps", steps, "faces", faces)
     f = f0 if f0 is not None else synth.random_populations(Q, (nz, ny, nx), amp=1e-2, seed=11)
     g = gpu_lattice(name, storage, shape, nu, cs=cs, rates=rates, faces=faces, face_u=face_u,
-                    inlet=inlet, amp=amp, seed=seed)
+                    inlet=inlet, amp=amp, seed=seed, face_drho=face_drho)
     o = oracle_lattice(name, shape, nu, cs=cs, rates=rates, faces=faces, face_u=face_u,
-                       inlet=inlet, amp=amp, seed=seed)
+                       inlet=inlet, amp=amp, seed=seed, face_drho=face_drho)
     g.set_populations(torch.from_numpy(f), t0)
     snaps = []
     for k in steps:
@@ -63,7 +64,8 @@ def test_periodic_step_parity_fp64(name, shape):
 @pytest.mark.parametrize("name", NAMES)
 @pytest.mark.parametrize("layout", ["jet", "zoutflow_lo", "x_inlet", "y_inlet_walls",
                                     "xwalls_only", "channel_thin", "freeslip_y", "jet_slip_top",
-                                    "slip_x_edges", "slip_box"])
+                                    "slip_x_edges", "slip_box", "jet_pressure", "pressure_x",
+                                    "pressure_slip_outflow", "pressure_box"])
 def test_boundary_step_parity_fp64(name, layout):
     fu = face_velocities(0.002)
     fu[4] = [0.0, 0.0, 0.0]
@@ -88,11 +90,20 @@ def test_boundary_step_parity_fp64(name, layout):
         faces, inlet = [F, F, F, W, I, O], synth.jet_inlet(nx, ny, 4.0, 0.05, 0.002)
     elif layout == "slip_box":
         faces, inlet = [F] * 6, None
+    elif layout == "jet_pressure":  # fixed-pressure outlet, edges with walls and the inlet
+        faces, inlet = [W, W, W, W, I, PR], synth.jet_inlet(nx, ny, 4.0, 0.05, 0.002)
+    elif layout == "pressure_x":  # pressure drop along x, edges with walls and the outflow
+        faces, inlet = [PR, PR, P, P, W, O], None
+    elif layout == "pressure_slip_outflow":  # pressure meets free slip, a wall, the outflow
+        faces, inlet = [PR, W, F, F, O, PR], None
+    elif layout == "pressure_box":
+        faces, inlet = [PR] * 6, None
     else:  # walls two nodes apart in y: no interior rows at all
         faces, inlet = [W, W, W, W, I, O], synth.jet_inlet(nx, 2, 2.0, 0.04, 0.001)
         shape = (nx, 2, nz)
     errs = _run_pair(name, "f64", shape, 0.02, [1, 2, 6], faces=faces, face_u=fu, inlet=inlet,
-                     amp=5e-4, seed=12060389, t0=3)
+                     amp=5e-4, seed=12060389, t0=3,
+                     face_drho=[0.002, -0.001, 0.003, -0.002, 0.001, -0.003])
     assert max(errs) <= TOL["f64"], errs
 
 
