@@ -37,6 +37,9 @@ Parity status of each oracle function (what pins it, see tests/):
   PRESSURE faces (run)        plug flow from a velocity inlet to a pressure
                               outlet is a fixed point; a closed box with a
                               pressure face relaxes to the face's density
+  interpolated bounce-back    q = 1/2 is the halfway rule; steady Couette
+  (run, link_q)               flow puts the no-slip point at the wall's
+                              distance q (halfway: at 1/2)
 """
 from __future__ import annotations
 
@@ -87,6 +90,7 @@ class Params(ctypes.Structure):
         ("inlet_na", ctypes.c_int32), ("inlet_nb", ctypes.c_int32),
         ("solid", ctypes.POINTER(ctypes.c_uint8)),
         ("face_drho", ctypes.c_double * 6),
+        ("link_q", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -257,12 +261,15 @@ class Lattice:
     solid: optional [nz][ny][nx] mask of interior solid nodes; a population
     whose source is solid bounces back off a wall at rest, and solid nodes
     keep their (meaningless) populations unchanged.
+    link_q: optional [Q][nz][ny][nx] wall distances of the links from fluid
+    node x towards solid x + e_i, as fractions of the link (0: halfway);
+    those links bounce back with Bouzidi's linear interpolation.
     """
 
     def __init__(self, model, nx, ny, nz, nu, cs_smag=0.0, basis=BASIS_TABLE1,
                  rates=None, faces=(PERIODIC,) * 6, face_u=None, inlet_u=None,
                  inlet_mask=None, inlet_amp=0.0, seed=0, origin=(0, 0, 0),
-                 inlet_extent=None, solid=None, face_drho=None):
+                 inlet_extent=None, solid=None, face_drho=None, link_q=None):
         p = Params()
         p.model = model
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -305,6 +312,11 @@ class Lattice:
             self._keep.append(sm)
             self.solid = sm
             p.solid = sm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if link_q is not None:
+            lq = _f64(link_q)
+            assert lq.shape == (q_of(model), nz, ny, nx)
+            self._keep.append(lq)
+            p.link_q = _dp(lq)
         self.p = p
         self.model = model
         self.Q = q_of(model)

@@ -55,6 +55,9 @@ typedef struct orc_params {
   int32_t inlet_na, inlet_nb; // global extent of the inlet face arrays
   const uint8_t* solid;       // [N] nonzero = solid node (may be null)
   double face_drho[6];        // density deviation of PRESSURE faces
+  const double* link_q;       // [Q][N] wall distance of the link from node x
+                              // towards the solid x + e_i, as a fraction of
+                              // the link (0 or null: halfway)
 } orc_params;
 
 }  // extern "C"
@@ -448,8 +451,15 @@ inline long node_index(const orc_params* p, int x, int y, int z) {
 //  * beyond an INLET face: the same with the inlet velocity at the node;
 //  * beyond OUTFLOW faces only: the post-collision value of the nearest
 //    boundary node (a ghost layer copying the last plane);
-//  * a solid node inside the domain: halfway bounce-back off a wall at
-//    rest, f_i = f*_opp(i)(x) (the same rule as a WALL face with u_w = 0);
+//  * a solid node inside the domain: bounce-back off a wall at rest. With
+//    no link distance (or q = 1/2) halfway, f_i = f*_opp(i)(x), the same
+//    rule as a WALL face with u_w = 0; otherwise Bouzidi's linear
+//    interpolation along the link (k = opp(i), the direction from x to the
+//    wall, q its distance fraction):
+//      q < 1/2:  f_i(x) = 2q f*_k(x) + (1 - 2q) f*_k(x - e_k)
+//      q >= 1/2: f_i(x) = f*_k(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+//    where x - e_k must be a fluid node inside the domain (periodic axes
+//    wrap); where it is not, the halfway rule stays;
 //  * beyond FREESLIP faces (and possibly OUTFLOW faces): halfway specular
 //    reflection, f_i = f*_k(s) with k = i mirrored across every crossed
 //    FREESLIP face (its normal component reversed) and s = x - e_i with
@@ -531,7 +541,24 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
   if (src.kind == SRC_NORMAL || src.kind == SRC_OUTFLOW) return fpost[i * N + src.node];
   if (src.kind == SRC_FREESLIP) return fpost[src.face * N + src.node];
   const int io = opposite(Q, i);
-  if (src.kind == SRC_SOLID) return fpost[io * N + src.node];
+  if (src.kind == SRC_SOLID) {
+    const double fk = fpost[io * N + src.node];
+    const double q = p->link_q ? p->link_q[io * N + src.node] : 0.0;
+    if (!(q > 0.0 && q <= 1.0) || q == 0.5) return fk;
+    // the fluid node behind x along the link (x - e_k = x + e_i)
+    const int n[3] = {p->nx, p->ny, p->nz};
+    int b[3] = {x + E[i][0], y + E[i][1], z + E[i][2]};
+    for (int d = 0; d < 3; ++d) {
+      if (b[d] >= 0 && b[d] < n[d]) continue;
+      const int face = b[d] < 0 ? 2 * d : 2 * d + 1;
+      if (p->face_type[face] != ORC_PERIODIC) return fk;
+      b[d] = (b[d] + n[d]) % n[d];
+    }
+    const long behind = node_index(p, b[0], b[1], b[2]);
+    if (p->solid && p->solid[behind]) return fk;
+    if (q < 0.5) return 2.0 * q * fk + (1.0 - 2.0 * q) * fpost[io * N + behind];
+    return fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fpost[i * N + src.node];
+  }
   if (src.kind == SRC_PRESSURE) {
     // the node's velocity: momentum and mass are those of its state at t
     double d = 0.0, j[3] = {0, 0, 0};
