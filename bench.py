@@ -76,7 +76,7 @@ def workload(name):
     kind, model, storage = name.split("-")
     shapes = {"jet256": (256, 256, 512), "tgv256": (256, 256, 512), "tgv128": (128, 128, 128),
               "jet128": (128, 128, 256), "ref128": (128, 128, 256),
-              "nozzle256": (256, 256, 512)}
+              "nozzle256": (256, 256, 512), "nozzlecurved256": (256, 256, 512)}
     return model, storage, shapes[kind], kind
 
 
@@ -163,6 +163,17 @@ def make_lattice(name, P, torch, synth):
             sm = nozzle_mask(nx, ny, nz, diam)
             lat.set_solids(torch.from_numpy(sm))
             extra = ", solid nozzle tube (wall 2, length 16, %d solid nodes)" % int(sm.sum())
+        if kind == "nozzlecurved256":
+            # the tube's round surfaces as curved walls: wall distances of
+            # every fluid-solid link, found in a box around the tube
+            m = int(diam) // 2 + 4
+            box = (18, 2 * m, 2 * m)
+            org = (nx // 2 - m, ny // 2 - m, 0)
+            _, nodes, q = synth.link_distances(synth.nozzle_tube(nx, ny, diam, 2.0, 16.0), box,
+                                               P.VELOCITIES[:lat.Q], origin=org,
+                                               full_shape=(nz, ny, nx))
+            lat.set_links(torch.from_numpy(nodes), torch.from_numpy(q))
+            extra += ", interpolated bounce-back on %d nodes" % len(nodes)
         desc = {"workload": "round jet %dx%dx%d, D=%d inlet u=0.05 +1%% seeded perturbation, "
                             "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4%s"
                             % (nx, ny, nz, int(diam), extra),
@@ -369,7 +380,7 @@ def main():
         for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-mrt-f32", "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
-                     "ref128-mrt-f32", "nozzle256-fclb-f32"]:
+                     "ref128-mrt-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:
             if name == args.workload:
                 continue
             r = measure(name, P, torch, synth, args.other_steps, 10)

@@ -212,6 +212,32 @@ int lbm_get_populations(lbm_lattice* lat, void* f, int dtype);
  * calls (lbm_step_record, lbm_adjoint_step) refuse a lattice with solids. */
 int lbm_set_solids(lbm_lattice* lat, const uint8_t* solid, uint32_t* masks);
 
+/* Curved no-slip walls (the second-order interpolated walls of the paper's
+ * nozzle, Section 3): Bouzidi's linear interpolated bounce-back on links from
+ * fluid nodes to the solid nodes set by lbm_set_solids. For a link from fluid
+ * node x towards the solid x + e_k whose wall lies at the fraction q of the
+ * link, with i = opp(k) the returning direction:
+ *   q <  1/2:  f_i(x) = 2q f*_k(x) + (1 - 2q) f*_k(x - e_k)
+ *   q >= 1/2:  f_i(x) = f*_k(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+ * replacing the halfway value f*_k(x). Where x - e_k is not a fluid node
+ * inside the domain (solid, or beyond a non-periodic face), the halfway
+ * value stays.
+ *   nodes  device int32 [n]: linear node indices x + nx (y + ny z) of the
+ *          fluid nodes that have links, each at most once (a repeated node
+ *          gives unspecified results).
+ *   q      device float [n][Q]: q[j][k] is the wall distance of the link of
+ *          nodes[j] in direction k (ABI order); entries outside (0, 1], or
+ *          in a direction whose neighbour is not solid, are ignored (q = 1/2
+ *          is the halfway rule itself).
+ * Both buffers are owned by the caller and read by every later step: they
+ * must stay allocated and unchanged until the links are cleared (n = 0),
+ * lbm_set_solids or lbm_set_boundaries is called (both clear them) or the
+ * lattice is destroyed. Indices outside [0, N) and solid nodes are skipped.
+ * Each step then runs one extra kernel over the n listed nodes.
+ * Errors: LBM_EINVAL (n < 0 or n >= 2^31, n > 0 with NULL buffers or no
+ * solids set), LBM_EUNBOUND, LBM_ESTATE (odd in-place parity). */
+int lbm_set_links(lbm_lattice* lat, const int32_t* nodes, const float* q, int64_t n);
+
 /* Advance n >= 0 collide-and-stream steps (asynchronous). */
 int lbm_step(lbm_lattice* lat, int64_t n);
 

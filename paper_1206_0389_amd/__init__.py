@@ -25,6 +25,13 @@ F64, F32, F16 = 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
 PERIODIC, WALL, INLET, OUTFLOW, FREESLIP, PRESSURE = 0, 1, 2, 3, 4, 5
+
+# The ABI's velocity order (the tables of Section 2; D3Q19 is the first 19),
+# e.g. for the direction index of the wall distances given to set_links.
+VELOCITIES = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+              (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+              (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1), (1, 1, 1), (-1, 1, 1),
+              (1, -1, 1), (1, 1, -1), (-1, -1, 1), (-1, 1, -1), (1, -1, -1), (-1, -1, -1))
 RHO_FULL, RHO_DEVIATION = 0, 1
 
 STORAGE = {"f64": F64, "f32": F32, "f16": F16}
@@ -78,6 +85,7 @@ _SIGS = {
     "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_set_links": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
     "lbm_stats_finalize": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                            ctypes.c_int, ctypes.c_int],
@@ -233,6 +241,17 @@ def set_solids(h, solid, masks):
     if solid.dtype != torch.uint8 or masks.dtype != torch.int32 or masks.numel() != solid.numel():
         raise TypeError("solid must be uint8 and masks int32 of the same size")
     _check(lib().lbm_set_solids(h, _dev(solid), _dev(masks)), "lbm_set_solids")
+
+
+def set_links(h, nodes, q):
+    if nodes is None:
+        _check(lib().lbm_set_links(h, None, None, 0), "lbm_set_links")
+        return
+    if nodes.dtype != torch.int32 or q.dtype != torch.float32:
+        raise TypeError("nodes must be int32 and q float32")
+    if q.dim() != 2 or q.shape[0] != nodes.numel():
+        raise TypeError("q must be [n][Q] for n nodes")
+    _check(lib().lbm_set_links(h, _dev(nodes), _dev(q), int(nodes.numel())), "lbm_set_links")
 
 
 def stats_accumulate(h, sums: torch.Tensor):
@@ -405,7 +424,8 @@ class Lattice:
         bc.seed = int(seed)
         set_boundaries(self.h, bc)
         self._keep = keep
-        self._solid_bufs = None  # new boundaries clear the solids
+        self._solid_bufs = None  # new boundaries clear the solids and links
+        self._link_bufs = None
 
     def _expect(self, t, shape, what):
         if tuple(t.shape) != tuple(shape):
@@ -447,13 +467,31 @@ class Lattice:
         if solid is None:
             set_solids(self.h, None, None)
             self._solid_bufs = None
+            self._link_bufs = None
             return
         solid = torch.as_tensor(solid).to(device=self.device, dtype=torch.uint8).contiguous()
         self._expect(solid, self.shape3, "solid")
         masks = torch.empty(self.shape3, dtype=torch.int32, device=self.device)
         self._solid_bufs = None
+        self._link_bufs = None
         set_solids(self.h, solid, masks)
         self._solid_bufs = (solid, masks)
+
+    def set_links(self, nodes, q):
+        """Curved walls: Bouzidi's interpolated bounce-back on the links of
+        the listed fluid nodes (int32 linear indices x + nx (y + ny z)) to
+        solid neighbours, q[j][k] the wall's distance along direction k as a
+        fraction of the link (other entries ignored); None clears them. The
+        solids must be set first; the buffers are kept by this object."""
+        if nodes is None:
+            set_links(self.h, None, None)
+            self._link_bufs = None
+            return
+        nodes = torch.as_tensor(nodes).to(device=self.device, dtype=torch.int32).contiguous()
+        q = torch.as_tensor(q).to(device=self.device, dtype=torch.float32).contiguous()
+        self._expect(q, (nodes.numel(), self.Q), "q")
+        set_links(self.h, nodes, q)
+        self._link_bufs = (nodes, q)
 
     def stats_buffer(self):
         """Zeroed FP64 running sums for stats_accumulate ([6][nz][ny][nx])."""

@@ -781,6 +781,58 @@ __global__ __launch_bounds__(256) void solid_mask_kernel(const LatArgs a, const 
   if ((m >> 31) && (n.atface & a.bc.outflow)) flag[0] = 1;
 }
 
+// Bouzidi's linear interpolated bounce-back (the curved no-slip walls of
+// the paper's nozzle, Section 3) on the links from listed fluid nodes x to
+// solid neighbours x + e_K, run right after a step over the slot the halfway
+// rule filled. With q the wall's distance along the link (fraction of it)
+// and I = opp(K) the returning direction:
+//   q < 1/2:  f_I(x) = 2q f*_K(x) + (1 - 2q) f*_K(x - e_K)
+//   q >= 1/2: f_I(x) = f*_K(x) / (2q) + (2q - 1)/(2q) f*_I(x)
+// In AA form each value sits in a known slot: f*_K(x) in slot opp(K) of x
+// (the halfway value, replaced here) after either step; after an even step
+// f*_K(x - e_K) is in slot opp(K) of x - e_K and f*_I(x) in slot K of x,
+// after an odd step the other way round. A link needs x - e_K to be a fluid
+// node inside the domain, else the halfway value stays. No other node's
+// links touch these slots (x + e_K is solid), and a node reads all its
+// links' values before it writes any.
+template <int Q, typename S, bool AFTER_ODD>
+__global__ __launch_bounds__(256) void link_kernel(const LatArgs a, const int32_t* nodes,
+                                                   const float* q, long long n) {
+  using real = typename Compute<S>::type;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int self = nodes[k];
+  if (self < 0 || (long long)self >= a.N) return;
+  const uint32_t sb = a.solid_nb[self];
+  if (sb >> 31) return;
+  const Node nd = make_node(a, self % a.nx, (self / a.nx) % a.ny, self / (a.nx * a.ny));
+  S* F = (S*)a.f;
+  const size_t N = (size_t)a.N;
+  const float* qk = q + (size_t)k * Q;
+  real v[Q];
+  uint32_t act = 0;
+  static_for<1, Q>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int KO = opposite<Q>(K);
+    const float d = qk[K];
+    const bool link = ((sb >> KO) & 1u) && !((sb >> K) & 1u) &&
+                      (nd.atface & pull_faces(K)) == 0 && d > 0.f && d <= 1.f && d != 0.5f;
+    if (link) {
+      const int b = nd.at(-cx(K), -cy(K), -cz(K));
+      const real A = ld<real>(F + (size_t)KO * N + self);
+      const real B = ld<real>(AFTER_ODD ? F + (size_t)K * N + self : F + (size_t)KO * N + b);
+      const real C = ld<real>(AFTER_ODD ? F + (size_t)KO * N + b : F + (size_t)K * N + self);
+      const real t = real(2) * real(d);
+      v[K] = d < 0.5f ? t * A + (real(1) - t) * B : A / t + (t - real(1)) / t * C;
+      act |= 1u << K;
+    }
+  });
+  static_for<1, Q>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if ((act >> K) & 1u) st(F + (size_t)opposite<Q>(K) * N + self, v[K]);
+  });
+}
+
 template <int Q, typename S, bool BC, typename O>
 __global__ __launch_bounds__(256) void get_populations_kernel(const LatArgs a, int parity,
                                                               long long t, O* out) {

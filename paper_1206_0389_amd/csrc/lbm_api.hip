@@ -32,6 +32,10 @@ struct lbm_lattice {
   int parity = 0;
   bool has_bc = false;
   bool solids = false;  // interior solid nodes set (general kernel only)
+  // interpolated bounce-back links (caller-owned device buffers)
+  const int32_t* link_nodes = nullptr;
+  const float* link_q = nullptr;
+  long long nlinks = 0;
   LatArgs args;
   dim3 grid, block;
   // odd steps with boundaries split into wall rows (x and y faces walls or
@@ -124,6 +128,33 @@ void step_dispatch(lbm_lattice* L, bool odd, long long t) {
     case LBM_F64: step_dispatch_s<double>(L, odd, t); break;
     case LBM_F32: step_dispatch_s<float>(L, odd, t); break;
     default: step_dispatch_s<_Float16>(L, odd, t); break;
+  }
+}
+
+// Interpolated bounce-back over the link list after a step.
+template <typename S>
+void links_dispatch_s(const lbm_lattice* L, bool after_odd) {
+  const dim3 grid((unsigned)((L->nlinks + 255) / 256)), block(256);
+  auto go = [&](auto q_c, auto odd_c) {
+    constexpr int Q = decltype(q_c)::value;
+    constexpr bool ODD = decltype(odd_c)::value;
+    hipLaunchKernelGGL((link_kernel<Q, S, ODD>), grid, block, 0, L->stream, L->args,
+                       L->link_nodes, L->link_q, L->nlinks);
+  };
+  if (L->Q == 27) {
+    if (after_odd) go(std::integral_constant<int, 27>{}, std::true_type{});
+    else go(std::integral_constant<int, 27>{}, std::false_type{});
+  } else {
+    if (after_odd) go(std::integral_constant<int, 19>{}, std::true_type{});
+    else go(std::integral_constant<int, 19>{}, std::false_type{});
+  }
+}
+
+void links_dispatch(const lbm_lattice* L, bool after_odd) {
+  switch (L->cfg.storage) {
+    case LBM_F64: links_dispatch_s<double>(L, after_odd); break;
+    case LBM_F32: links_dispatch_s<float>(L, after_odd); break;
+    default: links_dispatch_s<_Float16>(L, after_odd); break;
   }
 }
 
@@ -397,8 +428,11 @@ int lbm_set_boundaries(lbm_lattice* L, const lbm_boundaries* bc) {
   if (n_out) b.ghost_n = (long long)n3[0] * n3[1];
   fill_wall_terms(b, L->Q);
   L->args.bc = b;
-  L->args.solid_nb = nullptr;  // new boundaries clear the solids
+  L->args.solid_nb = nullptr;  // new boundaries clear the solids and links
   L->solids = false;
+  L->link_nodes = nullptr;
+  L->link_q = nullptr;
+  L->nlinks = 0;
   L->has_bc = b.nonper != 0;
   plan_rows(L);
   return LBM_OK;
@@ -467,6 +501,7 @@ int lbm_step(lbm_lattice* L, int64_t n) {
   if (!L->base) return LBM_EUNBOUND;
   for (int64_t k = 0; k < n; ++k) {
     step_dispatch(L, L->parity == 1, (long long)L->t);
+    if (L->nlinks > 0) links_dispatch(L, L->parity == 1);
     L->t += 1;
     L->parity ^= 1;
   }
@@ -513,6 +548,9 @@ int lbm_set_solids(lbm_lattice* L, const uint8_t* solid, uint32_t* masks) {
   if (L->parity != 0) return LBM_ESTATE;
   L->args.solid_nb = nullptr;
   L->solids = false;
+  L->link_nodes = nullptr;  // new solids clear the links
+  L->link_q = nullptr;
+  L->nlinks = 0;
   L->has_bc = L->args.bc.nonper != 0;
   if (solid) {
     if (!masks) return LBM_EINVAL;
@@ -541,6 +579,17 @@ int lbm_set_solids(lbm_lattice* L, const uint8_t* solid, uint32_t* masks) {
     L->has_bc = true;
   }
   plan_rows(L);
+  return LBM_OK;
+}
+
+int lbm_set_links(lbm_lattice* L, const int32_t* nodes, const float* q, int64_t n) {
+  if (!L || n < 0 || n >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  if (L->parity != 0) return LBM_ESTATE;
+  if (n > 0 && (!nodes || !q || !L->solids)) return LBM_EINVAL;
+  L->link_nodes = n > 0 ? nodes : nullptr;
+  L->link_q = n > 0 ? q : nullptr;
+  L->nlinks = n;
   return LBM_OK;
 }
 

@@ -157,3 +157,62 @@ def tiled_populations(q: int, shape, amp: float = 1e-2, seed: int = 0, period=(3
     xs = np.arange(lo[0], hi[0]) % period[2]
     qsel = range(q) if qs is None else qs
     return np.stack([base[k][np.ix_(zs, ys, xs)] for k in qsel])
+
+
+def link_distances(is_solid, shape, dirs, iters: int = 40, origin=(0, 0, 0), full_shape=None):
+    """Solid nodes and wall distances of a body given by a point predicate.
+
+    is_solid(x, y, z) takes float coordinate arrays (node (i, j, k) sits at
+    (i, j, k)) and returns a bool array. dirs: the velocity table, a list of
+    (ex, ey, ez). A link runs from a fluid node p to an in-domain solid
+    neighbour p + e (no wrap); its distance q in (0, 1] is where the segment
+    first enters the body, found by bisection. Returns (solid uint8
+    [nz][ny][nx], nodes int32 [n] linear indices x + nx (y + ny z), q
+    float32 [n][len(dirs)], zero where there is no link).
+    A sub-box of a larger lattice (full_shape = (NZ, NY, NX)) starting at
+    node origin = (x0, y0, z0) gives the same links if the body stays one
+    node inside it (or touches only the lattice's own faces); the node
+    indices are then those of the larger lattice and solid covers the box."""
+    nz, ny, nx = shape
+    x0, y0, z0 = origin
+    NZ, NY, NX = full_shape if full_shape is not None else shape
+    z, y, x = np.meshgrid(np.arange(z0, z0 + nz), np.arange(y0, y0 + ny), np.arange(x0, x0 + nx),
+                          indexing="ij")
+    solid = is_solid(x.astype(float), y.astype(float), z.astype(float))
+    n = nx * ny * nz
+    qfull = np.zeros((len(dirs), n), np.float32)
+    fluid = ~solid
+    for k, (ex, ey, ez) in enumerate(dirs):
+        if ex == ey == ez == 0:
+            continue
+        xs, ys, zs = x - x0 + ex, y - y0 + ey, z - z0 + ez
+        inside = (xs >= 0) & (xs < nx) & (ys >= 0) & (ys < ny) & (zs >= 0) & (zs < nz)
+        cand = fluid & inside
+        cand[cand] = solid[zs[cand], ys[cand], xs[cand]]
+        if not cand.any():
+            continue
+        px, py, pz = x[cand].astype(float), y[cand].astype(float), z[cand].astype(float)
+        lo = np.zeros(px.shape)
+        hi = np.ones(px.shape)
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            s = is_solid(px + mid * ex, py + mid * ey, pz + mid * ez)
+            hi = np.where(s, mid, hi)
+            lo = np.where(s, lo, mid)
+        qfull[k][cand.reshape(-1)] = hi.astype(np.float32)
+    local = np.nonzero((qfull != 0).any(axis=0))[0]
+    nodes = ((z.reshape(-1)[local] * NY + y.reshape(-1)[local]) * NX +
+             x.reshape(-1)[local]).astype(np.int32)
+    return solid.astype(np.uint8), nodes, np.ascontiguousarray(qfull[:, local].T)
+
+
+def nozzle_tube(nx: int, ny: int, diameter: float, wall: float, length: float):
+    """Point predicate of a round tube along z around the lattice's centre
+    line (x, y) = (nx/2 - 1/2, ny/2 - 1/2): inner radius diameter/2,
+    thickness wall, from z = -1/2 to z = length - 1/2."""
+    cx, cy, r0 = nx / 2.0 - 0.5, ny / 2.0 - 0.5, diameter / 2.0
+
+    def inside(x, y, z):
+        r = np.hypot(x - cx, y - cy)
+        return (r >= r0) & (r < r0 + wall) & (z < length - 0.5)
+    return inside

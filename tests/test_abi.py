@@ -117,6 +117,11 @@ def test_required_bytes_and_binding_checks(P):
     assert fin(h, fake, 1, fake, fake, fake, P.DTYPE_F64, 2, 16, 0) == P.EINVAL  # x0 >= nx
     assert fin(h, fake, 1, fake, fake, fake, P.DTYPE_F64, 0, 0, 4) == P.EINVAL  # z0 >= nz
     assert fin(h, fake, 1, fake, fake, fake, 7, 2, 0, 0) == P.EINVAL  # dtype
+    # curved-wall links: refused before any launch
+    assert P.lib().lbm_set_links(h, fake, fake, 4) == P.EUNBOUND
+    assert P.lib().lbm_set_links(h, fake, fake, -1) == P.EINVAL
+    assert P.lib().lbm_set_links(h, fake, fake, 1 << 31) == P.EINVAL
+    assert P.lib().lbm_set_links(None, None, None, 0) == P.EINVAL
     P.lib().lbm_destroy(h)
 
 
