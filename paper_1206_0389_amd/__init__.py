@@ -477,7 +477,7 @@ class Lattice:
         set_solids(self.h, solid, masks)
         self._solid_bufs = (solid, masks)
 
-    def set_links(self, nodes, q):
+    def set_links(self, nodes, q=None):
         """Curved walls: Bouzidi's interpolated bounce-back on the links of
         the listed fluid nodes (int32 linear indices x + nx (y + ny z)) to
         solid neighbours, q[j][k] the wall's distance along direction k as a
