@@ -37,6 +37,10 @@ Parity status of each oracle function (what pins it, see tests/):
   PRESSURE faces (run)        plug flow from a velocity inlet to a pressure
                               outlet is a fixed point; a closed box with a
                               pressure face relaxes to the face's density
+  jet_profile (Eqs. 23-24)    a field linear in the section (bilinear
+                              exact): closed-form crossing radii; Gaussian
+                              and elliptic jets: r_e at the e-folding radius
+                              of each axis; axis permutations agree
   interpolated bounce-back    q = 1/2 is the halfway rule; steady Couette
   (run, link_q)               flow puts the no-slip point at the wall's
                               distance q (halfway: at 1/2)
@@ -251,6 +255,73 @@ def velocity_statistics(us, axis=2, point=None):
     shape[2 - axis] = -1
     ti = rms[axis] / axis_mean.reshape(shape)
     return mean, rms, ti
+
+
+# Fraction of the axis velocity at the radius r_e that defines the spreading
+# width (Eqs. (23)-(24): u = 0.368 u_m at half the width).
+SPREAD_FRACTION = 0.368
+
+
+def jet_profile(mean, axis, center, ndir, dr, nr):
+    """Spreading of a jet from its time-averaged velocity (Section 3: the
+    width of Eq. (23) and the profile of Eq. (24)), on every cross-section.
+
+    mean: [3][nz][ny][nx]; axis: the jet axis; center: the jet centre (a, b)
+    in the two other coordinates in increasing axis order (node units). On
+    cross-section p, the streamwise mean u is interpolated bilinearly in
+    (a, b); u_m = u at the centre. Rays leave the centre at the angles 2 pi
+    j / ndir (from the a axis towards b), sampled at r_k = k dr, k < nr,
+    while the sample lies within the cross-section's nodes. The radius r_e
+    of a ray is the first point where u falls to SPREAD_FRACTION u_m,
+    interpolated linearly between the two samples around it.
+
+    Returns um [np], re [3][np] (minimum, maximum and mean of r_e over the
+    rays that reach it; NaN if none does) and prof [np][nr], the mean of
+    u(r_k) / u_m over the rays whose sample k lies within the section (NaN
+    if none)."""
+    u = np.moveaxis(np.asarray(mean, dtype=np.float64)[axis], 2 - axis, 0)  # [p][b][a]
+    npl, nb, na = u.shape
+    c0, c1 = float(center[0]), float(center[1])
+
+    def bilinear(P, a, b):
+        i = min(int(np.floor(a)), na - 2)
+        j = min(int(np.floor(b)), nb - 2)
+        fa, fb = a - i, b - j
+        return ((1 - fa) * (1 - fb) * P[j, i] + fa * (1 - fb) * P[j, i + 1] +
+                (1 - fa) * fb * P[j + 1, i] + fa * fb * P[j + 1, i + 1])
+
+    def inside(a, b):
+        return 0.0 <= a <= na - 1 and 0.0 <= b <= nb - 1
+
+    um = np.zeros(npl)
+    re = np.full((3, npl), np.nan)
+    prof = np.full((npl, nr), np.nan)
+    for p in range(npl):
+        P = u[p]
+        um[p] = bilinear(P, c0, c1)
+        thr = SPREAD_FRACTION * um[p]
+        radii = []
+        sums, counts = np.zeros(nr), np.zeros(nr)
+        for j in range(ndir):
+            th = 2.0 * np.pi * j / ndir
+            ca, sa = np.cos(th), np.sin(th)
+            prev, found = um[p], False
+            for k in range(nr):
+                a, b = c0 + k * dr * ca, c1 + k * dr * sa
+                if not inside(a, b):
+                    break
+                v = bilinear(P, a, b)
+                sums[k] += v / um[p]
+                counts[k] += 1
+                if k > 0 and not found and v <= thr:
+                    radii.append((k - 1) * dr + dr * (prev - thr) / (prev - v))
+                    found = True
+                prev = v
+        if radii:
+            re[:, p] = (min(radii), max(radii), sum(radii) / len(radii))
+        ok = counts > 0
+        prof[p, ok] = sums[ok] / counts[ok]
+    return um, re, prof
 
 
 class Lattice:
