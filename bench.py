@@ -308,10 +308,23 @@ def measure_stats(P, torch, synth, name="jet256-fclb-f32", reps=50):
     n = shape[0] * shape[1] * shape[2]
     per_node = (27 if model == "fclb" else 19) * BYTES[storage] + 2 * 6 * 8
     gbs = per_node * n / (ms * 1e-3) / 1e9
-    del lat, sums
+    # the jet's spreading (Eqs. (23)-(24)) from the mean: 32 rays x 64 radii
+    # on each of the 512 cross-sections
+    mean, rms, _ = lat.stats_finalize(sums, reps + 1)
+    del rms
+    lat.jet_profile(mean, ndir=32, dr=0.5, nr=64)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        _, re, _ = lat.jet_profile(mean, ndir=32, dr=0.5, nr=64)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_prof = e0.elapsed_time(e1) / 10
+    del lat, sums, mean
     torch.cuda.empty_cache()
     return {"name": name + "-stats", "kernel": "stats_accumulate_kernel", "ms_per_call": ms,
-            "bytes_per_node": per_node, "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+            "bytes_per_node": per_node, "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
+            "jet_profile_ms": ms_prof, "jet_profile": "32 rays x 64 radii (dr 0.5) on 512 sections"}
 
 
 def copy_bandwidth(P, torch, nbytes=4 << 30, reps=10):

@@ -263,6 +263,31 @@ int lbm_reduce(lbm_lattice* lat, double out[5]);
  * Errors: LBM_EINVAL (null pointer), LBM_EUNBOUND. */
 int lbm_stats_accumulate(lbm_lattice* lat, double* sums);
 
+/* Spreading of the jet (Section 3: the width of Eq. (23), the profile of
+ * Eq. (24)) from a time-averaged velocity, on every cross-section normal to
+ * the jet axis. mean: device [3][nz][ny][nx] of dtype (LBM_DTYPE_F64/F32),
+ * e.g. the mean of lbm_stats_finalize. The streamwise component is
+ * interpolated bilinearly in the section's coordinates (a, b) (the two other
+ * axes in increasing order); u_m is its value at the jet centre (c0, c1).
+ * Rays leave the centre at the angles 2 pi j / ndir (j < ndir, from a
+ * towards b), sampled at r_k = k dr (k < nr) while the sample lies within
+ * the section's nodes; a ray's radius r_e is the first point where u falls
+ * to 0.368 u_m (half the spreading width), interpolated linearly between
+ * the samples around it. Outputs (device, FP64, n_p = the axis extent):
+ *   um    [n_p]     u_m of each section;
+ *   re    [3][n_p]  minimum, maximum and mean of r_e over the rays that
+ *                   reach it (NaN where none does);
+ *   prof  [n_p][nr] (may be NULL) mean of u(r_k) / u_m over the rays whose
+ *                   sample k lies within the section (NaN where none).
+ * Meaningful for u_m > 0 (a jet). Asynchronous on the lattice's stream; the
+ * lattice's populations are not read. Errors: LBM_EINVAL (null mean, um or
+ * re; bad dtype or axis; ndir outside [1, 65536], nr outside [2, 65536],
+ * dr not positive; a section narrower than 2 nodes; the centre outside
+ * [0, n_a - 1] x [0, n_b - 1]). */
+int lbm_jet_profile(const lbm_lattice* lat, const void* mean, int dtype, int axis, double c0,
+                    double c1, int ndir, double dr, int nr, double* um, double* re,
+                    double* prof);
+
 /* Averages of count >= 1 accumulated states, in dtype (LBM_DTYPE_F64/F32):
  * mean ([3][N]) = sums / count; rms ([3][N]) = sqrt(<u_a^2> - <u_a>^2), the
  * root-mean-square fluctuation (0 where rounding makes the difference

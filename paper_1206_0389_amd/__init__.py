@@ -86,6 +86,9 @@ _SIGS = {
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_links": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+    "lbm_jet_profile": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                        ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_stats_finalize": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                            ctypes.c_int, ctypes.c_int],
@@ -252,6 +255,16 @@ def set_links(h, nodes, q):
     if q.dim() != 2 or q.shape[0] != nodes.numel():
         raise TypeError("q must be [n][Q] for n nodes")
     _check(lib().lbm_set_links(h, _dev(nodes), _dev(q), int(nodes.numel())), "lbm_set_links")
+
+
+def jet_profile(h, mean, axis, center, ndir, dr, nr, um, re, prof=None):
+    for t in (um, re) + ((prof,) if prof is not None else ()):
+        if t.dtype != torch.float64:
+            raise TypeError("um, re and prof must be float64")
+    _check(lib().lbm_jet_profile(h, _dev(mean), _dtype_code(mean), int(axis), float(center[0]),
+                                 float(center[1]), int(ndir), float(dr), int(nr), _dev(um),
+                                 _dev(re), _dev(prof) if prof is not None else None),
+           "lbm_jet_profile")
 
 
 def stats_accumulate(h, sums: torch.Tensor):
@@ -492,6 +505,25 @@ class Lattice:
         self._expect(q, (nodes.numel(), self.Q), "q")
         set_links(self.h, nodes, q)
         self._link_bufs = (nodes, q)
+
+    def jet_profile(self, mean, axis=2, center=None, ndir=32, dr=0.5, nr=64, profile=True):
+        """Spreading of the jet from a mean velocity [3][nz][ny][nx] (float64
+        or float32): per cross-section normal to axis, u_m at the centre (the
+        two other coordinates in increasing order; default the lattice's
+        middle), the radius where the bilinear mean falls to 0.368 u_m on
+        ndir rays (min, max, mean) and the ray-averaged profile u(k dr) / u_m
+        (k < nr). Returns (um [n_p], re [3][n_p], prof [n_p][nr] or None)."""
+        self._expect(mean, (3,) + self.shape3, "mean")
+        n3 = (self.nx, self.ny, self.nz)
+        other = [d for d in range(3) if d != axis]
+        if center is None:
+            center = tuple((n3[d] - 1) / 2.0 for d in other)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        um = torch.empty(n3[axis], **f64)
+        re = torch.empty((3, n3[axis]), **f64)
+        prof = torch.empty((n3[axis], nr), **f64) if profile else None
+        jet_profile(self.h, mean.contiguous(), axis, center, ndir, dr, nr, um, re, prof)
+        return um, re, prof
 
     def stats_buffer(self):
         """Zeroed FP64 running sums for stats_accumulate ([6][nz][ny][nx])."""

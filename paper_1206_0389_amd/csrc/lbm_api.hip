@@ -10,6 +10,7 @@
 
 #include "../../include/lbm.h"
 #include "adjoint.h"
+#include "jetprofile.h"
 #include "kernels.h"
 
 using namespace lbm;
@@ -620,6 +621,33 @@ int lbm_stats_finalize(const lbm_lattice* L, const double* sums, int64_t count, 
   else
     hipLaunchKernelGGL((stats_finalize_kernel<float>), L->grid, L->block, 0, L->stream, L->args,
                        sums, inv, (float*)mean, (float*)rms, (float*)ti, axis, p0, p1);
+  return check_launch();
+}
+
+int lbm_jet_profile(const lbm_lattice* L, const void* mean, int dtype, int axis, double c0,
+                    double c1, int ndir, double dr, int nr, double* um, double* re,
+                    double* prof) {
+  if (!L || !mean || !um || !re || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (axis < 0 || axis > 2 || ndir < 1 || ndir > 65536 || nr < 2 || nr > 65536) return LBM_EINVAL;
+  if (!std::isfinite(dr) || !(dr > 0.0)) return LBM_EINVAL;
+  const long long nx = L->cfg.nx, ny = L->cfg.ny, nz = L->cfg.nz;
+  JetSections s{};
+  s.comp = axis * nx * ny * nz;
+  if (axis == 2) {
+    s.sp = nx * ny, s.sa = 1, s.sb = nx, s.np = (int)nz, s.na = (int)nx, s.nb = (int)ny;
+  } else if (axis == 1) {
+    s.sp = nx, s.sa = 1, s.sb = nx * ny, s.np = (int)ny, s.na = (int)nx, s.nb = (int)nz;
+  } else {
+    s.sp = 1, s.sa = nx, s.sb = nx * ny, s.np = (int)nx, s.na = (int)ny, s.nb = (int)nz;
+  }
+  if (s.na < 2 || s.nb < 2) return LBM_EINVAL;
+  if (!(c0 >= 0.0 && c0 <= s.na - 1 && c1 >= 0.0 && c1 <= s.nb - 1)) return LBM_EINVAL;
+  if (dtype == LBM_DTYPE_F64)
+    hipLaunchKernelGGL((jet_profile_kernel<double>), dim3(s.np), dim3(256), 0, L->stream,
+                       (const double*)mean, s, c0, c1, ndir, dr, nr, um, re, prof);
+  else
+    hipLaunchKernelGGL((jet_profile_kernel<float>), dim3(s.np), dim3(256), 0, L->stream,
+                       (const float*)mean, s, c0, c1, ndir, dr, nr, um, re, prof);
   return check_launch();
 }
 
