@@ -13,6 +13,10 @@ Parity status of each oracle function (what pins it, see tests/):
   central_moments (Eq. 15)    Table 2 printed raw->central polynomials
   fclb_collide                conservation, product-equilibrium fixed point,
                               omega = 1 map, moment self-consistency, symmetry
+  clb_collide (CLB27)         conservation, fixed point, equal to the FCLB at
+                              omega = 1, post-collision central moments of
+                              orders 4 and 6 those of the Gaussian (computed
+                              from the populations), shear-wave decay rate
   run (streaming + BCs)       exact first-moment transport law, shear-wave
                               and Taylor-Green decay rates, Couette profile
   splitmix64                  published test vector
@@ -57,7 +61,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.cpp")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
-MRT19, FCLB27 = 1, 2
+MRT19, FCLB27, CLB27 = 1, 2, 3
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
 PERIODIC, WALL, INLET, OUTFLOW, FREESLIP, PRESSURE = 0, 1, 2, 3, 4, 5
 
@@ -120,6 +124,7 @@ def lib():
                                       dp, dp, dp]
         L.orc_central_moments.argtypes = [dp, dp, dp, dp]
         L.orc_fclb_collide.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_clb_collide.argtypes = [dp, ctypes.c_double, dp]
         L.orc_splitmix64.argtypes = [ctypes.c_uint64]
         L.orc_splitmix64.restype = ctypes.c_uint64
         L.orc_inlet_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
@@ -220,6 +225,13 @@ def central_moments(F):
 def fclb_collide(f27, omega):
     out = np.zeros(27)
     lib().orc_fclb_collide(_dp(_f64(f27)), float(omega), _dp(out))
+    return out
+
+
+def clb_collide(f27, omega):
+    """The cascaded collision with Gaussian higher-order equilibria."""
+    out = np.zeros(27)
+    lib().orc_clb_collide(_dp(_f64(f27)), float(omega), _dp(out))
     return out
 
 

@@ -31,14 +31,14 @@
 
 extern "C" {
 
-enum { ORC_MRT19 = 1, ORC_FCLB27 = 2 };
+enum { ORC_MRT19 = 1, ORC_FCLB27 = 2, ORC_CLB27 = 3 };
 enum { ORC_BASIS_TABLE1 = 0, ORC_BASIS_DHUMIERES = 1 };
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_INLET = 2, ORC_OUTFLOW = 3, ORC_FREESLIP = 4,
        ORC_PRESSURE = 5 };
 
 // Must match the ctypes structure in oracle/__init__.py.
 typedef struct orc_params {
-  int32_t model;        // ORC_MRT19 or ORC_FCLB27
+  int32_t model;        // ORC_MRT19, ORC_FCLB27 or ORC_CLB27
   int32_t nx, ny, nz;   // lattice (or window) extent
   double nu;            // lattice kinematic viscosity -> tau0 = 3 nu + 1/2
   double cs_smag;       // Smagorinsky constant (MRT only; 0 = off)
@@ -350,9 +350,14 @@ void central_moments(const T* F, T* rho_out, T* u, T* kappa) {
 }
 
 // FCLB collision (Section 2, Table 1 groups applied to central moments,
-// Table 2 equilibria, all rates except the shear rate equal to 1).
+// Table 2 equilibria, all rates except the shear rate equal to 1). With
+// gaussian set, the cascaded scheme before the factorization (the CLB the
+// paper starts from, Section 2): the fourth- and sixth-order central moments
+// relax to those of the Gaussian whose variance is the squared speed of
+// sound (1/9, 0 and 1/27 per unit mass) instead of to products of the
+// relaxed second order.
 template <typename T>
-void fclb_collide(const T* f, double omega, T* fout) {
+void fclb_collide(const T* f, double omega, T* fout, bool gaussian = false) {
   T F[27];
   for (int i = 0; i < 27; ++i) F[i] = T(weight(27, i)) + f[i];
   T rho, u[3], k[27];
@@ -385,6 +390,11 @@ void fclb_collide(const T* f, double omega, T* fout) {
   ks[9 + 3 + 2] = k002 * k110;
   // sixth order
   ks[9 * 2 + 3 * 2 + 2] = k200 * k020 * k002;
+  if (gaussian) {
+    ks[9 * 2 + 3 * 2 + 0] = ks[9 * 2 + 0 + 2] = ks[0 + 3 * 2 + 2] = 1.0 / 9.0;
+    ks[9 * 2 + 3 + 1] = ks[9 + 3 * 2 + 1] = ks[9 + 3 + 2] = 0.0;
+    ks[9 * 2 + 3 * 2 + 2] = 1.0 / 27.0;
+  }
   // back to populations: sum_i F*_i prod_a (e_ia - u_a)^{n_a} = rho kappa*
   T A[27 * 27], b[27];
   for (int a = 0; a < 3; ++a)
@@ -405,7 +415,7 @@ void collide_node(const orc_params* p, const double* f, double* fout) {
   if (p->model == ORC_MRT19)
     mrt_collide(f, tau0, p->cs_smag, p->mrt_basis, p->rates, fout, nullptr);
   else
-    fclb_collide(f, 1.0 / tau0, fout);
+    fclb_collide(f, 1.0 / tau0, fout, p->model == ORC_CLB27);
 }
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): one output for a state.
@@ -640,6 +650,10 @@ void orc_mrt_collide(const double* f, double tau0, double cs, int basis,
 
 void orc_central_moments(const double* F, double* rho, double* u, double* kappa) {
   central_moments(F, rho, u, kappa);
+}
+
+void orc_clb_collide(const double* f, double omega, double* fout) {
+  fclb_collide(f, omega, fout, true);
 }
 
 void orc_fclb_collide(const double* f, double omega, double* fout) {

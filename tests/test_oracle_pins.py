@@ -421,7 +421,7 @@ def _shear_decay_nu(model, n, nu, steps, u0=1e-4):
     return np.log(amps[0] / amps[1]) / (steps * k * k)
 
 
-@pytest.mark.parametrize("model", [oracle.MRT19, oracle.FCLB27])
+@pytest.mark.parametrize("model", [oracle.MRT19, oracle.FCLB27, oracle.CLB27])
 def test_shear_wave_viscosity_converges(model):
     """Shear-wave amplitude decays as exp(-nu k^2 t) with nu = (1/omega-1/2)/3
     (Eq. 13); the lattice error is O(k^2), so it shrinks 4x per refinement."""
