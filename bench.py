@@ -210,7 +210,7 @@ def measure(name, P, torch, synth, steps, warmup):
     ms = time_steps(lat, torch, steps, warmup)
     red = lat.reduce(check=False)
     model, storage, shape, _ = workload(name)
-    q = 27 if model == "fclb" else 19
+    q = 19 if model == "mrt" else 27
     n = getattr(lat, "updates_per_step", shape[0] * shape[1] * shape[2])
     alg_bytes = 2 * q * BYTES[storage] * n
     gbs = alg_bytes / (ms * 1e-3) / 1e9
@@ -390,7 +390,8 @@ def main():
     print("bench: main done %.1f MLUPS" % main_res["mlups"], flush=True)
     others = []
     if not args.no_others:
-        for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-mrt-f32", "jet256-mrt-f16",
+        for name in ["jet256-fclb-f16", "jet256-fclb-f64", "jet256-clb-f32", "jet256-mrt-f32",
+                     "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
                      "ref128-mrt-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:

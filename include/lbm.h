@@ -53,6 +53,7 @@ extern "C" {
 /* ---- enumerations ----------------------------------------------------- */
 #define LBM_D3Q19_MRT_LES 1  /* Eq. (12) + Eqs. (16)-(21), incompressible */
 #define LBM_D3Q27_FCLB 2     /* Table 2 central moments, compressible     */
+#define LBM_D3Q27_CLB 3      /* cascaded, Gaussian higher-order equilibria */
 
 #define LBM_F64 1            /* population storage types                  */
 #define LBM_F32 2
@@ -78,7 +79,11 @@ typedef struct lbm_lattice lbm_lattice;
 
 /*
  * Lattice configuration (copied at create; no pointer is kept).
- *   model      LBM_D3Q19_MRT_LES or LBM_D3Q27_FCLB.
+ *   model      LBM_D3Q19_MRT_LES, LBM_D3Q27_FCLB or LBM_D3Q27_CLB (the
+ *              cascaded scheme before the factorization, Section 2: the same
+ *              central moments and rates as the FCLB, with the fourth- and
+ *              sixth-order central moments relaxed to those of the Gaussian,
+ *              rho/9, 0 and rho/27; uniform lattices only, no adjoint).
  *   storage    LBM_F64, LBM_F32 or LBM_F16 (population deviations).
  *   nx,ny,nz   lattice nodes, each >= 1; nx*ny*nz < 2^31.
  *   nu         lattice kinematic viscosity, > 0; the molecular relaxation

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 OK, EINVAL, ENOMEM, EUNBOUND, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
-D3Q19_MRT_LES, D3Q27_FCLB = 1, 2
+D3Q19_MRT_LES, D3Q27_FCLB, D3Q27_CLB = 1, 2, 3
 F64, F32, F16 = 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 1, 2
 BASIS_TABLE1, BASIS_DHUMIERES = 0, 1
@@ -35,7 +35,7 @@ VELOCITIES = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1)
 RHO_FULL, RHO_DEVIATION = 0, 1
 
 STORAGE = {"f64": F64, "f32": F32, "f16": F16}
-MODEL = {"mrt": D3Q19_MRT_LES, "fclb": D3Q27_FCLB}
+MODEL = {"mrt": D3Q19_MRT_LES, "fclb": D3Q27_FCLB, "clb": D3Q27_CLB}
 
 
 class LbmError(RuntimeError):
@@ -378,7 +378,7 @@ class Lattice:
                  cs_smag=0.0, mrt_basis=BASIS_TABLE1, rates=None, device="cuda", stream=None):
         self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
         self.h = create_lattice(self.cfg)
-        self.Q = 27 if self.cfg.model == D3Q27_FCLB else 19
+        self.Q = 19 if self.cfg.model == D3Q19_MRT_LES else 27
         self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
         self.N = self.nx * self.ny * self.nz
         self.device = torch.device(device)
@@ -598,7 +598,7 @@ class RefinedLattice:
                  fine_inlet_mask=None, inlet_amp=0.0, seed=0, device="cuda", stream=None):
         import numpy as np
         self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
-        self.Q = 27 if self.cfg.model == D3Q27_FCLB else 19
+        self.Q = 19 if self.cfg.model == D3Q19_MRT_LES else 27
         self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
         self.device = torch.device(device)
         m = np.ascontiguousarray(mask, dtype=np.uint8)

@@ -106,7 +106,10 @@ __device__ __forceinline__ FclbState<real> fclb_relax(const real (&f)[27], real 
 
 // Post-collision central moments G = rho kappa* minus the central moments
 // of the rest weights about u, then the inverse transform to deviations.
-template <typename real>
+// GAUSS: the cascaded scheme before the factorization (CLB): orders 4 and 6
+// relax to the Gaussian's central moments (rho/9, 0, rho/27) instead of the
+// products of the relaxed second order.
+template <typename real, bool GAUSS = false>
 __device__ __forceinline__ void fclb_post(const FclbState<real>& s, real (&A)[3][3][3]) {
   const real drho = s.drho, inv = s.inv, ux = s.ux, uy = s.uy, uz = s.uz;
   const real ax = s.ax, ay = s.ay, az = s.az, bxy = s.bxy, bxz = s.bxz, byz = s.byz;
@@ -132,18 +135,31 @@ __device__ __forceinline__ void fclb_post(const FclbState<real>& s, real (&A)[3]
   A[0][1][2] = uy * c2z;
   A[1][1][1] = ux * uy * uz;
   const real ninth = real(1.0 / 9.0);
-  A[2][2][0] = ninth * drho + third * (ax + ay - ux2 - uy2) + ax * ay * inv - ux2 * uy2;
-  A[2][0][2] = ninth * drho + third * (ax + az - ux2 - uz2) + ax * az * inv - ux2 * uz2;
-  A[0][2][2] = ninth * drho + third * (ay + az - uy2 - uz2) + ay * az * inv - uy2 * uz2;
-  A[2][1][1] = third * (byz - uy * uz) + ax * inv * byz - ux2 * uy * uz;
-  A[1][2][1] = third * (bxz - ux * uz) + ay * inv * bxz - uy2 * ux * uz;
-  A[1][1][2] = third * (bxy - ux * uy) + az * inv * bxy - uz2 * ux * uy;
+  if constexpr (GAUSS) {
+    A[2][2][0] = ninth * drho - third * (ux2 + uy2) - ux2 * uy2;
+    A[2][0][2] = ninth * drho - third * (ux2 + uz2) - ux2 * uz2;
+    A[0][2][2] = ninth * drho - third * (uy2 + uz2) - uy2 * uz2;
+    A[2][1][1] = -(third + ux2) * uy * uz;
+    A[1][2][1] = -(third + uy2) * ux * uz;
+    A[1][1][2] = -(third + uz2) * ux * uy;
+  } else {
+    A[2][2][0] = ninth * drho + third * (ax + ay - ux2 - uy2) + ax * ay * inv - ux2 * uy2;
+    A[2][0][2] = ninth * drho + third * (ax + az - ux2 - uz2) + ax * az * inv - ux2 * uz2;
+    A[0][2][2] = ninth * drho + third * (ay + az - uy2 - uz2) + ay * az * inv - uy2 * uz2;
+    A[2][1][1] = third * (byz - uy * uz) + ax * inv * byz - ux2 * uy * uz;
+    A[1][2][1] = third * (bxz - ux * uz) + ay * inv * bxz - uy2 * ux * uz;
+    A[1][1][2] = third * (bxy - ux * uy) + az * inv * bxy - uz2 * ux * uy;
+  }
   A[2][2][1] = c2x * c2y * uz;
   A[2][1][2] = c2x * uy * c2z;
   A[1][2][2] = ux * c2y * c2z;
-  A[2][2][2] = real(1.0 / 27.0) * drho + ninth * (ax + ay + az - uu) +
-               third * inv * (ax * ay + ax * az + ay * az) + ax * ay * az * inv * inv -
-               third * (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) - ux2 * uy2 * uz2;
+  if constexpr (GAUSS)
+    A[2][2][2] = real(1.0 / 27.0) * drho - ninth * uu -
+                 third * (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) - ux2 * uy2 * uz2;
+  else
+    A[2][2][2] = real(1.0 / 27.0) * drho + ninth * (ax + ay + az - uu) +
+                 third * inv * (ax * ay + ax * az + ay * az) + ax * ay * az * inv * inv -
+                 third * (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) - ux2 * uy2 * uz2;
 
 #pragma unroll
   for (int b = 0; b < 3; ++b)
@@ -159,11 +175,11 @@ __device__ __forceinline__ void fclb_post(const FclbState<real>& s, real (&A)[3]
     for (int b = 0; b < 3; ++b) uncentral3(A[a][b][0], A[a][b][1], A[a][b][2], uz);
 }
 
-template <typename real>
+template <typename real, bool GAUSS = false>
 __device__ __forceinline__ void fclb_collide(real (&f)[27], real omega) {
   const FclbState<real> s = fclb_relax(f, omega);
   real A[3][3][3];
-  fclb_post(s, A);
+  fclb_post<real, GAUSS>(s, A);
 #pragma unroll
   for (int i = 0; i < 27; ++i) f[i] = A[cx(i) + 1][cy(i) + 1][cz(i) + 1];
 }

@@ -209,6 +209,14 @@ struct Model<2> {  // D3Q27 FCLB
     fclb_collide<real>(f, real(a.omega));
   }
 };
+template <>
+struct Model<3> {  // D3Q27 CLB: Gaussian fourth- and sixth-order equilibria
+  static constexpr int Q = 27;
+  template <typename real, typename Args>
+  __device__ static void collide(real (&f)[27], const Args& a) {
+    fclb_collide<real, true>(f, real(a.omega));
+  }
+};
 
 // Compile-time loop: calls fn(integral_constant<int, I>) for I = 0..N-1.
 template <int I, int N, typename Fn>
@@ -919,7 +927,7 @@ __global__ __launch_bounds__(256) void macroscopic_kernel(const LatArgs a, int p
     j[1] += cy(i) * f[i];
     j[2] += cz(i) * f[i];
   }
-  const double r = (KIND == 2) ? 1.0 + d : 1.0;
+  const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
   if (rho) rho[n.self] = O(rho_mode == 0 ? 1.0 + d : d);
   if (u) {
     const size_t N = (size_t)a.N;
@@ -949,7 +957,7 @@ __global__ __launch_bounds__(256) void stats_accumulate_kernel(const LatArgs a, 
     j[1] += cy(i) * f[i];
     j[2] += cz(i) * f[i];
   }
-  const double r = (KIND == 2) ? 1.0 + d : 1.0;
+  const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
   const size_t N = (size_t)a.N;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1014,7 +1022,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const LatArgs a, in
       j[1] += cy(i) * f[i];
       j[2] += cz(i) * f[i];
     }
-    const double r = (KIND == 2) ? 1.0 + d : 1.0;
+    const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
     v[0] = d;
     v[1] = j[0];
     v[2] = j[1];

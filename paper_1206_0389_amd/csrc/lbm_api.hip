@@ -120,6 +120,7 @@ void step_dispatch_s(lbm_lattice* L, bool odd, long long t) {
   switch (L->kind) {
     case 0: step_model<0, S>(L, odd, t, nullptr); break;
     case 1: step_model<1, S>(L, odd, t, nullptr); break;
+    case 3: step_model<3, S>(L, odd, t, nullptr); break;
     default: step_model<2, S>(L, odd, t, nullptr); break;
   }
 }
@@ -246,6 +247,7 @@ void with_config(const lbm_lattice* L, Fn&& fn) {
   switch (L->kind) {
     case 0: by_s(std::integral_constant<int, 0>{}); break;
     case 1: by_s(std::integral_constant<int, 1>{}); break;
+    case 3: by_s(std::integral_constant<int, 3>{}); break;
     default: by_s(std::integral_constant<int, 2>{}); break;
   }
 }
@@ -283,7 +285,8 @@ const char* lbm_strerror(int status) {
 int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
   if (!cfg || !out) return LBM_EINVAL;
   const lbm_config& c = *cfg;
-  if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB) return LBM_EINVAL;
+  if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB && c.model != LBM_D3Q27_CLB)
+    return LBM_EINVAL;
   if (c.storage != LBM_F64 && c.storage != LBM_F32 && c.storage != LBM_F16) return LBM_EINVAL;
   if (c.nx < 1 || c.ny < 1 || c.nz < 1) return LBM_EINVAL;
   const double nnodes = (double)c.nx * c.ny * c.nz;
@@ -306,8 +309,10 @@ int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out) {
   lbm_lattice* L = new (std::nothrow) lbm_lattice();
   if (!L) return LBM_EINVAL;
   L->cfg = c;
-  L->kind = c.model == LBM_D3Q27_FCLB ? 2 : (c.mrt_basis == LBM_BASIS_TABLE1 ? 0 : 1);
-  L->Q = c.model == LBM_D3Q27_FCLB ? 27 : 19;
+  L->kind = c.model == LBM_D3Q27_FCLB ? 2
+            : c.model == LBM_D3Q27_CLB  ? 3
+                                        : (c.mrt_basis == LBM_BASIS_TABLE1 ? 0 : 1);
+  L->Q = c.model == LBM_D3Q19_MRT_LES ? 19 : 27;
   L->N = (size_t)c.nx * c.ny * c.nz;
   L->elem = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
   L->stream = (hipStream_t)c.stream;

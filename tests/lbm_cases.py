@@ -9,7 +9,10 @@ MODELS = {  # name: (model code, mrt basis)
     "fclb": (oracle.FCLB27, oracle.BASIS_TABLE1),
     "mrt_table1": (oracle.MRT19, oracle.BASIS_TABLE1),
     "mrt_dhumieres": (oracle.MRT19, oracle.BASIS_DHUMIERES),
+    "clb": (oracle.CLB27, oracle.BASIS_TABLE1),
 }
+# the refined lattice runs the FCLB and the MRT only
+REFINED_MODELS = [n for n in MODELS if n != "clb"]
 W, I, O, P = oracle.WALL, oracle.INLET, oracle.OUTFLOW, oracle.PERIODIC
 JET_FACES = [W, W, W, W, I, O]
 

@@ -136,6 +136,12 @@ def test_adjoint_rejects_mrt_and_aliasing():
         h.adjoint_step(f, lam, torch.empty_like(f))
     with pytest.raises(Pk.LbmError):
         h.step_record(torch.empty_like(f))
+    # no adjoint of the CLB variant either
+    c = Pk.Lattice(model="clb", storage="f64", shape=(4, 4, 4), nu=0.02)
+    with pytest.raises(Pk.LbmError):
+        c.adjoint_step(f, lam, torch.empty_like(f))
+    with pytest.raises(Pk.LbmError):
+        c.step_record(torch.empty_like(f))
     # nor through fixed-pressure faces
     h.set_boundaries([Pk.PRESSURE] * 2 + [Pk.PERIODIC] * 4, face_drho=[0.001] * 6)
     with pytest.raises(Pk.LbmError):

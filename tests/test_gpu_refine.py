@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from lbm_cases import MODELS, rel_err
+from lbm_cases import MODELS, REFINED_MODELS, rel_err
 from test_oracle_refine import _jet_case
 
 pytestmark = pytest.mark.gpu
@@ -75,7 +75,7 @@ def _oracle_reduce(R, c, fc, ff):
     return out
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", REFINED_MODELS)
 @pytest.mark.parametrize("jet", [True, False])
 def test_refined_step_parity_fp64(name, jet):
     g, R, c = _pair(name, "f64", jet=jet)
@@ -113,7 +113,7 @@ def test_refined_fp32_within_tolerance(name):
     assert ec <= 1e-5 and ef <= 1e-5, (ec, ef)
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", REFINED_MODELS)
 def test_refined_uniform_flow_and_readouts(name):
     """Uniform co-flow through walls moving with it, a uniform inlet and the
     outflow stays exactly uniform on both levels; macroscopic readouts of
