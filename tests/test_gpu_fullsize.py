@@ -15,6 +15,9 @@ Tolerances per step, as in the small-lattice parity tests: FP64 1e-12, FP32
 4e-6, FP16 2e-3 of the largest population; the oracle starts from the state
 rounded to the storage precision, exactly as the GPU stored it.
 
+The same is done for the jet with the round nozzle tube as curved walls
+(interpolated bounce-back), in boxes across the tube.
+
 The two-level refined workload is checked at full size through properties
 that hold at any size (uniform flow preserved exactly; FP32 against FP64).
 A 512 x 512 x 256 FP64 lattice checks the path taken when 32-bit offsets
@@ -86,6 +89,66 @@ def test_jet256_boxes_against_oracle(workload):
         g = got[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
         err = rel_err(g, ref)
         worst = max(worst, err)
+        assert err <= STEPS * TOL[storage], (lo, hi, err)
+    print(workload, "worst box error", worst, flush=True)
+
+
+NOZZLE_BOXES = [  # across the tube wall, at the tube's end, on its diagonal at the inlet
+    ((106, 124, 4), (114, 132, 12)),
+    ((106, 124, 12), (114, 132, 20)),
+    ((112, 112, 0), (120, 120, 8)),
+    ((140, 124, 4), (148, 132, 12)),
+]
+
+
+def test_nozzlecurved256_boxes_against_oracle():
+    """The jet with the round nozzle tube as curved walls (solid nodes plus
+    interpolated bounce-back on every fluid-solid link), built as bench.py
+    builds it, three steps from the noise state; boxes across the tube's
+    wall, its end and its diagonal at the inlet against the oracle window
+    with the same solid nodes and link distances."""
+    import bench
+    import paper_1206_0389_amd as P
+    workload = "nozzlecurved256-fclb-f32"
+    print("case full size", workload, flush=True)
+    model, storage, shape, _ = bench.workload(workload)
+    nx, ny, nz = shape
+    lat, _ = bench.make_lattice(workload, P, torch, synth)
+    js = bench.jet_setup(nx, ny, synth)
+    f = torch.empty((27, nz, ny, nx), dtype=torch.float64, device="cuda")
+    for q in range(27):
+        f[q] = torch.from_numpy(synth.tiled_populations(27, (nz, ny, nx), AMP, SEED,
+                                                        qs=[q])[0]).cuda()
+    lat.set_populations(f, t0=T0)
+    del f
+    lat.step(STEPS)
+    torch.cuda.synchronize()
+    got = lat.populations()
+    body = synth.nozzle_tube(nx, ny, js["diameter"], 2.0, 16.0)
+    worst = 0.0
+    for lo, hi in NOZZLE_BOXES:
+        wlo, whi, wf, inner = window((nx, ny, nz), JET, lo, hi, STEPS)
+        wsh = (whi[2] - wlo[2], whi[1] - wlo[1], whi[0] - wlo[0])
+        solid, nodes, q = synth.link_distances(body, wsh, P.VELOCITIES, origin=tuple(wlo),
+                                               full_shape=(nz, ny, nx))
+        lq = np.zeros((27,) + wsh)
+        z, r = np.divmod(nodes, nx * ny)
+        y, x = np.divmod(r, nx)
+        lq[:, z - wlo[2], y - wlo[1], x - wlo[0]] = q.T.astype(np.float64)
+        f0 = synth.tiled_populations(27, (nz, ny, nx), AMP, SEED, lo=wlo, hi=whi)
+        f0 = f0.astype(np.float32).astype(np.float64)
+        o = oracle.Lattice(oracle.FCLB27, wsh[2], wsh[1], wsh[0], nu=js["nu"], faces=wf,
+                           face_u=js["face_u"], inlet_u=js["inlet_u"],
+                           inlet_mask=js["inlet_mask"], inlet_amp=js["inlet_amp"],
+                           seed=js["seed"], origin=tuple(wlo), inlet_extent=(nx, ny),
+                           solid=solid, link_q=lq)
+        ref = o.run(f0, T0, STEPS)[:, inner[2], inner[1], inner[0]]
+        g = got[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        fl = solid[inner[2], inner[1], inner[0]] == 0
+        assert (~fl).any() or lo[2] >= 12  # the boxes cut the tube (or its end)
+        err = rel_err(g[:, fl], ref[:, fl])
+        worst = max(worst, err)
+        print("nozzle box", lo, "links", len(nodes), "error", err, flush=True)
         assert err <= STEPS * TOL[storage], (lo, hi, err)
     print(workload, "worst box error", worst, flush=True)
 
