@@ -45,6 +45,9 @@ Parity status of each oracle function (what pins it, see tests/):
                               exact): closed-form crossing radii; Gaussian
                               and elliptic jets: r_e at the e-folding radius
                               of each axis; axis permutations agree
+  jet_fit (Eqs. 22-24)        exact power laws and Gaussian profiles give
+                              their constants and zero residual; a known
+                              profile offset gives that residual
   interpolated bounce-back    q = 1/2 is the halfway rule; steady Couette
   (run, link_q)               flow puts the no-slip point at the wall's
                               distance q (halfway: at 1/2)
@@ -334,6 +337,46 @@ def jet_profile(mean, axis, center, ndir, dr, nr):
         ok = counts > 0
         prof[p, ok] = sums[ok] / counts[ok]
     return um, re, prof
+
+
+def jet_fit(um, re, prof, dr, x0, u0, d, p0, p1):
+    """The jet laws of Section 3 fitted to a jet_profile result over the
+    cross-sections p0 <= p < p1 downstream of the nozzle exit x0 (distance
+    x = p - x0 > 0; sections with a NaN input are skipped).
+
+    k_par: least squares of u_m = u0 k_par d / x (Eq. (22)); k_perp: least
+    squares of b_g = k_perp x (Eq. (23)) with b_g the mean radius r_e (where
+    the velocity is 0.368 u_m); res: root mean square over those sections
+    and the radii r_k = k dr <= 2 r_e of prof - 0.938 exp(-0.944 (r_k /
+    r_e)^2) (Eq. (24)). Returns (k_par, k_perp, res, number of profile
+    samples); NaN where nothing enters a fit."""
+    um, re, prof = (np.asarray(a, dtype=np.float64) for a in (um, re, prof))
+    s1 = s2 = s3 = s4 = s5 = 0.0
+    n = 0
+    for p in range(p0, p1):
+        x = p - x0
+        if x <= 0:
+            continue
+        if not np.isnan(um[p]):
+            a = u0 * d / x
+            s1 += um[p] * a
+            s2 += a * a
+        r_e = re[2, p]
+        if np.isnan(r_e):
+            continue
+        s3 += r_e * x
+        s4 += x * x
+        for k in range(prof.shape[1]):
+            r = k * dr
+            if r > 2.0 * r_e or np.isnan(prof[p, k]):
+                continue
+            g = 0.938 * np.exp(-0.944 * (r / r_e) ** 2)
+            s5 += (prof[p, k] - g) ** 2
+            n += 1
+    k_par = s1 / s2 if s2 > 0 else np.nan
+    k_perp = s3 / s4 if s4 > 0 else np.nan
+    res = np.sqrt(s5 / n) if n > 0 else np.nan
+    return k_par, k_perp, res, n
 
 
 class Lattice:

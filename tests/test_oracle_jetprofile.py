@@ -97,3 +97,31 @@ def test_axis_permutations_agree():
     got = oracle.jet_profile(my, 1, c, 12, 0.5, 12)
     for g, r in zip(got, ref):
         np.testing.assert_array_equal(g, r)
+
+
+def test_jet_laws_recover_their_constants():
+    """Sections that follow Eqs. (22)-(24) exactly give back k_par, k_perp
+    and a zero residual; an offset added to the profile comes back as the
+    residual; sections at or upstream of the nozzle exit are ignored."""
+    npl, nr, dr = 40, 30, 0.5
+    x0, u0, d, kp, kq = 3.0, 0.05, 8.0, 6.104, 0.109
+    p = np.arange(npl)
+    x = p - x0
+    um = np.where(x > 0, u0 * kp * d / np.where(x > 0, x, 1.0), 0.3)
+    re = np.zeros((3, npl))
+    re[2] = np.where(x > 0, kq * np.maximum(x, 1.0), np.nan)
+    prof = np.full((npl, nr), np.nan)
+    for q in range(npl):
+        if x[q] > 0:
+            r = dr * np.arange(nr)
+            prof[q] = 0.938 * np.exp(-0.944 * (r / re[2, q]) ** 2)
+    k_par, k_perp, res, n = oracle.jet_fit(um, re, prof, dr, x0, u0, d, 0, npl)
+    assert abs(k_par - kp) <= 1e-12 * kp and abs(k_perp - kq) <= 1e-12 * kq
+    assert res <= 1e-15 and n > 0
+    _, _, res2, n2 = oracle.jet_fit(um, re, prof + 0.01, dr, x0, u0, d, 0, npl)
+    assert abs(res2 - 0.01) <= 1e-12 and n2 == n
+    # a single section, by hand: samples up to 2 r_e
+    q = 20
+    k_par1, k_perp1, _, n1 = oracle.jet_fit(um, re, prof, dr, x0, u0, d, q, q + 1)
+    assert n1 == int(np.floor(2 * re[2, q] / dr)) + 1
+    assert abs(k_perp1 - re[2, q] / x[q]) <= 1e-15
