@@ -293,6 +293,24 @@ int lbm_jet_profile(const lbm_lattice* lat, const void* mean, int dtype, int axi
                     double c1, int ndir, double dr, int nr, double* um, double* re,
                     double* prof);
 
+/* The jet laws of Section 3 fitted to an lbm_jet_profile result (um [np],
+ * re [3][np], prof [np][nr], all device FP64, with its dr) over the
+ * sections p0 <= p < p1 downstream of the nozzle exit at axis coordinate x0
+ * (distance x = p - x0 > 0; sections with NaN inputs are skipped), for the
+ * inflow speed u0 and nozzle diameter d (lattice units):
+ *   out[0]  k_par, least squares of u_m = u0 k_par d / x      (Eq. (22))
+ *   out[1]  k_perp, least squares of b_g = k_perp x, b_g the mean r_e
+ *           (the radius of 0.368 u_m)                          (Eq. (23))
+ *   out[2]  root mean square of prof - 0.938 exp(-0.944 (r / r_e)^2)
+ *           over the samples r = k dr <= 2 r_e                 (Eq. (24))
+ *   out[3]  the number of profile samples in out[2]
+ * NaN where nothing enters a fit. out: device, 4 doubles. Asynchronous on
+ * the lattice's stream. Errors: LBM_EINVAL (null pointers; np or nr < 1;
+ * not 0 <= p0 < p1 <= np; dr or d not positive; u0 zero; non-finite x0). */
+int lbm_jet_fit(const lbm_lattice* lat, const double* um, const double* re, const double* prof,
+                int np, int nr, double dr, double x0, double u0, double d, int p0, int p1,
+                double* out);
+
 /* Averages of count >= 1 accumulated states, in dtype (LBM_DTYPE_F64/F32):
  * mean ([3][N]) = sums / count; rms ([3][N]) = sqrt(<u_a^2> - <u_a>^2), the
  * root-mean-square fluctuation (0 where rounding makes the difference

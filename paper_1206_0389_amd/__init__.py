@@ -86,6 +86,10 @@ _SIGS = {
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_links": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+    "lbm_jet_fit": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                    ctypes.c_void_p],
     "lbm_jet_profile": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -524,6 +528,24 @@ class Lattice:
         prof = torch.empty((n3[axis], nr), **f64) if profile else None
         jet_profile(self.h, mean.contiguous(), axis, center, ndir, dr, nr, um, re, prof)
         return um, re, prof
+
+    def jet_fit(self, um, re, prof, dr, x0, u0, d, p0=0, p1=None):
+        """Jet laws fitted to a jet_profile result (Eqs. (22)-(24)): returns
+        a float64 device tensor (k_par, k_perp, profile residual, number of
+        profile samples) over the sections p0 <= p < p1 past the exit x0."""
+        np_ = um.numel()
+        p1 = np_ if p1 is None else p1
+        self._expect(re, (3, np_), "re")
+        if prof is None or prof.dim() != 2 or prof.shape[0] != np_:
+            raise ValueError("prof must be [n_p][nr]")
+        for t in (um, re, prof):
+            if t.dtype != torch.float64:
+                raise TypeError("um, re and prof must be float64")
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        _check(lib().lbm_jet_fit(self.h, _dev(um), _dev(re), _dev(prof), int(np_),
+                                 int(prof.shape[1]), float(dr), float(x0), float(u0), float(d),
+                                 int(p0), int(p1), _dev(out)), "lbm_jet_fit")
+        return out
 
     def stats_buffer(self):
         """Zeroed FP64 running sums for stats_accumulate ([6][nz][ny][nx])."""

@@ -118,4 +118,59 @@ __global__ __launch_bounds__(256) void jet_profile_kernel(const T* mean, const J
   }
 }
 
+// The jet laws of Section 3 fitted to a jet_profile_kernel result over the
+// sections p0 <= p < p1 downstream of the nozzle exit x0 (x = p - x0 > 0;
+// NaN inputs skipped): k_par by least squares of u_m = u0 k_par d / x
+// (Eq. (22)), k_perp of b_g = k_perp x with b_g the mean r_e (Eq. (23)), and
+// the root mean square of prof - 0.938 exp(-0.944 (r / r_e)^2) over the
+// samples r = k dr <= 2 r_e (Eq. (24)). out: k_par, k_perp, residual, the
+// number of profile samples. One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void jet_fit_kernel(const double* um, const double* re,
+                                                      const double* prof, int np, int nr,
+                                                      double dr, double x0, double u0, double d,
+                                                      int p0, int p1, double* out) {
+  __shared__ double sh[5][256];
+  __shared__ int sn[256];
+  const int tid = threadIdx.x;
+  double s[5] = {0, 0, 0, 0, 0};
+  int n = 0;
+  for (int p = p0 + tid; p < p1; p += blockDim.x) {
+    const double x = p - x0;
+    if (!(x > 0.0)) continue;
+    if (!isnan(um[p])) {
+      const double a = u0 * d / x;
+      s[0] += um[p] * a;
+      s[1] += a * a;
+    }
+    const double r_e = re[2 * np + p];
+    if (isnan(r_e)) continue;
+    s[2] += r_e * x;
+    s[3] += x * x;
+    for (int k = 0; k < nr; ++k) {
+      const double r = k * dr, v = prof[(size_t)p * nr + k];
+      if (r > 2.0 * r_e || isnan(v)) continue;
+      const double t = r / r_e;
+      const double e = v - 0.938 * exp(-0.944 * (t * t));
+      s[4] += e * e;
+      ++n;
+    }
+  }
+  for (int i = 0; i < 5; ++i) sh[i][tid] = s[i];
+  sn[tid] = n;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      for (int i = 0; i < 5; ++i) sh[i][tid] += sh[i][tid + w];
+      sn[tid] += sn[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = sh[1][0] > 0.0 ? sh[0][0] / sh[1][0] : NAN;
+    out[1] = sh[3][0] > 0.0 ? sh[2][0] / sh[3][0] : NAN;
+    out[2] = sn[0] > 0 ? sqrt(sh[4][0] / sn[0]) : NAN;
+    out[3] = (double)sn[0];
+  }
+}
+
 }  // namespace lbm

@@ -656,6 +656,19 @@ int lbm_jet_profile(const lbm_lattice* L, const void* mean, int dtype, int axis,
   return check_launch();
 }
 
+int lbm_jet_fit(const lbm_lattice* L, const double* um, const double* re, const double* prof,
+                int np, int nr, double dr, double x0, double u0, double d, int p0, int p1,
+                double* out) {
+  if (!L || !um || !re || !prof || !out) return LBM_EINVAL;
+  if (np < 1 || nr < 1 || p0 < 0 || p1 > np || p0 >= p1) return LBM_EINVAL;
+  if (!std::isfinite(dr) || !(dr > 0.0) || !std::isfinite(x0) || !std::isfinite(u0) ||
+      !(u0 != 0.0) || !std::isfinite(d) || !(d > 0.0))
+    return LBM_EINVAL;
+  hipLaunchKernelGGL(jet_fit_kernel, dim3(1), dim3(256), 0, L->stream, um, re, prof, np, nr, dr,
+                     x0, u0, d, p0, p1, out);
+  return check_launch();
+}
+
 int lbm_reduce(lbm_lattice* L, double out[5]) {
   if (!L || !out) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;

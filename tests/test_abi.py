@@ -122,6 +122,16 @@ def test_required_bytes_and_binding_checks(P):
     assert P.lib().lbm_set_links(h, fake, fake, -1) == P.EINVAL
     assert P.lib().lbm_set_links(h, fake, fake, 1 << 31) == P.EINVAL
     assert P.lib().lbm_set_links(None, None, None, 0) == P.EINVAL
+    # jet profile and fits: argument checks before any launch
+    jp = P.lib().lbm_jet_profile
+    assert jp(h, fake, P.DTYPE_F64, 2, 7.5, 3.5, 8, 0.5, 1, fake, fake, None) == P.EINVAL  # nr
+    assert jp(h, fake, P.DTYPE_F64, 2, 16.0, 3.5, 8, 0.5, 8, fake, fake, None) == P.EINVAL  # c0
+    assert jp(h, fake, P.DTYPE_F64, 3, 7.5, 3.5, 8, 0.5, 8, fake, fake, None) == P.EINVAL  # axis
+    assert jp(h, fake, P.DTYPE_F64, 2, 7.5, 3.5, 8, 0.0, 8, fake, fake, None) == P.EINVAL  # dr
+    jf = P.lib().lbm_jet_fit
+    assert jf(h, fake, fake, fake, 10, 8, 0.5, 0.0, 0.05, 8.0, 4, 4, fake) == P.EINVAL  # empty
+    assert jf(h, fake, fake, fake, 10, 8, 0.5, 0.0, 0.0, 8.0, 0, 10, fake) == P.EINVAL  # u0
+    assert jf(h, fake, fake, fake, 10, 8, 0.5, 0.0, 0.05, 8.0, 0, 11, fake) == P.EINVAL  # p1
     P.lib().lbm_destroy(h)
 
 

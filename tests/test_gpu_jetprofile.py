@@ -93,3 +93,37 @@ def test_jet_profile_of_time_averages():
         g.jet_profile(mean, axis=2, center=(nx, 0.0))
     with pytest.raises(Pk.LbmError):
         g.jet_profile(mean, axis=2, nr=1)
+
+
+@pytest.mark.parametrize("axis", [2, 0])
+def test_jet_fit_against_oracle(axis):
+    """The jet-law fits (lbm_jet_fit, Eqs. (22)-(24)) of each side's own
+    spreading profile of the same synthetic jet, and of seeded arrays that
+    follow the laws exactly."""
+    shape = (20, 18, 24) if axis == 2 else (24, 20, 18)
+    print("case jet_fit axis", axis, flush=True)
+    mean, center = _jet_mean(shape, axis, 51 + axis)
+    g = gpu_lattice("fclb", "f32", shape, 0.01)
+    um, re, prof = g.jet_profile(torch.from_numpy(mean).cuda(), axis=axis, center=center,
+                                 ndir=24, dr=0.35, nr=40)
+    got = g.jet_fit(um, re, prof, 0.35, -2.5, 0.05, 6.0, 1, um.numel() - 1).cpu().numpy()
+    rum, rre, rprof = oracle.jet_profile(mean, axis, center, 24, 0.35, 40)
+    ref = np.array(oracle.jet_fit(rum, rre, rprof, 0.35, -2.5, 0.05, 6.0, 1, rum.size - 1))
+    assert got[3] == ref[3]
+    np.testing.assert_allclose(got[:3], ref[:3], rtol=1e-11)
+    # arrays that follow the laws exactly
+    npl, nr, dr = 40, 30, 0.5
+    x = np.arange(npl) - 3.0
+    um2 = np.where(x > 0, 0.05 * 6.104 * 8.0 / np.where(x > 0, x, 1.0), 0.3)
+    re2 = np.full((3, npl), np.nan)
+    re2[2] = np.where(x > 0, 0.109 * np.maximum(x, 1.0), np.nan)
+    r = dr * np.arange(nr)
+    prof2 = 0.938 * np.exp(-0.944 * (r[None, :] / np.where(x > 0, re2[2], 1.0)[:, None]) ** 2)
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (um2, re2, prof2)]
+    got2 = g.jet_fit(*t, dr, 3.0, 0.05, 8.0).cpu().numpy()
+    ref2 = np.array(oracle.jet_fit(um2, re2, prof2, dr, 3.0, 0.05, 8.0, 0, npl))
+    np.testing.assert_allclose(got2[:2], [6.104, 0.109], rtol=1e-12)
+    assert got2[2] <= 1e-15 and got2[3] == ref2[3]
+    import paper_1206_0389_amd as Pk
+    with pytest.raises(Pk.LbmError):
+        g.jet_fit(*t, dr, 3.0, 0.05, 8.0, p0=5, p1=5)
