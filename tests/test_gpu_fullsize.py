@@ -55,15 +55,15 @@ ROUND = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
 
 
 @pytest.mark.parametrize("workload", ["jet256-fclb-f32", "jet256-mrt-f32", "jet256-fclb-f16",
-                                      "jet256-fclb-f64"])
+                                      "jet256-fclb-f64", "jet256-clb-f32"])
 def test_jet256_boxes_against_oracle(workload):
     import bench
     import paper_1206_0389_amd as P
     print("case full size", workload, flush=True)
     model, storage, shape, _ = bench.workload(workload)
     nx, ny, nz = shape
-    name = "fclb" if model == "fclb" else "mrt_table1"
-    Q = 27 if model == "fclb" else 19
+    name = "mrt_table1" if model == "mrt" else model
+    Q = 19 if model == "mrt" else 27
     lat, _ = bench.make_lattice(workload, P, torch, synth)
     js = bench.jet_setup(nx, ny, synth)
     f = torch.empty((Q, nz, ny, nx), dtype=torch.float64, device="cuda")
