@@ -206,7 +206,7 @@ int lbm_get_populations(lbm_lattice* lat, void* f, int dtype);
  * solids are cleared (solid = NULL), lbm_set_boundaries is called (which
  * clears them) or the lattice is destroyed. A population whose pull source
  * is a solid node bounces back off a wall at rest halfway between the nodes
- * (the rule of a WALL face with zero velocity). Solid nodes are not updated;
+ * (the rule of a WALL face with zero velocity). Solid nodes take no part in the flow;
  * their populations are unspecified, lbm_get_populations returns zeros and
  * lbm_get_macroscopic the rest state (rho = 1, u = 0) there, and the
  * reductions, statistics and probe count them as rest. Steps then run the

@@ -617,7 +617,9 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   const Node n = make_node(a, x, y, z);
   S* __restrict__ F = (S*)a.f;
   const size_t N = (size_t)a.N;
-  // interior solids: solid nodes are not updated
+  // interior solids: solid nodes are skipped (the even step runs this only
+  // with PRESSURE faces; otherwise solid nodes run it harmlessly on their own
+  // slots, which nothing reads)
   uint32_t sb = 0;
   if constexpr (BC && EXT) {
     if (a.solid_nb) {
@@ -802,43 +804,58 @@ __global__ __launch_bounds__(256) void solid_mask_kernel(const LatArgs a, const 
 // after an odd step the other way round. A link needs x - e_K to be a fluid
 // node inside the domain, else the halfway value stays. No other node's
 // links touch these slots (x + e_K is solid), and a node reads all its
-// links' values before it writes any.
+// links' values before it writes any (a link reads the slot the opposite
+// link writes).
+// One 32-lane group per listed node, lane K handling direction K: a block
+// of 256 threads holds 8 whole nodes, and its barrier puts every read of
+// the block before any write.
 template <int Q, typename S, bool AFTER_ODD>
 __global__ __launch_bounds__(256) void link_kernel(const LatArgs a, const int32_t* nodes,
                                                    const float* q, long long n) {
   using real = typename Compute<S>::type;
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int self = nodes[k];
-  if (self < 0 || (long long)self >= a.N) return;
-  const uint32_t sb = a.solid_nb[self];
-  if (sb >> 31) return;
-  const Node nd = make_node(a, self % a.nx, (self / a.nx) % a.ny, self / (a.nx * a.ny));
-  S* F = (S*)a.f;
-  const size_t N = (size_t)a.N;
-  const float* qk = q + (size_t)k * Q;
-  real v[Q];
-  uint32_t act = 0;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long k = t >> 5;
+  const int K = (int)(t & 31);
+  // the lane's direction, selected from the compile-time tables
+  int ex = 0, ey = 0, ez = 0, ko = 0;
+  uint32_t pf = 0;
   static_for<1, Q>([&](auto kc) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int KO = opposite<Q>(K);
-    const float d = qk[K];
-    const bool link = ((sb >> KO) & 1u) && !((sb >> K) & 1u) &&
-                      (nd.atface & pull_faces(K)) == 0 && d > 0.f && d <= 1.f && d != 0.5f;
-    if (link) {
-      const int b = nd.at(-cx(K), -cy(K), -cz(K));
-      const real A = ld<real>(F + (size_t)KO * N + self);
-      const real B = ld<real>(AFTER_ODD ? F + (size_t)K * N + self : F + (size_t)KO * N + b);
-      const real C = ld<real>(AFTER_ODD ? F + (size_t)KO * N + b : F + (size_t)K * N + self);
-      const real t = real(2) * real(d);
-      v[K] = d < 0.5f ? t * A + (real(1) - t) * B : A / t + (t - real(1)) / t * C;
-      act |= 1u << K;
+    constexpr int D = decltype(kc)::value;
+    if (K == D) {
+      ex = cx(D);
+      ey = cy(D);
+      ez = cz(D);
+      ko = opposite<Q>(D);
+      pf = pull_faces(D);
     }
   });
-  static_for<1, Q>([&](auto kc) {
-    constexpr int K = decltype(kc)::value;
-    if ((act >> K) & 1u) st(F + (size_t)opposite<Q>(K) * N + self, v[K]);
-  });
+  S* F = (S*)a.f;
+  const size_t N = (size_t)a.N;
+  bool link = false;
+  real v = 0;
+  int self = 0;
+  if (k < n && K >= 1 && K < Q) {
+    self = nodes[k];
+    if (self >= 0 && (long long)self < a.N) {
+      const uint32_t sb = a.solid_nb[self];
+      const float d = q[(size_t)k * Q + K];
+      if (!(sb >> 31) && ((sb >> ko) & 1u) && !((sb >> K) & 1u) && d > 0.f && d <= 1.f &&
+          d != 0.5f) {
+        const Node nd = make_node(a, self % a.nx, (self / a.nx) % a.ny, self / (a.nx * a.ny));
+        if ((nd.atface & pf) == 0) {
+          link = true;
+          const int b = nd.at(-ex, -ey, -ez);
+          const real A = ld<real>(F + (size_t)ko * N + self);
+          const real B = ld<real>(AFTER_ODD ? F + (size_t)K * N + self : F + (size_t)ko * N + b);
+          const real C = ld<real>(AFTER_ODD ? F + (size_t)ko * N + b : F + (size_t)K * N + self);
+          const real tq = real(2) * real(d);
+          v = d < 0.5f ? tq * A + (real(1) - tq) * B : A / tq + (tq - real(1)) / tq * C;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (link) st(F + (size_t)ko * N + self, v);
 }
 
 template <int Q, typename S, bool BC, typename O>

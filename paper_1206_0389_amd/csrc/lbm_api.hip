@@ -106,10 +106,15 @@ void step_model_ext(const lbm_lattice* L, bool odd, long long t, void* rec) {
 }
 
 // Lattices without interior solids, FREESLIP or PRESSURE faces run the
-// general kernel compiled without their rules.
+// general kernel compiled without their rules. The even step touches only
+// each node's own slots, which no other node reads: solid nodes may run it
+// (their populations are never read) and free slip has no even-step rule,
+// so there the rules are compiled in only for PRESSURE faces.
 template <int KIND, typename S>
 void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
-  if (L->solids || L->args.bc.freeslip || L->args.bc.pressure)
+  const bool ext = odd ? (L->solids || L->args.bc.freeslip || L->args.bc.pressure)
+                       : L->args.bc.pressure != 0;
+  if (ext)
     step_model_ext<KIND, S, true>(L, odd, t, rec);
   else
     step_model_ext<KIND, S, false>(L, odd, t, rec);
@@ -136,7 +141,7 @@ void step_dispatch(lbm_lattice* L, bool odd, long long t) {
 // Interpolated bounce-back over the link list after a step.
 template <typename S>
 void links_dispatch_s(const lbm_lattice* L, bool after_odd) {
-  const dim3 grid((unsigned)((L->nlinks + 255) / 256)), block(256);
+  const dim3 grid((unsigned)((L->nlinks + 7) / 8)), block(256);  // 32 lanes per node
   auto go = [&](auto q_c, auto odd_c) {
     constexpr int Q = decltype(q_c)::value;
     constexpr bool ODD = decltype(odd_c)::value;
