@@ -178,3 +178,30 @@ def test_strerror(P):
     assert "invalid" in P.strerror(P.EINVAL)
     assert P.strerror(P.ENONFINITE)
     assert P.strerror(12345) == "unknown status"
+
+
+def test_product_never_imports_the_oracle():
+    """The library's Python side holds no path to the oracle (test
+    infrastructure): no import of it anywhere in the package."""
+    pkg = os.path.join(ROOT, "paper_1206_0389_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, re.M), fn
+                assert "lbm_oracle" not in txt, fn
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every call raises: there is no fallback."""
+    import paper_1206_0389_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "liblbm.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(RuntimeError):
+        P.lib()
+
+
+def test_binding_mirrors_every_declared_entry_point():
+    import paper_1206_0389_amd as P
+    missing = [n for n in _declared() if n not in P._SIGS]
+    assert not missing, missing
