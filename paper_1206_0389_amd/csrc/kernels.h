@@ -758,7 +758,7 @@ __device__ __forceinline__ void fetch_natural(const LatArgs& a, const Node& n, i
   if (parity == 0) {
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ld<double>(F + (size_t)I * N + n.self);
+      f[I] = ld<double, true>(F + (size_t)I * N + n.self);
     });
   } else {
     double uin[3] = {0, 0, 0};
@@ -976,11 +976,14 @@ __global__ __launch_bounds__(256) void stats_accumulate_kernel(const LatArgs a, 
   }
   const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
   const size_t N = (size_t)a.N;
+  // the running sums are streamed once per call (non-temporal hint)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double u = j[c] / r;
-    sums[c * N + n.self] += u;
-    sums[(3 + c) * N + n.self] += u * u;
+    double* s1 = sums + c * N + n.self;
+    double* s2 = sums + (3 + c) * N + n.self;
+    st<true>(s1, ld<double, true>(s1) + u);
+    st<true>(s2, ld<double, true>(s2) + u * u);
   }
 }
 
