@@ -128,3 +128,41 @@ def test_links_errors_and_clearing():
     g2.step(3)
     got2 = g2.populations().cpu().numpy()
     assert np.abs(got2[:, fluid] - ref[:, fluid]).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["fclb", "mrt_table1"])
+@pytest.mark.parametrize("q", [0.2, 0.8])
+def test_couette_no_slip_at_the_wall_distance(name, q):
+    """Physics on the GPU, at any size: steady Couette flow between a solid
+    layer whose wall lies a fraction q of a link from the first fluid plane
+    (curved-wall links) and a moving WALL face is linear with its no-slip
+    point at the wall (the oracle's pin, here on the GPU path)."""
+    Q = 19 if MODELS[name][0] == oracle.MRT19 else 27
+    nx, ny, nz = 1, 10, 1
+    U = 1e-3
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    fu = [[0.0] * 3 for _ in range(6)]
+    fu[3] = [U, 0.0, 0.0]
+    import paper_1206_0389_amd as Pk
+    g = gpu_lattice(name, "f64", (nx, ny, nz), 1.0 / 6.0,
+                    faces=[Pk.PERIODIC, Pk.PERIODIC, Pk.WALL, Pk.WALL, Pk.PERIODIC, Pk.PERIODIC],
+                    face_u=fu)
+    g.set_solids(torch.from_numpy(solid))
+    nodes = np.array([1 * nx], dtype=np.int32)  # the fluid node at y = 1
+    qq = np.zeros((1, Q), np.float32)
+    for k in range(Q):
+        if E[k][1] == -1:
+            qq[0, k] = q
+    g.set_links(torch.from_numpy(nodes), torch.from_numpy(qq))
+    d0, u0 = synth.uniform_fields(nx, ny, nz)
+    g.init_equilibrium(torch.from_numpy(d0), torch.from_numpy(u0))
+    g.step(2500)
+    _, u = g.macroscopic()
+    ux = u[0, 0, 1:, 0].cpu().numpy()
+    y = np.arange(1, ny, dtype=float)
+    y_w = 1.0 - float(np.float32(q))
+    exact = U * (y - y_w) / (ny - 0.5 - y_w)
+    err = np.abs(ux - exact).max() / exact.max()
+    print(name, q, "Couette error", err, flush=True)
+    assert err <= 1e-9, err
