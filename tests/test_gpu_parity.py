@@ -175,6 +175,33 @@ def test_pressure_driven_channel_flow(name):
     assert np.abs(ux - ux[::-1]).max() <= 1e-6 * exact.max()
 
 
+@pytest.mark.parametrize("name", ["mrt_table1", "fclb"])
+def test_free_slip_top_halves_the_channel(name):
+    """Physics of the free-slip faces: the pressure-driven channel of
+    test_pressure_driven_channel_flow with a FREESLIP top instead of a wall
+    is the lower half of a channel twice as high (no shear at the plane
+    half a link above the last node): u(y) = G (y + 1/2)(2 ny - y - 1/2) /
+    (2 nu) for the local gradient G, within 0.5 % mid-channel."""
+    nx, ny, nz = 48, 9, 1
+    nu, d_in, d_out = 0.1, 0.0015, -0.0015
+    faces = [PR, PR, W, F, P, P]
+    g = gpu_lattice(name, "f64", (nx, ny, nz), nu, faces=faces, face_u=[[0.0] * 3] * 6,
+                    face_drho=[d_in, d_out, 0, 0, 0, 0])
+    d0, u0 = synth.uniform_fields(nx, ny, nz)
+    g.init_equilibrium(torch.from_numpy(d0), torch.from_numpy(u0))
+    g.step(12000)
+    d, u = (t.cpu().numpy() for t in g.macroscopic())
+    dc = d[0, ny // 2, :]
+    G = -(dc[nx // 2 + 5] - dc[nx // 2 - 5]) / 10 / 3.0
+    y = np.arange(ny)
+    ux = u[0, 0, :, nx // 2]
+    exact = G * (y + 0.5) * (2 * ny - y - 0.5) / (2 * nu)
+    err = np.abs(ux - exact).max() / exact.max()
+    print(name, "half-channel error", err, flush=True)
+    assert err <= 5e-3, err
+    assert np.abs(u[1, 0, :, nx // 2]).max() <= 1e-4 * exact.max()
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_equilibrium_macroscopic_and_reductions(name):
     shape = (16, 8, 6)
