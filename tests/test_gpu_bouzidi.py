@@ -3,7 +3,7 @@ bounce-back on links to solid nodes) against the oracle.
 
 Fluid nodes are compared element by element after 1, 2 and 5 steps (both
 in-place parities) with the bounds of test_gpu_parity.py (FP64 1e-12, FP32
-4e-6 per step of the largest population). Geometries come from a point
+4e-6, FP16 2e-3 per step of the largest population). Geometries come from a point
 predicate with wall distances found by bisection (synth.link_distances): a
 sphere in a periodic box (every q in (0, 1], links in all directions) and
 the round nozzle tube of the jet workload at reduced size (walls, inlet,
@@ -24,7 +24,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-TOL = {"f64": 1e-12, "f32": 4e-6}
+TOL = {"f64": 1e-12, "f32": 4e-6, "f16": 2e-3}
 
 
 def _sphere(nx, ny, nz, c, r):
@@ -69,14 +69,15 @@ def _oracle(name, shape, solid, lq, kw):
 
 @pytest.mark.parametrize("name", ["fclb", "mrt_table1", "mrt_dhumieres"])
 @pytest.mark.parametrize("kind", ["sphere_periodic", "nozzle_jet"])
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_links_against_oracle(name, kind, storage):
     Q = 19 if MODELS[name][0] == oracle.MRT19 else 27
     shape, solid, nodes, q, kw = _case(kind, Q)
     nx, ny, nz = shape
     print("case links", name, kind, storage, shape, "nodes", len(nodes), flush=True)
     f0 = synth.random_populations(Q, (nz, ny, nx), amp=1e-2, seed=29)
-    f0 = f0.astype(np.float32 if storage == "f32" else np.float64).astype(np.float64)
+    f0 = f0.astype({"f64": np.float64, "f32": np.float32, "f16": np.float16}[storage])
+    f0 = f0.astype(np.float64)
     g = gpu_lattice(name, storage, shape, 0.02, cs=0.1, **kw)
     g.set_solids(torch.from_numpy(solid))
     g.set_links(torch.from_numpy(nodes), torch.from_numpy(q))
