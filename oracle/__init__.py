@@ -37,10 +37,12 @@ Parity status of each oracle function (what pins it, see tests/):
                               across a periodic box blocks all transport
   FREESLIP faces (run)        free-slip y faces equal the mirror-symmetric
                               half of a periodic lattice twice as high;
-                              uniform tangential flow is kept exactly
+                              uniform tangential flow is kept exactly; a
+                              free-slip top halves a pressure-driven channel
   PRESSURE faces (run)        plug flow from a velocity inlet to a pressure
                               outlet is a fixed point; a closed box with a
-                              pressure face relaxes to the face's density
+                              pressure face relaxes to the face's density;
+                              a pressure drop drives plane Poiseuille flow
   jet_profile (Eqs. 23-24)    a field linear in the section (bilinear
                               exact): closed-form crossing radii; Gaussian
                               and elliptic jets: r_e at the e-folding radius

@@ -66,3 +66,20 @@ def test_uniform_tangential_flow_is_kept(model, Q):
             assert np.abs(f - f0).max() <= 1e-12 * np.abs(f0).max()
         else:
             assert np.abs(v[0] - 0.04).max() > 1e-3
+
+
+def test_free_slip_top_halves_a_pressure_driven_channel():
+    """A pressure-driven channel with a FREESLIP top is the lower half of a
+    channel twice as high: no shear at the plane half a link above the last
+    node, u = G (y + 1/2)(2 ny - y - 1/2) / (2 nu) mid-channel (0.5 %)."""
+    P, W, PR, F = oracle.PERIODIC, oracle.WALL, oracle.PRESSURE, oracle.FREESLIP
+    nx, ny, nz, nu = 48, 9, 1, 0.1
+    o = oracle.Lattice(oracle.MRT19, nx, ny, nz, nu=nu, faces=[PR, PR, W, F, P, P],
+                       face_drho=[0.0015, -0.0015, 0, 0, 0, 0])
+    f = o.run(o.init_equilibrium(np.zeros((nz, ny, nx)), np.zeros((3, nz, ny, nx))), 0, 12000)
+    d, u = o.macroscopic(f)
+    dc = d[0, ny // 2, :]
+    G = -(dc[nx // 2 + 5] - dc[nx // 2 - 5]) / 10 / 3.0
+    y = np.arange(ny)
+    exact = G * (y + 0.5) * (2 * ny - y - 0.5) / (2 * nu)
+    assert np.abs(u[0, 0, :, nx // 2] - exact).max() <= 5e-3 * exact.max()
