@@ -83,7 +83,7 @@ typedef struct lbm_lattice lbm_lattice;
  *              cascaded scheme before the factorization, Section 2: the same
  *              central moments and rates as the FCLB, with the fourth- and
  *              sixth-order central moments relaxed to those of the Gaussian,
- *              rho/9, 0 and rho/27; uniform lattices only, no adjoint).
+ *              rho/9, 0 and rho/27; no adjoint).
  *   storage    LBM_F64, LBM_F32 or LBM_F16 (population deviations).
  *   nx,ny,nz   lattice nodes, each >= 1; nx*ny*nz < 2^31.
  *   nu         lattice kinematic viscosity, > 0; the molecular relaxation

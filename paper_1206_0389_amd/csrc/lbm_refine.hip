@@ -312,6 +312,7 @@ void with_kind_s(const lbm_refined* R, Fn&& fn) {
   switch (R->kind) {
     case 0: by_s(std::integral_constant<int, 0>{}); break;
     case 1: by_s(std::integral_constant<int, 1>{}); break;
+    case 3: by_s(std::integral_constant<int, 3>{}); break;
     default: by_s(std::integral_constant<int, 2>{}); break;
   }
 }
@@ -501,7 +502,8 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask
                        lbm_refined** out) {
   if (!cfg || !mask || !out) return LBM_EINVAL;
   const lbm_config& c = *cfg;
-  if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB) return LBM_EINVAL;
+  if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB && c.model != LBM_D3Q27_CLB)
+    return LBM_EINVAL;
   if (c.storage != LBM_F64 && c.storage != LBM_F32 && c.storage != LBM_F16) return LBM_EINVAL;
   if (block < 2 || c.nx < 4 || c.ny < 4 || c.nz < 4) return LBM_EINVAL;
   if (c.nx % block || c.ny % block || c.nz % block) return LBM_EINVAL;
@@ -516,8 +518,10 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask
   lbm_refined* R = new (std::nothrow) lbm_refined();
   if (!R) return LBM_EINVAL;
   R->cfg = c;
-  R->kind = c.model == LBM_D3Q27_FCLB ? 2 : (c.mrt_basis == LBM_BASIS_TABLE1 ? 0 : 1);
-  R->Q = c.model == LBM_D3Q27_FCLB ? 27 : 19;
+  R->kind = c.model == LBM_D3Q27_FCLB ? 2
+            : c.model == LBM_D3Q27_CLB  ? 3
+                                        : (c.mrt_basis == LBM_BASIS_TABLE1 ? 0 : 1);
+  R->Q = c.model == LBM_D3Q19_MRT_LES ? 19 : 27;
   R->elem = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
   R->relem = c.storage == LBM_F64 ? 8 : 4;
   R->B = block;

@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void masked_reduce_kernel(const Level L, int w
         j[1] += cy(i) * fi;
         j[2] += cz(i) * fi;
       }
-      const double r = (KIND == 2) ? 1.0 + d : 1.0;
+      const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
       v[0] = w * d;
       v[1] = w * j[0];
       v[2] = w * j[1];

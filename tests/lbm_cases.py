@@ -11,8 +11,8 @@ MODELS = {  # name: (model code, mrt basis)
     "mrt_dhumieres": (oracle.MRT19, oracle.BASIS_DHUMIERES),
     "clb": (oracle.CLB27, oracle.BASIS_TABLE1),
 }
-# the refined lattice runs the FCLB and the MRT only
-REFINED_MODELS = [n for n in MODELS if n != "clb"]
+# the models the refined lattice runs (all of them)
+REFINED_MODELS = list(MODELS)
 W, I, O, P = oracle.WALL, oracle.INLET, oracle.OUTFLOW, oracle.PERIODIC
 JET_FACES = [W, W, W, W, I, O]
 
