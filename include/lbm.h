@@ -447,7 +447,8 @@ int lbm_refined_required_bytes(const lbm_refined* r, size_t* bytes);
 int lbm_refined_bind_memory(lbm_refined* r, void* dev, size_t bytes);
 
 /* Boundary description of the domain (as lbm_set_boundaries, applied on
- * both levels; outflow may be any face). With an inlet face the fine level
+ * both levels, LBM_FREESLIP and LBM_PRESSURE faces included; outflow may be
+ * any face). With an inlet face the fine level
  * needs its own inlet arrays at fine resolution, [3][2 nb][2 na] and
  * [2 nb][2 na] (mask may be NULL), same dtype; it draws its perturbation
  * with seed + 1 and the fine step index. Must precede

@@ -1000,10 +1000,44 @@ double fine_pull(const Refine& R, const double* in, int i, int lx, int ly, int l
         return in[io * Nf + self] +
                6.0 * weight(Q, i) * (E[i][0] * uin[0] + E[i][1] * uin[1] + E[i][2] * uin[2]);
       }
+    // PRESSURE and FREESLIP faces: the rules of classify() and pull() on the
+    // fine level's box
+    for (int face = 0; face < 6; ++face)
+      if (crossed[face] && p->face_type[face] == ORC_PRESSURE) {
+        double d = 0.0, jm[3] = {0, 0, 0};
+        for (int k = 0; k < Q; ++k) {
+          const double v = in[k * Nf + self];
+          d += v;
+          for (int a = 0; a < 3; ++a) jm[a] += v * E[k][a];
+        }
+        const double rho = (p->model == ORC_MRT19) ? 1.0 : 1.0 + d;
+        const double ub[3] = {jm[0] / rho, jm[1] / rho, jm[2] / rho};
+        const double drho = p->face_drho[face];
+        double feq[27];
+        if (p->model == ORC_MRT19) {
+          feq_incomp(19, drho, ub, feq);
+        } else {
+          for (int k = 0; k < 27; ++k)
+            feq[k] = (1.0 + drho) * phi(E[k][0], ub[0]) * phi(E[k][1], ub[1]) *
+                         phi(E[k][2], ub[2]) -
+                     weight(27, k);
+        }
+        return -in[io * Nf + self] + feq[i] + feq[io];
+      }
     for (int d = 0; d < 3; ++d) {
       if (s[d] < 0) s[d] = 0;
       if (s[d] >= n[d]) s[d] = n[d] - 1;
     }
+    int e[3] = {E[i][0], E[i][1], E[i][2]};
+    bool mirrored = false;
+    for (int face = 0; face < 6; ++face)
+      if (crossed[face] && p->face_type[face] == ORC_FREESLIP) {
+        e[face / 2] = -e[face / 2];
+        mirrored = true;
+      }
+    if (mirrored)
+      return in[velocity_index(Q, e[0], e[1], e[2]) * Nf +
+                fidx(R, s[0] - R.lo[0], s[1] - R.lo[1], s[2] - R.lo[2])];
   }
   return in[i * Nf + fidx(R, s[0] - R.lo[0], s[1] - R.lo[1], s[2] - R.lo[2])];
 }
@@ -1064,6 +1098,9 @@ void* orc_refine_create(const orc_params* coarse, int block, const uint8_t* mask
       R->f.inlet_nb = n2[d == 2 ? 1 : 2];
     }
   R->f.seed = coarse->seed + 1;
+  R->f.solid = nullptr;  // neither level has interior solids or curved links
+  R->f.link_q = nullptr;
+  R->c.link_q = nullptr;
   for (int k = 0; k < 3; ++k) R->f.origin[k] = 0;
   const double tc = 3.0 * coarse->nu + 0.5, tf = 3.0 * R->f.nu + 0.5;
   R->r = (tf - 1.0) / (2.0 * (tc - 1.0));

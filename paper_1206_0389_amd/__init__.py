@@ -617,7 +617,8 @@ class RefinedLattice:
     def __init__(self, model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01, cs_smag=0.0,
                  mrt_basis=BASIS_TABLE1, rates=None, block=16, mask=None, faces=None,
                  face_u=None, inlet_u=None, inlet_mask=None, fine_inlet_u=None,
-                 fine_inlet_mask=None, inlet_amp=0.0, seed=0, device="cuda", stream=None):
+                 fine_inlet_mask=None, inlet_amp=0.0, seed=0, device="cuda", stream=None,
+                 face_drho=None):
         import numpy as np
         self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
         self.Q = 19 if self.cfg.model == D3Q19_MRT_LES else 27
@@ -640,6 +641,9 @@ class RefinedLattice:
                 for k in range(6):
                     for c in range(3):
                         bc.face_u[k][c] = float(face_u[k][c])
+            if face_drho is not None:
+                for k in range(6):
+                    bc.face_drho[k] = float(face_drho[k])
             fiu = fim = None
             if inlet_u is not None:
                 ax = [k for k in range(6) if int(faces[k]) == INLET][0] // 2

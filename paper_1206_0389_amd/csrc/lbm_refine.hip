@@ -647,7 +647,7 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
   int n_inlet = 0, n_out = 0;
   for (int f = 0; f < 6; ++f) {
     const int ty = bc->face_type[f];
-    if (ty < LBM_PERIODIC || ty > LBM_OUTFLOW) return LBM_EINVAL;
+    if (ty < LBM_PERIODIC || ty > LBM_PRESSURE) return LBM_EINVAL;
     if (ty != LBM_PERIODIC) b.nonper |= 1u << f;
     for (int k = 0; k < 3; ++k) {
       if (!std::isfinite(bc->face_u[f][k])) return LBM_EINVAL;
@@ -662,6 +662,12 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
     if (ty == LBM_OUTFLOW) {
       b.outflow |= 1u << f;
       ++n_out;
+    }
+    if (ty == LBM_FREESLIP) b.freeslip |= 1u << f;
+    if (ty == LBM_PRESSURE) {
+      if (!std::isfinite(bc->face_drho[f]) || !(bc->face_drho[f] > -1.0)) return LBM_EINVAL;
+      b.pressure |= 1u << f;
+      b.face_drho[f] = bc->face_drho[f];
     }
   }
   for (int d = 0; d < 3; ++d)

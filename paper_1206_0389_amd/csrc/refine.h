@@ -132,8 +132,10 @@ __device__ __forceinline__ BoxNode make_box_node(const Level& L, int lx, int ly,
 
 // Pull of population I in two-array post-collision storage: the source
 // node's own slot I; across a WALL/INLET face the node's slot opp(I) (plus
-// the bounce-back term, pull_term); across an OUTFLOW face slot I of the
-// source with the crossed coordinates kept.
+// the bounce-back term, pull_term); across a PRESSURE face the same slot
+// (completed by ab_pressure); across FREESLIP faces slot k (I mirrored
+// across them) of the source with the crossed coordinates kept; across an
+// OUTFLOW face slot I of that source.
 template <int Q, int I, typename S>
 __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, const BoxNode& n) {
   constexpr int IO = opposite<Q>(I);
@@ -145,8 +147,39 @@ __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, con
   const int ky = (crossed & 12u) ? 0 : -cy(I);
   const int kz = (crossed & 48u) ? 0 : -cz(I);
   const S* outflow = A + (size_t)I * N + n.at(kx, ky, kz);
-  const bool bb = (crossed & (L.bc.wall | L.bc.inlet)) != 0;
-  return bb ? own : (crossed ? outflow : normal);
+  const bool bb = (crossed & (L.bc.wall | L.bc.inlet | L.bc.pressure)) != 0;
+  const uint32_t fs = crossed & L.bc.freeslip;
+  const S* slip = A + (size_t)mirror_slot<Q, I, false>(slip_axes(fs)) * N + n.at(kx, ky, kz);
+  return bb ? own : (fs ? slip : (crossed ? outflow : normal));
+}
+
+// Completes the pull at a node on PRESSURE faces: f_I = -f*_opp(I) +
+// feq_I + feq_opp(I) (anti-bounce-back at the face density) for the
+// directions entering through one and through no WALL or INLET face, with
+// the node's velocity of its post-collision state, slot K holding f*_K.
+template <int Q, typename real, typename S>
+__device__ __forceinline__ void ab_pressure(const Level& L, const S* A, const BoxNode& n,
+                                            real (&f)[Q]) {
+  constexpr int KQ = Q == 27 ? 2 : 0;
+  const size_t N = (size_t)L.Nbox;
+  real d = 0, j[3] = {0, 0, 0};
+  static_for<0, Q>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const real v = ld<real>(A + (size_t)K * N + n.self);
+    d += v;
+    j[0] += real(cx(K)) * v;
+    j[1] += real(cy(K)) * v;
+    j[2] += real(cz(K)) * v;
+  });
+  const real rho = Q == 27 ? real(1) + d : real(1);
+  const real u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  static_for<0, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const uint32_t crossed = n.atface & pull_faces(I);
+    if ((crossed & L.bc.pressure) && !(crossed & (L.bc.wall | L.bc.inlet)))
+      f[I] = -f[I] + pressure_pair<KQ, I, real>(
+                         real(pressure_drho(L.bc, crossed & L.bc.pressure)), u);
+  });
 }
 
 // Wall-row pull (rows off every non-periodic z face and off y faces that are
@@ -230,6 +263,7 @@ __global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows 
         constexpr int I = decltype(ic)::value;
         f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
       });
+      if (n.atface & L.bc.pressure) ab_pressure<Q, real, S>(L, A, n, f);
     }
   } else if constexpr (BCM == BC_WALLS) {
     static_for<0, Q>([&](auto ic) {

@@ -26,14 +26,14 @@ FACE_U = [[0.0, 0.001, 0.002], [0.0, 0.0, 0.002], [0.001, 0.0, 0.002], [0.0, 0.0
           [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]]
 
 
-def _pair(name, storage, jet=True, nu=0.02, cs=0.1):
+def _pair(name, storage, jet=True, nu=0.02, cs=0.1, faces=None, face_drho=None):
     import paper_1206_0389_amd as Pk
     model, basis = MODELS[name]
-    print("case refine", name, storage, "jet" if jet else "slab", flush=True)
+    print("case refine", name, storage, "jet" if jet else "slab", faces, flush=True)
     if jet:
         n, nz, B, mask = _jet_case(model)
         nx = ny = n
-        faces = [W, W, W, W, I, O]
+        faces = faces or [W, W, W, W, I, O]
         iu, im = synth.jet_inlet(n, n, 4.0, 0.05, 0.002)
         fiu, fim = synth.jet_inlet(2 * n, 2 * n, 8.0, 0.05, 0.002)
     else:
@@ -41,7 +41,7 @@ def _pair(name, storage, jet=True, nu=0.02, cs=0.1):
         nz = 64
         mask = np.zeros((16, 1, 1), dtype=np.uint8)
         mask[6:10] = 1
-        faces = [P] * 6
+        faces = faces or [P] * 6
         iu = im = fiu = fim = None
     g = Pk.RefinedLattice(model=model, storage=storage, shape=(nx, ny, nz), nu=nu, cs_smag=cs,
                           mrt_basis=basis, block=B, mask=mask, faces=faces, face_u=FACE_U,
@@ -49,9 +49,10 @@ def _pair(name, storage, jet=True, nu=0.02, cs=0.1):
                           inlet_mask=None if im is None else torch.from_numpy(im),
                           fine_inlet_u=None if fiu is None else torch.from_numpy(fiu),
                           fine_inlet_mask=None if fim is None else torch.from_numpy(fim),
-                          inlet_amp=5e-4, seed=11)
+                          inlet_amp=5e-4, seed=11, face_drho=face_drho)
     c = oracle.Lattice(model, nx, ny, nz, nu=nu, cs_smag=cs, basis=basis, faces=faces,
-                       face_u=FACE_U, inlet_u=iu, inlet_mask=im, inlet_amp=5e-4, seed=11)
+                       face_u=FACE_U, inlet_u=iu, inlet_mask=im, inlet_amp=5e-4, seed=11,
+                       face_drho=face_drho)
     R = oracle.Refined(c, B, mask, fiu, fim)
     assert g.fine_lo == R.lo and g.fine_dims == R.M
     assert g.counts == R.counts
@@ -76,9 +77,17 @@ def _oracle_reduce(R, c, fc, ff):
 
 
 @pytest.mark.parametrize("name", REFINED_MODELS)
-@pytest.mark.parametrize("jet", [True, False])
+@pytest.mark.parametrize("jet", [True, False, "slip_pressure", "slab_slip_pressure"])
 def test_refined_step_parity_fp64(name, jet):
-    g, R, c = _pair(name, "f64", jet=jet)
+    F, PR = oracle.FREESLIP, oracle.PRESSURE
+    if jet == "slip_pressure":  # a free-slip top and a fixed-pressure outlet (coarse level)
+        g, R, c = _pair(name, "f64", jet=True, faces=[W, W, W, F, I, PR],
+                        face_drho=[0, 0, 0, 0, 0, -0.002])
+    elif jet == "slab_slip_pressure":  # the fine slab spans free-slip x and pressure y faces
+        g, R, c = _pair(name, "f64", jet=False, faces=[F, F, PR, PR, P, P],
+                        face_drho=[0, 0, 0.001, -0.001, 0, 0])
+    else:
+        g, R, c = _pair(name, "f64", jet=jet)
     Q = c.Q
     fc = synth.random_populations(Q, c.shape, 1e-2, seed=1)
     ff = synth.random_populations(Q, R.fine_shape, 1e-2, seed=2)
