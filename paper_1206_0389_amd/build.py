@@ -29,23 +29,46 @@ def hipcc() -> str:
 
 
 def flags():
-    return ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-shared",
+    return ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + ["-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def _errors(stderr: str) -> str:
     noise = "is not a recognized feature for this target"
-    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if err.strip() and verbose:
-        print(err, file=sys.stderr)
+    return "\n".join(l for l in stderr.splitlines() if noise not in l)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles the sources to objects concurrently, then links them."""
+    import tempfile
+    tmp = LIB + ".tmp"
+    with tempfile.TemporaryDirectory(prefix="lbm_build_") as tdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tdir, os.path.basename(src) + ".o")
+            cmd = [hipcc()] + flags() + ["-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                          text=True))
+            objs.append(obj)
+        failed = []
+        for pr in procs:
+            _, err = pr.communicate()
+            err = _errors(err)
+            if pr.returncode != 0:
+                failed.append(err)
+            elif err.strip() and verbose:
+                print(err, file=sys.stderr)
+        if failed:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + _errors(res.stderr))
     os.replace(tmp, LIB)
     return LIB
 
