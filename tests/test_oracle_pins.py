@@ -527,3 +527,105 @@ def test_inlet_outflow_plug_flow_carries_inlet_flux(model):
     rho = 1.0 if model == oracle.MRT19 else 1.0 + drho
     assert np.allclose(rho * u[2], uin, rtol=1e-3)
     assert np.abs(u[0]).max() < 1e-12 and np.abs(u[1]).max() < 1e-12
+
+
+# Moment polynomials typed here from their published definitions, independent
+# of the oracle's tables: d'Humieres et al. (2002) orthogonal D3Q19 basis with
+# the name of the rate each row relaxes with ("nu" = the viscous rate 1/tau).
+_DH_ROWS = [
+    ("rho", lambda x, y, z: 1.0, None),
+    ("e", lambda x, y, z: 19 * (x * x + y * y + z * z) - 30, "s_e"),
+    ("eps", lambda x, y, z: (21 * (x * x + y * y + z * z) ** 2
+                             - 53 * (x * x + y * y + z * z) + 24) / 2, "s_eps"),
+    ("jx", lambda x, y, z: x, None),
+    ("qx", lambda x, y, z: (5 * (x * x + y * y + z * z) - 9) * x, "s_q"),
+    ("jy", lambda x, y, z: y, None),
+    ("qy", lambda x, y, z: (5 * (x * x + y * y + z * z) - 9) * y, "s_q"),
+    ("jz", lambda x, y, z: z, None),
+    ("qz", lambda x, y, z: (5 * (x * x + y * y + z * z) - 9) * z, "s_q"),
+    ("pxx", lambda x, y, z: 3 * x * x - (x * x + y * y + z * z), "nu"),
+    ("pixx", lambda x, y, z: (3 * (x * x + y * y + z * z) - 5)
+     * (3 * x * x - (x * x + y * y + z * z)), "s_pi"),
+    ("pww", lambda x, y, z: y * y - z * z, "nu"),
+    ("piww", lambda x, y, z: (3 * (x * x + y * y + z * z) - 5) * (y * y - z * z), "s_pi"),
+    ("pxy", lambda x, y, z: x * y, "nu"),
+    ("pyz", lambda x, y, z: y * z, "nu"),
+    ("pxz", lambda x, y, z: x * z, "nu"),
+    ("mx", lambda x, y, z: (y * y - z * z) * x, "s_m"),
+    ("my", lambda x, y, z: (z * z - x * x) * y, "s_m"),
+    ("mz", lambda x, y, z: (x * x - y * y) * z, "s_m"),
+]
+
+# Table 1 of the paper: moment groups and their rate names (s1 = the shear
+# rate 1/tau; the two fourth-order rows printed with the label s7 relax at s7,
+# and the third the same: "for D3Q19 only s1, s2, s3, s4, s7").
+_T1_ROWS = [
+    (lambda x, y, z: 1.0, None), (lambda x, y, z: x, None), (lambda x, y, z: y, None),
+    (lambda x, y, z: z, None),
+    (lambda x, y, z: x * y, "s1"), (lambda x, y, z: x * z, "s1"),
+    (lambda x, y, z: y * z, "s1"), (lambda x, y, z: x * x - y * y, "s1"),
+    (lambda x, y, z: x * x - z * z, "s1"), (lambda x, y, z: x * x + y * y + z * z, "s2"),
+    (lambda x, y, z: x * y * y + x * z * z, "s3"), (lambda x, y, z: x * x * y + y * z * z, "s3"),
+    (lambda x, y, z: x * x * z + y * y * z, "s3"),
+    (lambda x, y, z: x * y * y - x * z * z, "s4"), (lambda x, y, z: x * x * y - y * z * z, "s4"),
+    (lambda x, y, z: x * x * z - y * y * z, "s4"),
+    (lambda x, y, z: x * x * y * y - 2 * x * x * z * z + y * y * z * z, "s7"),
+    (lambda x, y, z: x * x * y * y + x * x * z * z - 2 * y * y * z * z, "s7"),
+    (lambda x, y, z: x * x * y * y + x * x * z * z + y * y * z * z, "s7"),
+]
+
+
+def _typed_basis(rows):
+    e, _, _ = oracle.stencil(19)
+    return np.array([[r[1 if len(r) == 3 else 0](*e[i]) for i in range(19)]
+                     for r in rows], dtype=float)
+
+
+def test_dhumieres_rates_relax_their_named_moments():
+    """Perturb the rest state along one published d'Humieres moment (its row
+    itself: the basis is orthogonal, so no other moment is excited; the
+    perturbation has no mass or momentum, so f_eq stays 0 and the collision
+    is linear). With C_S = 0 the named moment must relax by (1 - s_named)
+    and every other published moment must stay 0. Distinct rates per group
+    (and a viscous rate 1/tau0 different from all of them) make any swap of
+    the rate-to-row mapping fail."""
+    Mt = _typed_basis(_DH_ROWS)
+    G = Mt @ Mt.T
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-12  # the typed rows are orthogonal
+    tau0 = 0.8
+    named = {"s_e": 1.11, "s_eps": 1.33, "s_q": 1.55, "s_pi": 1.77, "s_m": 1.91,
+             "nu": 1.0 / tau0}
+    rates = [named[k] for k in ("s_e", "s_eps", "s_q", "s_pi", "s_m")]
+    for k, (name, _, rate) in enumerate(_DH_ROWS):
+        if rate is None:
+            continue
+        f = 1e-3 * Mt[k]
+        fs, tau = oracle.mrt_collide(f, tau0, cs=0.0, basis=oracle.BASIS_DHUMIERES,
+                                     rates=rates)
+        assert abs(tau - tau0) < 1e-15
+        m0, m1 = Mt @ f, Mt @ fs
+        want = m0.copy()
+        want[k] *= 1.0 - named[rate]
+        assert np.abs(m1 - want).max() < 1e-15 * np.abs(m0).max() * 10, name
+
+
+def test_table1_rates_relax_their_named_groups():
+    """The same check for the Table 1 groups (not orthogonal: the test
+    inverts its own typed basis to excite one moment alone): the perturbed
+    moment relaxes by (1 - s) of its group, the other 18 moments stay."""
+    Mt = _typed_basis(_T1_ROWS)
+    Minv = np.linalg.inv(Mt)
+    tau0 = 0.8
+    named = {"s1": 1.0 / tau0, "s2": 1.1, "s3": 1.35, "s4": 1.6, "s7": 1.85}
+    rates = [named[k] for k in ("s2", "s3", "s4", "s7")]
+    for k, (_, rate) in enumerate(_T1_ROWS):
+        if rate is None:
+            continue
+        unit = np.zeros(19)
+        unit[k] = 1e-3
+        f = Minv @ unit
+        fs, _ = oracle.mrt_collide(f, tau0, cs=0.0, basis=oracle.BASIS_TABLE1, rates=rates)
+        m1 = Mt @ fs
+        want = unit.copy()
+        want[k] *= 1.0 - named[rate]
+        assert np.abs(m1 - want).max() < 1e-16, (k, rate)
