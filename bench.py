@@ -28,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -192,22 +193,30 @@ def make_lattice(name, P, torch, synth):
     return lat, desc
 
 
-def time_steps(lat, torch, steps, warmup):
+def time_steps(lat, torch, steps, warmup, windows=5):
+    """ms per step: the median over `windows` consecutive windows that split
+    the K timed steps (HIP events on the kernels' stream at each window
+    boundary; one synchronisation before and after the K steps)."""
     stream = torch.cuda.current_stream()
     lat.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lat.step(steps)
-    e1.record(stream)
+    windows = max(1, min(windows, steps))
+    sizes = [steps // windows + (1 if k < steps % windows else 0) for k in range(windows)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(windows + 1)]
+    ev[0].record(stream)
+    for k, n in enumerate(sizes):
+        lat.step(n)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps  # ms per step
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) / sizes[k] for k in range(windows))
+    total = ev[0].elapsed_time(ev[windows]) / steps
+    return per[len(per) // 2], {"windows": windows, "ms_per_step_windows": per,
+                                "ms_per_step_mean": total}
 
 
 def measure(name, P, torch, synth, steps, warmup):
     lat, desc = make_lattice(name, P, torch, synth)
-    ms = time_steps(lat, torch, steps, warmup)
+    ms, spread = time_steps(lat, torch, steps, warmup)
     red = lat.reduce(check=False)
     model, storage, shape, _ = workload(name)
     q = 19 if model == "mrt" else 27
@@ -217,7 +226,7 @@ def measure(name, P, torch, synth, steps, warmup):
     out = {"name": name, "mlups": n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
            "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
            "bytes_per_lup": 2 * q * BYTES[storage], "finite": all(map(lambda v: v == v, red)),
-           "config": desc}
+           "timing": spread, "config": desc}
     del lat
     torch.cuda.empty_cache()
     return out
@@ -345,13 +354,23 @@ def copy_bandwidth(P, torch, nbytes=4 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(model_name, target_s=15.0):
-    """The FP64 oracle on the host cores, on a 64^3 cut-down of the jet."""
-    if "OMP_NUM_THREADS" not in os.environ:
-        os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
-    cores = int(os.environ["OMP_NUM_THREADS"])
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
+
+
+def cpu_baseline(model_name, target_s=10.0):
+    """The FP64 oracle on the host, on a 64^3 cut-down of the jet: all the
+    cores this process may use, then a single core (OpenMP team size)."""
     import oracle
     import synth
+    cores = len(os.sched_getaffinity(0))
     model = oracle.FCLB27 if model_name == "fclb" else oracle.MRT19
     n = 64
     iu, im = synth.jet_inlet(n, n, 8.0, 0.05, 0.002)
@@ -360,18 +379,25 @@ def cpu_baseline(model_name, target_s=15.0):
                          faces=[oracle.WALL] * 4 + [oracle.INLET, oracle.OUTFLOW], face_u=fu,
                          inlet_u=iu, inlet_mask=im, inlet_amp=5e-4, seed=12060389)
     d, u = synth.uniform_fields(n, n, n, u=(0.0, 0.0, 0.002))
-    f = lat.init_equilibrium(d, u)
-    t0 = time.perf_counter()
-    f = lat.run(f, 0, 1)
-    per = time.perf_counter() - t0
-    steps = max(1, min(200, int(target_s / max(per, 1e-3))))
-    t0 = time.perf_counter()
-    lat.run(f, 1, steps)
-    dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": "FP64 oracle, %s, jet cut-down %d^3 (D=8), %d steps in %.1f s"
-                      % (model_name, n, steps, dt)}
+    f0 = lat.init_equilibrium(d, u)
+    res = {}
+    for label, threads in (("all", cores), ("single", 1)):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        f = lat.run(f0, 0, 1)
+        per = time.perf_counter() - t0
+        steps = max(1, min(200, int(target_s / max(per, 1e-3))))
+        t0 = time.perf_counter()
+        lat.run(f, 1, steps)
+        dt = time.perf_counter() - t0
+        res[label] = (n ** 3 * steps / dt / 1e6, steps, dt, oracle.max_threads())
+    oracle.set_threads(cores)
+    (v_all, s_all, dt_all, c_all), (v_one, s_one, dt_one, _) = res["all"], res["single"]
+    return {"value": v_all, "unit": "MLUPS", "cores": c_all, "kind": "oracle",
+            "single_core_value": v_one, "cpu_model": cpu_model(),
+            "sample": "FP64 oracle, %s, jet cut-down %d^3 (D=8): %d steps in %.1f s on %d "
+                      "threads; %d steps in %.1f s on 1 thread"
+                      % (model_name, n, s_all, dt_all, c_all, s_one, dt_one)}
 
 
 def main():

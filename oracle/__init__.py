@@ -158,8 +158,19 @@ def lib():
         i32p = ctypes.POINTER(ctypes.c_int32)
         L.orc_probe_ke.argtypes = [pp, dp, i32p, i32p, dp]
         L.orc_probe_ke.restype = ctypes.c_double
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """OpenMP team size of the oracle's loops (timing only)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def _dp(a):

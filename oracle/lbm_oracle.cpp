@@ -23,6 +23,7 @@
 // contraction, so results do not depend on the host compiler's choices).
 
 #include <cmath>
+#include <omp.h>
 #include <cstdint>
 #include <cstdlib>
 #include <algorithm>
@@ -613,6 +614,11 @@ void collide_jvp(const orc_params* p, const double* f, const double* v, double* 
 }  // namespace
 
 extern "C" {
+
+// OpenMP team size of the oracle's parallel loops (timing only: the
+// results do not depend on it, every loop writes disjoint entries).
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads() { return omp_get_max_threads(); }
 
 int orc_stencil(int Q, int* e, double* w, int* opp) {
   if (Q != 19 && Q != 27) return -1;

@@ -58,6 +58,8 @@ class InletProbeObjective:
         self._final = None
         self._rec = []    # recorded pre-collision states of one segment
         self._inlet = None
+        self._fwd_inlet = None  # inlet of the last forward pass (its checkpoints)
+        self.forward_count = 0  # forward passes so far (checkpoint generation)
 
     # -- forward ----------------------------------------------------------
     def _reset(self, delta):
@@ -97,10 +99,14 @@ class InletProbeObjective:
             c[1], c[2] = save_state(lat.h, c[0])
             lat.step(min(self.every, self.nsteps - s * self.every))
         self._final[1], self._final[2] = save_state(lat.h, self._final[0])
+        self._fwd_inlet = self._inlet
+        self.forward_count += 1
         return lat.probe_ke(self.lo, self.hi)
 
     def value(self, delta) -> float:
-        """J(delta) without keeping checkpoints (for finite differences)."""
+        """J(delta) without keeping checkpoints (for finite differences). The
+        checkpoints of the last forward pass stay valid: backward restores that
+        pass's inlet before recomputing."""
         self._reset(delta)
         self.lat.step(self.nsteps)
         return self.lat.probe_ke(self.lo, self.hi)
@@ -108,8 +114,17 @@ class InletProbeObjective:
     # -- backward ---------------------------------------------------------
     def backward(self):
         """dJ/du_in on the whole inlet face ([3, nb, na], float64) and
-        dJ/df at the initial state, for the last forward pass."""
+        dJ/df at the initial state, for the last forward pass (whatever ran
+        since: a value() call changes the lattice's inlet, so the forward
+        pass's boundaries are applied again, at the first checkpoint, whose
+        in-place parity is even)."""
+        if self.forward_count == 0:
+            raise RuntimeError("backward needs a forward pass first")
         lat = self.lat
+        buf, t, parity = self._ckpt[0]
+        lat.load_state(buf, t, parity)
+        lat.set_boundaries(self.faces, face_u=self.face_u, inlet_u=self._fwd_inlet)
+        self._inlet = self._fwd_inlet
         dt = lat.adjoint_dtype
         shape = (lat.Q,) + lat.shape3
         lam = torch.empty(shape, dtype=dt, device=lat.device)
@@ -140,11 +155,15 @@ class _ProbeKE(torch.autograd.Function):
     def forward(ctx, delta, obj):
         J = obj.forward(delta)
         ctx.obj = obj
+        ctx.generation = obj.forward_count
         ctx.dtype = delta.dtype
         return torch.tensor(J, dtype=torch.float64, device=delta.device)
 
     @staticmethod
     def backward(ctx, gJ):
+        if ctx.obj.forward_count != ctx.generation:
+            raise RuntimeError("the objective ran another forward pass after the one being "
+                               "differentiated: its checkpoints are gone")
         grad, _ = ctx.obj.backward()
         b0, b1, a0, a1 = ctx.obj.square
         g = grad[2, b0:b1, a0:a1]

@@ -232,8 +232,29 @@ def test_cutdown_gradient_fp32():
     g = grad[2, b0:b1, a0:a1].cpu().numpy()
     rel = float(np.linalg.norm(g - go[2]) / np.linalg.norm(go[2]))
     print("FP32 gradient relative L2 vs FP64 oracle", rel, "J", J, Jo, flush=True)
-    assert abs(J - Jo) <= 1e-3 * abs(Jo)
-    assert rel <= 1e-3
+    assert abs(J - Jo) <= 1e-4 * abs(Jo)
+    assert rel <= 1e-4
+
+
+def test_backward_after_value_and_second_forward():
+    """A value() call between forward and backward (a finite-difference probe
+    at another delta, which changes the lattice's inlet) leaves the gradient
+    of the forward pass unchanged; a second forward through the autograd
+    function before the first one's backward is refused."""
+    obj, c = _jet_objective("f64")
+    delta = torch.from_numpy(c["delta"]).cuda()
+    obj.forward(delta)
+    g1, l1 = obj.backward()
+    obj.forward(delta)
+    obj.value(delta + 1e-3)
+    g2, l2 = obj.backward()
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    d1 = delta.clone().requires_grad_(True)
+    J1 = obj(d1)
+    J2 = obj(delta.clone().requires_grad_(True))
+    with pytest.raises(RuntimeError):
+        J1.backward()
+    J2.backward()
 
 
 def test_checkpoint_spacing_does_not_change_gradient():
@@ -272,8 +293,8 @@ def test_full_jet_fp32_gradient_close_to_fp64():
     (J64, g64), (J32, g32) = r["f64"], r["f32"]
     rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
     print("full jet: J", J64, J32, "FP32 vs FP64 gradient relative L2", rel, flush=True)
-    assert abs(J32 - J64) <= 1e-3 * abs(J64)
-    assert rel <= 1e-3
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    assert rel <= 1e-4
 
 
 @pytest.mark.parametrize("part", range(4))
