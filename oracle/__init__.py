@@ -141,23 +141,26 @@ def lib():
         L.orc_init_equilibrium.argtypes = [pp, dp, dp, dp]
         L.orc_reduce.argtypes = [pp, dp, dp]
         u8p = ctypes.POINTER(ctypes.c_uint8)
-        L.orc_refine_create.argtypes = [pp, ctypes.c_int, u8p, dp, u8p]
-        L.orc_refine_create.restype = ctypes.c_void_p
-        L.orc_refine_destroy.argtypes = [ctypes.c_void_p]
-        L.orc_refine_geometry.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
-                                          ctypes.POINTER(ctypes.c_int32),
-                                          ctypes.POINTER(ctypes.c_int64), dp]
-        L.orc_refine_types.argtypes = [ctypes.c_void_p, u8p, u8p]
-        L.orc_refine_ghosts.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), dp, dp]
-        L.orc_refine_rescale.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
-        L.orc_refine_inject.argtypes = [ctypes.c_void_p, dp, dp]
-        L.orc_refine_run.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int64, ctypes.c_int64]
         L.orc_collide_jvp.argtypes = [pp, dp, dp, dp]
         L.orc_tangent_step.argtypes = [pp, dp, dp, dp]
         L.orc_adjoint_step.argtypes = [pp, dp, dp, dp, dp]
         i32p = ctypes.POINTER(ctypes.c_int32)
         L.orc_probe_ke.argtypes = [pp, dp, i32p, i32p, dp]
         L.orc_probe_ke.restype = ctypes.c_double
+        L.orc_mlref_info.argtypes = [ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64)]
+        L.orc_mlref_types.argtypes = [ctypes.c_void_p, ctypes.c_int, u8p]
+        L.orc_mlref_set_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        L.orc_mlref_get_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        L.orc_mlref_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int32), dp, dp]
+        L.orc_mlref_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, ctypes.c_int, dp]
+        L.orc_mlref_reduce.argtypes = [ctypes.c_void_p, dp]
+        L.orc_mlref_half_step.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp,
+                                          ctypes.c_int, dp]
+        L.orc_mlref_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_mlref_ghost_count.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
@@ -557,90 +560,140 @@ class Lattice:
 
 
 class Refined:
-    """Two-level nested refinement in the oracle (post-collision storage).
+    """Nested time refinement in the oracle: post-collision storage, every
+    level held over its whole domain (see the refinement section of
+    lbm_oracle.cpp for the readings).
 
-    coarse: a :class:`Lattice` describing the full coarse domain; block: the
-    block edge in coarse nodes; mask: uint8 [nz/B][ny/B][nx/B]; fine inlet
-    arrays at fine resolution when the coarse lattice has an inlet face.
+    coarse: a :class:`Lattice` for level 0 (faces, inlet, seed, model).
+    block: block edge B in level-0 nodes. level_map: uint8 [nz/B][ny/B][nx/B],
+    the finest level of each block (a 0/1 mask gives two levels).
+    nlevels: number of levels (default: largest map entry + 1).
+    Per-level lists indexed by level (entries may be None): inlet_u
+    [3][nb][na] and inlet_mask [nb][na] at that level's resolution (levels
+    >= 1 need them when level 0 has an inlet face), solid [nz][ny][nx] masks
+    and link_q [Q][nz][ny][nx] wall distances over the level's whole domain.
     """
 
-    def __init__(self, coarse: Lattice, block: int, mask, fine_inlet_u=None,
-                 fine_inlet_mask=None):
+    def __init__(self, coarse: Lattice, block: int, level_map, nlevels=None, inlet_u=None,
+                 inlet_mask=None, solid=None, link_q=None):
         self.coarse = coarse
-        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.map = np.ascontiguousarray(level_map, dtype=np.uint8)
+        self.L = int(nlevels) if nlevels is not None else int(self.map.max()) + 1
+        self.B = int(block)
+        self.Q = coarse.Q
+        L = self.L
         u8p = ctypes.POINTER(ctypes.c_uint8)
-        self._keep = [self.mask]
-        fu = fm = None
-        if fine_inlet_u is not None:
-            fu = _f64(fine_inlet_u)
-            self._keep.append(fu)
-            fu = _dp(fu)
-        if fine_inlet_mask is not None:
-            fm = np.ascontiguousarray(fine_inlet_mask, dtype=np.uint8)
-            self._keep.append(fm)
-            fm = fm.ctypes.data_as(u8p)
-        self.h = lib().orc_refine_create(ctypes.byref(coarse.p), int(block),
-                                         self.mask.ctypes.data_as(u8p), fu, fm)
+        self._keep = [self.map]
+
+        def arr(vals, conv, ptype):
+            if vals is None:
+                return None
+            a = (ptype * L)()
+            for l in range(min(L, len(vals))):
+                if vals[l] is not None:
+                    v = conv(vals[l])
+                    self._keep.append(v)
+                    a[l] = v.ctypes.data_as(ptype)
+            return a
+
+        u8 = lambda v: np.ascontiguousarray(v, dtype=np.uint8)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib().orc_mlref_create.restype = ctypes.c_void_p
+        lib().orc_mlref_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int,
+                                           u8p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+        self.h = lib().orc_mlref_create(ctypes.byref(coarse.p), self.B, L,
+                                        self.map.ctypes.data_as(u8p),
+                                        arr(inlet_u, _f64, dp), arr(inlet_mask, u8, u8p),
+                                        arr(solid, u8, u8p), arr(link_q, _f64, dp))
         if not self.h:
             raise ValueError("invalid refinement configuration")
-        lo = (ctypes.c_int32 * 3)()
-        M = (ctypes.c_int32 * 3)()
-        cnt = (ctypes.c_int64 * 4)()
-        r = ctypes.c_double()
-        lib().orc_refine_geometry(self.h, lo, M, cnt, ctypes.byref(r))
-        self.lo = tuple(lo)
-        self.M = tuple(M)  # (Mx, My, Mz)
-        self.counts = dict(zip(("fluid", "ghost", "covered", "band"), tuple(cnt)))
-        self.r = r.value
-        self.Q = coarse.Q
-        self.fine_shape = (self.M[2], self.M[1], self.M[0])
+        self.levels = []
+        for l in range(L):
+            n = (ctypes.c_int32 * 3)()
+            box = (ctypes.c_int32 * 6)()
+            cnt = (ctypes.c_int64 * 6)()
+            lib().orc_mlref_info(ctypes.c_void_p(self.h), l, n, box, cnt)
+            self.levels.append({
+                "n": tuple(n), "shape": (n[2], n[1], n[0]), "lo": tuple(box[:3]),
+                "hi": tuple(box[3:]),
+                "counts": dict(zip(("fluid", "band", "covered", "ghost", "solid", "unused"),
+                                   tuple(cnt)))})
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_refine_destroy(self.h)
+            lib().orc_mlref_destroy(ctypes.c_void_p(self.h))
             self.h = None
 
-    def types(self):
-        ct = np.zeros(self.coarse.shape, dtype=np.uint8)
-        ft = np.zeros(self.fine_shape, dtype=np.uint8)
-        u8p = ctypes.POINTER(ctypes.c_uint8)
-        lib().orc_refine_types(self.h, ct.ctypes.data_as(u8p), ft.ctypes.data_as(u8p))
-        return ct, ft
+    def types(self, l):
+        """Node types of level l: 0 unused, 1 fluid, 2 band (inside the next
+        level's region, updated on this level), 3 covered, 4 ghost, 5 solid."""
+        t = np.zeros(self.levels[l]["shape"], dtype=np.uint8)
+        lib().orc_mlref_types(ctypes.c_void_p(self.h), l,
+                              t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        return t
 
-    def ghosts(self, fc=None):
-        ng = self.counts["ghost"]
+    def set_state(self, l, f):
+        f = _f64(f)
+        assert f.shape == (self.Q,) + self.levels[l]["shape"]
+        lib().orc_mlref_set_state(ctypes.c_void_p(self.h), l, _dp(f))
+
+    def state(self, l):
+        f = np.zeros((self.Q,) + self.levels[l]["shape"])
+        lib().orc_mlref_get_state(ctypes.c_void_p(self.h), l, _dp(f))
+        return f
+
+    def run(self, t0, n):
+        lib().orc_mlref_run.restype = ctypes.c_int64
+        bad = lib().orc_mlref_run(ctypes.c_void_p(self.h), ctypes.c_int64(int(t0)),
+                                  ctypes.c_int64(int(n)))
+        if bad:
+            raise RuntimeError("refinement geometry error: %d pulls from unused nodes" % bad)
+
+    def ghosts(self, l, parent=None):
+        """Ghost coordinates of level l >= 1 ([ng][3], x y z) and the raw
+        spatial interpolation of a level l-1 field parent ([Q][...]) at them."""
+        lib().orc_mlref_ghost_count.restype = ctypes.c_int64
+        ng = int(lib().orc_mlref_ghost_count(ctypes.c_void_p(self.h), l))
         coords = np.zeros((ng, 3), dtype=np.int32)
-        g = None
-        if fc is not None:
-            g = np.zeros((self.Q, ng))
-            lib().orc_refine_ghosts(self.h, coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                    _dp(_f64(fc)), _dp(g))
-        else:
-            lib().orc_refine_ghosts(self.h, coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                    None, None)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        if parent is None:
+            lib().orc_mlref_ghosts(ctypes.c_void_p(self.h), l, coords.ctypes.data_as(i32p),
+                                   None, None)
+            return coords, None
+        g = np.zeros((self.Q, ng))
+        lib().orc_mlref_ghosts(ctypes.c_void_p(self.h), l, coords.ctypes.data_as(i32p),
+                               _dp(_f64(parent)), _dp(g))
         return coords, g
 
-    def rescale(self, f, s):
+    def rescale(self, l, f, direction):
+        """Non-equilibrium rescaling of one node between level l-1 and level l
+        (direction +1: a level l-1 state to level l; -1: back). Returns the
+        rescaled populations and the shear ratio."""
         out = np.zeros(self.Q)
-        lib().orc_refine_rescale(self.h, _dp(_f64(f)), float(s), _dp(out))
+        lib().orc_mlref_rescale.restype = ctypes.c_double
+        r = lib().orc_mlref_rescale(ctypes.c_void_p(self.h), l, _dp(_f64(f)), int(direction),
+                                    _dp(out))
+        return out, float(r)
+
+    def half_step(self, l, gm1, g0, gp1, have_prev=True):
+        """Half-step ghost values of level l from raw parent interpolations at
+        t-1, t and t+1 ([Q][ng] each), as a refined step fills them."""
+        ng = g0.shape[1]
+        out = np.zeros((self.Q, ng))
+        lib().orc_mlref_half_step(ctypes.c_void_p(self.h), l, _dp(_f64(gm1)), _dp(_f64(g0)),
+                                  _dp(_f64(gp1)), int(bool(have_prev)), _dp(out))
         return out
 
-    def inject(self, fc, ff):
-        fc = _f64(fc).copy()
-        lib().orc_refine_inject(self.h, _dp(fc), _dp(_f64(ff)))
-        return fc
+    def reduce(self):
+        out = np.zeros(5)
+        lib().orc_mlref_reduce(ctypes.c_void_p(self.h), _dp(out))
+        return out
 
-    def run(self, fc, ff, t0, n):
-        fc = _f64(fc).copy()
-        ff = _f64(ff).copy()
-        lib().orc_refine_run(self.h, _dp(fc), _dp(ff), int(t0), int(n))
-        return fc, ff
-
-    def fine_lattice(self):
-        """An oracle Lattice describing the fine box (fine viscosity), for
-        equilibria and macroscopic readouts of the fine level."""
+    def level_lattice(self, l):
+        """An oracle Lattice with level l's parameters (viscosity 2^l nu_0)
+        over its whole domain, for equilibria and macroscopic readouts."""
         c = self.coarse
-        lat = Lattice(c.model, self.M[0], self.M[1], self.M[2], nu=2.0 * c.p.nu,
-                      cs_smag=c.p.cs_smag, basis=c.p.mrt_basis,
-                      rates=list(c.p.rates)[:5])
-        return lat
+        nx, ny, nz = self.levels[l]["n"]
+        return Lattice(c.model, nx, ny, nz, nu=c.p.nu * 2 ** l, cs_smag=c.p.cs_smag,
+                       basis=c.p.mrt_basis, rates=list(c.p.rates)[:5])

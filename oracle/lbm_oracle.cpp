@@ -770,59 +770,107 @@ void orc_reduce(const orc_params* p, const double* f, double* out) {
 }  // extern "C"
 
 // ===========================================================================
-// Two-level nested time refinement (Section 1: hierarchical block grid with a
-// nested time step, Yu et al.'s interpolation and rescaling; Section 3:
-// refinement levels, constant CFL). The paper cites the method and prints no
-// formulas; this follows the readings recorded in the design notes:
-//  * 2:1 vertex-centred nesting: fine node j sits at coarse coordinate j/2;
-//    a refined coarse block of B^3 nodes carries (2B)^3 fine nodes;
-//    dt_f = dt_c / 2, so in lattice units nu_f = 2 nu_c (tau_f - 1/2 =
-//    2 (tau_c - 1/2)) and velocities are equal on both levels.
-//  * Both levels store post-collision values and advance by pull + collide.
-//  * Fine ghost nodes (outside the refined region, next to it) hold coarse
-//    post-collision populations interpolated in space (tensor 4-point cubic
-//    Lagrange, one-sided near non-periodic domain faces) and in time (linear
-//    between the coarse states at t and t+1 for the half step), rescaled
-//    f_f = f_eq + r (f_c - f_eq), r = (tau_f - 1) / (2 (tau_c - 1)).
-//  * Covered coarse nodes (refined, outside every ghost stencil) receive
-//    f_c = f_eq + (f_f - f_eq) / r from the coincident fine node after each
-//    coarse step.
+// Nested time refinement on a hierarchical block grid (Section 1: block grid
+// with a nested time step and Yu et al.'s interpolation and rescaling of the
+// non-equilibrium part; Section 3: refinement levels, constant CFL number).
+// The paper cites the interface method and prints no formulas; the readings
+// used here are:
+//  * Levels l = 0 .. L-1. Level l has spacing and time step 2^-l of level 0
+//    (the velocity scale, hence the CFL number, is the same on every level),
+//    lattice viscosity 2^l nu_0 (tau_l - 1/2 = 2^l (tau_0 - 1/2)); the
+//    Smagorinsky constant acts in each level's own lattice units.
+//  * A map over the level-0 blocks (B^3 nodes) names the finest level of
+//    each block; R_l is the union of the blocks whose entry is >= l.
+//  * Cell-centred 2:1 nesting: level-(l+1) node j lies at level-l coordinate
+//    j/2 - 1/4 (node i's cell holds the children 2i, 2i+1 on each axis), so
+//    the halfway walls and faces of all levels coincide.
+//  * Every level stores post-collision populations; a level step pulls and
+//    collides.
+//  * Level-(l+1) ghost nodes (the layer just outside R_{l+1}) receive
+//    level-l post-collision values interpolated in space (tensor 4-point
+//    cubic Lagrange; windows kept inside non-periodic domains) and in time
+//    (three-point quadratic over the level-l states at t-1, t, t+1 for the
+//    half step, weights -1/8, 3/4, 3/8; linear for the first step after a
+//    state change, when t-1 is unknown), then rescaled.
+//  * Covered level-l nodes (inside R_{l+1}, read by no ghost stencil)
+//    receive the mean of their 8 children, rescaled back, once the two
+//    level-(l+1) substeps are done.
+//  * Rescaling of the non-equilibrium part from a parent level c to its
+//    child f (Chapman-Enskog: the post-collision non-equilibrium of a moment
+//    relaxed at 1/tau scales as (tau - 1) dt): FCLB/CLB one ratio
+//    r = (tau_f - 1) / (2 (tau_c - 1)); MRT per moment group with tau = 1/s
+//    (non-shear rates are the same on both levels: r = 1/2, and 0 where the
+//    rate is 1, whose post-collision non-equilibrium vanishes), the shear
+//    group with the total relaxation times of Eq. (20): tau_c,tot recovered
+//    from the post-collision traceless stress of the interpolated state (the
+//    stress taken traceless before the collision), tau_f,tot = tau0_f +
+//    (tau_c,tot - tau0_c) / 2 (the eddy viscosity halves in fine lattice
+//    units). Back from f to c: the inverse ratios, tau_c,tot = tau0_c +
+//    2 (tau_f,tot - tau0_f).
+// Every level is held over its whole domain here (plain, not memory-lean).
 // ===========================================================================
 
 namespace {
 
-struct Refine {
-  orc_params c;      // coarse lattice (full domain)
-  orc_params f;      // fine level: global fine extent 2N, fine viscosity
-  int B;             // block size (coarse nodes)
-  int nb[3];         // blocks per axis
-  std::vector<uint8_t> mask;
-  int lo[3], M[3];   // fine box origin (global fine coords) and extent
-  std::vector<uint8_t> ctype;  // 0 outside R, 1 refined (band), 2 covered
-  std::vector<uint8_t> ftype;  // 0 inactive, 1 fluid, 2 ghost
-  std::vector<long> ghosts;    // fine box indices of ghost nodes
-  double r;
-  int Q;
-  std::vector<double> g0, g1;  // interpolated coarse values at ghosts [Q][ng]
-  bool have_g0 = false;
+enum { T_UNUSED = 0, T_FLUID = 1, T_BAND = 2, T_COVERED = 3, T_GHOST = 4, T_SOLID = 5 };
+
+struct MLevel {
+  orc_params p;                   // this level's lattice over its whole domain
+  int n[3];
+  long N;
+  std::vector<uint8_t> type;      // [N]
+  std::vector<double> f, g;       // post-collision state and a work array [Q][N]
+  std::vector<long> ghosts;       // node indices of the ghost layer (l >= 1)
+  std::vector<double> G[3];       // parent values at the ghosts at t-1, t, t+1
+  bool have_cur = false, have_prev = false;
+  std::vector<uint8_t> solid;
+  std::vector<double> link_q, inlet_u;
+  std::vector<uint8_t> inlet_mask;
+  int box_lo[3], box_hi[3];       // bounding box of the non-unused nodes
+  long bad_pull = 0;              // pulls from unused nodes (geometry error)
 };
 
-bool refined_block(const Refine& R, int bx, int by, int bz) {
-  return R.mask[((long)bz * R.nb[1] + by) * R.nb[0] + bx] != 0;
+struct MLRefine {
+  int L, B, Q, nb[3];
+  std::vector<uint8_t> map;
+  std::vector<MLevel> lev;
+};
+
+int block_level(const MLRefine& R, int bx, int by, int bz) {
+  return R.map[((long)bz * R.nb[1] + by) * R.nb[0] + bx];
 }
 
-bool coarse_in_R(const Refine& R, int x, int y, int z) {
-  return refined_block(R, x / R.B, y / R.B, z / R.B);
+// Is node x of level l inside R_m (m <= l)?
+bool in_region(const MLRefine& R, int l, int m, const int x[3]) {
+  const MLevel& V = R.lev[l];
+  int b[3];
+  for (int d = 0; d < 3; ++d) {
+    if (x[d] < 0 || x[d] >= V.n[d]) return false;
+    b[d] = x[d] / (R.B << l);
+  }
+  return block_level(R, b[0], b[1], b[2]) >= m;
 }
 
-bool fine_in_R(const Refine& R, int jx, int jy, int jz) {
-  const int n2[3] = {2 * R.c.nx, 2 * R.c.ny, 2 * R.c.nz};
-  if (jx < 0 || jy < 0 || jz < 0 || jx >= n2[0] || jy >= n2[1] || jz >= n2[2]) return false;
-  return refined_block(R, jx / (2 * R.B), jy / (2 * R.B), jz / (2 * R.B));
+long lidx(const MLevel& V, const int x[3]) {
+  return ((long)x[2] * V.n[1] + x[1]) * V.n[0] + x[0];
 }
 
-long fidx(const Refine& R, int lx, int ly, int lz) {
-  return ((long)lz * R.M[1] + ly) * R.M[0] + lx;
+void lcoords(const MLevel& V, long k, int x[3]) {
+  x[0] = (int)(k % V.n[0]);
+  x[1] = (int)((k / V.n[0]) % V.n[1]);
+  x[2] = (int)(k / ((long)V.n[0] * V.n[1]));
+}
+
+// Neighbour of x by offset d inside the level's domain (periodic axes wrap);
+// false beyond a non-periodic face.
+bool neighbour(const MLevel& V, const int x[3], const int d[3], int y[3]) {
+  for (int a = 0; a < 3; ++a) {
+    y[a] = x[a] + d[a];
+    if (y[a] >= 0 && y[a] < V.n[a]) continue;
+    if (V.p.face_type[2 * a] != ORC_PERIODIC) return false;
+    y[a] = (y[a] + V.n[a]) % V.n[a];
+  }
+  return true;
 }
 
 // 4-point Lagrange weights at position p on nodes s..s+3.
@@ -835,58 +883,39 @@ void lagrange4(double p, int s, double w[4]) {
   }
 }
 
-// Stencil of fine coordinate j along an axis of n coarse nodes: nodes and
-// weights (1 node if j is even, 4 otherwise; indices wrapped if periodic).
-int stencil1d(int j, int n, bool periodic, int idx[4], double w[4]) {
-  if (j % 2 == 0) {
-    int c = j / 2;
-    if (periodic) c = ((c % n) + n) % n;
-    idx[0] = c;
-    w[0] = 1.0;
-    return 1;
-  }
-  const double p = 0.5 * j;
-  int s = (j - 1) / 2 - 1;
-  if (!periodic) {
-    if (s < 0) s = 0;
-    if (s > n - 4) s = n - 4;
-  }
+// Level-l window of the cubic interpolant at child coordinate j: nodes
+// s..s+3 (wrapped if periodic) and Lagrange weights at p = j/2 - 1/4.
+void child_stencil(const MLevel& parent, int d, int j, int idx[4], double w[4]) {
+  const double p = 0.5 * j - 0.25;
+  int s = (int)std::floor(p) - 1;
+  const int n = parent.n[d];
+  const bool periodic = parent.p.face_type[2 * d] == ORC_PERIODIC;
+  if (!periodic) s = std::max(0, std::min(s, n - 4));
   lagrange4(p, s, w);
   for (int a = 0; a < 4; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
-  return 4;
 }
 
-void ghost_global(const Refine& R, long gi, int j[3]) {
-  const long l = R.ghosts[gi];
-  const int lx = (int)(l % R.M[0]), ly = (int)((l / R.M[0]) % R.M[1]),
-            lz = (int)(l / ((long)R.M[0] * R.M[1]));
-  j[0] = lx + R.lo[0];
-  j[1] = ly + R.lo[1];
-  j[2] = lz + R.lo[2];
-}
-
-// Spatial interpolation of coarse post-collision values at every ghost.
-void interp_ghosts(const Refine& R, const double* fc, std::vector<double>& out) {
-  const long ng = (long)R.ghosts.size();
-  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
-  const int n3[3] = {R.c.nx, R.c.ny, R.c.nz};
+// Raw spatial interpolation of the parent state at every ghost of level l.
+void interp_ghosts(const MLRefine& R, int l, const std::vector<double>& fp,
+                   std::vector<double>& out) {
+  const MLevel& V = R.lev[l];
+  const MLevel& P = R.lev[l - 1];
+  const long ng = (long)V.ghosts.size();
   out.assign((size_t)R.Q * ng, 0.0);
   #pragma omp parallel for schedule(static)
   for (long gi = 0; gi < ng; ++gi) {
-    int j[3];
-    ghost_global(R, gi, j);
+    int x[3];
+    lcoords(V, V.ghosts[gi], x);
     int idx[3][4];
     double w[3][4];
-    int cnt[3];
-    for (int d = 0; d < 3; ++d)
-      cnt[d] = stencil1d(j[d], n3[d], R.c.face_type[2 * d] == ORC_PERIODIC, idx[d], w[d]);
+    for (int d = 0; d < 3; ++d) child_stencil(P, d, x[d], idx[d], w[d]);
     for (int q = 0; q < R.Q; ++q) {
       double s = 0.0;
-      for (int c = 0; c < cnt[2]; ++c)
-        for (int b = 0; b < cnt[1]; ++b)
-          for (int a = 0; a < cnt[0]; ++a) {
-            const long n = ((long)idx[2][c] * R.c.ny + idx[1][b]) * R.c.nx + idx[0][a];
-            s += w[0][a] * w[1][b] * w[2][c] * fc[q * Nc + n];
+      for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < 4; ++a) {
+            const int y[3] = {idx[0][a], idx[1][b], idx[2][c]};
+            s += w[0][a] * w[1][b] * w[2][c] * fp[(size_t)q * P.N + lidx(P, y)];
           }
       out[(size_t)q * ng + gi] = s;
     }
@@ -912,362 +941,549 @@ void equilibrium_of(int model, const double* f, double* feq) {
   }
 }
 
-// f_eq + s (f - f_eq) for one node.
-void rescale_node(int model, const double* f, double s, double* out) {
-  double feq[27];
-  equilibrium_of(model, f, feq);
-  for (int i = 0; i < nq(model); ++i) out[i] = feq[i] + s * (f[i] - feq[i]);
+bool mrt_shear_row(int basis, int k) {
+  if (basis == ORC_BASIS_TABLE1) return k >= 4 && k <= 8;
+  return k == 9 || k == 11 || k == 13 || k == 14 || k == 15;
 }
 
-void fill_ghosts(const Refine& R, const std::vector<double>& g, double* ff) {
-  const long ng = (long)R.ghosts.size();
-  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+bool mrt_conserved_row(int basis, int k) {
+  if (basis == ORC_BASIS_TABLE1) return k <= 3;
+  return k == 0 || k == 3 || k == 5 || k == 7;
+}
+
+// Total relaxation time of a post-collision state of the MRT-LES model:
+// the traceless stress T of its non-equilibrium part gives Qp = sqrt(2 T:T)
+// = Q |1 - 1/tau| with Q the pre-collision value of Eq. (21); with Eq. (20)
+// (tau^2 - tau0 tau = 9/2 C_S^2 Q) this is the root that tends to tau0 as
+// Qp -> 0: tau = (1 + tau0 -+ sqrt((1 - tau0)^2 -+ 18 C_S^2 Qp)) / 2 (upper
+// signs for tau0 < 1; a negative radicand, out of reach of a collision's
+// output, is clamped to 0).
+double tau_from_post(const double* neq, double tau0, double cs) {
+  double P[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double s = 0.0;
+      for (int i = 0; i < 19; ++i) s += E[i][a] * E[i][b] * neq[i];
+      P[a][b] = s;
+    }
+  const double tr = (P[0][0] + P[1][1] + P[2][2]) / 3.0;
+  double t2 = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double v = P[a][b] - (a == b ? tr : 0.0);
+      t2 += v * v;
+    }
+  const double Qp = std::sqrt(2.0 * t2);
+  const double k = 18.0 * cs * cs * Qp;
+  if (tau0 < 1.0) {
+    const double rad = std::max(0.0, (1.0 - tau0) * (1.0 - tau0) - k);
+    return 0.5 * (1.0 + tau0 - std::sqrt(rad));
+  }
+  return 0.5 * (1.0 + tau0 + std::sqrt((tau0 - 1.0) * (tau0 - 1.0) + k));
+}
+
+// Non-equilibrium rescaling of one node between a parent level c and its
+// child f: dir > 0 maps a parent state to the child, dir < 0 back. Returns
+// the shear ratio used (child over parent).
+double rescale_node(const orc_params* pc, const orc_params* pf, const double* in, int dir,
+                    double* out) {
+  const int model = pc->model;
+  const int Q = nq(model);
+  double feq[27], neq[27];
+  equilibrium_of(model, in, feq);
+  for (int i = 0; i < Q; ++i) neq[i] = in[i] - feq[i];
+  const double t0c = 3.0 * pc->nu + 0.5, t0f = 3.0 * pf->nu + 0.5;
+  if (model != ORC_MRT19) {
+    const double r = (t0f - 1.0) / (2.0 * (t0c - 1.0));
+    const double s = dir > 0 ? r : 1.0 / r;
+    for (int i = 0; i < Q; ++i) out[i] = feq[i] + s * neq[i];
+    return r;
+  }
+  double tc, tf;
+  if (dir > 0) {
+    tc = tau_from_post(neq, t0c, pc->cs_smag);
+    tf = t0f + 0.5 * (tc - t0c);
+  } else {
+    tf = tau_from_post(neq, t0f, pf->cs_smag);
+    tc = t0c + 2.0 * (tf - t0f);
+  }
+  const double r_shear = (tf - 1.0) / (2.0 * (tc - 1.0));
+  const MrtBasis& Bm = get_basis(pc->mrt_basis);
+  double s[19];
+  mrt_rates(pc->mrt_basis, pc->rates, 0.0, s);
+  double m[19];
+  for (int k = 0; k < 19; ++k) {
+    double v = 0.0;
+    for (int i = 0; i < 19; ++i) v += Bm.M[k * 19 + i] * neq[i];
+    double r;
+    if (mrt_conserved_row(pc->mrt_basis, k)) r = 0.0;  // no non-equilibrium part
+    else if (mrt_shear_row(pc->mrt_basis, k)) r = dir > 0 ? r_shear : 1.0 / r_shear;
+    else if (s[k] == 1.0) r = 0.0;                      // relaxed to equilibrium
+    else r = dir > 0 ? 0.5 : 2.0;                       // same rate on both levels
+    m[k] = r * v;
+  }
+  for (int i = 0; i < 19; ++i) {
+    double v = 0.0;
+    for (int k = 0; k < 19; ++k) v += Bm.Minv[i * 19 + k] * m[k];
+    out[i] = feq[i] + v;
+  }
+  return r_shear;
+}
+
+// Ghosts of level l := rescale(c0 G[0] + c1 G[1] + c2 G[2]).
+void fill_ghosts(MLRefine& R, int l, double c0, double c1, double c2) {
+  MLevel& V = R.lev[l];
+  const MLevel& P = R.lev[l - 1];
+  const long ng = (long)V.ghosts.size();
   #pragma omp parallel for schedule(static)
   for (long gi = 0; gi < ng; ++gi) {
     double a[27], b[27];
-    for (int q = 0; q < R.Q; ++q) a[q] = g[(size_t)q * ng + gi];
-    rescale_node(R.c.model, a, R.r, b);
-    for (int q = 0; q < R.Q; ++q) ff[q * Nf + R.ghosts[gi]] = b[q];
+    for (int q = 0; q < R.Q; ++q) {
+      const size_t k = (size_t)q * ng + gi;
+      a[q] = c1 * V.G[1][k] + c2 * V.G[2][k];
+      if (c0 != 0.0) a[q] += c0 * V.G[0][k];
+    }
+    rescale_node(&P.p, &V.p, a, +1, b);
+    for (int q = 0; q < R.Q; ++q) V.f[(size_t)q * V.N + V.ghosts[gi]] = b[q];
   }
 }
 
-void inject(const Refine& R, double* fc, const double* ff) {
-  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
-  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
+// Time weights of the parent states at t-1, t, t+1 for the child's half
+// step t + 1/2: three-point quadratic Lagrange (-1/8, 3/4, 3/8), or linear
+// (0, 1/2, 1/2) while the state at t-1 is unknown.
+void half_step_weights(bool have_prev, double w[3]) {
+  w[0] = have_prev ? -0.125 : 0.0;
+  w[1] = have_prev ? 0.75 : 0.5;
+  w[2] = have_prev ? 0.375 : 0.5;
+}
+
+// Covered nodes of level l := the rescaled mean of their 8 children.
+void inject(MLRefine& R, int l) {
+  MLevel& V = R.lev[l];
+  const MLevel& C = R.lev[l + 1];
   #pragma omp parallel for schedule(static)
-  for (long n = 0; n < Nc; ++n) {
-    if (R.ctype[n] != 2) continue;
-    const int x = (int)(n % R.c.nx), y = (int)((n / R.c.nx) % R.c.ny),
-              z = (int)(n / ((long)R.c.nx * R.c.ny));
-    const long l = fidx(R, 2 * x - R.lo[0], 2 * y - R.lo[1], 2 * z - R.lo[2]);
+  for (long k = 0; k < V.N; ++k) {
+    if (V.type[k] != T_COVERED) continue;
+    int x[3];
+    lcoords(V, k, x);
     double a[27], b[27];
-    for (int q = 0; q < R.Q; ++q) a[q] = ff[q * Nf + l];
-    rescale_node(R.c.model, a, 1.0 / R.r, b);
-    for (int q = 0; q < R.Q; ++q) fc[q * Nc + n] = b[q];
-  }
-}
-
-// Coarse step in post-collision storage: out = C(pull(in)) on nodes that
-// are not covered (covered nodes are left as they are).
-void coarse_step(const Refine& R, const double* in, double* out, int64_t t) {
-  const orc_params* p = &R.c;
-  const long N = (long)p->nx * p->ny * p->nz;
-  const int Q = R.Q;
-  #pragma omp parallel for schedule(static)
-  for (int z = 0; z < p->nz; ++z)
-    for (int y = 0; y < p->ny; ++y)
-      for (int x = 0; x < p->nx; ++x) {
-        const long n = node_index(p, x, y, z);
-        if (R.ctype[n] == 2) continue;
-        double a[27], b[27];
-        for (int i = 0; i < Q; ++i) a[i] = pull(p, in, Q, i, x, y, z, t);
-        collide_node(p, a, b);
-        for (int i = 0; i < Q; ++i) out[i * N + n] = b[i];
-      }
-}
-
-// Pull on the fine level: sources inside the box come from the box (fluid
-// or ghost nodes); sources beyond a domain face follow the boundary rules on
-// the fine level (R.f: global fine extent, fine inlet arrays).
-double fine_pull(const Refine& R, const double* in, int i, int lx, int ly, int lz, int64_t t) {
-  const orc_params* p = &R.f;
-  const int j[3] = {lx + R.lo[0], ly + R.lo[1], lz + R.lo[2]};
-  const int n[3] = {p->nx, p->ny, p->nz};
-  int s[3] = {j[0] - E[i][0], j[1] - E[i][1], j[2] - E[i][2]};
-  int crossed[6] = {0, 0, 0, 0, 0, 0};
-  bool any = false;
-  for (int d = 0; d < 3; ++d) {
-    int face = -1;
-    if (s[d] < 0) face = 2 * d;
-    else if (s[d] >= n[d]) face = 2 * d + 1;
-    if (face < 0) continue;
-    if (p->face_type[face] == ORC_PERIODIC) {
-      s[d] = (s[d] + n[d]) % n[d];
-    } else {
-      crossed[face] = 1;
-      any = true;
+    for (int q = 0; q < R.Q; ++q) a[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int y[3] = {2 * x[0] + (c & 1), 2 * x[1] + ((c >> 1) & 1), 2 * x[2] + (c >> 2)};
+      const long kc = lidx(C, y);
+      for (int q = 0; q < R.Q; ++q) a[q] += C.f[(size_t)q * C.N + kc];
     }
+    for (int q = 0; q < R.Q; ++q) a[q] *= 0.125;
+    rescale_node(&V.p, &C.p, a, -1, b);
+    for (int q = 0; q < R.Q; ++q) V.f[(size_t)q * V.N + k] = b[q];
   }
-  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
-  const long self = fidx(R, lx, ly, lz);
-  const int Q = R.Q;
-  if (any) {
-    const int io = opposite(Q, i);
-    for (int face = 0; face < 6; ++face)
-      if (crossed[face] && p->face_type[face] == ORC_WALL) {
-        const double* uw = p->face_u[face];
-        return in[io * Nf + self] + 6.0 * weight(Q, i) *
-                                        (E[i][0] * uw[0] + E[i][1] * uw[1] + E[i][2] * uw[2]);
+}
+
+// One step of level l at its step index t: f := C(pull(f)) on fluid and
+// band nodes; the others keep their values.
+void level_step(MLevel& V, int Q, int64_t t) {
+  long bad = 0;
+  #pragma omp parallel for schedule(static) reduction(+ : bad)
+  for (long k = 0; k < V.N; ++k) {
+    const uint8_t ty = V.type[k];
+    if (ty != T_FLUID && ty != T_BAND) {
+      for (int q = 0; q < Q; ++q) V.g[(size_t)q * V.N + k] = V.f[(size_t)q * V.N + k];
+      continue;
+    }
+    int x[3];
+    lcoords(V, k, x);
+    for (int i = 0; i < Q; ++i) {  // every in-domain source must hold a state
+      const int d[3] = {-E[i][0], -E[i][1], -E[i][2]};
+      int y[3];
+      if (neighbour(V, x, d, y) && V.type[lidx(V, y)] == T_UNUSED) ++bad;
+    }
+    double a[27], b[27];
+    for (int i = 0; i < Q; ++i) a[i] = pull(&V.p, V.f.data(), Q, i, x[0], x[1], x[2], t);
+    collide_node(&V.p, a, b);
+    for (int q = 0; q < Q; ++q) V.g[(size_t)q * V.N + k] = b[q];
+  }
+  V.bad_pull += bad;
+  V.f.swap(V.g);
+}
+
+// Advance level l by one of its steps (index t); recursively the finer
+// levels by two steps each.
+void advance(MLRefine& R, int l, int64_t t) {
+  MLevel& V = R.lev[l];
+  const bool child = l + 1 < R.L;
+  if (child && !R.lev[l + 1].have_cur) {
+    interp_ghosts(R, l + 1, V.f, R.lev[l + 1].G[1]);
+    R.lev[l + 1].have_cur = true;
+    R.lev[l + 1].have_prev = false;
+  }
+  level_step(V, R.Q, t);
+  if (!child) return;
+  MLevel& C = R.lev[l + 1];
+  interp_ghosts(R, l + 1, V.f, C.G[2]);
+  fill_ghosts(R, l + 1, 0.0, 1.0, 0.0);
+  advance(R, l + 1, 2 * t);
+  double w[3];
+  half_step_weights(C.have_prev, w);
+  fill_ghosts(R, l + 1, w[0], w[1], w[2]);
+  advance(R, l + 1, 2 * t + 1);
+  inject(R, l);
+  C.G[0].swap(C.G[1]);
+  C.G[1].swap(C.G[2]);
+  C.have_prev = true;
+}
+
+bool build_levels(MLRefine& R, const orc_params* coarse, const double* const* inlet_u,
+                  const uint8_t* const* inlet_mask, const uint8_t* const* solid,
+                  const double* const* link_q) {
+  const int L = R.L, Q = R.Q;
+  // nesting: the neighbours of a block at level m >= 2 are at level >= m - 1
+  for (int bz = 0; bz < R.nb[2]; ++bz)
+    for (int by = 0; by < R.nb[1]; ++by)
+      for (int bx = 0; bx < R.nb[0]; ++bx) {
+        const int m = block_level(R, bx, by, bz);
+        if (m >= L) return false;
+        if (m < 2) continue;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int b[3] = {bx + dx, by + dy, bz + dz};
+              bool inside = true;
+              for (int d = 0; d < 3; ++d) {
+                if (b[d] >= 0 && b[d] < R.nb[d]) continue;
+                if (coarse->face_type[2 * d] != ORC_PERIODIC) inside = false;
+                b[d] = (b[d] + R.nb[d]) % R.nb[d];
+              }
+              if (inside && block_level(R, b[0], b[1], b[2]) < m - 1) return false;
+            }
       }
-    for (int face = 0; face < 6; ++face)
-      if (crossed[face] && p->face_type[face] == ORC_INLET) {
-        double uin[3];
-        inlet_velocity(p, face, j[0], j[1], j[2], t, uin);
-        return in[io * Nf + self] +
-               6.0 * weight(Q, i) * (E[i][0] * uin[0] + E[i][1] * uin[1] + E[i][2] * uin[2]);
-      }
-    // PRESSURE and FREESLIP faces: the rules of classify() and pull() on the
-    // fine level's box
-    for (int face = 0; face < 6; ++face)
-      if (crossed[face] && p->face_type[face] == ORC_PRESSURE) {
-        double d = 0.0, jm[3] = {0, 0, 0};
-        for (int k = 0; k < Q; ++k) {
-          const double v = in[k * Nf + self];
-          d += v;
-          for (int a = 0; a < 3; ++a) jm[a] += v * E[k][a];
-        }
-        const double rho = (p->model == ORC_MRT19) ? 1.0 : 1.0 + d;
-        const double ub[3] = {jm[0] / rho, jm[1] / rho, jm[2] / rho};
-        const double drho = p->face_drho[face];
-        double feq[27];
-        if (p->model == ORC_MRT19) {
-          feq_incomp(19, drho, ub, feq);
-        } else {
-          for (int k = 0; k < 27; ++k)
-            feq[k] = (1.0 + drho) * phi(E[k][0], ub[0]) * phi(E[k][1], ub[1]) *
-                         phi(E[k][2], ub[2]) -
-                     weight(27, k);
-        }
-        return -in[io * Nf + self] + feq[i] + feq[io];
-      }
+  // a refined region on a periodic axis spans it or keeps off its ends
+  for (int l = 1; l < L; ++l)
     for (int d = 0; d < 3; ++d) {
-      if (s[d] < 0) s[d] = 0;
-      if (s[d] >= n[d]) s[d] = n[d] - 1;
+      if (coarse->face_type[2 * d] != ORC_PERIODIC) continue;
+      int lo = R.nb[d], hi = -1;
+      for (int bz = 0; bz < R.nb[2]; ++bz)
+        for (int by = 0; by < R.nb[1]; ++by)
+          for (int bx = 0; bx < R.nb[0]; ++bx)
+            if (block_level(R, bx, by, bz) >= l) {
+              const int b3[3] = {bx, by, bz};
+              lo = std::min(lo, b3[d]);
+              hi = std::max(hi, b3[d]);
+            }
+      if (hi < 0) continue;
+      const bool full = lo == 0 && hi == R.nb[d] - 1;
+      if (!full && (lo == 0 || hi == R.nb[d] - 1)) return false;
     }
-    int e[3] = {E[i][0], E[i][1], E[i][2]};
-    bool mirrored = false;
+  R.lev.resize(L);
+  for (int l = 0; l < L; ++l) {
+    MLevel& V = R.lev[l];
+    V.p = *coarse;
+    V.p.nx = coarse->nx << l;
+    V.p.ny = coarse->ny << l;
+    V.p.nz = coarse->nz << l;
+    V.p.nu = coarse->nu * (double)(1 << l);
+    V.p.seed = coarse->seed + (uint64_t)l;
+    for (int d = 0; d < 3; ++d) V.p.origin[d] = 0;
+    V.n[0] = V.p.nx;
+    V.n[1] = V.p.ny;
+    V.n[2] = V.p.nz;
+    V.N = (long)V.n[0] * V.n[1] * V.n[2];
     for (int face = 0; face < 6; ++face)
-      if (crossed[face] && p->face_type[face] == ORC_FREESLIP) {
-        e[face / 2] = -e[face / 2];
-        mirrored = true;
+      if (coarse->face_type[face] == ORC_INLET) {
+        const int d = face / 2;
+        V.p.inlet_na = V.n[d == 0 ? 1 : 0];
+        V.p.inlet_nb = V.n[d == 2 ? 1 : 2];
+        if (l > 0) {
+          const long nf = (long)V.p.inlet_na * V.p.inlet_nb;
+          if (!inlet_u || !inlet_u[l]) return false;
+          V.inlet_u.assign(inlet_u[l], inlet_u[l] + 3 * nf);
+          V.p.inlet_u = V.inlet_u.data();
+          if (inlet_mask && inlet_mask[l]) {
+            V.inlet_mask.assign(inlet_mask[l], inlet_mask[l] + nf);
+            V.p.inlet_mask = V.inlet_mask.data();
+          } else {
+            V.p.inlet_mask = nullptr;
+          }
+        }
       }
-    if (mirrored)
-      return in[velocity_index(Q, e[0], e[1], e[2]) * Nf +
-                fidx(R, s[0] - R.lo[0], s[1] - R.lo[1], s[2] - R.lo[2])];
+    V.p.solid = nullptr;
+    V.p.link_q = nullptr;
+    if (solid && solid[l]) {
+      V.solid.assign(solid[l], solid[l] + V.N);
+      V.p.solid = V.solid.data();
+    }
+    if (link_q && link_q[l]) {
+      V.link_q.assign(link_q[l], link_q[l] + (size_t)Q * V.N);
+      V.p.link_q = V.link_q.data();
+    }
+    const double tau = 3.0 * V.p.nu + 0.5;
+    if (L > 1 && std::fabs(tau - 1.0) < 1e-6) return false;
+    // node types
+    V.type.assign(V.N, T_UNUSED);
+    for (long k = 0; k < V.N; ++k) {
+      int x[3];
+      lcoords(V, k, x);
+      if (in_region(R, l, l, x)) {
+        V.type[k] = (l + 1 < L && in_region(R, l, l + 1, x)) ? T_COVERED : T_FLUID;
+        continue;
+      }
+      for (int c = 0; c < 27 && V.type[k] == T_UNUSED; ++c) {
+        const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+        int y[3];
+        if (neighbour(V, x, d, y) && in_region(R, l, l, y)) V.type[k] = T_GHOST;
+      }
+    }
+    V.ghosts.clear();
+    if (l > 0)
+      for (long k = 0; k < V.N; ++k)
+        if (V.type[k] == T_GHOST) V.ghosts.push_back(k);
   }
-  return in[i * Nf + fidx(R, s[0] - R.lo[0], s[1] - R.lo[1], s[2] - R.lo[2])];
-}
-
-void fine_step(const Refine& R, const double* in, double* out, int64_t t) {
-  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
-  const int Q = R.Q;
-  #pragma omp parallel for schedule(static)
-  for (int lz = 0; lz < R.M[2]; ++lz)
-    for (int ly = 0; ly < R.M[1]; ++ly)
-      for (int lx = 0; lx < R.M[0]; ++lx) {
-        const long l = fidx(R, lx, ly, lz);
-        if (R.ftype[l] != 1) continue;
-        double a[27], b[27];
-        for (int i = 0; i < Q; ++i) a[i] = fine_pull(R, in, i, lx, ly, lz, t);
-        collide_node(&R.f, a, b);
-        for (int i = 0; i < Q; ++i) out[i * Nf + l] = b[i];
+  // band: parent nodes read by a child's ghost stencils stay parent-updated
+  for (int l = 1; l < L; ++l) {
+    MLevel& V = R.lev[l];
+    MLevel& P = R.lev[l - 1];
+    for (long gk : V.ghosts) {
+      int x[3];
+      lcoords(V, gk, x);
+      int idx[3][4];
+      double w[3][4];
+      for (int d = 0; d < 3; ++d) child_stencil(P, d, x[d], idx[d], w[d]);
+      for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < 4; ++a) {
+            const int y[3] = {idx[0][a], idx[1][b], idx[2][c]};
+            uint8_t& t = P.type[lidx(P, y)];
+            if (t == T_COVERED) t = T_BAND;
+            if (t != T_FLUID && t != T_BAND) return false;  // stencil off the parent's state
+          }
+    }
+  }
+  // solids: off the interface (ghosts, ghost stencils, covered nodes that a
+  // parent-updated node pulls from, and their children)
+  for (int l = 0; l < L; ++l) {
+    MLevel& V = R.lev[l];
+    if (V.solid.empty()) continue;
+    for (long k = 0; k < V.N; ++k) {
+      if (!V.solid[k]) continue;
+      const uint8_t t = V.type[k];
+      if (t == T_GHOST || t == T_BAND) return false;
+      if (t == T_FLUID) V.type[k] = T_SOLID;
+      if (t == T_COVERED) V.type[k] = T_SOLID;
+    }
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    MLevel& V = R.lev[l];
+    const MLevel& C = R.lev[l + 1];
+    for (long k = 0; k < V.N; ++k) {
+      if (V.type[k] != T_FLUID && V.type[k] != T_BAND) continue;
+      int x[3];
+      lcoords(V, k, x);
+      for (int i = 1; i < Q; ++i) {
+        const int d[3] = {-E[i][0], -E[i][1], -E[i][2]};
+        int y[3];
+        if (!neighbour(V, x, d, y)) continue;
+        const uint8_t t = V.type[lidx(V, y)];
+        if (t == T_SOLID && in_region(R, l, l + 1, y)) return false;
+        if (t != T_COVERED) continue;
+        if (C.solid.empty()) continue;
+        for (int c = 0; c < 8; ++c) {
+          const int z[3] = {2 * y[0] + (c & 1), 2 * y[1] + ((c >> 1) & 1), 2 * y[2] + (c >> 2)};
+          if (C.solid[lidx(C, z)]) return false;
+        }
       }
+    }
+  }
+  for (int l = 1; l < L; ++l) {  // children of every stencil or covered read: fluid
+    const MLevel& V = R.lev[l];
+    if (V.solid.empty()) continue;
+    for (long gk : V.ghosts)
+      for (int c = 0; c < 27; ++c) {
+        int x[3], y[3];
+        lcoords(V, gk, x);
+        const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+        if (neighbour(V, x, d, y) && V.solid[lidx(V, y)]) return false;
+      }
+  }
+  for (int l = 0; l < L; ++l) {
+    MLevel& V = R.lev[l];
+    for (int d = 0; d < 3; ++d) {
+      V.box_lo[d] = V.n[d];
+      V.box_hi[d] = 0;
+    }
+    for (long k = 0; k < V.N; ++k)
+      if (V.type[k] != T_UNUSED) {
+        int x[3];
+        lcoords(V, k, x);
+        for (int d = 0; d < 3; ++d) {
+          V.box_lo[d] = std::min(V.box_lo[d], x[d]);
+          V.box_hi[d] = std::max(V.box_hi[d], x[d] + 1);
+        }
+      }
+    V.f.assign((size_t)Q * V.N, 0.0);
+    V.g.assign((size_t)Q * V.N, 0.0);
+  }
+  return true;
 }
 
 }  // namespace
 
 extern "C" {
 
-// Build the two-level geometry. coarse: full-domain lattice parameters;
-// block: block edge in coarse nodes (must divide nx, ny, nz); mask:
-// [nz/B][ny/B][nx/B], 1 = refined; fine inlet arrays at fine resolution
-// ([3][2 nb][2 na], may be null if there is no inlet). Returns null on a
-// bad configuration.
-void* orc_refine_create(const orc_params* coarse, int block, const uint8_t* mask,
-                        const double* fine_inlet_u, const uint8_t* fine_inlet_mask) {
-  if (block < 2 || coarse->nx % block || coarse->ny % block || coarse->nz % block) return nullptr;
-  Refine* R = new Refine();
-  R->c = *coarse;
-  R->c.solid = nullptr;  // the refined lattice has no interior solids
+// Build the levels. coarse: level-0 lattice parameters (faces, inlet, seed,
+// model, viscosity); block: block edge B in level-0 nodes (divides nx, ny,
+// nz); nlevels >= 1; map: [nz/B][ny/B][nx/B] finest level of each block (<
+// nlevels). Per-level arrays (entry l for level l; the arrays and entries may
+// be null): inlet_u [3][nb][na] and inlet_mask [nb][na] at the level's
+// resolution (levels >= 1; level 0 takes coarse's own), solid [N_l] and
+// link_q [Q][N_l] over the level's whole domain. Returns null on a bad
+// configuration (nesting, periodic extent, solids on the interface, tau = 1).
+void* orc_mlref_create(const orc_params* coarse, int block, int nlevels, const uint8_t* map,
+                       const double* const* inlet_u, const uint8_t* const* inlet_mask,
+                       const uint8_t* const* solid, const double* const* link_q) {
+  if (block < 2 || nlevels < 1 || nlevels > 8) return nullptr;
+  if (coarse->nx % block || coarse->ny % block || coarse->nz % block) return nullptr;
+  const int n3[3] = {coarse->nx, coarse->ny, coarse->nz};
+  for (int d = 0; d < 3; ++d)  // the one-sided windows need 4 nodes
+    if (coarse->face_type[2 * d] != ORC_PERIODIC && n3[d] < 4) return nullptr;
+  MLRefine* R = new MLRefine();
+  R->L = nlevels;
   R->B = block;
   R->Q = nq(coarse->model);
   R->nb[0] = coarse->nx / block;
   R->nb[1] = coarse->ny / block;
   R->nb[2] = coarse->nz / block;
-  const long nblk = (long)R->nb[0] * R->nb[1] * R->nb[2];
-  R->mask.assign(mask, mask + nblk);
-  // fine level parameters
-  R->f = *coarse;
-  R->f.nx = 2 * coarse->nx;
-  R->f.ny = 2 * coarse->ny;
-  R->f.nz = 2 * coarse->nz;
-  R->f.nu = 2.0 * coarse->nu;
-  R->f.inlet_u = fine_inlet_u;
-  R->f.inlet_mask = fine_inlet_mask;
-  R->f.inlet_na = 0;
-  R->f.inlet_nb = 0;
-  for (int face = 0; face < 6; ++face)
-    if (coarse->face_type[face] == ORC_INLET) {
-      const int d = face / 2;
-      const int n2[3] = {R->f.nx, R->f.ny, R->f.nz};
-      R->f.inlet_na = n2[d == 0 ? 1 : 0];
-      R->f.inlet_nb = n2[d == 2 ? 1 : 2];
-    }
-  R->f.seed = coarse->seed + 1;
-  R->f.solid = nullptr;  // neither level has interior solids or curved links
-  R->f.link_q = nullptr;
-  R->c.link_q = nullptr;
-  for (int k = 0; k < 3; ++k) R->f.origin[k] = 0;
-  const double tc = 3.0 * coarse->nu + 0.5, tf = 3.0 * R->f.nu + 0.5;
-  R->r = (tf - 1.0) / (2.0 * (tc - 1.0));
-  // fine box: bounding box of the refined blocks, one ghost layer beyond
-  // every side that is not a domain face
-  int blo[3] = {1 << 30, 1 << 30, 1 << 30}, bhi[3] = {-1, -1, -1};
-  for (int bz = 0; bz < R->nb[2]; ++bz)
-    for (int by = 0; by < R->nb[1]; ++by)
-      for (int bx = 0; bx < R->nb[0]; ++bx)
-        if (refined_block(*R, bx, by, bz)) {
-          const int b3[3] = {bx, by, bz};
-          for (int d = 0; d < 3; ++d) {
-            blo[d] = std::min(blo[d], b3[d]);
-            bhi[d] = std::max(bhi[d], b3[d] + 1);
-          }
-        }
-  for (int d = 0; d < 3 && bhi[0] >= 0; ++d)
-    if (coarse->face_type[2 * d] == ORC_PERIODIC) {
-      const bool full = blo[d] == 0 && bhi[d] == R->nb[d];
-      const bool inside = blo[d] > 0 && bhi[d] < R->nb[d];
-      if (!full && !inside) {  // a wrapped fine pull would leave the box
-        delete R;
-        return nullptr;
-      }
-    }
-  if (bhi[0] < 0) {  // nothing refined: an empty fine level
-    for (int d = 0; d < 3; ++d) {
-      R->lo[d] = 0;
-      R->M[d] = 0;
-    }
-  } else {
-    const int n2[3] = {R->f.nx, R->f.ny, R->f.nz};
-    for (int d = 0; d < 3; ++d) {
-      int a = 2 * block * blo[d], b = 2 * block * bhi[d];
-      if (a > 0) a -= 1;
-      if (b < n2[d]) b += 1;
-      R->lo[d] = a;
-      R->M[d] = b - a;
-    }
-  }
-  const long Nf = (long)R->M[0] * R->M[1] * R->M[2];
-  R->ftype.assign(Nf, 0);
-  for (int lz = 0; lz < R->M[2]; ++lz)
-    for (int ly = 0; ly < R->M[1]; ++ly)
-      for (int lx = 0; lx < R->M[0]; ++lx) {
-        const int jx = lx + R->lo[0], jy = ly + R->lo[1], jz = lz + R->lo[2];
-        uint8_t t = 0;
-        if (fine_in_R(*R, jx, jy, jz)) {
-          t = 1;
-        } else {
-          for (int dz = -1; dz <= 1 && !t; ++dz)
-            for (int dy = -1; dy <= 1 && !t; ++dy)
-              for (int dx = -1; dx <= 1 && !t; ++dx)
-                if (fine_in_R(*R, jx + dx, jy + dy, jz + dz)) t = 2;
-        }
-        R->ftype[fidx(*R, lx, ly, lz)] = t;
-        if (t == 2) R->ghosts.push_back(fidx(*R, lx, ly, lz));
-      }
-  // coarse types: refined nodes are covered unless a ghost stencil uses them
-  const long Nc = (long)coarse->nx * coarse->ny * coarse->nz;
-  R->ctype.assign(Nc, 0);
-  for (int z = 0; z < coarse->nz; ++z)
-    for (int y = 0; y < coarse->ny; ++y)
-      for (int x = 0; x < coarse->nx; ++x)
-        if (coarse_in_R(*R, x, y, z)) R->ctype[((long)z * coarse->ny + y) * coarse->nx + x] = 2;
-  const int n3[3] = {coarse->nx, coarse->ny, coarse->nz};
-  for (long gi = 0; gi < (long)R->ghosts.size(); ++gi) {
-    int j[3];
-    ghost_global(*R, gi, j);
-    int idx[3][4];
-    double w[3][4];
-    int cnt[3];
-    for (int d = 0; d < 3; ++d)
-      cnt[d] = stencil1d(j[d], n3[d], coarse->face_type[2 * d] == ORC_PERIODIC, idx[d], w[d]);
-    for (int c = 0; c < cnt[2]; ++c)
-      for (int b = 0; b < cnt[1]; ++b)
-        for (int a = 0; a < cnt[0]; ++a) {
-          const long n = ((long)idx[2][c] * coarse->ny + idx[1][b]) * coarse->nx + idx[0][a];
-          if (R->ctype[n] == 2) R->ctype[n] = 1;
-        }
+  R->map.assign(map, map + (long)R->nb[0] * R->nb[1] * R->nb[2]);
+  if (!build_levels(*R, coarse, inlet_u, inlet_mask, solid, link_q)) {
+    delete R;
+    return nullptr;
   }
   return R;
 }
 
-void orc_refine_destroy(void* h) { delete (Refine*)h; }
+void orc_mlref_destroy(void* h) { delete (MLRefine*)h; }
 
-// lo[3], M[3]; counts = {fluid, ghost, covered, band}; ratio r.
-void orc_refine_geometry(void* h, int32_t* lo, int32_t* M, int64_t* counts, double* r) {
-  const Refine& R = *(Refine*)h;
+// Level l: domain n[3]; box [lo, hi) of its used nodes; counts = {fluid,
+// band, covered, ghost, solid, unused}.
+void orc_mlref_info(void* h, int l, int32_t* n, int32_t* box, int64_t* counts) {
+  const MLevel& V = ((MLRefine*)h)->lev[l];
   for (int d = 0; d < 3; ++d) {
-    lo[d] = R.lo[d];
-    M[d] = R.M[d];
+    n[d] = V.n[d];
+    box[d] = V.box_lo[d];
+    box[3 + d] = V.box_hi[d];
   }
-  int64_t nf = 0, ng = 0, nc = 0, nbnd = 0;
-  for (uint8_t t : R.ftype) {
-    nf += t == 1;
-    ng += t == 2;
+  for (int k = 0; k < 6; ++k) counts[k] = 0;
+  for (uint8_t t : V.type) {
+    const int slot = t == T_FLUID ? 0 : t == T_BAND ? 1 : t == T_COVERED ? 2
+                     : t == T_GHOST ? 3 : t == T_SOLID ? 4 : 5;
+    ++counts[slot];
   }
-  for (uint8_t t : R.ctype) {
-    nc += t == 2;
-    nbnd += t == 1;
-  }
-  counts[0] = nf;
-  counts[1] = ng;
-  counts[2] = nc;
-  counts[3] = nbnd;
-  *r = R.r;
 }
 
-void orc_refine_types(void* h, uint8_t* ctype, uint8_t* ftype) {
-  const Refine& R = *(Refine*)h;
-  std::memcpy(ctype, R.ctype.data(), R.ctype.size());
-  std::memcpy(ftype, R.ftype.data(), R.ftype.size());
+void orc_mlref_types(void* h, int l, uint8_t* type) {
+  const MLevel& V = ((MLRefine*)h)->lev[l];
+  std::memcpy(type, V.type.data(), V.type.size());
 }
 
-// Ghost fine global coordinates [ng][3] and the raw (not rescaled) spatial
-// interpolation of a coarse field fc ([Q][Nc]) at them, [Q][ng].
-void orc_refine_ghosts(void* h, int32_t* coords, const double* fc, double* g) {
-  const Refine& R = *(Refine*)h;
-  for (long gi = 0; gi < (long)R.ghosts.size(); ++gi) {
-    int j[3];
-    ghost_global(R, gi, j);
-    for (int d = 0; d < 3; ++d) coords[3 * gi + d] = j[d];
+// Post-collision state of level l over its whole domain, [Q][N_l]. Setting
+// any level forgets the interface history (the next step rebuilds it).
+void orc_mlref_set_state(void* h, int l, const double* f) {
+  MLRefine& R = *(MLRefine*)h;
+  MLevel& V = R.lev[l];
+  std::memcpy(V.f.data(), f, sizeof(double) * V.f.size());
+  for (MLevel& W : R.lev) W.have_cur = W.have_prev = false;
+}
+
+void orc_mlref_get_state(void* h, int l, double* f) {
+  const MLevel& V = ((MLRefine*)h)->lev[l];
+  std::memcpy(f, V.f.data(), sizeof(double) * V.f.size());
+}
+
+// Advance n level-0 steps from level-0 time t0 (level l takes step indices
+// t 2^l + k). Returns the number of pulls from unused nodes (0 for a valid
+// geometry).
+int64_t orc_mlref_run(void* h, int64_t t0, int64_t n) {
+  MLRefine& R = *(MLRefine*)h;
+  for (int64_t t = t0; t < t0 + n; ++t) advance(R, 0, t);
+  int64_t bad = 0;
+  for (const MLevel& V : R.lev) bad += V.bad_pull;
+  return bad;
+}
+
+int64_t orc_mlref_ghost_count(void* h, int l) {
+  return (int64_t)((MLRefine*)h)->lev[l].ghosts.size();
+}
+
+// Ghost coordinates of level l >= 1 ([ng][3]) and, if parent is given (a
+// level l-1 field [Q][N_{l-1}]), its raw spatial interpolation at them
+// ([Q][ng]).
+void orc_mlref_ghosts(void* h, int l, int32_t* coords, const double* parent, double* g) {
+  const MLRefine& R = *(MLRefine*)h;
+  const MLevel& V = R.lev[l];
+  for (size_t gi = 0; gi < V.ghosts.size(); ++gi) {
+    int x[3];
+    lcoords(V, V.ghosts[gi], x);
+    for (int d = 0; d < 3; ++d) coords[3 * gi + d] = x[d];
   }
-  if (fc && g) {
-    std::vector<double> out;
-    interp_ghosts(R, fc, out);
+  if (parent && g) {
+    const MLevel& P = R.lev[l - 1];
+    std::vector<double> fp(parent, parent + (size_t)R.Q * P.N), out;
+    interp_ghosts(R, l, fp, out);
     std::memcpy(g, out.data(), out.size() * sizeof(double));
   }
 }
 
-// f_eq + s (f - f_eq) on one node of the refined model.
-void orc_refine_rescale(void* h, const double* f, double s, double* out) {
-  const Refine& R = *(Refine*)h;
-  rescale_node(R.c.model, f, s, out);
+// Rescale one node between level l-1 and level l (dir > 0: parent state to
+// the child level; dir < 0: back). Returns the shear ratio used.
+double orc_mlref_rescale(void* h, int l, const double* f, int dir, double* out) {
+  const MLRefine& R = *(MLRefine*)h;
+  return rescale_node(&R.lev[l - 1].p, &R.lev[l].p, f, dir, out);
 }
 
-void orc_refine_inject(void* h, double* fc, const double* ff) {
-  inject(*(Refine*)h, fc, ff);
+// The half-step ghost values of level l >= 1 that a step fills from raw
+// parent interpolations at t-1, t, t+1 (each [Q][ng]; gm1 ignored unless
+// have_prev): time weights, then the rescaling, as in a refined step. out:
+// [Q][ng]. The level's stored interface history is left as it was.
+void orc_mlref_half_step(void* h, int l, const double* gm1, const double* g0, const double* gp1,
+                         int have_prev, double* out) {
+  MLRefine& R = *(MLRefine*)h;
+  MLevel& V = R.lev[l];
+  const size_t n = (size_t)R.Q * V.ghosts.size();
+  std::vector<double> keep[3] = {V.G[0], V.G[1], V.G[2]};
+  V.G[0].assign(have_prev ? gm1 : g0, (have_prev ? gm1 : g0) + n);
+  V.G[1].assign(g0, g0 + n);
+  V.G[2].assign(gp1, gp1 + n);
+  std::vector<double> fsave = V.f;
+  double w[3];
+  half_step_weights(have_prev != 0, w);
+  fill_ghosts(R, l, w[0], w[1], w[2]);
+  for (int q = 0; q < R.Q; ++q)
+    for (size_t gi = 0; gi < V.ghosts.size(); ++gi)
+      out[(size_t)q * V.ghosts.size() + gi] = V.f[(size_t)q * V.N + V.ghosts[gi]];
+  V.f.swap(fsave);
+  for (int k = 0; k < 3; ++k) V.G[k].swap(keep[k]);
 }
 
-// Advance n coarse steps from coarse time t0. fc: coarse post-collision
-// state [Q][Nc]; ff: fine box post-collision state [Q][M]; both in place.
-// Fine step indices (inlet perturbation) are 2t and 2t+1.
-void orc_refine_run(void* h, double* fc, double* ff, int64_t t0, int64_t n) {
-  Refine& R = *(Refine*)h;
-  const long Nc = (long)R.c.nx * R.c.ny * R.c.nz;
-  const long Nf = (long)R.M[0] * R.M[1] * R.M[2];
-  std::vector<double> bc(fc, fc + (size_t)R.Q * Nc), bf(ff, ff + (size_t)R.Q * Nf);
-  std::vector<double> g0, g1;
-  for (int64_t t = t0; t < t0 + n; ++t) {
-    interp_ghosts(R, fc, g0);
-    fill_ghosts(R, g0, ff);
-    coarse_step(R, fc, bc.data(), t);
-    fine_step(R, ff, bf.data(), 2 * t);
-    interp_ghosts(R, bc.data(), g1);
-    for (size_t k = 0; k < g0.size(); ++k) g0[k] = 0.5 * (g0[k] + g1[k]);
-    fill_ghosts(R, g0, bf.data());
-    fine_step(R, bf.data(), ff, 2 * t + 1);
-    std::memcpy(fc, bc.data(), sizeof(double) * R.Q * Nc);
-    inject(R, fc, ff);
+// FP64 sums over the domain: the fluid nodes of every level that no finer
+// level covers, weighted by their volume 8^-l in level-0 cells: sum of
+// rho - 1, momentum, |j|^2 / (2 rho) (rho = 1 for the MRT).
+void orc_mlref_reduce(void* h, double* out) {
+  const MLRefine& R = *(MLRefine*)h;
+  for (int k = 0; k < 5; ++k) out[k] = 0.0;
+  for (int l = 0; l < R.L; ++l) {
+    const MLevel& V = R.lev[l];
+    const double w = std::ldexp(1.0, -3 * l);
+    for (long k = 0; k < V.N; ++k) {
+      if (V.type[k] != T_FLUID) continue;
+      double d = 0.0, j[3] = {0, 0, 0};
+      for (int q = 0; q < R.Q; ++q) {
+        const double v = V.f[(size_t)q * V.N + k];
+        d += v;
+        for (int a = 0; a < 3; ++a) j[a] += v * E[q][a];
+      }
+      const double rho = V.p.model == ORC_MRT19 ? 1.0 : 1.0 + d;
+      out[0] += w * d;
+      for (int a = 0; a < 3; ++a) out[1 + a] += w * j[a];
+      out[4] += w * 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho;
+    }
   }
 }
 
