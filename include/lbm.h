@@ -404,87 +404,137 @@ int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next,
                      int dtype, double* grad_inlet);
 
 /* ======================================================================
- * Two-level nested time refinement on a block grid (the hierarchical
- * block grid with nested time steps of Section 1 and of the numerical
+ * Nested time refinement on a hierarchical block grid (the block grid with
+ * nested time steps of Section 1 and the refinement levels of the numerical
  * set-up in Section 3; interface interpolation and rescaling after Yu et
- * al., cited there without formulas: the readings are in the design notes).
+ * al., cited there without formulas).
  *
- * Level 0 is the coarse lattice cfg->nx x ny x nz (lattice viscosity
- * cfg->nu). Level 1 refines by 2 in space and time the union of the blocks
- * (block^3 coarse nodes each) whose refine_mask entry is 1: fine node j of
- * an axis sits at coarse coordinate j/2, the fine viscosity in fine lattice
- * units is 2 nu, velocities are equal on both levels. The fine level is
- * stored over a box (lbm_refined_geometry: origin lo in fine coordinates,
- * extent dims) holding the refined nodes plus one layer of ghost nodes.
- * Both levels hold post-collision populations (deviations, ABI order);
- * one lbm_refined_step advances one coarse step = two fine steps.
- * Covered coarse nodes (refined and not read by the interface
- * interpolation) are overwritten from the fine level after each step.
+ * Level 0 is the lattice cfg->nx x ny x nz (lattice viscosity cfg->nu),
+ * divided into blocks of block^3 nodes. A level map gives, per level-0
+ * block, the finest level that covers it; R_l, the region of level l, is
+ * the union of the blocks whose entry is >= l. Level l has 2^l times the
+ * resolution in space and time (the same velocity scale: constant CFL
+ * number), lattice viscosity 2^l nu (tau_l - 1/2 = 2^l (tau_0 - 1/2)); the
+ * Smagorinsky constant acts in each level's own lattice units. Nesting is
+ * cell-centred: level-(l+1) node j lies at level-l coordinate j/2 - 1/4 (a
+ * node's cell holds the children 2i and 2i+1 on each axis), so the halfway
+ * walls, inlets and faces of all levels coincide.
+ *
+ * One lbm_refined_step advances one level-0 step: level l steps 2^l times,
+ * recursively (each level steps once, then its child level twice). Every
+ * level holds post-collision populations (deviations, ABI order) in a box:
+ * R_l plus the layer of ghost nodes around it, with its x origin and row
+ * pitch rounded to multiples of 32 nodes (extra nodes are unused).
+ * Interface per parent step t:
+ *   child ghosts, first substep:  rescale(G(t)),
+ *   child ghosts, second substep: rescale(-1/8 G(t-1) + 3/4 G(t) + 3/8
+ *     G(t+1)) (1/2 G(t) + 1/2 G(t+1) on the first step after a state
+ *     change), G = the parent state interpolated at the ghosts (tensor
+ *     4-point cubic Lagrange at the child positions; windows kept inside
+ *     non-periodic domains);
+ *   rescale = the model's equilibrium plus the non-equilibrium part scaled
+ *     by Chapman-Enskog: FCLB/CLB by r = (tau_f - 1)/(2 (tau_c - 1)); MRT
+ *     per moment group (tau = 1/s, same non-shear rates on both levels:
+ *     1/2, or 0 for rate 1), the shear group with the total relaxation
+ *     times of Eq. (20) (tau_c,tot recovered from the interpolated state's
+ *     post-collision traceless stress, tau_f,tot = tau0_f + (tau_c,tot -
+ *     tau0_c)/2);
+ *   covered parent nodes (inside R_{l+1}, read by no ghost interpolation)
+ *     whose eight children are fluid take the mean of the children,
+ *     rescaled back, after the two child substeps.
+ * Node types (lbm_refined_types): 0 unused, 1 fluid, 2 band (inside the
+ * next level's region but updated on this level, read by its ghost
+ * interpolation), 3 covered, 4 ghost, 5 solid.
  * ====================================================================== */
 typedef struct lbm_refined lbm_refined;
 
-/* refine_mask: host uint8 [nz/block][ny/block][nx/block] (copied); block
- * >= 2 divides nx, ny, nz; every extent >= 4; tau = 3 nu + 1/2 must differ
- * from 1 on both levels (the rescale factor (tau_f-1)/(2(tau_c-1)) and its
- * inverse must exist). */
-int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* refine_mask,
-                       lbm_refined** out);
+/* nlevels in [1, 8]; level_map: host uint8 [nz/block][ny/block][nx/block],
+ * entries < nlevels (copied); block >= 2 divides nx, ny, nz (block >= 3
+ * with three or more levels). Nesting: every block whose entry is m >= 2
+ * has its 26 neighbour blocks (periodic axes wrapping) at m - 1 or more;
+ * on a periodic axis each region either spans the axis or keeps off both
+ * ends; non-periodic axes need 4 or more nodes. tau = 3 nu 2^l + 1/2 must
+ * differ from 1 on every level of a refined lattice (the rescale factor and
+ * its inverse must exist) and omega < 2. A configuration that is valid only
+ * with non-periodic faces is created and needs lbm_refined_set_boundaries
+ * before binding. */
+int lbm_refined_create(const lbm_config* cfg, int32_t block, int32_t nlevels,
+                       const uint8_t* level_map, lbm_refined** out);
 
-/* Fine box origin lo (fine coordinates) and extent dims; counts = {fine
- * nodes, ghost nodes, covered coarse nodes, coarse nodes read by the
- * interpolation}. */
-int lbm_refined_geometry(const lbm_refined* r, int32_t lo[3], int32_t dims[3],
-                         int64_t counts[4]);
+/* Box of level l: origin lo (level coordinates), extent dims (dims[0] is the
+ * row pitch, a multiple of 32); counts = {fluid, band, covered, ghost,
+ * solid} nodes. LBM_ESTATE while the configuration waits for boundaries. */
+int lbm_refined_geometry(const lbm_refined* r, int32_t level, int32_t lo[3], int32_t dims[3],
+                         int64_t counts[5]);
 
-/* Bytes of device memory (two arrays per level, node types, ghost and
- * covered lists, interpolation buffers, reduction scratch). Valid after
- * the last lbm_refined_set_boundaries. */
+/* Node types of level l's box (host uint8 [dims z][y][x], codes above). */
+int lbm_refined_types(const lbm_refined* r, int32_t level, uint8_t* types);
+
+/* Bytes of device memory (two arrays per level, node types, tile lists,
+ * ghost lists and interface history, solid lists, reduction scratch). Valid
+ * after the last set_boundaries / set_solids / set_links. */
 int lbm_refined_required_bytes(const lbm_refined* r, size_t* bytes);
 
 /* Hand over the device block (256-byte aligned) and upload the geometry;
- * blocking. LBM_ESTATE if the refined region touches a periodic axis it
- * does not span (set non-periodic boundaries first). */
+ * blocking. Resets the time to 0. LBM_ESTATE if the configuration still
+ * waits for boundaries. */
 int lbm_refined_bind_memory(lbm_refined* r, void* dev, size_t bytes);
 
 /* Boundary description of the domain (as lbm_set_boundaries, applied on
- * both levels, LBM_FREESLIP and LBM_PRESSURE faces included; outflow may be
- * any face). With an inlet face the fine level
- * needs its own inlet arrays at fine resolution, [3][2 nb][2 na] and
- * [2 nb][2 na] (mask may be NULL), same dtype; it draws its perturbation
- * with seed + 1 and the fine step index. Must precede
- * lbm_refined_bind_memory (LBM_ESTATE after it). */
+ * every level; LBM_FREESLIP and LBM_PRESSURE faces included; outflow may be
+ * any face). With an inlet face each level l >= 1 needs its own inlet arrays
+ * at its resolution: level_inlet_u[l] ([3][2^l nb][2^l na], bc->inlet_dtype)
+ * and, if bc->inlet_mask is given, level_inlet_mask[l] ([2^l nb][2^l na]);
+ * both host arrays of nlevels device pointers, entry 0 unused (level 0 takes
+ * bc's own). Level l draws its perturbation with seed + l and its own step
+ * index. Must precede lbm_refined_bind_memory (LBM_ESTATE after it); the
+ * device buffers must stay valid while the lattice steps. */
 int lbm_refined_set_boundaries(lbm_refined* r, const lbm_boundaries* bc,
-                               const void* fine_inlet_u, const uint8_t* fine_inlet_mask);
+                               const void* const* level_inlet_u,
+                               const uint8_t* const* level_inlet_mask);
 
-/* Equilibrium state of one level (0 coarse: fields over nx*ny*nz; 1 fine:
- * fields over the fine box), as lbm_init_equilibrium. Sets the time. */
+/* Interior solid nodes of level l (the nozzle of the paper's set-up,
+ * Section 3): host uint8 over the level's box ([dims z][y][x], copied),
+ * nonzero = solid; NULL clears. Populations whose source is solid bounce
+ * back halfway (a wall at rest) or along curved links (lbm_refined_set_links).
+ * Solids keep off the interfaces: no solid ghost or band node, no solid
+ * next to a ghost, and no solid child under a covered node that a parent-
+ * updated node reads (LBM_EINVAL, solids unchanged). Clears the level's
+ * links. Must precede lbm_refined_bind_memory (LBM_ESTATE after it). */
+int lbm_refined_set_solids(lbm_refined* r, int32_t level, const uint8_t* solid);
+
+/* Curved walls on level l (Bouzidi's linear interpolated bounce-back, the
+ * rule of lbm_set_links): host arrays, copied: nodes [n] box indices of fluid
+ * nodes, q [n][Q] wall distances (entries outside (0, 1], or where the
+ * neighbour is not solid, ignored; where the node behind along the link is
+ * solid or beyond a face the halfway rule stays). Needs solids on that
+ * level (LBM_EINVAL otherwise); must precede lbm_refined_bind_memory. */
+int lbm_refined_set_links(lbm_refined* r, int32_t level, const int32_t* nodes, const float* q,
+                          int64_t n);
+
+/* Equilibrium state of one level's box (fields [dims] and [3][dims]), as
+ * lbm_init_equilibrium. Sets the time; the interface history restarts. */
 int lbm_refined_init_equilibrium(lbm_refined* r, int level, const void* drho, const void* u,
                                  int dtype, int64_t t0);
 
-/* Post-collision populations of one level, [Q][box] (set / get). On level
- * 1 the ghost nodes (the layer around the refined region) hold interface
- * values already prepared for the next fine substep, not state: get returns
- * them as they are, and after a set or init they are rebuilt from the coarse
- * level at the next step. */
+/* Post-collision populations of one level's box, [Q][dims] (set / get).
+ * Ghost nodes hold interface values prepared for the next substep, not
+ * state; solid nodes hold values of the solid pre-pass; covered nodes over
+ * a finer level's covered nodes are not updated. A set restarts the
+ * interface history and sets the time. */
 int lbm_refined_set_populations(lbm_refined* r, int level, const void* f, int dtype,
                                 int64_t t0);
 int lbm_refined_get_populations(lbm_refined* r, int level, void* f, int dtype);
 
-/* Advance n coarse steps (asynchronous, ordered on the lattice's stream).
- * Within a step the coarse update and the interface interpolation run on a
- * second, library-owned stream (created at the first call, default
- * priority) concurrently with the first fine substep, and the next step's
- * interface values are rescaled there during the second; events fork it
- * from and join it back to the lattice's stream, so callers see ordinary
- * single-stream semantics. */
+/* Advance n level-0 steps (asynchronous, on the lattice's stream). */
 int lbm_refined_step(lbm_refined* r, int64_t n);
 
 /* rho and u of one level's box (as lbm_get_macroscopic). */
 int lbm_refined_get_macroscopic(lbm_refined* r, int level, void* rho, void* u, int dtype,
                                 int rho_mode);
 
-/* Blocking FP64 sums over the domain: coarse nodes outside the refined
- * region plus fine nodes weighted by 1/8 (their volume in coarse cells). */
+/* Blocking FP64 sums over the domain: the fluid nodes of every level that
+ * no finer level covers, weighted by their volume 8^-l in level-0 cells. */
 int lbm_refined_reduce(lbm_refined* r, double out[5]);
 
 int lbm_refined_get_time(const lbm_refined* r, int64_t* t);

@@ -112,14 +112,19 @@ _SIGS = {
     "lbm_step_record": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "lbm_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_int, ctypes.c_void_p],
-    "lbm_refined_create": [ctypes.POINTER(Config), ctypes.c_int32,
+    "lbm_refined_create": [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int32,
                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_void_p)],
-    "lbm_refined_geometry": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+    "lbm_refined_geometry": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)],
+    "lbm_refined_types": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)],
+    "lbm_refined_set_solids": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)],
+    "lbm_refined_set_links": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_float), ctypes.c_int64],
     "lbm_refined_required_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "lbm_refined_bind_memory": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
-    "lbm_refined_set_boundaries": [ctypes.c_void_p, ctypes.POINTER(Boundaries), ctypes.c_void_p,
-                                   ctypes.c_void_p],
+    "lbm_refined_set_boundaries": [ctypes.c_void_p, ctypes.POINTER(Boundaries),
+                                   ctypes.POINTER(ctypes.c_void_p),
+                                   ctypes.POINTER(ctypes.c_void_p)],
     "lbm_refined_init_equilibrium": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_int64],
     "lbm_refined_set_populations": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
@@ -605,34 +610,48 @@ class Lattice:
 
 
 class RefinedLattice:
-    """Two-level nested time refinement (C ABI lbm_refined_*).
+    """Nested time refinement on a block grid (C ABI lbm_refined_*).
 
-    shape = coarse (nx, ny, nz); mask = uint8 [nz/B][ny/B][nx/B]. With
-    boundaries (faces, face_u, inlet arrays at both resolutions) they are
-    set before the device block is bound, as the ABI requires. Both levels
-    hold post-collision populations; level 1 is the fine box of extent
-    ``fine_shape3`` (nz, ny, nx) at origin ``fine_lo`` (fine coordinates).
+    shape = level-0 (nx, ny, nz); level_map = uint8 [nz/B][ny/B][nx/B], the
+    finest level of each block (``mask``, a 0/1 map, gives two levels).
+    Boundaries (faces, face_u, inlet arrays per level: ``level_inlet_u`` /
+    ``level_inlet_mask`` lists indexed by level, entry 0 unused, or for two
+    levels ``fine_inlet_u`` / ``fine_inlet_mask``), solids and curved links are
+    set before the device block is bound, as the ABI requires. ``solids``:
+    per-level list of uint8 masks over the level's whole domain (nz_l, ny_l,
+    nx_l) or None; ``links``: per-level list of (nodes, q) with nodes linear
+    indices over the level's whole domain and q [n][Q] float32, or None.
+    Every level holds post-collision populations over its box: ``levels[l]``
+    gives its origin ``lo`` (x, y, z), extent ``dims`` (x pitch, y, z) and
+    node counts; ``shape3(l)`` is (dims z, dims y, dims x).
     """
 
     def __init__(self, model="fclb", storage="f32", shape=(32, 32, 32), nu=0.01, cs_smag=0.0,
-                 mrt_basis=BASIS_TABLE1, rates=None, block=16, mask=None, faces=None,
-                 face_u=None, inlet_u=None, inlet_mask=None, fine_inlet_u=None,
-                 fine_inlet_mask=None, inlet_amp=0.0, seed=0, device="cuda", stream=None,
-                 face_drho=None):
+                 mrt_basis=BASIS_TABLE1, rates=None, block=16, level_map=None, nlevels=None,
+                 mask=None, faces=None, face_u=None, inlet_u=None, inlet_mask=None,
+                 level_inlet_u=None, level_inlet_mask=None, fine_inlet_u=None,
+                 fine_inlet_mask=None, inlet_amp=0.0, seed=0, solids=None, links=None,
+                 device="cuda", stream=None, face_drho=None):
         import numpy as np
         self.cfg = make_config(model, storage, shape, nu, cs_smag, mrt_basis, rates, stream)
         self.Q = 19 if self.cfg.model == D3Q19_MRT_LES else 27
         self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
         self.device = torch.device(device)
-        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if level_map is None:
+            level_map = mask
+        m = np.ascontiguousarray(level_map, dtype=np.uint8)
         if m.shape != (self.nz // block, self.ny // block, self.nx // block):
-            raise ValueError("mask must have shape (nz/B, ny/B, nx/B)")
-        self._mask = m
+            raise ValueError("level map must have shape (nz/B, ny/B, nx/B)")
+        self.L = int(nlevels) if nlevels is not None else int(m.max()) + 1
+        self._map = m
         self.h = ctypes.c_void_p()
-        _check(lib().lbm_refined_create(ctypes.byref(self.cfg), int(block),
+        _check(lib().lbm_refined_create(ctypes.byref(self.cfg), int(block), self.L,
                                         m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                         ctypes.byref(self.h)), "lbm_refined_create")
         self._keep = []
+        if level_inlet_u is None and fine_inlet_u is not None:
+            level_inlet_u = [None, fine_inlet_u]
+            level_inlet_mask = [None, fine_inlet_mask]
         if faces is not None:
             bc = Boundaries()
             for k in range(6):
@@ -644,41 +663,60 @@ class RefinedLattice:
             if face_drho is not None:
                 for k in range(6):
                     bc.face_drho[k] = float(face_drho[k])
-            fiu = fim = None
+            ptr_u = (ctypes.c_void_p * self.L)()
+            ptr_m = (ctypes.c_void_p * self.L)()
             if inlet_u is not None:
                 ax = [k for k in range(6) if int(faces[k]) == INLET][0] // 2
                 dims = (self.nx, self.ny, self.nz)
                 na = dims[1] if ax == 0 else dims[0]
                 nb = dims[1] if ax == 2 else dims[2]
-                if tuple(inlet_u.shape) != (3, nb, na) or \
-                        tuple(fine_inlet_u.shape) != (3, 2 * nb, 2 * na):
-                    raise ValueError("inlet arrays must be (3, nb, na) and (3, 2nb, 2na)")
                 iu = inlet_u.to(self.device).contiguous()
-                fiu = fine_inlet_u.to(device=self.device, dtype=iu.dtype).contiguous()
-                self._keep += [iu, fiu]
+                if tuple(iu.shape) != (3, nb, na):
+                    raise ValueError("inlet_u must be (3, nb, na)")
+                self._keep.append(iu)
                 bc.inlet_u = iu.data_ptr()
                 bc.inlet_dtype = _dtype_code(iu)
                 if inlet_mask is not None:
                     im = inlet_mask.to(device=self.device, dtype=torch.uint8).contiguous()
-                    fim = fine_inlet_mask.to(device=self.device, dtype=torch.uint8).contiguous()
-                    if tuple(im.shape) != (nb, na) or tuple(fim.shape) != (2 * nb, 2 * na):
-                        raise ValueError("inlet masks must be (nb, na) and (2nb, 2na)")
-                    self._keep += [im, fim]
+                    if tuple(im.shape) != (nb, na):
+                        raise ValueError("inlet_mask must be (nb, na)")
+                    self._keep.append(im)
                     bc.inlet_mask = im.data_ptr()
+                for l in range(1, self.L):
+                    lu = level_inlet_u[l].to(device=self.device, dtype=iu.dtype).contiguous()
+                    if tuple(lu.shape) != (3, nb << l, na << l):
+                        raise ValueError("level %d inlet_u must be (3, %d, %d)"
+                                         % (l, nb << l, na << l))
+                    self._keep.append(lu)
+                    ptr_u[l] = lu.data_ptr()
+                    if inlet_mask is not None:
+                        lm = level_inlet_mask[l].to(device=self.device,
+                                                    dtype=torch.uint8).contiguous()
+                        if tuple(lm.shape) != (nb << l, na << l):
+                            raise ValueError("level %d inlet_mask must be (%d, %d)"
+                                             % (l, nb << l, na << l))
+                        self._keep.append(lm)
+                        ptr_m[l] = lm.data_ptr()
             bc.inlet_amp = float(inlet_amp)
             bc.seed = int(seed)
-            _check(lib().lbm_refined_set_boundaries(
-                self.h, ctypes.byref(bc),
-                ctypes.c_void_p(fiu.data_ptr()) if fiu is not None else None,
-                ctypes.c_void_p(fim.data_ptr()) if fim is not None else None),
-                "lbm_refined_set_boundaries")
-        lo = (ctypes.c_int32 * 3)()
-        dims = (ctypes.c_int32 * 3)()
-        cnt = (ctypes.c_int64 * 4)()
-        _check(lib().lbm_refined_geometry(self.h, lo, dims, cnt), "lbm_refined_geometry")
-        self.fine_lo = tuple(lo)
-        self.fine_dims = tuple(dims)
-        self.counts = dict(zip(("fluid", "ghost", "covered", "band"), tuple(cnt)))
+            _check(lib().lbm_refined_set_boundaries(self.h, ctypes.byref(bc), ptr_u, ptr_m),
+                   "lbm_refined_set_boundaries")
+        self._geometry()
+        for l in range(self.L):
+            sm = solids[l] if solids is not None and l < len(solids) else None
+            if sm is not None:
+                box = self._to_box(l, np.asarray(sm, dtype=np.uint8))
+                _check(lib().lbm_refined_set_solids(
+                    self.h, l, box.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+                    "lbm_refined_set_solids")
+            lk = links[l] if links is not None and l < len(links) else None
+            if lk is not None:
+                nodes, q = self._links_to_box(l, *lk)
+                _check(lib().lbm_refined_set_links(
+                    self.h, l, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    q.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(nodes)),
+                    "lbm_refined_set_links")
+        self._geometry()
         n = ctypes.c_size_t()
         _check(lib().lbm_refined_required_bytes(self.h, ctypes.byref(n)),
                "lbm_refined_required_bytes")
@@ -688,6 +726,67 @@ class RefinedLattice:
         _check(lib().lbm_refined_bind_memory(self.h, _dev(self._view), n.value),
                "lbm_refined_bind_memory")
 
+    def _geometry(self):
+        self.levels = []
+        for l in range(self.L):
+            lo = (ctypes.c_int32 * 3)()
+            dims = (ctypes.c_int32 * 3)()
+            cnt = (ctypes.c_int64 * 5)()
+            _check(lib().lbm_refined_geometry(self.h, l, lo, dims, cnt), "lbm_refined_geometry")
+            self.levels.append({"lo": tuple(lo), "dims": tuple(dims),
+                                "n": (self.nx << l, self.ny << l, self.nz << l),
+                                "counts": dict(zip(("fluid", "band", "covered", "ghost",
+                                                    "solid"), tuple(cnt)))})
+        if self.L > 1:  # the two-level names used by callers of the fine level
+            self.fine_lo = self.levels[1]["lo"]
+            self.fine_dims = self.levels[1]["dims"]
+        c = {k: 0 for k in ("fluid", "band", "covered", "ghost", "solid")}
+        for v in self.levels[1:]:
+            c["fluid"] += v["counts"]["fluid"] + v["counts"]["band"]
+            c["ghost"] += v["counts"]["ghost"]
+        c["covered"] = sum(v["counts"]["covered"] for v in self.levels)
+        c["band"] = sum(v["counts"]["band"] for v in self.levels)
+        self.counts = c
+
+    def box_slices(self, level):
+        """(z, y, x) slices of the box in the level's domain and, for x, the
+        number of box columns inside the domain."""
+        v = self.levels[level]
+        (ox, oy, oz), (mx, my, mz), (nx, _, _) = v["lo"], v["dims"], v["n"]
+        wx = min(mx, nx - ox)
+        return slice(oz, oz + mz), slice(oy, oy + my), slice(ox, ox + wx), wx
+
+    def to_box(self, level, a):
+        """A [..., nz_l, ny_l, nx_l] array of the level's whole domain cut to
+        its box (columns beyond the domain zero)."""
+        import numpy as np
+        sz, sy, sx, wx = self.box_slices(level)
+        mx, my, mz = self.levels[level]["dims"]
+        out = np.zeros(a.shape[:-3] + (mz, my, mx), dtype=a.dtype)
+        out[..., :wx] = a[..., sz, sy, sx]
+        return out
+
+    _to_box = to_box
+
+    def _links_to_box(self, level, nodes, q):
+        import numpy as np
+        nx, ny, nz = self.levels[level]["n"]
+        (ox, oy, oz), (mx, my, mz) = self.levels[level]["lo"], self.levels[level]["dims"]
+        nodes = np.asarray(nodes, dtype=np.int64)
+        x, y, z = nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)
+        bx, by, bz = x - ox, y - oy, z - oz
+        keep = (bx >= 0) & (bx < mx) & (by >= 0) & (by < my) & (bz >= 0) & (bz < mz)
+        box = ((bz * my + by) * mx + bx)[keep].astype(np.int32)
+        return np.ascontiguousarray(box), np.ascontiguousarray(np.asarray(q, np.float32)[keep])
+
+    def types(self, level):
+        import numpy as np
+        t = np.zeros(self.shape3(level), dtype=np.uint8)
+        _check(lib().lbm_refined_types(self.h, level,
+                                       t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+               "lbm_refined_types")
+        return t
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and _lib is not None:
@@ -695,9 +794,8 @@ class RefinedLattice:
             self.h = None
 
     def shape3(self, level):
-        if level == 0:
-            return (self.nz, self.ny, self.nx)
-        return (self.fine_dims[2], self.fine_dims[1], self.fine_dims[0])
+        d = self.levels[level]["dims"]
+        return (d[2], d[1], d[0])
 
     def init_equilibrium(self, level, drho, u, t0=0):
         drho = torch.as_tensor(drho).to(self.device).contiguous()

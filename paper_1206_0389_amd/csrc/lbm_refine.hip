@@ -1,13 +1,15 @@
-// Host runtime of the two-level refined lattice (lbm_refined_* in
-// include/lbm.h): geometry of the block-refined region, memory layout inside
-// the caller's block, and the per-coarse-step launch sequence.
+// Host runtime of the refined lattice (lbm_refined_* in include/lbm.h):
+// geometry of the nested block-refined levels, memory layout inside the
+// caller's block, and the recursive launch sequence of a level-0 step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -15,47 +17,54 @@
 
 using namespace lbm;
 
+namespace {
+
+constexpr int kMaxLevels = 8;
+
+struct HostLevel {
+  int o[3] = {0, 0, 0}, M[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+  uint32_t span = 0;
+  size_t Nbox = 0;
+  std::vector<uint8_t> type;
+  // tiles (3 ints each) in the order plain+inj | plain | general+inj | general
+  std::vector<int32_t> tiles;
+  size_t nt[4] = {0, 0, 0, 0};
+  std::vector<int32_t> ghosts, gcode;
+  std::vector<GhostGroup> groups;
+  std::vector<uint8_t> solid;               // host copy over the box (empty: none)
+  std::vector<int32_t> link_nodes;          // user links: box indices
+  std::vector<float> link_q;                // [n][Q]
+  std::vector<int32_t> pre_nodes;           // solid pre-pass list
+  std::vector<uint32_t> pre_dirs;
+  std::vector<float> pre_q;
+  // device offsets
+  size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
+         off_groups = 0, off_G[3] = {0, 0, 0}, off_pre_nodes = 0, off_pre_dirs = 0,
+         off_pre_q = 0;
+  int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
+  bool have_cur = false, have_prev = false;
+  Lev dev;
+  double tau0 = 0.5;
+};
+
+int hip_fail(hipError_t e);
+}  // namespace
+
 struct lbm_refined {
   lbm_config cfg;
-  int kind, Q;
-  size_t elem, relem;  // bytes per stored value / per compute value
-  int B, nb[3];
-  std::vector<uint8_t> mask;
-  int lo[3], M[3];
-  size_t Nc, Nf;
-  std::vector<uint8_t> ctype, ftype;
-  std::vector<int32_t> ghosts, covered;
-  std::vector<int32_t> gcode;       // per ghost: stencil code (GhostGroup)
-  std::vector<GhostGroup> groups;   // ghost groups staged by one workgroup
-  double r;
-  hipStream_t stream;
-  // second stream (default priority, non-blocking) on which the coarse step
-  // runs concurrently with the first fine substep, joined by events
-  hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr, sub1_ev = nullptr;
-  bool side_tried = false;
-  // device layout
+  int kind = 0, Q = 27;
+  size_t elem = 4, relem = 4;
+  int B = 16, nb[3] = {0, 0, 0}, L = 1;
+  std::vector<uint8_t> map;
+  HostLevel lev[kMaxLevels];
+  BcArgs bc;
+  const void* inlet_u[kMaxLevels] = {nullptr};
+  const uint8_t* inlet_mask[kMaxLevels] = {nullptr};
+  bool geometry_ok = false;
   char* base = nullptr;
-  size_t off[14] = {0};
-  size_t req = 0;
-  Level Lc, Lf;
-  void *g0 = nullptr, *g1 = nullptr;
-  double* partial = nullptr;
-  double* result = nullptr;
-  size_t nblocks_c = 0, nblocks_f = 0;
-  dim3 grid_c, block_c, grid_f, block_f;
-  bool g0_valid = false;
+  size_t req = 0, off_partial = 0, off_result = 0, max_rblocks = 1;
+  hipStream_t stream = nullptr;
   int64_t t = 0;
-  bool has_bc = false;
-  bool geometry_ok = false;  // false until a valid boundary set is known
-  // per level (0 coarse, 1 fine): wall rows (off the non-periodic z domain
-  // faces and off y faces that are not walls; wall kernel) and the rows on
-  // those faces (general kernel)
-  struct Plan {
-    int mode;  // 0: no boundary logic, 1: wall rows + face rows, 2: general
-    Rows all, inner, face;
-    dim3 grid_all, grid_inner, grid_face, block, block_face;
-  } plan[2];
 };
 
 namespace {
@@ -74,230 +83,440 @@ int check_launch() {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-void shape_for(int nx, int ny, int nz, dim3& grid, dim3& block, size_t& nblocks) {
-  int bx = nx < 256 ? nx : 256;
-  if (bx < 1) bx = 1;
-  int by = 256 / bx;
-  if (by > ny) by = ny;
-  if (by < 1) by = 1;
-  block = dim3(bx, by, 1);
-  grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
-  nblocks = (size_t)grid.x * grid.y * grid.z;
+int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+bool periodic_axis(const lbm_refined* R, int d) { return ((R->bc.nonper >> (2 * d)) & 1u) == 0; }
+
+int block_level(const lbm_refined* R, int bx, int by, int bz) {
+  return R->map[((size_t)bz * R->nb[1] + by) * R->nb[0] + bx];
 }
 
-bool block_refined(const lbm_refined* R, int bx, int by, int bz) {
-  return R->mask[((size_t)bz * R->nb[1] + by) * R->nb[0] + bx] != 0;
+// Is level-l node g (level coordinates, inside the domain) in R_m?
+bool in_region(const lbm_refined* R, int l, int m, const int g[3]) {
+  const int s = R->B << l;
+  return block_level(R, g[0] / s, g[1] / s, g[2] / s) >= m;
 }
 
-// Is fine global node j inside the refined region?
-bool fine_refined(const lbm_refined* R, const int j[3]) {
-  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
+// Neighbour of g by d on level l: periodic axes wrap; false beyond a
+// non-periodic face.
+bool neighbour(const lbm_refined* R, int l, const int g[3], const int d[3], int y[3]) {
+  const HostLevel& V = R->lev[l];
+  for (int a = 0; a < 3; ++a) {
+    y[a] = g[a] + d[a];
+    if (y[a] >= 0 && y[a] < V.n[a]) continue;
+    if (!periodic_axis(R, a)) return false;
+    y[a] = (y[a] + V.n[a]) % V.n[a];
+  }
+  return true;
+}
+
+// Box index of level coordinates g (inside the box), or -1.
+long box_index(const HostLevel& V, const int g[3]) {
   int b[3];
   for (int d = 0; d < 3; ++d) {
-    if (j[d] < 0 || j[d] >= 2 * n3[d]) return false;
-    b[d] = j[d] / (2 * R->B);
+    b[d] = g[d] - V.o[d];
+    if (b[d] < 0 || b[d] >= V.M[d]) return -1;
   }
-  return block_refined(R, b[0], b[1], b[2]);
+  return ((long)b[2] * V.M[1] + b[1]) * V.M[0] + b[0];
 }
 
-// Orders the ghost list by group (coarse cube of kGhostCube^3 cells, then
-// stencil shape, then box index: the lanes of a wave mostly share one
-// shape), splits each cube into groups of at most kGhostMax ghosts, and sets
-// each group's coarse patch and each ghost's stencil code relative to it. A
-// group whose patch would exceed kPatchEdge on an axis is split into single
-// ghosts (patches of at most 4 nodes per axis).
-void group_ghosts(lbm_refined* R, uint32_t nonper) {
-  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
-  const size_t ng = R->ghosts.size();
+void box_coords(const HostLevel& V, long k, int g[3]) {
+  g[0] = (int)(k % V.M[0]) + V.o[0];
+  g[1] = (int)((k / V.M[0]) % V.M[1]) + V.o[1];
+  g[2] = (int)(k / ((long)V.M[0] * V.M[1])) + V.o[2];
+}
+
+// Parent window of child coordinate j on axis d of level l-1.
+void child_stencil(const lbm_refined* R, int lp, int d, int j, int idx[4], int& start, int& code) {
+  const HostLevel& P = R->lev[lp];
+  const bool per = periodic_axis(R, d);
+  code = child_window(j, P.n[d], per, start);
+  for (int a = 0; a < 4; ++a) idx[a] = per ? (((start + a) % P.n[d]) + P.n[d]) % P.n[d] : start + a;
+}
+
+// Ghost groups of level l (parent cube of the stencil starts, then box
+// index), their parent patches and each ghost's stencil code.
+void group_ghosts(lbm_refined* R, int l) {
+  HostLevel& V = R->lev[l];
   struct Item {
-    long long key;
-    int32_t l;
+    std::tuple<int, int, int> cube;
+    int32_t k;
     int start[3], code[3];
   };
-  std::vector<Item> it(ng);
-  int ncube[3];
-  for (int d = 0; d < 3; ++d) ncube[d] = (n3[d] + kGhostCube - 1) / kGhostCube;
-  for (size_t g = 0; g < ng; ++g) {
-    const int32_t l = R->ghosts[g];
-    const int lx = l % R->M[0], ly = (l / R->M[0]) % R->M[1], lz = l / (R->M[0] * R->M[1]);
-    const int j[3] = {lx + R->lo[0], ly + R->lo[1], lz + R->lo[2]};
-    Item& e = it[g];
-    e.l = l;
-    int cube[3], shape = 0;
-    for (int d = 0; d < 3; ++d) {
-      e.code[d] = stencil_code(j[d], n3[d], ((nonper >> (2 * d)) & 1u) == 0, e.start[d]);
-      cube[d] = (j[d] >> 1) / kGhostCube;
-      shape |= e.code[d] != 0 ? 1 << d : 0;
-    }
-    const long long c = ((long long)cube[2] * ncube[1] + cube[1]) * ncube[0] + cube[0];
-    e.key = (c * 8 + shape) * (1ll << 32) + l;
+  std::vector<Item> it(V.ghosts.size());
+  for (size_t gi = 0; gi < V.ghosts.size(); ++gi) {
+    int g[3];
+    box_coords(V, V.ghosts[gi], g);
+    Item& e = it[gi];
+    e.k = V.ghosts[gi];
+    int idx[4];
+    for (int d = 0; d < 3; ++d) child_stencil(R, l - 1, d, g[d], idx, e.start[d], e.code[d]);
+    e.cube = std::make_tuple(floor_div(e.start[2], kGhostCube), floor_div(e.start[1], kGhostCube),
+                             floor_div(e.start[0], kGhostCube));
   }
-  std::sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
-  R->gcode.assign(ng, 0);
-  R->groups.clear();
-  auto add_group = [&](size_t b, size_t e) {
+  std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) {
+    return a.cube < b.cube || (a.cube == b.cube && a.k < b.k);
+  });
+  V.gcode.assign(it.size(), 0);
+  V.groups.clear();
+  auto add = [&](size_t b, size_t e) {
     GhostGroup gr;
     gr.gbeg = (int)b;
     gr.gend = (int)e;
     for (int d = 0; d < 3; ++d) {
-      int lo = it[b].start[d], hi = lo;
+      int lo = it[b].start[d], hi = it[b].start[d] + 3;
       for (size_t k = b; k < e; ++k) {
         lo = std::min(lo, it[k].start[d]);
-        hi = std::max(hi, it[k].start[d] + (it[k].code[d] ? 3 : 0));
+        hi = std::max(hi, it[k].start[d] + 3);
       }
       gr.lo[d] = lo;
       gr.m[d] = hi - lo + 1;
     }
     for (size_t k = b; k < e; ++k) {
-      int code = 0;
-      for (int d = 0; d < 3; ++d) code |= ((it[k].start[d] - gr.lo[d]) | (it[k].code[d] << 3)) << (6 * d);
-      R->gcode[k] = code;
+      int c = 0;
+      for (int d = 0; d < 3; ++d) c |= ((it[k].start[d] - gr.lo[d]) | (it[k].code[d] << 3)) << (6 * d);
+      V.gcode[k] = c;
     }
-    R->groups.push_back(gr);
+    V.groups.push_back(gr);
     return gr.m[0] <= kPatchEdge && gr.m[1] <= kPatchEdge && gr.m[2] <= kPatchEdge;
   };
   size_t b = 0;
-  while (b < ng) {
-    const long long cube = it[b].key >> 35;
+  while (b < it.size()) {
     size_t e = b;
-    while (e < ng && (it[e].key >> 35) == cube && e - b < (size_t)kGhostMax) ++e;
-    if (!add_group(b, e)) {
-      R->groups.pop_back();
-      for (size_t k = b; k < e; ++k) add_group(k, k + 1);
+    while (e < it.size() && it[e].cube == it[b].cube && e - b < (size_t)kGhostMax) ++e;
+    if (!add(b, e)) {
+      V.groups.pop_back();
+      for (size_t k = b; k < e; ++k) add(k, k + 1);
     }
     b = e;
   }
-  for (size_t g = 0; g < ng; ++g) R->ghosts[g] = it[g].l;
+  for (size_t gi = 0; gi < it.size(); ++gi) V.ghosts[gi] = it[gi].k;
 }
 
-// Box, node types, ghost and covered lists. Returns false if a refined
-// region touches a periodic axis without spanning it.
-bool build_geometry(lbm_refined* R, const uint32_t nonper) {
-  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
-  int blo[3] = {R->nb[0], R->nb[1], R->nb[2]}, bhi[3] = {0, 0, 0};
-  bool any = false;
+// Tile lists of level l: aligned 32 x 4 x 2 tiles holding fluid or band
+// nodes; plain if every active node lies on no domain face and reads only
+// in-box neighbours without wrapping; inj if a parent node of the tile is
+// covered (the child's second substep then injects).
+void build_tiles(lbm_refined* R, int l) {
+  HostLevel& V = R->lev[l];
+  std::vector<int32_t> lists[4];
+  const int tx0 = V.o[0], ty0 = floor_div(V.o[1], 4) * 4, tz0 = floor_div(V.o[2], 2) * 2;
+  for (int tz = tz0; tz < V.o[2] + V.M[2]; tz += 2)
+    for (int ty = ty0; ty < V.o[1] + V.M[1]; ty += 4)
+      for (int tx = tx0; tx < V.o[0] + V.M[0]; tx += 32) {
+        bool any = false, plain = true, inj = false;
+        for (int k = 0; k < 256; ++k) {
+          const int g[3] = {tx + (k & 31), ty + ((k >> 5) & 3), tz + (k >> 7)};
+          const long bi = box_index(V, g);
+          if (bi < 0) continue;
+          const uint8_t ty_ = V.type[bi];
+          if (ty_ != RT_FLUID && ty_ != RT_BAND) continue;
+          any = true;
+          for (int d = 0; d < 3 && plain; ++d)
+            if (g[d] == 0 || g[d] == V.n[d] - 1) plain = false;
+          for (int c = 0; c < 27 && plain; ++c) {
+            const int h[3] = {g[0] + c % 3 - 1, g[1] + (c / 3) % 3 - 1, g[2] + c / 9 - 1};
+            if (box_index(V, h) < 0) plain = false;
+          }
+        }
+        if (!any) continue;
+        if (l > 0) {
+          const HostLevel& P = R->lev[l - 1];
+          for (int k = 0; k < 32 && !inj; ++k) {
+            const int pg[3] = {tx / 2 + (k & 15), ty / 2 + (k >> 4), tz / 2};
+            const long pi = box_index(P, pg);
+            if (pi >= 0 && P.type[pi] == RT_COVERED) inj = true;
+          }
+        }
+        const int which = (plain ? 0 : 2) + (inj ? 0 : 1);
+        lists[which].push_back(tx);
+        lists[which].push_back(ty);
+        lists[which].push_back(tz);
+      }
+  V.tiles.clear();
+  for (int k = 0; k < 4; ++k) {
+    V.nt[k] = lists[k].size() / 3;
+    V.tiles.insert(V.tiles.end(), lists[k].begin(), lists[k].end());
+  }
+}
+
+// Geometry of every level from the block map, the periodic axes, the solids
+// and the links. Returns false for an invalid configuration.
+bool build_geometry(lbm_refined* R) {
+  const int L = R->L, B = R->B, Q = R->Q;
+  const int n0[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
+  // nesting: the neighbours of a block at level m >= 2 are at level >= m - 1
   for (int bz = 0; bz < R->nb[2]; ++bz)
     for (int by = 0; by < R->nb[1]; ++by)
       for (int bx = 0; bx < R->nb[0]; ++bx) {
-        if (!block_refined(R, bx, by, bz)) continue;
-        any = true;
-        const int b[3] = {bx, by, bz};
-        for (int d = 0; d < 3; ++d) {
-          blo[d] = std::min(blo[d], b[d]);
-          bhi[d] = std::max(bhi[d], b[d] + 1);
+        const int m = block_level(R, bx, by, bz);
+        if (m >= L) return false;
+        if (m < 2) continue;
+        for (int c = 0; c < 27; ++c) {
+          int b[3] = {bx + c % 3 - 1, by + (c / 3) % 3 - 1, bz + c / 9 - 1};
+          bool inside = true;
+          for (int d = 0; d < 3; ++d) {
+            if (b[d] >= 0 && b[d] < R->nb[d]) continue;
+            if (!periodic_axis(R, d)) inside = false;
+            b[d] = (b[d] + R->nb[d]) % R->nb[d];
+          }
+          if (inside && block_level(R, b[0], b[1], b[2]) < m - 1) return false;
         }
       }
-  for (int d = 0; d < 3; ++d) {
-    if (!any) {
-      R->lo[d] = 0;
-      R->M[d] = 0;
-      continue;
-    }
-    const bool periodic = ((nonper >> (2 * d)) & 1u) == 0;
-    if (periodic && !((blo[d] == 0 && bhi[d] == R->nb[d]) || (blo[d] > 0 && bhi[d] < R->nb[d])))
-      return false;
-    int a = 2 * R->B * blo[d], b = 2 * R->B * bhi[d];
-    if (a > 0) --a;
-    if (b < 2 * n3[d]) ++b;
-    R->lo[d] = a;
-    R->M[d] = b - a;
-  }
-  R->Nf = (size_t)R->M[0] * R->M[1] * R->M[2];
-  R->ftype.assign(R->Nf, 0);
-  R->ghosts.clear();
-  for (int lz = 0; lz < R->M[2]; ++lz)
-    for (int ly = 0; ly < R->M[1]; ++ly)
-      for (int lx = 0; lx < R->M[0]; ++lx) {
-        const int j[3] = {lx + R->lo[0], ly + R->lo[1], lz + R->lo[2]};
-        const size_t l = ((size_t)lz * R->M[1] + ly) * R->M[0] + lx;
-        if (fine_refined(R, j)) {
-          R->ftype[l] = 1;
+  for (int l = 0; l < L; ++l) {
+    HostLevel& V = R->lev[l];
+    int blo[3] = {R->nb[0], R->nb[1], R->nb[2]}, bhi[3] = {-1, -1, -1};
+    for (int bz = 0; bz < R->nb[2]; ++bz)
+      for (int by = 0; by < R->nb[1]; ++by)
+        for (int bx = 0; bx < R->nb[0]; ++bx)
+          if (block_level(R, bx, by, bz) >= l) {
+            const int b3[3] = {bx, by, bz};
+            for (int d = 0; d < 3; ++d) {
+              blo[d] = std::min(blo[d], b3[d]);
+              bhi[d] = std::max(bhi[d], b3[d] + 1);
+            }
+          }
+    V.span = 0;
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      V.n[d] = n0[d] << l;
+      if (bhi[0] < 0) {  // nothing on this level
+        lo[d] = hi[d] = 0;
+        continue;
+      }
+      const int s = B << l;
+      const bool full = blo[d] == 0 && bhi[d] == R->nb[d];
+      if (periodic_axis(R, d)) {
+        if (full) {
+          V.span |= 1u << d;
+          lo[d] = 0;
+          hi[d] = V.n[d];
           continue;
         }
-        bool near = false;
-        for (int k = 0; k < 27 && !near; ++k) {
-          const int jj[3] = {j[0] + k % 3 - 1, j[1] + (k / 3) % 3 - 1, j[2] + k / 9 - 1};
-          near = fine_refined(R, jj);
-        }
-        if (near) {
-          R->ftype[l] = 2;
-          R->ghosts.push_back((int32_t)l);
+        if (blo[d] == 0 || bhi[d] == R->nb[d]) return false;  // touches a periodic end
+      }
+      lo[d] = std::max(0, blo[d] * s - 1);
+      hi[d] = std::min(V.n[d], bhi[d] * s + 1);
+    }
+    V.o[0] = floor_div(lo[0], 32) * 32;
+    V.M[0] = hi[0] > lo[0] ? ((hi[0] - V.o[0] + 31) / 32) * 32 : 0;
+    V.o[1] = lo[1];
+    V.M[1] = hi[1] - lo[1];
+    V.o[2] = lo[2];
+    V.M[2] = hi[2] - lo[2];
+    if (V.M[0] == 0 || V.M[1] == 0 || V.M[2] == 0) V.M[0] = V.M[1] = V.M[2] = 0;
+    V.Nbox = (size_t)V.M[0] * V.M[1] * V.M[2];
+    if ((double)V.Nbox * 8.0 >= 2147483647.0) return false;  // 32-bit box offsets
+    V.type.assign(V.Nbox, RT_UNUSED);
+    V.ghosts.clear();
+    for (size_t k = 0; k < V.Nbox; ++k) {
+      int g[3];
+      box_coords(V, (long)k, g);
+      if (g[0] >= V.n[0]) continue;
+      if (in_region(R, l, l, g)) {
+        V.type[k] = (l + 1 < L && in_region(R, l, l + 1, g)) ? RT_COVERED : RT_FLUID;
+        continue;
+      }
+      for (int c = 0; c < 27; ++c) {
+        const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+        int y[3];
+        if (neighbour(R, l, g, d, y) && in_region(R, l, l, y)) {
+          V.type[k] = RT_GHOST;
+          V.ghosts.push_back((int32_t)k);
+          break;
         }
       }
-  group_ghosts(R, nonper);
-  R->ctype.assign(R->Nc, 0);
-  for (int z = 0; z < n3[2]; ++z)
-    for (int y = 0; y < n3[1]; ++y)
-      for (int x = 0; x < n3[0]; ++x)
-        if (block_refined(R, x / R->B, y / R->B, z / R->B))
-          R->ctype[((size_t)z * n3[1] + y) * n3[0] + x] = 2;
-  // nodes read by a ghost stencil stay coarse-updated ("band")
-  for (int32_t l : R->ghosts) {
-    const int lx = l % R->M[0], ly = (l / R->M[0]) % R->M[1], lz = l / (R->M[0] * R->M[1]);
-    const int j[3] = {lx + R->lo[0], ly + R->lo[1], lz + R->lo[2]};
-    int idx[3][4], cnt[3];
-    double w[3][4];
-    for (int d = 0; d < 3; ++d)
-      cnt[d] = interp_stencil(j[d], n3[d], ((nonper >> (2 * d)) & 1u) == 0, idx[d], w[d]);
-    for (int c = 0; c < cnt[2]; ++c)
-      for (int b = 0; b < cnt[1]; ++b)
-        for (int a = 0; a < cnt[0]; ++a) {
-          uint8_t& t = R->ctype[((size_t)idx[2][c] * n3[1] + idx[1][b]) * n3[0] + idx[0][a]];
-          if (t == 2) t = 1;
-        }
+    }
   }
-  R->covered.clear();
-  for (size_t i = 0; i < R->Nc; ++i)
-    if (R->ctype[i] == 2) R->covered.push_back((int32_t)i);
+  // band: parent nodes read by a child's ghost stencils stay parent-updated
+  for (int l = 1; l < L; ++l) {
+    HostLevel& V = R->lev[l];
+    HostLevel& P = R->lev[l - 1];
+    for (int32_t gk : V.ghosts) {
+      int g[3], idx[3][4], s, c;
+      box_coords(V, gk, g);
+      for (int d = 0; d < 3; ++d) child_stencil(R, l - 1, d, g[d], idx[d], s, c);
+      for (int cz = 0; cz < 4; ++cz)
+        for (int cy = 0; cy < 4; ++cy)
+          for (int cx_ = 0; cx_ < 4; ++cx_) {
+            const int pg[3] = {idx[0][cx_], idx[1][cy], idx[2][cz]};
+            const long pi = box_index(P, pg);
+            if (pi < 0) return false;
+            uint8_t& t = P.type[pi];
+            if (t == RT_COVERED) t = RT_BAND;
+            if (t != RT_FLUID && t != RT_BAND) return false;
+          }
+    }
+  }
+  // solids: off the interface
+  for (int l = 0; l < L; ++l) {
+    HostLevel& V = R->lev[l];
+    if (V.solid.empty()) continue;
+    for (size_t k = 0; k < V.Nbox; ++k) {
+      if (!V.solid[k]) continue;
+      uint8_t& t = V.type[k];
+      if (t == RT_GHOST || t == RT_BAND) return false;
+      if (t == RT_FLUID || t == RT_COVERED) t = RT_SOLID;
+    }
+  }
+  for (int l = 0; l < L; ++l) {
+    HostLevel& V = R->lev[l];
+    const bool child = l + 1 < L;
+    for (size_t k = 0; k < V.Nbox; ++k) {
+      if (V.type[k] != RT_FLUID && V.type[k] != RT_BAND) continue;
+      int g[3];
+      box_coords(V, (long)k, g);
+      for (int i = 0; i < 27; ++i) {
+        const int d[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+        int y[3];
+        if (!neighbour(R, l, g, d, y)) continue;
+        const long yi = box_index(V, y);
+        if (yi < 0 || V.type[yi] == RT_UNUSED) return false;
+        if (!child) continue;
+        if (V.type[yi] == RT_SOLID && in_region(R, l, l + 1, y)) return false;
+        if (V.type[yi] != RT_COVERED || R->lev[l + 1].solid.empty()) continue;
+        const HostLevel& C = R->lev[l + 1];
+        for (int c = 0; c < 8; ++c) {
+          const int z[3] = {2 * y[0] + (c & 1), 2 * y[1] + ((c >> 1) & 1), 2 * y[2] + (c >> 2)};
+          const long zi = box_index(C, z);
+          if (zi >= 0 && C.solid[zi]) return false;
+        }
+      }
+    }
+    if (l > 0 && !V.solid.empty())
+      for (int32_t gk : V.ghosts) {
+        int g[3];
+        box_coords(V, gk, g);
+        for (int c = 0; c < 27; ++c) {
+          const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+          int y[3];
+          if (!neighbour(R, l, g, d, y)) continue;
+          const long yi = box_index(V, y);
+          if (yi >= 0 && V.solid[yi]) return false;
+        }
+      }
+  }
+  // solid pre-pass lists (with the curved links' distances)
+  for (int l = 0; l < L; ++l) {
+    HostLevel& V = R->lev[l];
+    V.pre_nodes.clear();
+    V.pre_dirs.clear();
+    V.pre_q.clear();
+    if (V.solid.empty()) continue;
+    std::map<int32_t, size_t> lk;
+    for (size_t j = 0; j < V.link_nodes.size(); ++j) lk[V.link_nodes[j]] = j;
+    for (size_t k = 0; k < V.Nbox; ++k) {
+      if (V.type[k] != RT_FLUID && V.type[k] != RT_BAND) continue;
+      int g[3];
+      box_coords(V, (long)k, g);
+      uint32_t dirs = 0;
+      float q[27];
+      for (int i = 0; i < 27; ++i) q[i] = 0.5f;
+      auto it = lk.find((int32_t)k);
+      for (int i = 1; i < Q; ++i) {
+        const int d[3] = {-cx(i), -cy(i), -cz(i)};
+        int s[3];
+        if (!neighbour(R, l, g, d, s)) continue;
+        if (V.type[box_index(V, s)] != RT_SOLID) continue;
+        dirs |= 1u << i;
+        const int kdir = Q == 27 ? opposite<27>(i) : opposite<19>(i);
+        if (it == lk.end()) continue;
+        const float qq = V.link_q[it->second * Q + kdir];
+        if (!(qq > 0.0f && qq <= 1.0f)) continue;
+        // the node behind x along the link (x + e_i) must be a fluid node
+        // inside the domain, else the halfway rule stays (either branch)
+        const int db[3] = {cx(i), cy(i), cz(i)};
+        int bh[3];
+        if (!neighbour(R, l, g, db, bh)) continue;
+        const uint8_t tb = V.type[box_index(V, bh)];
+        if (tb == RT_SOLID || tb == RT_UNUSED) continue;
+        q[kdir] = qq;
+      }
+      if (!dirs) continue;
+      V.pre_nodes.push_back((int32_t)k);
+      V.pre_dirs.push_back(dirs);
+      V.pre_q.insert(V.pre_q.end(), q, q + Q);
+    }
+  }
+  for (int l = 0; l < L; ++l) build_tiles(R, l);
+  for (int l = 1; l < L; ++l) group_ghosts(R, l);
   return true;
 }
 
 void layout(lbm_refined* R) {
-  const size_t pc = align256(R->Nc * R->Q * R->elem), pf = align256(R->Nf * R->Q * R->elem);
-  const size_t ng = R->ghosts.size();
   size_t o = 0;
-  R->off[0] = o; o += pc;                                    // coarse A
-  R->off[1] = o; o += pc;                                    // coarse B
-  R->off[2] = o; o += pf;                                    // fine A
-  R->off[3] = o; o += pf;                                    // fine B
-  R->off[4] = o; o += align256(R->Nc);                       // coarse types
-  R->off[5] = o; o += align256(R->Nf);                       // fine types
-  R->off[6] = o; o += align256(ng * 4);                      // ghosts
-  R->off[7] = o; o += align256(R->covered.size() * 4);       // covered
-  R->off[8] = o; o += align256(ng * R->Q * R->relem);        // G0
-  R->off[9] = o; o += align256(ng * R->Q * R->relem);        // G1
-  R->off[12] = o; o += align256(ng * 4);                     // stencil codes
-  R->off[13] = o; o += align256(R->groups.size() * sizeof(GhostGroup));  // groups
-  const size_t nbmax = std::max(R->nblocks_c, R->nblocks_f);
-  R->off[10] = o; o += align256(nbmax * 5 * sizeof(double));  // partials
-  R->off[11] = o; o += 256;                                  // result
+  R->max_rblocks = 1;
+  for (int l = 0; l < R->L; ++l) {
+    HostLevel& V = R->lev[l];
+    const size_t pa = align256(V.Nbox * R->Q * R->elem);
+    const size_t ng = V.ghosts.size();
+    V.off_a = o; o += pa;
+    V.off_b = o; o += pa;
+    V.off_type = o; o += align256(V.Nbox);
+    V.off_tiles = o; o += align256(V.tiles.size() * 4);
+    V.off_ghosts = o; o += align256(ng * 4);
+    V.off_gcode = o; o += align256(ng * 4);
+    V.off_groups = o; o += align256(V.groups.size() * sizeof(GhostGroup));
+    for (int k = 0; k < 3; ++k) {
+      V.off_G[k] = o;
+      o += align256(ng * R->Q * R->relem);
+    }
+    V.off_pre_nodes = o; o += align256(V.pre_nodes.size() * 4);
+    V.off_pre_dirs = o; o += align256(V.pre_dirs.size() * 4);
+    V.off_pre_q = o; o += align256(V.pre_q.size() * 4);
+    R->max_rblocks = std::max(R->max_rblocks, (V.Nbox + 255) / 256);
+  }
+  R->off_partial = o;
+  o += align256(R->max_rblocks * 5 * sizeof(double));
+  R->off_result = o;
+  o += 256;
   R->req = o;
 }
 
-void level_physics(Level& L, const lbm_config& c, double nu) {
+void level_physics(const lbm_refined* R, int l, Lev& D) {
+  const lbm_config& c = R->cfg;
+  const double nu = c.nu * (double)(1 << l);
   const double tau0 = 3.0 * nu + 0.5;
-  L.mrt.tau0 = tau0;
-  L.mrt.cs18 = 18.0 * c.cs_smag * c.cs_smag;
-  L.omega = 1.0 / tau0;
-  const double t1[5] = {1, 1, 1, 1, 1}, dh[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+  D.mrt.tau0 = tau0;
+  D.mrt.cs18 = 18.0 * c.cs_smag * c.cs_smag;
+  D.omega = 1.0 / tau0;
+  const double dh[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
   for (int k = 0; k < 5; ++k)
-    L.mrt.rates[k] = c.use_default_rates ? (c.mrt_basis == LBM_BASIS_TABLE1 ? t1[k] : dh[k])
+    D.mrt.rates[k] = c.use_default_rates ? (c.mrt_basis == LBM_BASIS_TABLE1 ? 1.0 : dh[k])
                                          : c.rates[k];
 }
 
-GhostArgs ghost_args(const lbm_refined* R) {
-  GhostArgs g;
-  g.ghosts = (const int*)(R->base + R->off[6]);
-  g.ng = (long long)R->ghosts.size();
-  g.gcode = (const int*)(R->base + R->off[12]);
-  g.groups = (const int*)(R->base + R->off[13]);
-  g.ngroups = (long long)R->groups.size();
-  g.cn[0] = R->cfg.nx;
-  g.cn[1] = R->cfg.ny;
-  g.cn[2] = R->cfg.nz;
-  g.Nc = (long long)R->Nc;
-  g.Nf = (long long)R->Nf;
-  return g;
+// Kernel arguments of every level (after bind or a change of boundaries).
+void make_levels(lbm_refined* R) {
+  for (int l = 0; l < R->L; ++l) {
+    HostLevel& V = R->lev[l];
+    Lev& D = V.dev;
+    std::memset(&D, 0, sizeof(Lev));
+    D.a = R->base ? R->base + V.off_a : nullptr;
+    D.b = R->base ? R->base + V.off_b : nullptr;
+    D.type = R->base ? (const uint8_t*)(R->base + V.off_type) : nullptr;
+    for (int d = 0; d < 3; ++d) {
+      D.o[d] = V.o[d];
+      D.M[d] = V.M[d];
+      D.n[d] = V.n[d];
+    }
+    D.span = V.span;
+    D.Nbox = (long long)V.Nbox;
+    level_physics(R, l, D);
+    V.tau0 = D.mrt.tau0;
+    BcArgs b = R->bc;
+    if (b.inlet) {
+      const int ax = b.inlet_axis;
+      b.inlet_u = R->inlet_u[l];
+      b.inlet_mask = R->inlet_mask[l];
+      b.inlet_na = V.n[ax == 0 ? 1 : 0];
+      b.inlet_nb = V.n[ax == 2 ? 1 : 2];
+      b.seed = R->bc.seed + (uint64_t)l;  // each level draws its own perturbation
+    }
+    fill_wall_terms(b, R->Q);
+    D.bc = b;
+    V.have_cur = V.have_prev = false;
+  }
 }
 
 template <typename Fn>
@@ -319,202 +538,224 @@ void with_kind_s(const lbm_refined* R, Fn&& fn) {
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
-// Row sets of one level's box: the wall rows (global z on no non-periodic
-// domain face, global y on no non-periodic y face other than a wall), and
-// the other rows (listed as whole z planes first, then single y rows).
-void plan_level(lbm_refined::Plan& p, const Level& L, dim3 block, size_t elem, int Q) {
-  const uint32_t np = L.bc.nonper;
-  const int Mx = L.M[0], My = L.M[1], Mz = L.M[2];
-  Rows all{};
-  all.ny_in = My;
-  all.nz_in = Mz;
-  p.all = all;
-  p.block = block;
-  p.grid_all = dim3((Mx + block.x - 1) / block.x, (My + block.y - 1) / block.y, Mz);
-  Rows in = all, f{};
-  // y faces that are walls stay in the wall rows
-  const bool ywall = (L.bc.wall & 12u) == 12u;
-  const bool ylo = !ywall && (np & 4u) && L.lo[1] == 0;
-  const bool yhi = !ywall && (np & 8u) && L.lo[1] + My == L.n[1];
-  const bool zlo = (np & 16u) && L.lo[2] == 0, zhi = (np & 32u) && L.lo[2] + Mz == L.n[2];
-  if (ylo) f.yb[f.yb_n++] = 0;
-  if (yhi) f.yb[f.yb_n++] = My - 1;
-  if (zlo) f.zb[f.zb_n++] = 0;
-  if (zhi) f.zb[f.zb_n++] = Mz - 1;
-  in.y0 = ylo ? 1 : 0;
-  in.ny_in = My - (ylo ? 1 : 0) - (yhi ? 1 : 0);
-  in.z0 = zlo ? 1 : 0;
-  in.nz_in = Mz - (zlo ? 1 : 0) - (zhi ? 1 : 0);
-  f.zi0 = zlo ? 1 : 0;
-  p.inner = in;
-  p.face = f;
-  const long long nrows = (long long)f.zb_n * My + (long long)f.yb_n * (Mz - f.zb_n);
-  p.grid_inner = dim3((Mx + block.x - 1) / block.x,
-                      in.ny_in > 0 ? (in.ny_in + block.y - 1) / block.y : 0,
-                      in.nz_in > 0 ? in.nz_in : 0);
-  const int bbx = Mx < 256 ? (Mx > 0 ? Mx : 1) : 256;
-  p.block_face = dim3(bbx, 1, 1);
-  p.grid_face = dim3((Mx + bbx - 1) / bbx, (unsigned)(nrows > 0 ? nrows : 0), 1);
-  const bool x_walls = (L.bc.inlet & 3u) == 0 && ((np & 3u) == 0 || (L.bc.wall & 3u) == 3u);
-  // the box and wall-row kernels address a population and its opposite from
-  // the lower slab with 32-bit byte offsets; larger boxes take the general
-  // kernel
-  const double span = 1.0 + (Q == 27 ? max_opposite_distance<27>() : max_opposite_distance<19>());
-  const bool o32 = span * (double)L.Nbox * (double)elem < 4294967296.0;
-  if (!o32)
-    p.mode = 2;
-  else if (np == 0)
-    p.mode = 0;
-  else if (x_walls && nrows <= 65535)
-    p.mode = 1;
-  else
-    p.mode = 2;
-}
-
-template <int KIND, typename S>
-void level_step(const lbm_refined* R, hipStream_t stream, const Level& L,
-                const lbm_refined::Plan& p, int mode,
-                long long t) {
-  if (L.Nbox == 0) return;
-  if (p.mode == 0) {
-    hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_NONE, ROWS_BOX>), p.grid_all, p.block, 0,
-                       stream, L, p.all, mode, t);
-  } else if (p.mode == 2) {
-    hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_BOX>), p.grid_all, p.block, 0,
-                       stream, L, p.all, mode, t);
-  } else {
-    if (p.grid_inner.y > 0 && p.grid_inner.z > 0)
-      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_WALLS, ROWS_BOX>), p.grid_inner, p.block, 0,
-                         stream, L, p.inner, mode, t);
-    if (p.grid_face.y > 0)
-      hipLaunchKernelGGL((ab_step_kernel<KIND, S, BC_GENERAL, ROWS_LIST>), p.grid_face,
-                         p.block_face, 0, stream, L, p.face, mode, t);
+GhostArgs ghost_args(const lbm_refined* R, int l) {
+  const HostLevel& V = R->lev[l];
+  const HostLevel& P = R->lev[l - 1];
+  GhostArgs g;
+  g.ghosts = (const int*)(R->base + V.off_ghosts);
+  g.ng = (long long)V.ghosts.size();
+  g.gcode = (const int*)(R->base + V.off_gcode);
+  g.groups = (const int*)(R->base + V.off_groups);
+  g.ngroups = (long long)V.groups.size();
+  for (int d = 0; d < 3; ++d) {
+    g.po[d] = P.o[d];
+    g.pM[d] = P.M[d];
+    g.pn[d] = P.n[d];
   }
+  g.pspan = P.span;
+  g.pN = (long long)P.Nbox;
+  g.cN = (long long)V.Nbox;
+  return g;
 }
 
-// Ghosts of the fine array ff := rescale(c0 G0 + c1 G), G = the
-// interpolation of the coarse state fc (stored into G); G0 may be null
-// (then c0 is unused).
+RescaleArgs rescale_args(const lbm_refined* R, int l) {
+  RescaleArgs a;
+  a.tau0_c = R->lev[l - 1].tau0;
+  a.tau0_f = R->lev[l].tau0;
+  a.cs = R->cfg.cs_smag;
+  a.r = (a.tau0_f - 1.0) / (2.0 * (a.tau0_c - 1.0));
+  for (int k = 0; k < 5; ++k) a.rates[k] = R->lev[l].dev.mrt.rates[k];
+  return a;
+}
+
 template <int KIND, typename S>
-void ghost_patch(const lbm_refined* R, hipStream_t stream, const GhostArgs& ga, const void* fc,
-                 void* G, const void* G0, double c0, double c1, void* ff) {
+void* G_ptr(const lbm_refined* R, const HostLevel& V, int which) {
+  return R->base + V.off_G[V.gi[which]];
+}
+
+// Ghosts of child level l in array ff := rescale(c0 G(t-1) + c1 G(t) + c2
+// Gnew), Gnew = the interpolation of parent state fp, stored as G(t+1) (or
+// as G(t) when `init`).
+template <int KIND, typename S>
+void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, double c1, double c2,
+                 bool init) {
   using Rt = typename Compute<S>::type;
-  if (ga.ngroups == 0) return;
-  hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)ga.ngroups), dim3(256), 0,
-                     stream, ga, (const S*)fc, (Rt*)G, (const Rt*)G0, c0, c1, R->r, (S*)ff);
+  HostLevel& V = R->lev[l];
+  if (V.groups.empty()) return;
+  const GhostArgs ga = ghost_args(R, l);
+  const RescaleArgs ra = rescale_args(R, l);
+  void* Gn = G_ptr<KIND, S>(R, V, init ? 1 : 2);
+  hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
+                     dim3(256), 0, R->stream, ga, (const S*)fp, (Rt*)Gn,
+                     (const Rt*)G_ptr<KIND, S>(R, V, 1), (const Rt*)G_ptr<KIND, S>(R, V, 0), c0,
+                     c1, c2, ra, (S*)ff);
 }
 
-// Ghosts of ff := rescale(G) from the stored interpolation G.
 template <int KIND, typename S>
-void ghost_rescale(const lbm_refined* R, hipStream_t stream, const GhostArgs& ga, const void* G,
-                   void* ff) {
+void ghost_rescale(lbm_refined* R, int l, int which, void* ff) {
   using Rt = typename Compute<S>::type;
-  if (ga.ngroups == 0) return;
-  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3((unsigned)ga.ngroups), dim3(256),
-                     0, stream, ga, (const Rt*)G, 1.0, R->r, (S*)ff);
+  HostLevel& V = R->lev[l];
+  if (V.groups.empty()) return;
+  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
+                     dim3(256), 0, R->stream, ghost_args(R, l),
+                     (const Rt*)G_ptr<KIND, S>(R, V, which), rescale_args(R, l), (S*)ff);
 }
 
-// One coarse step: the coarse update (Lc.a -> Lc.b), two fine substeps
-// (Lf.a -> Lf.b -> Lf.a) and the interface. Ghost slots are written only by
-// the interface kernels and fluid slots only by the fine updates, so with
-// the side stream the work runs as two chains:
-//   main: fine substep 1 ............ [wait interp] fine substep 2 + injection
-//   side: coarse step -> G1, half-step ghosts of Lf.b -> [wait substep 1]
-//         next-step ghosts of Lf.a
-// (the half-step ghosts rescale(G0/2 + G1/2) are read only by substep 2; the
-// next-step ghosts rescale(G1) go into Lf.a, which substep 1 reads, so they
-// wait for it). The main stream joins the side stream at the end.
 template <int KIND, typename S>
-void one_coarse_step(lbm_refined* R, long long t) {
-  const GhostArgs ga = ghost_args(R);
-  const bool fine = R->Nf > 0;
-  // The ghosts of the first fine substep come from the previous coarse
-  // step; after a change of state they are rebuilt.
-  if (fine && !R->g0_valid)
-    ghost_patch<KIND, S>(R, R->stream, ga, R->Lc.a, R->g0, nullptr, 0.0, 1.0, R->Lf.a);
-  const bool fork = fine && R->side != nullptr;
-  hipStream_t side = fork ? R->side : R->stream;
-  if (fork) {
-    (void)hipEventRecord(R->fork_ev, R->stream);
-    (void)hipStreamWaitEvent(R->side, R->fork_ev, 0);
+void level_step(lbm_refined* R, int l, long long t, bool second) {
+  HostLevel& V = R->lev[l];
+  if (V.Nbox == 0) return;
+  const Lev& D = V.dev;
+  if (!V.pre_nodes.empty()) {
+    constexpr int Q = Model<KIND>::Q;
+    hipLaunchKernelGGL((solid_prepass_kernel<Q, S>), dim3(blocks_for((long long)V.pre_nodes.size())),
+                       dim3(256), 0, R->stream, D, (const int*)(R->base + V.off_pre_nodes),
+                       (const uint32_t*)(R->base + V.off_pre_dirs),
+                       (const float*)(R->base + V.off_pre_q), (long long)V.pre_nodes.size());
   }
-  level_step<KIND, S>(R, side, R->Lc, R->plan[0], 0, t);
-  if (!fine) {
-    std::swap(R->Lc.a, R->Lc.b);
-    R->g0_valid = false;
-    return;
+  InjArgs inj;
+  std::memset(&inj, 0, sizeof(inj));
+  const bool do_inj = second && l > 0;
+  if (do_inj) {
+    const HostLevel& P = R->lev[l - 1];
+    inj.dst = P.dev.b;
+    inj.type = P.dev.type;
+    for (int d = 0; d < 3; ++d) {
+      inj.o[d] = P.o[d];
+      inj.M[d] = P.M[d];
+    }
+    inj.Nbox = (long long)P.Nbox;
+    inj.tau0_c = P.tau0;
+    inj.tau0_f = V.tau0;
+    inj.cs = R->cfg.cs_smag;
+    inj.rinv = (2.0 * (P.tau0 - 1.0)) / (V.tau0 - 1.0);
+    for (int k = 0; k < 5; ++k) inj.rates[k] = D.mrt.rates[k];
   }
-  ghost_patch<KIND, S>(R, side, ga, R->Lc.b, R->g1, R->g0, 0.5, 0.5, R->Lf.b);
-  if (fork) (void)hipEventRecord(R->join_ev, R->side);
-  level_step<KIND, S>(R, R->stream, R->Lf, R->plan[1], 1, 2 * t);
-  // the last fine substep also injects into the covered nodes of the
-  // coarse state at t + 1 (read by no ghost stencil)
-  Level L2 = R->Lf;
-  std::swap(L2.a, L2.b);
-  if (!R->covered.empty()) {
-    L2.cinj = R->Lc.b;
-    L2.ctype = R->Lc.type;
-    for (int d = 0; d < 3; ++d) L2.cn[d] = R->Lc.n[d];
-    L2.Nc = (long long)R->Nc;
-    L2.rinv = 1.0 / R->r;
+  const int* tiles = (const int*)(R->base + V.off_tiles);
+  size_t start = 0;
+  for (int k = 0; k < 4; ++k) {
+    const size_t n = V.nt[k];
+    const int* tl = tiles + 3 * start;
+    start += n;
+    if (n == 0) continue;
+    const bool gen = k >= 2, inj_list = (k & 1) == 0;
+    const dim3 grid((unsigned)n), block(256);
+    if (do_inj && inj_list) {
+      if (gen)
+        hipLaunchKernelGGL((level_step_kernel<KIND, S, true, true>), grid, block, 0, R->stream, D,
+                           tl, t, inj);
+      else
+        hipLaunchKernelGGL((level_step_kernel<KIND, S, false, true>), grid, block, 0, R->stream,
+                           D, tl, t, inj);
+    } else {
+      if (gen)
+        hipLaunchKernelGGL((level_step_kernel<KIND, S, true, false>), grid, block, 0, R->stream,
+                           D, tl, t, inj);
+      else
+        hipLaunchKernelGGL((level_step_kernel<KIND, S, false, false>), grid, block, 0, R->stream,
+                           D, tl, t, inj);
+    }
   }
-  if (fork) {
-    (void)hipEventRecord(R->sub1_ev, R->stream);
-    (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
-    level_step<KIND, S>(R, R->stream, L2, R->plan[1], 1, 2 * t + 1);
-    (void)hipStreamWaitEvent(R->side, R->sub1_ev, 0);
-    ghost_rescale<KIND, S>(R, R->side, ga, R->g1, R->Lf.a);
-    (void)hipEventRecord(R->join_ev, R->side);
-    (void)hipStreamWaitEvent(R->stream, R->join_ev, 0);
-  } else {
-    ghost_rescale<KIND, S>(R, R->stream, ga, R->g1, R->Lf.a);
-    level_step<KIND, S>(R, R->stream, L2, R->plan[1], 1, 2 * t + 1);
+}
+
+void swap_arrays(HostLevel& V) { std::swap(V.dev.a, V.dev.b); }
+
+// Advance level l by one of its steps (index t), and recursively the finer
+// levels by two steps each; `second`: the second step of level l within its
+// parent's step (it injects into the parent's covered nodes).
+template <int KIND, typename S>
+void advance(lbm_refined* R, int l, long long t, bool second) {
+  HostLevel& V = R->lev[l];
+  const bool child = l + 1 < R->L && R->lev[l + 1].Nbox > 0;
+  if (child && !R->lev[l + 1].have_cur) {
+    HostLevel& C = R->lev[l + 1];
+    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true);
+    C.have_cur = true;
+    C.have_prev = false;
   }
-  std::swap(R->Lc.a, R->Lc.b);
-  std::swap(R->g0, R->g1);
-  R->g0_valid = true;
+  level_step<KIND, S>(R, l, t, second);
+  if (child) {
+    HostLevel& C = R->lev[l + 1];
+    const double c0 = C.have_prev ? -0.125 : 0.0, c1 = C.have_prev ? 0.75 : 0.5,
+                 c2 = C.have_prev ? 0.375 : 0.5;
+    ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false);
+    advance<KIND, S>(R, l + 1, 2 * t, false);
+    advance<KIND, S>(R, l + 1, 2 * t + 1, true);
+    ghost_rescale<KIND, S>(R, l + 1, 2, C.dev.a);
+    const int old = C.gi[0];
+    C.gi[0] = C.gi[1];
+    C.gi[1] = C.gi[2];
+    C.gi[2] = old;
+    C.have_prev = true;
+  }
+  swap_arrays(V);
 }
 
 bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
 
-// A LatArgs view of one level's current state (for the uniform-lattice
+// A LatArgs view of one level's current state box (the uniform lattice's
 // init/set/get/macroscopic kernels, parity 0, no boundary pulls).
 LatArgs level_view(const lbm_refined* R, int level) {
-  const Level& L = level == 0 ? R->Lc : R->Lf;
+  const HostLevel& V = R->lev[level];
   LatArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.f = L.a;
-  a.nx = L.M[0];
-  a.ny = L.M[1];
-  a.nz = L.M[2];
-  a.N = L.Nbox;
-  a.mrt = L.mrt;
-  a.omega = L.omega;
+  a.f = V.dev.a;
+  a.nx = V.M[0];
+  a.ny = V.M[1];
+  a.nz = V.M[2];
+  a.N = (long long)V.Nbox;
+  a.mrt = V.dev.mrt;
+  a.omega = V.dev.omega;
   a.bc.ghost_n = 1;
   return a;
 }
+
+void view_launch(const LatArgs& a, dim3& grid, dim3& block) {
+  int bx = a.nx < 256 ? a.nx : 256;
+  if (bx < 1) bx = 1;
+  int by = 256 / bx;
+  if (by > a.ny) by = a.ny;
+  if (by < 1) by = 1;
+  block = dim3(bx, by, 1);
+  grid = dim3((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
+}
+
+int upload(lbm_refined* R, size_t off, const void* src, size_t bytes) {
+  if (bytes == 0) return LBM_OK;
+  const hipError_t e = hipMemcpyAsync(R->base + off, src, bytes, hipMemcpyHostToDevice, R->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e);
+}
+
+void invalidate_history(lbm_refined* R) {
+  for (int l = 0; l < R->L; ++l) R->lev[l].have_cur = R->lev[l].have_prev = false;
+}
+
+bool level_ok(const lbm_refined* R, int level) { return level >= 0 && level < R->L; }
 
 }  // namespace
 
 extern "C" {
 
-int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask,
-                       lbm_refined** out) {
-  if (!cfg || !mask || !out) return LBM_EINVAL;
+int lbm_refined_create(const lbm_config* cfg, int32_t block, int32_t nlevels,
+                       const uint8_t* level_map, lbm_refined** out) {
+  if (!cfg || !level_map || !out) return LBM_EINVAL;
   const lbm_config& c = *cfg;
   if (c.model != LBM_D3Q19_MRT_LES && c.model != LBM_D3Q27_FCLB && c.model != LBM_D3Q27_CLB)
     return LBM_EINVAL;
   if (c.storage != LBM_F64 && c.storage != LBM_F32 && c.storage != LBM_F16) return LBM_EINVAL;
-  if (block < 2 || c.nx < 4 || c.ny < 4 || c.nz < 4) return LBM_EINVAL;
-  if (c.nx % block || c.ny % block || c.nz % block) return LBM_EINVAL;
-  if ((double)c.nx * c.ny * c.nz * 8.0 >= 2147483648.0) return LBM_EINVAL;
-  if (2 * c.nz > 65535) return LBM_EINVAL;
+  if (nlevels < 1 || nlevels > kMaxLevels) return LBM_EINVAL;
+  if (block < 2 || (nlevels >= 3 && block < 3)) return LBM_EINVAL;
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1 || c.nx % block || c.ny % block || c.nz % block)
+    return LBM_EINVAL;
   if (!(c.nu > 0.0) || !std::isfinite(c.nu) || !(c.cs_smag >= 0.0)) return LBM_EINVAL;
   if (c.model == LBM_D3Q19_MRT_LES && c.mrt_basis != LBM_BASIS_TABLE1 &&
       c.mrt_basis != LBM_BASIS_DHUMIERES)
     return LBM_EINVAL;
-  const double tc = 3.0 * c.nu + 0.5, tf = 6.0 * c.nu + 0.5;
-  if (std::fabs(tc - 1.0) < 1e-6 || std::fabs(tf - 1.0) < 1e-6) return LBM_EINVAL;
+  for (int l = 0; l < nlevels; ++l) {
+    const double tau = 3.0 * c.nu * (double)(1 << l) + 0.5;
+    if (nlevels > 1 && std::fabs(tau - 1.0) < 1e-6) return LBM_EINVAL;
+    if (1.0 / tau >= 2.0) return LBM_EINVAL;
+  }
   lbm_refined* R = new (std::nothrow) lbm_refined();
   if (!R) return LBM_EINVAL;
   R->cfg = c;
@@ -525,56 +766,66 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, const uint8_t* mask
   R->elem = c.storage == LBM_F64 ? 8 : (c.storage == LBM_F32 ? 4 : 2);
   R->relem = c.storage == LBM_F64 ? 8 : 4;
   R->B = block;
+  R->L = nlevels;
   R->nb[0] = c.nx / block;
   R->nb[1] = c.ny / block;
   R->nb[2] = c.nz / block;
-  R->mask.assign(mask, mask + (size_t)R->nb[0] * R->nb[1] * R->nb[2]);
-  R->Nc = (size_t)c.nx * c.ny * c.nz;
-  R->r = (tf - 1.0) / (2.0 * (tc - 1.0));
+  R->map.assign(level_map, level_map + (size_t)R->nb[0] * R->nb[1] * R->nb[2]);
   R->stream = (hipStream_t)c.stream;
-  // all faces periodic until boundaries are set; a region that touches a
-  // periodic axis without spanning it needs boundaries before binding
-  R->geometry_ok = build_geometry(R, 0u);
-  if (!R->geometry_ok) build_geometry(R, 0x3Fu);
-  std::memset(&R->Lc, 0, sizeof(Level));
-  std::memset(&R->Lf, 0, sizeof(Level));
-  level_physics(R->Lc, c, c.nu);
-  level_physics(R->Lf, c, 2.0 * c.nu);
-  R->Lc.n[0] = R->Lc.M[0] = c.nx;
-  R->Lc.n[1] = R->Lc.M[1] = c.ny;
-  R->Lc.n[2] = R->Lc.M[2] = c.nz;
-  R->Lc.Nbox = (long long)R->Nc;
-  R->Lf.n[0] = 2 * c.nx;
-  R->Lf.n[1] = 2 * c.ny;
-  R->Lf.n[2] = 2 * c.nz;
-  for (int d = 0; d < 3; ++d) {
-    R->Lf.lo[d] = R->lo[d];
-    R->Lf.M[d] = R->M[d];
+  std::memset(&R->bc, 0, sizeof(BcArgs));
+  R->bc.inlet_axis = 2;
+  R->bc.ghost_n = 1;
+  // all faces periodic until boundaries are set; a configuration that is
+  // only valid with other boundaries waits for them before binding
+  R->geometry_ok = build_geometry(R);
+  if (!R->geometry_ok) {
+    // one-sided windows need 4 nodes on non-periodic axes
+    for (int d = 0; d < 3; ++d) {
+      const int n = d == 0 ? c.nx : (d == 1 ? c.ny : c.nz);
+      if (n < 4) {
+        delete R;
+        return LBM_EINVAL;
+      }
+    }
+    R->bc.nonper = 0x3Fu;
+    const bool ok = build_geometry(R);
+    R->bc.nonper = 0;
+    if (!ok) {
+      delete R;
+      return LBM_EINVAL;
+    }
+    for (int l = 0; l < R->L; ++l) R->lev[l].type.clear();
   }
-  R->Lf.Nbox = (long long)R->Nf;
-  shape_for(c.nx, c.ny, c.nz, R->grid_c, R->block_c, R->nblocks_c);
-  shape_for(R->M[0], R->M[1], R->M[2], R->grid_f, R->block_f, R->nblocks_f);
+  make_levels(R);
   layout(R);
-  plan_level(R->plan[0], R->Lc, R->block_c, R->elem, R->Q);
-  plan_level(R->plan[1], R->Lf, R->block_f, R->elem, R->Q);
   *out = R;
   return LBM_OK;
 }
 
-int lbm_refined_geometry(const lbm_refined* R, int32_t lo[3], int32_t dims[3],
-                         int64_t counts[4]) {
-  if (!R || !lo || !dims || !counts) return LBM_EINVAL;
+int lbm_refined_geometry(const lbm_refined* R, int32_t level, int32_t lo[3], int32_t dims[3],
+                         int64_t counts[5]) {
+  if (!R || !lo || !dims || !counts || !level_ok(R, level)) return LBM_EINVAL;
+  if (!R->geometry_ok) return LBM_ESTATE;
+  const HostLevel& V = R->lev[level];
   for (int d = 0; d < 3; ++d) {
-    lo[d] = R->lo[d];
-    dims[d] = R->M[d];
+    lo[d] = V.o[d];
+    dims[d] = V.M[d];
   }
-  int64_t nf = 0, nb = 0;
-  for (uint8_t t : R->ftype) nf += t == 1;
-  for (uint8_t t : R->ctype) nb += t == 1;
-  counts[0] = nf;
-  counts[1] = (int64_t)R->ghosts.size();
-  counts[2] = (int64_t)R->covered.size();
-  counts[3] = nb;
+  for (int k = 0; k < 5; ++k) counts[k] = 0;
+  for (uint8_t t : V.type) {
+    if (t == RT_FLUID) ++counts[0];
+    if (t == RT_BAND) ++counts[1];
+    if (t == RT_COVERED) ++counts[2];
+    if (t == RT_GHOST) ++counts[3];
+    if (t == RT_SOLID) ++counts[4];
+  }
+  return LBM_OK;
+}
+
+int lbm_refined_types(const lbm_refined* R, int32_t level, uint8_t* types) {
+  if (!R || !types || !level_ok(R, level)) return LBM_EINVAL;
+  if (!R->geometry_ok) return LBM_ESTATE;
+  std::memcpy(types, R->lev[level].type.data(), R->lev[level].type.size());
   return LBM_OK;
 }
 
@@ -584,62 +835,41 @@ int lbm_refined_required_bytes(const lbm_refined* R, size_t* bytes) {
   return LBM_OK;
 }
 
-static int upload_geometry(lbm_refined* R) {
-  hipError_t e;
-  e = hipMemcpyAsync(R->base + R->off[4], R->ctype.data(), R->Nc, hipMemcpyHostToDevice, R->stream);
-  if (e != hipSuccess) return hip_fail(e);
-  if (R->Nf) {
-    e = hipMemcpyAsync(R->base + R->off[5], R->ftype.data(), R->Nf, hipMemcpyHostToDevice,
-                       R->stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (!R->ghosts.empty()) {
-    e = hipMemcpyAsync(R->base + R->off[6], R->ghosts.data(), R->ghosts.size() * 4,
-                       hipMemcpyHostToDevice, R->stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (!R->covered.empty()) {
-    e = hipMemcpyAsync(R->base + R->off[7], R->covered.data(), R->covered.size() * 4,
-                       hipMemcpyHostToDevice, R->stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (!R->ghosts.empty()) {
-    e = hipMemcpyAsync(R->base + R->off[12], R->gcode.data(), R->gcode.size() * 4,
-                       hipMemcpyHostToDevice, R->stream);
-    if (e != hipSuccess) return hip_fail(e);
-    e = hipMemcpyAsync(R->base + R->off[13], R->groups.data(),
-                       R->groups.size() * sizeof(GhostGroup), hipMemcpyHostToDevice, R->stream);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  e = hipStreamSynchronize(R->stream);
-  return e == hipSuccess ? LBM_OK : hip_fail(e);
-}
-
 int lbm_refined_bind_memory(lbm_refined* R, void* dev, size_t bytes) {
   if (!R || !dev || ((uintptr_t)dev & 255) != 0) return LBM_EINVAL;
   if (!R->geometry_ok) return LBM_ESTATE;
   if (bytes < R->req) return LBM_ENOMEM;
   R->base = (char*)dev;
-  R->Lc.a = R->base + R->off[0];
-  R->Lc.b = R->base + R->off[1];
-  R->Lf.a = R->base + R->off[2];
-  R->Lf.b = R->base + R->off[3];
-  R->Lc.type = (const uint8_t*)(R->base + R->off[4]);
-  R->Lf.type = (const uint8_t*)(R->base + R->off[5]);
-  R->g0 = R->base + R->off[8];
-  R->g1 = R->base + R->off[9];
-  R->partial = (double*)(R->base + R->off[10]);
-  R->result = (double*)(R->base + R->off[11]);
   R->t = 0;
-  R->g0_valid = false;
-  return upload_geometry(R);
+  make_levels(R);
+  for (int l = 0; l < R->L; ++l) {
+    HostLevel& V = R->lev[l];
+    int rc = upload(R, V.off_type, V.type.data(), V.Nbox);
+    if (!rc) rc = upload(R, V.off_tiles, V.tiles.data(), V.tiles.size() * 4);
+    if (!rc) rc = upload(R, V.off_ghosts, V.ghosts.data(), V.ghosts.size() * 4);
+    if (!rc) rc = upload(R, V.off_gcode, V.gcode.data(), V.gcode.size() * 4);
+    if (!rc) rc = upload(R, V.off_groups, V.groups.data(), V.groups.size() * sizeof(GhostGroup));
+    if (!rc) rc = upload(R, V.off_pre_nodes, V.pre_nodes.data(), V.pre_nodes.size() * 4);
+    if (!rc) rc = upload(R, V.off_pre_dirs, V.pre_dirs.data(), V.pre_dirs.size() * 4);
+    if (!rc) rc = upload(R, V.off_pre_q, V.pre_q.data(), V.pre_q.size() * 4);
+    if (rc) {
+      R->base = nullptr;
+      return rc;
+    }
+  }
+  const hipError_t e = hipStreamSynchronize(R->stream);
+  if (e != hipSuccess) {
+    R->base = nullptr;
+    return hip_fail(e);
+  }
+  return LBM_OK;
 }
 
 int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
-                               const void* fine_inlet_u, const uint8_t* fine_inlet_mask) {
+                               const void* const* level_inlet_u,
+                               const uint8_t* const* level_inlet_mask) {
   if (!R || !bc) return LBM_EINVAL;
   if (R->base) return LBM_ESTATE;  // the layout depends on the boundaries
-  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
   BcArgs b;
   std::memset(&b, 0, sizeof(b));
   b.inlet_axis = 2;
@@ -672,60 +902,99 @@ int lbm_refined_set_boundaries(lbm_refined* R, const lbm_boundaries* bc,
   }
   for (int d = 0; d < 3; ++d)
     if (((b.nonper >> (2 * d)) & 1u) != ((b.nonper >> (2 * d + 1)) & 1u)) return LBM_EINVAL;
+  const int n3[3] = {R->cfg.nx, R->cfg.ny, R->cfg.nz};
+  for (int d = 0; d < 3; ++d)
+    if (((b.nonper >> (2 * d)) & 1u) && n3[d] < 4) return LBM_EINVAL;
   if (n_inlet > 1 || n_out > 1) return LBM_EINVAL;
-  BcArgs bf = b;
+  const void* iu[kMaxLevels] = {nullptr};
+  const uint8_t* im[kMaxLevels] = {nullptr};
   if (n_inlet) {
-    if (!bc->inlet_u || !fine_inlet_u || (bc->inlet_dtype != LBM_DTYPE_F64 &&
-                                          bc->inlet_dtype != LBM_DTYPE_F32))
+    if (!bc->inlet_u || (bc->inlet_dtype != LBM_DTYPE_F64 && bc->inlet_dtype != LBM_DTYPE_F32))
       return LBM_EINVAL;
+    if (!std::isfinite(bc->inlet_amp)) return LBM_EINVAL;
     const int d = b.inlet_axis;
-    b.inlet_u = bc->inlet_u;
     b.inlet_f64 = bc->inlet_dtype == LBM_DTYPE_F64;
-    b.inlet_mask = bc->inlet_mask;
     b.inlet_amp = bc->inlet_amp;
     b.seed = bc->seed;
-    b.inlet_na = n3[d == 0 ? 1 : 0];
-    b.inlet_nb = n3[d == 2 ? 1 : 2];
-    bf.inlet_u = fine_inlet_u;
-    bf.inlet_f64 = b.inlet_f64;
-    bf.inlet_mask = fine_inlet_mask;
-    bf.inlet_amp = bc->inlet_amp;
-    bf.seed = bc->seed + 1;  // the fine level draws its own perturbations
-    bf.inlet_na = 2 * b.inlet_na;
-    bf.inlet_nb = 2 * b.inlet_nb;
-    if (bf.inlet_na >= 16384 || bf.inlet_nb >= 16384) return LBM_EINVAL;
+    iu[0] = bc->inlet_u;
+    im[0] = bc->inlet_mask;
+    for (int l = 1; l < R->L; ++l) {
+      if (!level_inlet_u || !level_inlet_u[l]) return LBM_EINVAL;
+      iu[l] = level_inlet_u[l];
+      im[l] = (bc->inlet_mask && level_inlet_mask) ? level_inlet_mask[l] : nullptr;
+      if ((n3[d == 0 ? 1 : 0] << l) >= 16384 || (n3[d == 2 ? 1 : 2] << l) >= 16384)
+        return LBM_EINVAL;
+    }
   }
-  // the geometry depends on which axes are periodic
-  if (!build_geometry(R, b.nonper)) {
-    R->geometry_ok = build_geometry(R, R->Lc.bc.nonper);
+  const BcArgs keep = R->bc;
+  R->bc = b;
+  if (!build_geometry(R)) {
+    R->bc = keep;
+    R->geometry_ok = build_geometry(R);
     return LBM_EINVAL;
   }
   R->geometry_ok = true;
-  for (int d = 0; d < 3; ++d) {
-    R->Lf.lo[d] = R->lo[d];
-    R->Lf.M[d] = R->M[d];
+  for (int l = 0; l < kMaxLevels; ++l) {
+    R->inlet_u[l] = iu[l];
+    R->inlet_mask[l] = im[l];
   }
-  R->Lf.Nbox = (long long)R->Nf;
-  shape_for(R->M[0], R->M[1], R->M[2], R->grid_f, R->block_f, R->nblocks_f);
+  make_levels(R);
   layout(R);
-  fill_wall_terms(b, R->Q);
-  fill_wall_terms(bf, R->Q);
-  R->Lc.bc = b;
-  R->Lf.bc = bf;
-  R->has_bc = b.nonper != 0;
-  R->g0_valid = false;
-  plan_level(R->plan[0], R->Lc, R->block_c, R->elem, R->Q);
-  plan_level(R->plan[1], R->Lf, R->block_f, R->elem, R->Q);
+  return LBM_OK;
+}
+
+int lbm_refined_set_solids(lbm_refined* R, int32_t level, const uint8_t* solid) {
+  if (!R || !level_ok(R, level)) return LBM_EINVAL;
+  if (R->base) return LBM_ESTATE;
+  if (!R->geometry_ok) return LBM_ESTATE;
+  HostLevel& V = R->lev[level];
+  std::vector<uint8_t> keep;
+  keep.swap(V.solid);
+  if (solid) V.solid.assign(solid, solid + V.Nbox);
+  if (!build_geometry(R)) {
+    V.solid.swap(keep);
+    build_geometry(R);
+    return LBM_EINVAL;
+  }
+  V.link_nodes.clear();  // new solids clear the links
+  V.link_q.clear();
+  build_geometry(R);
+  make_levels(R);
+  layout(R);
+  return LBM_OK;
+}
+
+int lbm_refined_set_links(lbm_refined* R, int32_t level, const int32_t* nodes, const float* q,
+                          int64_t n) {
+  if (!R || !level_ok(R, level) || n < 0 || n >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  if (R->base) return LBM_ESTATE;
+  if (!R->geometry_ok) return LBM_ESTATE;
+  HostLevel& V = R->lev[level];
+  if (n > 0 && (!nodes || !q || V.solid.empty())) return LBM_EINVAL;
+  V.link_nodes.assign(nodes, nodes + n);
+  V.link_q.assign(q, q + (size_t)n * R->Q);
+  for (int32_t k : V.link_nodes)
+    if (k < 0 || (size_t)k >= V.Nbox) {
+      V.link_nodes.clear();
+      V.link_q.clear();
+      build_geometry(R);
+      return LBM_EINVAL;
+    }
+  build_geometry(R);
+  layout(R);
   return LBM_OK;
 }
 
 int lbm_refined_init_equilibrium(lbm_refined* R, int level, const void* drho, const void* u,
                                  int dtype, int64_t t0) {
-  if (!R || (level != 0 && level != 1) || !drho || !u || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!R || !level_ok(R, level) || !drho || !u || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if (level == 1 && R->Nf == 0) return LBM_OK;
+  R->t = t0;
+  invalidate_history(R);
+  if (R->lev[level].Nbox == 0) return LBM_OK;
   const LatArgs a = level_view(R, level);
-  const dim3 grid = level == 0 ? R->grid_c : R->grid_f, block = level == 0 ? R->block_c : R->block_f;
+  dim3 grid, block;
+  view_launch(a, grid, block);
   with_kind_s(R, [&](auto kc, auto st_) {
     constexpr int KIND = decltype(kc)::value;
     using S = typename decltype(st_)::type;
@@ -736,17 +1005,18 @@ int lbm_refined_init_equilibrium(lbm_refined* R, int level, const void* drho, co
       hipLaunchKernelGGL((init_equilibrium_kernel<KIND, S, float>), grid, block, 0, R->stream, a,
                          (const float*)drho, (const float*)u);
   });
-  R->t = t0;
-  R->g0_valid = false;
   return check_launch();
 }
 
 int lbm_refined_set_populations(lbm_refined* R, int level, const void* f, int dtype, int64_t t0) {
-  if (!R || (level != 0 && level != 1) || !f || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!R || !level_ok(R, level) || !f || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if (level == 1 && R->Nf == 0) return LBM_OK;
+  R->t = t0;
+  invalidate_history(R);
+  if (R->lev[level].Nbox == 0) return LBM_OK;
   const LatArgs a = level_view(R, level);
-  const dim3 grid = level == 0 ? R->grid_c : R->grid_f, block = level == 0 ? R->block_c : R->block_f;
+  dim3 grid, block;
+  view_launch(a, grid, block);
   with_kind_s(R, [&](auto kc, auto st_) {
     constexpr int Q = Model<decltype(kc)::value>::Q;
     using S = typename decltype(st_)::type;
@@ -757,17 +1027,16 @@ int lbm_refined_set_populations(lbm_refined* R, int level, const void* f, int dt
       hipLaunchKernelGGL((set_populations_kernel<Q, S, float>), grid, block, 0, R->stream, a,
                          (const float*)f);
   });
-  R->t = t0;
-  R->g0_valid = false;
   return check_launch();
 }
 
 int lbm_refined_get_populations(lbm_refined* R, int level, void* f, int dtype) {
-  if (!R || (level != 0 && level != 1) || !f || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!R || !level_ok(R, level) || !f || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if (level == 1 && R->Nf == 0) return LBM_OK;
+  if (R->lev[level].Nbox == 0) return LBM_OK;
   const LatArgs a = level_view(R, level);
-  const dim3 grid = level == 0 ? R->grid_c : R->grid_f, block = level == 0 ? R->block_c : R->block_f;
+  dim3 grid, block;
+  view_launch(a, grid, block);
   with_kind_s(R, [&](auto kc, auto st_) {
     constexpr int Q = Model<decltype(kc)::value>::Q;
     using S = typename decltype(st_)::type;
@@ -783,12 +1052,13 @@ int lbm_refined_get_populations(lbm_refined* R, int level, void* f, int dtype) {
 
 int lbm_refined_get_macroscopic(lbm_refined* R, int level, void* rho, void* u, int dtype,
                                 int rho_mode) {
-  if (!R || (level != 0 && level != 1) || !valid_dtype(dtype)) return LBM_EINVAL;
+  if (!R || !level_ok(R, level) || !valid_dtype(dtype)) return LBM_EINVAL;
   if (rho_mode != LBM_RHO_FULL && rho_mode != LBM_RHO_DEVIATION) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if ((!rho && !u) || (level == 1 && R->Nf == 0)) return LBM_OK;
+  if ((!rho && !u) || R->lev[level].Nbox == 0) return LBM_OK;
   const LatArgs a = level_view(R, level);
-  const dim3 grid = level == 0 ? R->grid_c : R->grid_f, block = level == 0 ? R->block_c : R->block_f;
+  dim3 grid, block;
+  view_launch(a, grid, block);
   with_kind_s(R, [&](auto kc, auto st_) {
     constexpr int KIND = decltype(kc)::value;
     using S = typename decltype(st_)::type;
@@ -805,25 +1075,9 @@ int lbm_refined_get_macroscopic(lbm_refined* R, int level, void* rho, void* u, i
 int lbm_refined_step(lbm_refined* R, int64_t n) {
   if (!R || n < 0) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if (!R->side_tried) {
-    // without the side stream the coarse step simply runs in order
-    R->side_tried = true;
-    if (hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&R->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&R->join_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&R->sub1_ev, hipEventDisableTiming) != hipSuccess) {
-      if (R->side) (void)hipStreamDestroy(R->side);
-      if (R->fork_ev) (void)hipEventDestroy(R->fork_ev);
-      if (R->join_ev) (void)hipEventDestroy(R->join_ev);
-    if (R->sub1_ev) (void)hipEventDestroy(R->sub1_ev);
-      R->side = nullptr;
-      R->fork_ev = R->join_ev = R->sub1_ev = nullptr;
-      (void)hipGetLastError();
-    }
-  }
   for (int64_t k = 0; k < n; ++k) {
     with_kind_s(R, [&](auto kc, auto st_) {
-      one_coarse_step<decltype(kc)::value, typename decltype(st_)::type>(R, (long long)R->t);
+      advance<decltype(kc)::value, typename decltype(st_)::type>(R, 0, (long long)R->t, false);
     });
     R->t += 1;
   }
@@ -834,26 +1088,27 @@ int lbm_refined_reduce(lbm_refined* R, double out[5]) {
   if (!R || !out) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int level = 0; level < 2; ++level) {
-    const Level& L = level == 0 ? R->Lc : R->Lf;
-    if (L.Nbox == 0) continue;
-    const dim3 grid = level == 0 ? R->grid_c : R->grid_f, block = level == 0 ? R->block_c : R->block_f;
-    const size_t nb = level == 0 ? R->nblocks_c : R->nblocks_f;
+  double* partial = (double*)(R->base + R->off_partial);
+  double* result = (double*)(R->base + R->off_result);
+  for (int l = 0; l < R->L; ++l) {
+    const HostLevel& V = R->lev[l];
+    if (V.Nbox == 0) continue;
+    const unsigned nb = blocks_for((long long)V.Nbox);
     with_kind_s(R, [&](auto kc, auto st_) {
       constexpr int KIND = decltype(kc)::value;
       using S = typename decltype(st_)::type;
-      hipLaunchKernelGGL((masked_reduce_kernel<KIND, S>), grid, block, 0, R->stream, L,
-                         level == 0 ? 0 : 1, level == 0 ? 1.0 : 0.125, R->partial);
+      hipLaunchKernelGGL((level_reduce_kernel<KIND, S>), dim3(nb), dim3(256), 0, R->stream, V.dev,
+                         (int)RT_FLUID, std::ldexp(1.0, -3 * l), partial);
     });
     int rc = check_launch();
     if (rc) return rc;
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, R->stream, R->partial, nb,
-                       R->result);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, R->stream, partial,
+                       (size_t)nb, result);
     rc = check_launch();
     if (rc) return rc;
     double part[5];
-    hipError_t e =
-        hipMemcpyAsync(part, R->result, 5 * sizeof(double), hipMemcpyDeviceToHost, R->stream);
+    hipError_t e = hipMemcpyAsync(part, result, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                                  R->stream);
     if (e != hipSuccess) return hip_fail(e);
     e = hipStreamSynchronize(R->stream);
     if (e != hipSuccess) return hip_fail(e);
@@ -878,14 +1133,6 @@ int lbm_refined_set_stream(lbm_refined* R, void* stream) {
 }
 
 int lbm_refined_destroy(lbm_refined* R) {
-  if (R) {
-    if (R->side) {
-      (void)hipStreamSynchronize(R->side);
-      (void)hipStreamDestroy(R->side);
-    }
-    if (R->fork_ev) (void)hipEventDestroy(R->fork_ev);
-    if (R->join_ev) (void)hipEventDestroy(R->join_ev);
-  }
   delete R;
   return LBM_OK;
 }

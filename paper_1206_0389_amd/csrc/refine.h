@@ -1,143 +1,231 @@
-// gfx950 kernels of the two-level nested time refinement (hierarchical block
-// grid with nested time steps, Section 1 and the numerical set-up of
-// Section 3; interface treatment after Yu et al., cited there).
+// gfx950 kernels of the nested time refinement on a hierarchical block grid
+// (block grid with nested time steps, Section 1, and the refinement levels
+// of the numerical set-up, Section 3; interface interpolation and rescaling
+// after Yu et al., cited there without formulas).
 //
-// Geometry: 2:1 vertex-centred nesting. Fine node j (global fine index) sits
-// at coarse coordinate j/2; a refined coarse block of B^3 nodes carries
-// (2B)^3 fine nodes. Each level is stored densely over a box: the coarse box
-// is the whole domain, the fine box the refined blocks' bounding box plus
-// one ghost layer on every side that is not a domain face. A per-node type
-// byte marks what a kernel updates: coarse 0 = outside the refined region,
-// 1 = refined but read by a ghost stencil ("band"), 2 = covered (overwritten
-// from the fine level); fine 0 = unused, 1 = fluid, 2 = ghost.
+// Geometry: level l has spacing and time step 2^-l of level 0 and cell-
+// centred 2:1 nesting, level-(l+1) node j sitting at level-l coordinate
+// j/2 - 1/4 (a parent node's cell holds the children 2i, 2i+1 per axis), so
+// halfway walls and faces coincide on every level. Each level is stored
+// densely over a box (its refined region plus a ghost layer); the box's x
+// origin is a multiple of 32 nodes and its row pitch M[0] a multiple of 32,
+// so 32-node row segments are aligned. A type byte per box node says what a
+// kernel does with it:
+//   0 unused, 1 fluid, 2 band (inside the next level's region, read by that
+//   level's ghost interpolation, so updated on this level), 3 covered
+//   (inside the next level's region, receives the mean of its children),
+//   4 ghost (filled from the parent level), 5 solid (never updated).
 //
-// Both levels hold post-collision populations and advance by a two-array
-// pull-and-collide (f_i(x,t+1) = f*_i(x - e_i, t), then collide): the fine
-// level reads interpolated ghosts between the two arrays, so the in-place
-// AA parity bookkeeping of the uniform kernels is not used here; the bytes
-// moved per node update are the same.
+// Every level holds post-collision populations in two arrays and advances
+// by pull and collide (f_i(x, t+1) = f*_i(x - e_i, t), then the collision).
+// A level step runs over a list of tiles of 32 x 4 x 2 nodes that contain
+// fluid or band nodes; tiles whose nodes have all their neighbours inside
+// the box without wrapping and lie on no domain face take the plain kernel,
+// the others the general one (periodic wrap, the face rules of the uniform
+// lattice).
 //
-// Per coarse step t (dt_c = 2 dt_f, nu_f = 2 nu_c in lattice units):
-//   G0 = coarse values interpolated at the ghosts (tensor 4-point cubic
-//        Lagrange, one-sided near non-periodic faces), fill ghosts with
-//        rescale(G0): f = f_eq + r (g - f_eq), r = (tau_f - 1)/(2(tau_c - 1))
-//   coarse pull-collide (skips covered nodes)
-//   fine pull-collide at fine time 2t
-//   G1 = interpolation of the new coarse state; ghosts = rescale((G0+G1)/2)
-//   fine pull-collide at fine time 2t+1
-//   covered coarse nodes = f_eq + (f_fine - f_eq)/r of the coincident node.
+// Interface per parent step t (dt_parent = 2 dt_child):
+//   G(t+1) = parent state at t+1 interpolated at the child's ghosts (tensor
+//            4-point cubic Lagrange at the child positions, windows kept
+//            inside non-periodic domains);
+//   child substep 1 reads ghosts rescale(G(t)), substep 2 reads
+//   rescale(-1/8 G(t-1) + 3/4 G(t) + 3/8 G(t+1)) (linear, 1/2 G(t) + 1/2
+//   G(t+1), on the first step after a state change);
+//   rescale: the non-equilibrium part scaled per Chapman-Enskog (FCLB one
+//   ratio r = (tau_f - 1)/(2 (tau_c - 1)); MRT per moment group, the shear
+//   group with the total relaxation times of Eq. (20));
+//   covered parent nodes whose eight children are fluid or band take the
+//   rescaled mean of the children, written by the child's second substep.
+// Solid nodes: before each step a pre-pass writes into each solid node's
+// slot i the value its fluid neighbour x = s + e_i pulls from it (halfway
+// bounce-back, or Bouzidi's interpolation along a curved link), so the step
+// itself reads solid sources like any other neighbour.
 #pragma once
 
 #include "kernels.h"
 
 namespace lbm {
 
-struct Level {
-  void* a;              // [Q][Nbox] state read by a step
-  void* b;              // [Q][Nbox] state written by a step
+enum : uint8_t { RT_UNUSED = 0, RT_FLUID = 1, RT_BAND = 2, RT_COVERED = 3, RT_GHOST = 4,
+                 RT_SOLID = 5 };
+
+struct Lev {
+  void* a;              // [Q][Nbox] state read by the next step
+  void* b;              // [Q][Nbox] state written by it
   const uint8_t* type;  // [Nbox]
-  int lo[3];            // box origin in this level's global coordinates
-  int M[3];             // box extent
-  int n[3];             // domain extent of this level
+  int o[3];             // box origin (level coordinates); o[0] % 32 == 0
+  int M[3];             // box extent; M[0] (the row pitch) % 32 == 0
+  int n[3];             // domain extent of the level
+  uint32_t span;        // bit d: the box spans periodic axis d (wraps at n[d])
   long long Nbox;
   MrtParams mrt;
   double omega;
   BcArgs bc;
-  // Injection into the covered coarse nodes, done by the last fine substep
-  // of a coarse step (cinj null otherwise): the fine node coincident with a
-  // covered coarse node (all global fine coordinates even, coarse type 2)
-  // writes f_eq + rinv (f - f_eq) of its post-collision state into cinj.
-  void* cinj;
-  const uint8_t* ctype;
-  int cn[3];
-  long long Nc;
-  double rinv;
 };
 
-// 1-D interpolation stencil for fine coordinate j on an axis of n >= 4
-// coarse nodes. Code 0: one node, j/2 (j even, weight 1). Codes 1-4: the
-// four nodes s..s+3, s = (j-1)/2 - 1 (moved inside [0, n) on a non-periodic
-// axis), with the cubic Lagrange weights at t = j/2 - s = 1/2, 3/2, 5/2,
-// 7/2 (3/2 inside, the others next to a face). start is the first node
-// before wrapping on a periodic axis.
-__host__ __device__ inline int stencil_code(int j, int n, bool periodic, int& start) {
-  if ((j & 1) == 0) {
-    start = j / 2;
-    return 0;
+// Parent side of the fused injection: covered parent nodes receive the
+// rescaled mean of their eight children from the child's second substep.
+struct InjArgs {
+  void* dst;            // parent array being written this parent step
+  const uint8_t* type;  // parent types
+  int o[3], M[3];
+  long long Nbox;
+  // rescale back to the parent: tau0 of both levels and C_S (MRT), or the
+  // inverse of the FCLB ratio
+  double tau0_c, tau0_f, cs, rinv;
+  double rates[5];
+};
+
+// One interface ratio set (parent c -> child f).
+struct RescaleArgs {
+  double tau0_c, tau0_f, cs;  // molecular relaxation times, Smagorinsky C_S
+  double r;                   // FCLB ratio (tau0_f - 1)/(2 (tau0_c - 1))
+  double rates[5];            // MRT non-shear rates (both levels)
+};
+
+// ---------------------------------------------------------------- rescale
+// Total relaxation time of an MRT-LES post-collision state from the
+// traceless part T of its non-equilibrium stress: Qp = sqrt(2 T:T) = Q |1 -
+// 1/tau| with Q the pre-collision strain measure of Eq. (21); with Eq. (20)
+// the root tending to tau0 as Qp -> 0 is tau = (1 + tau0 -+ sqrt((1 -
+// tau0)^2 -+ 18 C_S^2 Qp)) / 2 (upper signs for tau0 < 1, radicand clamped
+// at 0).
+template <typename R>
+__device__ __forceinline__ R tau_from_post(const R (&d)[19], R tau0, R cs) {
+  R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    if (cx(i)) pxx += d[i];
+    if (cy(i)) pyy += d[i];
+    if (cz(i)) pzz += d[i];
+    if (cx(i) * cy(i)) pxy += cx(i) * cy(i) > 0 ? d[i] : -d[i];
+    if (cx(i) * cz(i)) pxz += cx(i) * cz(i) > 0 ? d[i] : -d[i];
+    if (cy(i) * cz(i)) pyz += cy(i) * cz(i) > 0 ? d[i] : -d[i];
   }
-  int s = (j - 1) / 2 - 1;
-  if (!periodic) s = s < 0 ? 0 : (s > n - 4 ? n - 4 : s);
-  start = s;
-  return (j - 2 * s + 1) / 2;  // 2t = 1, 3, 5, 7
+  const R tr = (pxx + pyy + pzz) / R(3);
+  const R a = pxx - tr, b = pyy - tr, c = pzz - tr;
+  const R t2 = a * a + b * b + c * c + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+  const R k = R(18) * cs * cs * sqrt(R(2) * t2);
+  if (tau0 < R(1)) {
+    R rad = (R(1) - tau0) * (R(1) - tau0) - k;
+    rad = rad < R(0) ? R(0) : rad;
+    return R(0.5) * (R(1) + tau0 - sqrt(rad));
+  }
+  return R(0.5) * (R(1) + tau0 + sqrt((tau0 - R(1)) * (tau0 - R(1)) + k));
 }
 
-// Weights of a stencil code (dyadic, exact in every precision used).
-__host__ __device__ inline void stencil_weights(int code, double w[4]) {
-  switch (code) {
-    case 0: w[0] = 1.0; w[1] = 0.0; w[2] = 0.0; w[3] = 0.0; break;
-    case 1: w[0] = 5.0 / 16; w[1] = 15.0 / 16; w[2] = -5.0 / 16; w[3] = 1.0 / 16; break;
-    case 2: w[0] = -1.0 / 16; w[1] = 9.0 / 16; w[2] = 9.0 / 16; w[3] = -1.0 / 16; break;
-    case 3: w[0] = 1.0 / 16; w[1] = -5.0 / 16; w[2] = 15.0 / 16; w[3] = 5.0 / 16; break;
-    default: w[0] = -5.0 / 16; w[1] = 21.0 / 16; w[2] = -35.0 / 16; w[3] = 35.0 / 16; break;
+// f := f_eq + rescaled (f - f_eq) in place, for one node. DIR > 0: a parent
+// state to the child level; DIR < 0: back.
+template <int KIND, int DIR, typename R>
+__device__ __forceinline__ void rescale_node(R (&f)[Model<KIND>::Q], double tau0_c,
+                                             double tau0_f, double cs, double r,
+                                             const double (&rates)[5]) {
+  constexpr int Q = Model<KIND>::Q;
+  R d = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    j[0] += R(cx(i)) * f[i];
+    j[1] += R(cy(i)) * f[i];
+    j[2] += R(cz(i)) * f[i];
+  }
+  R neq[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R feq = equilibrium_one<KIND, R>(d, j, cx(i), cy(i), cz(i));
+    neq[i] = f[i] - feq;
+    f[i] = feq;
+  }
+  if constexpr (Q == 27) {
+    const R s = DIR > 0 ? R(r) : R(1.0 / r);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] += s * neq[i];
+  } else {
+    constexpr int BASIS = KIND;
+    using T = MrtTables<BASIS>;
+    R tc, tf;
+    if constexpr (DIR > 0) {
+      tc = tau_from_post<R>(neq, R(tau0_c), R(cs));
+      tf = R(tau0_f) + R(0.5) * (tc - R(tau0_c));
+    } else {
+      tf = tau_from_post<R>(neq, R(tau0_f), R(cs));
+      tc = R(tau0_c) + R(2) * (tf - R(tau0_f));
+    }
+    const R rs = DIR > 0 ? (tf - R(1)) / (R(2) * (tc - R(1))) : (R(2) * (tc - R(1))) / (tf - R(1));
+    R m[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      m[k] = 0;
+      const int g = row_group(BASIS, k);
+      if (g == 0) continue;
+      R acc = 0;
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        if (is_nonzero(T::M.a[k][i])) acc += R(T::M.a[k][i]) * neq[i];
+      // shear: the ratio of the total times; other groups keep their rate on
+      // both levels: 1/2 (2 back), none left where the rate is 1
+      const R sk = g == 1 ? rs
+                          : (rates[g - 2] == 1.0 ? R(0) : (DIR > 0 ? R(0.5) : R(2)));
+      m[k] = sk * acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      R c = 0;
+#pragma unroll
+      for (int k = 0; k < 19; ++k)
+        if (row_group(BASIS, k) != 0 && is_nonzero(T::Minv.a[i][k]))
+          c += R(T::Minv.a[i][k]) * m[k];
+      f[i] += c;
+    }
   }
 }
 
-// Nodes (wrapped) and weights of the stencil; returns the node count.
-__host__ __device__ inline int interp_stencil(int j, int n, bool periodic, int idx[4],
-                                              double w[4]) {
-  int s;
-  const int code = stencil_code(j, n, periodic, s);
-  stencil_weights(code, w);
-  const int cnt = code == 0 ? 1 : 4;
-  for (int a = 0; a < cnt; ++a) idx[a] = periodic ? (((s + a) % n) + n) % n : s + a;
-  return cnt;
-}
-
+// ------------------------------------------------------------- addressing
 struct BoxNode {
-  int g[3];                 // global coordinates
+  int g[3];                 // level coordinates
   int self;                 // box index
-  int xo[3], yo[3], zo[3];  // box-local linear offsets of coordinates c-1, c, c+1
+  int xo[3], yo[3], zo[3];  // box offsets of coordinates c-1, c, c+1 (wrapped)
   uint32_t atface;          // non-periodic domain faces the node lies on
   __device__ __forceinline__ int at(int dx, int dy, int dz) const {
     return zo[dz + 1] + yo[dy + 1] + xo[dx + 1];
   }
 };
 
-// Neighbour coordinate in the box: wrapped on a periodic axis the box spans,
-// otherwise kept inside the box (valid configurations never need the clamp:
-// fluid nodes only read fluid or ghost neighbours or cross a domain face).
-__device__ __forceinline__ int box_nbr(int c, int d, int M, bool wrap) {
-  const int v = c + d;
-  if (wrap) return v < 0 ? M - 1 : (v >= M ? 0 : v);
-  return v < 0 ? 0 : (v >= M ? M - 1 : v);
+// Box coordinate of level coordinate g + d on axis ax: wrapped at the
+// domain extent on a spanned periodic axis; otherwise (valid geometries
+// never leave the box there) kept inside the box.
+__device__ __forceinline__ int box_coord(const Lev& L, int ax, int g, int d) {
+  int v = g + d;
+  if ((L.span >> ax) & 1u) v = v < 0 ? v + L.n[ax] : (v >= L.n[ax] ? v - L.n[ax] : v);
+  v -= L.o[ax];
+  return v < 0 ? 0 : (v >= L.M[ax] ? L.M[ax] - 1 : v);
 }
 
-__device__ __forceinline__ BoxNode make_box_node(const Level& L, int lx, int ly, int lz) {
+__device__ __forceinline__ BoxNode make_box_node(const Lev& L, const int (&g)[3]) {
   BoxNode n;
-  const int l3[3] = {lx, ly, lz};
   const int stride[3] = {1, L.M[0], L.M[0] * L.M[1]};
   int* off[3] = {n.xo, n.yo, n.zo};
   uint32_t m = 0;
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const bool wrap = ((L.bc.nonper >> (2 * d)) & 1u) == 0;
-    for (int k = -1; k <= 1; ++k) off[d][k + 1] = box_nbr(l3[d], k, L.M[d], wrap) * stride[d];
-    n.g[d] = l3[d] + L.lo[d];
-    if (n.g[d] == 0) m |= 1u << (2 * d);
-    if (n.g[d] == L.n[d] - 1) m |= 1u << (2 * d + 1);
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) off[d][k + 1] = box_coord(L, d, g[d], k) * stride[d];
+    n.g[d] = g[d];
+    if (g[d] == 0) m |= 1u << (2 * d);
+    if (g[d] == L.n[d] - 1) m |= 1u << (2 * d + 1);
   }
   n.atface = m & L.bc.nonper;
   n.self = n.zo[1] + n.yo[1] + n.xo[1];
   return n;
 }
 
-// Pull of population I in two-array post-collision storage: the source
-// node's own slot I; across a WALL/INLET face the node's slot opp(I) (plus
-// the bounce-back term, pull_term); across a PRESSURE face the same slot
-// (completed by ab_pressure); across FREESLIP faces slot k (I mirrored
-// across them) of the source with the crossed coordinates kept; across an
-// OUTFLOW face slot I of that source.
+// General pull source of population I: the source node's slot I; across a
+// WALL/INLET face the node's own slot opp(I) (plus the bounce-back term);
+// across a PRESSURE face the same slot (completed by gen_pressure); across
+// FREESLIP faces slot k (I mirrored) of the source with the crossed
+// coordinates kept; across an OUTFLOW face slot I of that source.
 template <int Q, int I, typename S>
-__device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, const BoxNode& n) {
+__device__ __forceinline__ const S* gen_pull_addr(const Lev& L, const S* A, const BoxNode& n) {
   constexpr int IO = opposite<Q>(I);
   const size_t N = (size_t)L.Nbox;
   const uint32_t crossed = n.atface & pull_faces(I);
@@ -154,13 +242,13 @@ __device__ __forceinline__ const S* ab_pull_addr(const Level& L, const S* A, con
 }
 
 // Completes the pull at a node on PRESSURE faces: f_I = -f*_opp(I) +
-// feq_I + feq_opp(I) (anti-bounce-back at the face density) for the
-// directions entering through one and through no WALL or INLET face, with
-// the node's velocity of its post-collision state, slot K holding f*_K.
-template <int Q, typename real, typename S>
-__device__ __forceinline__ void ab_pressure(const Level& L, const S* A, const BoxNode& n,
-                                            real (&f)[Q]) {
-  constexpr int KQ = Q == 27 ? 2 : 0;
+// feq_I + feq_opp(I) at the face density and the node's velocity of its
+// post-collision state (slot K holds f*_K), for the directions entering
+// through a PRESSURE and no WALL or INLET face.
+template <int KIND, typename real, typename S>
+__device__ __forceinline__ void gen_pressure(const Lev& L, const S* A, const BoxNode& n,
+                                             real (&f)[Model<KIND>::Q]) {
+  constexpr int Q = Model<KIND>::Q;
   const size_t N = (size_t)L.Nbox;
   real d = 0, j[3] = {0, 0, 0};
   static_for<0, Q>([&](auto kc) {
@@ -177,154 +265,191 @@ __device__ __forceinline__ void ab_pressure(const Level& L, const S* A, const Bo
     constexpr int I = decltype(ic)::value;
     const uint32_t crossed = n.atface & pull_faces(I);
     if ((crossed & L.bc.pressure) && !(crossed & (L.bc.wall | L.bc.inlet)))
-      f[I] = -f[I] + pressure_pair<KQ, I, real>(
+      f[I] = -f[I] + pressure_pair<Q == 27 ? 2 : 0, I, real>(
                          real(pressure_drho(L.bc, crossed & L.bc.pressure)), u);
   });
 }
 
-// Wall-row pull (rows off every non-periodic z face and off y faces that are
-// not walls; x and y faces WALL or periodic): population I entering through
-// an x or y wall is the node's own opposite slot plus a per-direction wall
-// term (the x face first where a node lies on both). Both sources are
-// offsets from the lower of the two slabs (one scalar-base load).
-template <int Q, int I, typename real, bool NT, typename S>
-__device__ __forceinline__ real ab_pull_walls(const Level& L, const S* A, const BoxNode& n) {
-  constexpr int IO = opposite<Q>(I);
-  constexpr uint32_t XB = pull_faces(I) & 3u, YB = pull_faces(I) & 12u;
-  const uint32_t sz = sizeof(S);
-  const uint32_t nb = (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * sz;
-  if constexpr ((XB | YB) == 0) {
-    return ldo<real, NT>(A + (size_t)I * L.Nbox, nb);
-  } else {
-    constexpr int LO = I < IO ? I : IO;
-    const uint32_t slab = (uint32_t)L.Nbox * sz;
-    const bool bx = (n.atface & XB) != 0, by = (n.atface & YB) != 0;
-    const bool bb = bx || by;
-    const uint32_t off = bb ? (IO - LO) * slab + (uint32_t)n.self * sz : (I - LO) * slab + nb;
-    const real v = ldo<real, NT>(A + (size_t)LO * L.Nbox, off);
-    const real term =
-        wall_row_term<I, real, XB, YB>(L.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
-    return bb ? v + term : v;
-  }
+// Lane -> node of a 32 x 4 x 2 tile: x fastest (a half wave is one aligned
+// 32-node row segment), then y, then z; tiles are aligned to even
+// coordinates, so the eight children of a parent node lie in one tile.
+__device__ __forceinline__ void tile_node(const int* tiles, int (&g)[3]) {
+  const int* t = tiles + 3 * (size_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  g[0] = t[0] + (lane & 31);
+  g[1] = t[1] + ((lane >> 5) & 3);
+  g[2] = t[2] + (lane >> 7);
 }
 
-// Equilibrium of the model (deviation form) for the moments of f.
-template <int KIND, typename R>
-__device__ __forceinline__ void equilibrium_dev(const R (&f)[Model<KIND>::Q],
-                                                R (&feq)[Model<KIND>::Q]) {
-  constexpr int Q = Model<KIND>::Q;
-  R d = 0, j[3] = {0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    d += f[i];
-    j[0] += R(cx(i)) * f[i];
-    j[1] += R(cy(i)) * f[i];
-    j[2] += R(cz(i)) * f[i];
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) feq[i] = equilibrium_one<KIND, R>(d, j, cx(i), cy(i), cz(i));
+__device__ __forceinline__ bool in_box(const Lev& L, const int (&g)[3], int& self) {
+  const int b0 = g[0] - L.o[0], b1 = g[1] - L.o[1], b2 = g[2] - L.o[2];
+  if (b0 < 0 || b1 < 0 || b2 < 0 || b0 >= L.M[0] || b1 >= L.M[1] || b2 >= L.M[2]) return false;
+  self = (b2 * L.M[1] + b1) * L.M[0] + b0;
+  return true;
 }
 
-// One pull-and-collide update of a level at time t over the rows r (box-
-// local coordinates). mode 0 updates every node whose type is not 2
-// (coarse), mode 1 only type-1 nodes (fine). BCM: BC_NONE (no non-periodic
-// face), BC_WALLS (wall rows, see ab_pull_walls) or BC_GENERAL.
-template <int KIND, typename S, int BCM, int ROWS>
-__global__ __launch_bounds__(256) void ab_step_kernel(const Level L, const Rows r, int mode,
-                                                      long long t) {
+// ------------------------------------------------------------- level step
+// One pull-and-collide step of level L at its step index t over a tile
+// list. GEN: periodic wrap and the domain-face rules (else plain offsets:
+// every source of a tile's active nodes lies in the box without wrapping).
+// INJ: also the fused injection into the parent's covered nodes (the
+// child's second substep of a parent step).
+template <int KIND, typename S, bool GEN, bool INJ>
+__global__ __launch_bounds__(256) void level_step_kernel(const Lev L, const int* tiles,
+                                                         long long t, const InjArgs inj) {
   using M = Model<KIND>;
   using real = typename Compute<S>::type;
   constexpr int Q = M::Q;
-  int lx, ly, lz;
-  {
-    LatArgs dims;
-    dims.nx = L.M[0];
-    dims.ny = L.M[1];
-    dims.nz = L.M[2];
-    if (!row_coords<ROWS>(dims, r, lx, ly, lz)) return;
+  int g[3], self = 0;
+  tile_node(tiles, g);
+  bool active = in_box(L, g, self);
+  if (active) {
+    const uint8_t ty = L.type[self];
+    active = ty == RT_FLUID || ty == RT_BAND;
   }
-  const int self = (lz * L.M[1] + ly) * L.M[0] + lx;
-  const uint8_t ty = L.type[self];
-  if (mode == 0 ? ty == 2 : ty != 1) return;
-  const BoxNode n = make_box_node(L, lx, ly, lz);
+  if (!INJ && !active) return;
   const S* A = (const S*)L.a;
   S* B = (S*)L.b;
+  const size_t N = (size_t)L.Nbox;
   real f[Q];
-  if constexpr (BCM == BC_GENERAL) {
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      f[I] = ld<real>(ab_pull_addr<Q, I, S>(L, A, n));
-    });
-    if (n.atface) {
-      double uin[3] = {0, 0, 0};
-      if (n.atface & L.bc.inlet) inlet_velocity(L.bc, n.g[0], n.g[1], n.g[2], t, uin);
-      const real up[3] = {real(uin[0]), real(uin[1]), real(uin[2])};
+  if (active) {
+    if constexpr (GEN) {
+      const BoxNode n = make_box_node(L, g);
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
-        f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
+        f[I] = ld<real>(gen_pull_addr<Q, I, S>(L, A, n));
       });
-      if (n.atface & L.bc.pressure) ab_pressure<Q, real, S>(L, A, n, f);
+      if (n.atface) {
+        double uin[3] = {0, 0, 0};
+        if (n.atface & L.bc.inlet) inlet_velocity(L.bc, g[0], g[1], g[2], t, uin);
+        const real up[3] = {real(uin[0]), real(uin[1]), real(uin[2])};
+        static_for<0, Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          f[I] += pull_term<Q, I, real>(L.bc, n.atface, up);
+        });
+        if (n.atface & L.bc.pressure) gen_pressure<KIND, real, S>(L, A, n, f);
+      }
+    } else {
+      const int sy = L.M[0], sz = L.M[0] * L.M[1];
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const int src = self - cx(I) - cy(I) * sy - cz(I) * sz;
+        f[I] = ldo<real, cx(I) == 0>(A + (size_t)I * N, (uint32_t)src * (uint32_t)sizeof(S));
+      });
     }
-  } else if constexpr (BCM == BC_WALLS) {
+    M::collide(f, L);
+    const uint32_t so = (uint32_t)self * (uint32_t)sizeof(S);
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f[I] = ab_pull_walls<Q, I, real, cx(I) == 0>(L, A, n);
-    });
-  } else {
-    const size_t N = (size_t)L.Nbox;
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      f[I] = ldo<real, cx(I) == 0>(A + (size_t)I * N,
-                                   (uint32_t)n.at(-cx(I), -cy(I), -cz(I)) * (uint32_t)sizeof(S));
+      sto<true>(B + (size_t)I * N, so, f[I]);
     });
   }
-  M::collide(f, L);
-  const size_t N = (size_t)L.Nbox;
-  if constexpr (BCM == BC_GENERAL) {
+  if constexpr (INJ) {
+    // children sums: x pairs (lanes 2i, 2i+1), y pairs (lanes +32) by
+    // cross-lane exchange, z pairs (waves w, w+2) through LDS; the stored
+    // (rounded) values are averaged, as a separate pass would read them
+    __shared__ real red[4][Q][16];
+    __shared__ int okz[4][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int ok = active ? 1 : 0;
+    ok &= __shfl_xor(ok, 1);
+    ok &= __shfl_xor(ok, 32);
+    const bool head = (lane & 33) == 0;  // even x, first y row of the wave
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      st(B + (size_t)I * N + self, f[I]);
+      real v = active ? real(S(f[I])) : real(0);
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 32);
+      if (head) red[w][I][(lane & 31) >> 1] = v;
     });
-  } else {
-    const uint32_t self_off = (uint32_t)self * (uint32_t)sizeof(S);
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      sto<true>(B + (size_t)I * N, self_off, f[I]);
-    });
-  }
-  if (L.cinj != nullptr && ((n.g[0] | n.g[1] | n.g[2]) & 1) == 0) {
-    const size_t ci = ((size_t)(n.g[2] >> 1) * L.cn[1] + (n.g[1] >> 1)) * L.cn[0] + (n.g[0] >> 1);
-    if (L.ctype[ci] == 2) {
-      real g[Q], feq[Q];
+    if (head) okz[w][(lane & 31) >> 1] = ok;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      const int k = threadIdx.x & 15, py = threadIdx.x >> 4;
+      const int* tl = tiles + 3 * (size_t)blockIdx.x;
+      const int pg[3] = {(tl[0] >> 1) + k, (tl[1] >> 1) + py, tl[2] >> 1};
+      const int b0 = pg[0] - inj.o[0], b1 = pg[1] - inj.o[1], b2 = pg[2] - inj.o[2];
+      if (okz[py][k] && okz[py + 2][k] && b0 >= 0 && b1 >= 0 && b2 >= 0 && b0 < inj.M[0] &&
+          b1 < inj.M[1] && b2 < inj.M[2]) {
+        const size_t pi = ((size_t)b2 * inj.M[1] + b1) * inj.M[0] + b0;
+        if (inj.type[pi] == RT_COVERED) {
+          real m[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = real(S(f[q]));  // the stored value
-      equilibrium_dev<KIND, real>(g, feq);
-      S* C = (S*)L.cinj;
+          for (int q = 0; q < Q; ++q) m[q] = real(0.125) * (red[py][q][k] + red[py + 2][q][k]);
+          rescale_node<KIND, -1, real>(m, inj.tau0_c, inj.tau0_f, inj.cs, 1.0 / inj.rinv,
+                                       inj.rates);
+          S* P = (S*)inj.dst;
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-        st(C + (size_t)q * (size_t)L.Nc + ci, feq[q] + real(L.rinv) * (g[q] - feq[q]));
+          for (int q = 0; q < Q; ++q) st(P + (size_t)q * (size_t)inj.Nbox + pi, m[q]);
+        }
+      }
     }
   }
 }
 
+// --------------------------------------------------------- solid pre-pass
+// Before a step: for every listed fluid node x and direction i whose source
+// s = x - e_i is solid, write into slot i of s the value x pulls from it,
+// from the post-collision state in A (k = opp(i), the link towards the
+// wall at the fraction q of it; q = 1/2 or a link without a fluid node
+// behind x is the halfway rule):
+//   halfway:   f*_k(x)
+//   q <  1/2:  2q f*_k(x) + (1 - 2q) f*_k(x + e_i)
+//   q >= 1/2:  f*_k(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+// Slot i of s has this one writer, and nothing the pass reads is written.
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void solid_prepass_kernel(const Lev L, const int* nodes,
+                                                            const uint32_t* dirs, const float* q,
+                                                            long long n) {
+  using real = typename Compute<S>::type;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int self = nodes[e];
+  const uint32_t m = dirs[e];
+  const int M0 = L.M[0], M1 = L.M[1];
+  const int b[3] = {self % M0, (self / M0) % M1, self / (M0 * M1)};
+  const int g[3] = {b[0] + L.o[0], b[1] + L.o[1], b[2] + L.o[2]};
+  const BoxNode nd = make_box_node(L, g);
+  S* A = (S*)L.a;
+  const size_t N = (size_t)L.Nbox;
+  static_for<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int K = opposite<Q>(I);
+    if ((m >> I) & 1u) {
+      const real fk = ld<real>(A + (size_t)K * N + self);
+      const real qq = real(q[(size_t)e * Q + K]);
+      real v = fk;
+      if (qq < real(0.5)) {
+        v = real(2) * qq * fk + (real(1) - real(2) * qq) * ld<real>(A + (size_t)K * N + nd.at(cx(I), cy(I), cz(I)));
+      } else if (qq > real(0.5)) {
+        v = fk / (real(2) * qq) + (real(2) * qq - real(1)) / (real(2) * qq) *
+                                      ld<real>(A + (size_t)I * N + self);
+      }
+      st(A + (size_t)I * N + nd.at(-cx(I), -cy(I), -cz(I)), v);
+    }
+  });
+}
+
+// ------------------------------------------------------------- interface
 struct GhostArgs {
-  const int* ghosts;  // fine box indices of the ghost nodes
+  const int* ghosts;  // child box indices of the ghost nodes
   long long ng;
-  // ghost groups (see GhostGroup) and per-ghost stencil codes
-  const int* groups;
-  const int* gcode;
+  const int* groups;  // GhostGroup records
+  const int* gcode;   // per ghost: stencil start and code per axis
   long long ngroups;
-  long long Nc, Nf;
-  int cn[3];          // coarse domain extent
+  // parent box
+  int po[3], pM[3], pn[3];
+  uint32_t pspan;
+  long long pN, cN;   // parent and child box sizes
 };
 
-// The ghosts are grouped by the coarse cube of kGhostCube^3 cells that holds
-// them (at most kGhostMax ghosts per group; ghosts [gbeg, gend) of the
-// list). A group's stencils read the coarse patch [lo, lo + m) (unwrapped
-// coordinates, wrapped on periodic axes; m <= kGhostCube + 3 per axis),
-// which one workgroup stages in LDS. A ghost's code holds, per axis d in
-// bits 6d..6d+5, its stencil's first node relative to lo (3 bits) and its
-// stencil code (3 bits).
+// Ghosts are grouped by the parent cube of kGhostCube^3 nodes holding their
+// stencil starts (at most kGhostMax per group); a group's stencils read the
+// parent patch [lo, lo + m) (level coordinates, wrapped on spanned periodic
+// axes; m <= kGhostCube + 3 per axis), staged in LDS by one workgroup. A
+// ghost's code holds per axis d, in bits 6d..6d+5, the stencil start
+// relative to lo (3 bits) and the stencil code c (3 bits): the child lies at
+// t = (2c - 1)/4 of the window s..s+3.
 constexpr int kGhostCube = 4;
 constexpr int kGhostMax = 64;
 constexpr int kPatchEdge = kGhostCube + 3;
@@ -334,122 +459,102 @@ struct GhostGroup {
   int lo[3], m[3];
 };
 
-// Tensor interpolation from a staged patch (x fastest, rows of m0 nodes,
-// planes of m01). The stencil shape is a compile-time count per axis so
-// the LDS reads are unrolled; summation order z, then y, then x.
-template <int C0, int C1, int C2, typename S, typename R>
-__device__ __forceinline__ R patch_interp_fixed(const S* sp, const int (&a)[3],
-                                                const double (&w)[3][4], int m0, int m01) {
-  R s = 0;
-#pragma unroll
-  for (int c = 0; c < C2; ++c)
-#pragma unroll
-    for (int b = 0; b < C1; ++b) {
-      const R wbc = R(w[1][b] * w[2][c]);
-      const S* row = sp + (a[2] + c) * m01 + (a[1] + b) * m0 + a[0];
-#pragma unroll
-      for (int x = 0; x < C0; ++x) s += R(w[0][x]) * wbc * R(row[x]);
-    }
-  return s;
+// Cubic Lagrange weights (dyadic, exact) at t = (2c - 1)/4, c = 0..7, on
+// the nodes 0..3 of a window.
+__host__ __device__ inline void stencil_weights(int c, double w[4]) {
+  const double t = (2.0 * c - 1.0) * 0.25;
+  w[0] = -(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0;
+  w[1] = t * (t - 2.0) * (t - 3.0) / 2.0;
+  w[2] = -t * (t - 1.0) * (t - 3.0) / 2.0;
+  w[3] = t * (t - 1.0) * (t - 2.0) / 6.0;
 }
 
+// Window start s and code c of child coordinate j on a parent axis of n
+// nodes: s = floor(j/2 - 1/4) - 1, moved inside [0, n - 4] on a
+// non-periodic axis; c = j - 2 s.
+__host__ __device__ inline int child_window(int j, int n, bool periodic, int& s) {
+  int f = (2 * j - 1) >= 0 ? (2 * j - 1) / 4 : -((-(2 * j - 1) + 3) / 4);  // floor((2j-1)/4)
+  s = f - 1;
+  if (!periodic) s = s < 0 ? 0 : (s > n - 4 ? n - 4 : s);
+  return j - 2 * s;
+}
+
+// Tensor interpolation from a staged patch (x fastest): 4 x 4 x 4 nodes,
+// summation z, then y, then x.
 template <typename S, typename R>
 __device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01) {
-  int a[3], shape = 0;
+  int a[3];
   double w[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int cd = (code >> (6 * d)) & 63;
     a[d] = cd & 7;
     stencil_weights(cd >> 3, w[d]);
-    shape |= (cd >> 3) != 0 ? 1 << d : 0;
   }
-  switch (shape) {
-    case 0: return patch_interp_fixed<1, 1, 1, S, R>(sp, a, w, m0, m01);
-    case 1: return patch_interp_fixed<4, 1, 1, S, R>(sp, a, w, m0, m01);
-    case 2: return patch_interp_fixed<1, 4, 1, S, R>(sp, a, w, m0, m01);
-    case 3: return patch_interp_fixed<4, 4, 1, S, R>(sp, a, w, m0, m01);
-    case 4: return patch_interp_fixed<1, 1, 4, S, R>(sp, a, w, m0, m01);
-    case 5: return patch_interp_fixed<4, 1, 4, S, R>(sp, a, w, m0, m01);
-    case 6: return patch_interp_fixed<1, 4, 4, S, R>(sp, a, w, m0, m01);
-    default: return patch_interp_fixed<4, 4, 4, S, R>(sp, a, w, m0, m01);
-  }
+  R s = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const R wbc = R(w[1][b] * w[2][c]);
+      const S* row = sp + (a[2] + c) * m01 + (a[1] + b) * m0 + a[0];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) s += R(w[0][x]) * wbc * R(row[x]);
+    }
+  return s;
 }
 
-// Rescaled ghost populations of one group: lanes take (ghost, population)
-// pairs population-major, v = c0 G0 + c1 G (G0 may be null), with the
-// moments of each ghost shared through LDS; every lane evaluates the
-// equilibrium of its own population and writes feq + r (v - feq) to ff
-// (Yu's rescaling of the non-equilibrium part).
+// Rescaled ghosts of one group: thread gl < ngg takes ghost gl's Q values
+// from sv, rescales them to the child level and writes them to ff.
 template <int KIND, typename S, typename R>
 __device__ __forceinline__ void rescale_group(const GhostArgs& ga, long long gbeg, int ngg,
                                               R (&sv)[Model<KIND>::Q][kGhostMax],
-                                              const int (&se)[Model<KIND>::Q][3], double r,
-                                              S* ff) {
+                                              const RescaleArgs& ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
-    const int q = k / kGhostMax, gl = k % kGhostMax;
-    if (gl >= ngg) continue;
-    R d = 0, j[3] = {0, 0, 0};
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      const R f = sv[I][gl];
-      d += f;
-      j[0] += R(cx(I)) * f;
-      j[1] += R(cy(I)) * f;
-      j[2] += R(cz(I)) * f;
-    });
-    const R feq = equilibrium_one<KIND, R>(d, j, se[q][0], se[q][1], se[q][2]);
+  for (int gl = threadIdx.x; gl < ngg; gl += blockDim.x) {
+    R f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = sv[q][gl];
+    rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
     const int l = ga.ghosts[gbeg + gl];
-    st(ff + (size_t)q * (size_t)ga.Nf + l, feq + R(r) * (sv[q][gl] - feq));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
   }
 }
 
-template <int Q>
-__device__ __forceinline__ void velocity_table(int (&se)[Q][3]) {
-  const int t = threadIdx.x;
-  if (t < Q) {
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      if (t == I) {
-        se[I][0] = cx(I);
-        se[I][1] = cy(I);
-        se[I][2] = cz(I);
-      }
-    });
-  }
-}
-
-// Interface update of one ghost group per workgroup: the coarse patch
-// (all populations of the coarse state fc) is staged in LDS, each ghost
-// population is interpolated from it (G, kept for the next coarse step),
-// and the ghosts of ff receive the rescaled c0 G0 + c1 G.
+// Interface update of one ghost group per workgroup: the parent patch of
+// the parent state fp is staged in LDS, every (ghost, population) is
+// interpolated from it into Gn (kept for the following steps), and the
+// ghosts of ff receive rescale(c0 Gm + c1 Gc + c2 Gn) (Gm, Gc not read where
+// their weight is 0).
 template <int KIND, typename S, typename R>
-__global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* fc, R* G,
-                                                          const R* G0, double c0, double c1,
-                                                          double r, S* ff) {
+__global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* fp, R* Gn,
+                                                          const R* Gc, const R* Gm, double c0,
+                                                          double c1, double c2,
+                                                          const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
   __shared__ S sp[Q][kPatchMax];
   __shared__ R sv[Q][kGhostMax];
-  __shared__ int se[Q][3];
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
   const int lo[3] = {grp->lo[0], grp->lo[1], grp->lo[2]};
   const int m0 = grp->m[0], m1 = grp->m[1], m01 = m0 * m1;
   const int P = m01 * grp->m[2];
-  velocity_table<Q>(se);
   for (int p = threadIdx.x; p < P; p += blockDim.x) {
     const int pz = p / m01, rem = p - pz * m01, py = rem / m0, px = rem - py * m0;
     const int g3[3] = {lo[0] + px, lo[1] + py, lo[2] + pz};
     int c[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      c[d] = g3[d] < 0 ? g3[d] + ga.cn[d] : (g3[d] >= ga.cn[d] ? g3[d] - ga.cn[d] : g3[d]);
-    const size_t idx = ((size_t)c[2] * ga.cn[1] + c[1]) * ga.cn[0] + c[0];
+    for (int d = 0; d < 3; ++d) {
+      int v = g3[d];
+      if ((ga.pspan >> d) & 1u) v = v < 0 ? v + ga.pn[d] : (v >= ga.pn[d] ? v - ga.pn[d] : v);
+      c[d] = v - ga.po[d];
+    }
+    const size_t idx = ((size_t)c[2] * ga.pM[1] + c[1]) * ga.pM[0] + c[0];
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      sp[I][p] = fc[(size_t)I * (size_t)ga.Nc + idx];
+      sp[I][p] = fp[(size_t)I * (size_t)ga.pN + idx];
     });
   }
   __syncthreads();
@@ -457,78 +562,72 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
     const int q = k / kGhostMax, gl = k % kGhostMax;
     if (gl >= ngg) continue;
     const long long gi = gbeg + gl;
-    const R g = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
+    const R v = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
     const size_t kk = (size_t)q * ga.ng + gi;
-    G[kk] = g;
-    sv[q][gl] = G0 ? R(c0) * G0[kk] + R(c1) * g : R(c1) * g;
+    Gn[kk] = v;
+    R s = R(c2) * v;
+    if (c1 != 0.0) s += R(c1) * Gc[kk];
+    if (c0 != 0.0) s += R(c0) * Gm[kk];
+    sv[q][gl] = s;
   }
   __syncthreads();
-  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, se, r, ff);
+  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, ra, ff);
 }
 
-// Ghosts of ff := rescale(c1 G) from stored interpolated values, by group.
+// Ghosts of ff := rescale(G) from stored interpolated values, by group.
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
-                                                            double c1, double r, S* ff) {
+                                                            const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
   __shared__ R sv[Q][kGhostMax];
-  __shared__ int se[Q][3];
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
-  velocity_table<Q>(se);
   for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
     const int q = k / kGhostMax, gl = k % kGhostMax;
-    if (gl < ngg) sv[q][gl] = R(c1) * G[(size_t)q * ga.ng + gbeg + gl];
+    if (gl < ngg) sv[q][gl] = G[(size_t)q * ga.ng + gbeg + gl];
   }
   __syncthreads();
-  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, se, r, ff);
+  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, ra, ff);
 }
 
-// FP64 partial sums over the nodes of a level box whose type equals want,
-// each weighted by w (the node's volume in coarse cells).
+// ------------------------------------------------------------- reductions
+// FP64 partial sums over the nodes of a level box of type want, each
+// weighted by w (the node's volume in level-0 cells).
 template <int KIND, typename S>
-__global__ __launch_bounds__(256) void masked_reduce_kernel(const Level L, int want, double w,
-                                                            double* partial) {
+__global__ __launch_bounds__(256) void level_reduce_kernel(const Lev L, int want, double w,
+                                                           double* partial) {
   constexpr int Q = Model<KIND>::Q;
   __shared__ double sh[5][256];
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int nthreads = blockDim.x * blockDim.y;
+  const int tid = threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
-  const int lx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ly = blockIdx.y * blockDim.y + threadIdx.y;
-  const int lz = blockIdx.z;
-  if (lx < L.M[0] && ly < L.M[1]) {
-    const size_t self = ((size_t)lz * L.M[1] + ly) * L.M[0] + lx;
-    if (L.type[self] == want) {
-      const S* A = (const S*)L.a;
-      double d = 0, j[3] = {0, 0, 0};
-      for (int i = 0; i < Q; ++i) {
-        const double fi = ld<double>(A + (size_t)i * (size_t)L.Nbox + self);
-        d += fi;
-        j[0] += cx(i) * fi;
-        j[1] += cy(i) * fi;
-        j[2] += cz(i) * fi;
-      }
-      const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
-      v[0] = w * d;
-      v[1] = w * j[0];
-      v[2] = w * j[1];
-      v[3] = w * j[2];
-      v[4] = w * 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / r;
+  const long long self = (long long)blockIdx.x * blockDim.x + tid;
+  if (self < L.Nbox && L.type[self] == want) {
+    const S* A = (const S*)L.a;
+    double d = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      const double fi = ld<double>(A + (size_t)i * (size_t)L.Nbox + self);
+      d += fi;
+      j[0] += cx(i) * fi;
+      j[1] += cy(i) * fi;
+      j[2] += cz(i) * fi;
     }
+    const double r = (Q == 27) ? 1.0 + d : 1.0;
+    v[0] = w * d;
+    v[1] = w * j[0];
+    v[2] = w * j[1];
+    v[3] = w * j[2];
+    v[4] = w * 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / r;
   }
   for (int k = 0; k < 5; ++k) sh[k][tid] = v[k];
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s && tid + s < nthreads)
+    if (tid < s)
       for (int k = 0; k < 5; ++k) sh[k][tid] += sh[k][tid + s];
     __syncthreads();
   }
-  if (tid == 0) {
-    const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    for (int k = 0; k < 5; ++k) partial[b * 5 + k] = sh[k][0];
-  }
+  if (tid == 0)
+    for (int k = 0; k < 5; ++k) partial[(size_t)blockIdx.x * 5 + k] = sh[k][0];
 }
 
 }  // namespace lbm

@@ -84,3 +84,50 @@ def window(shape, faces, lo, hi, margin):
         wf += [f_lo, f_hi]
         inner.append(slice(lo[d] - a, hi[d] - a))
     return wlo, whi, wf, inner
+
+
+# ------------------------------------------------ refined-lattice cases
+F, PR = oracle.FREESLIP, oracle.PRESSURE
+REFINED_FACE_U = [[0.0, 0.001, 0.002], [0.0, 0.0, 0.002], [0.001, 0.0, 0.002], [0.0, 0.0, 0.002],
+          [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]]
+
+
+def jet_map(n, nz, B, levels, r2=None):
+    """First four z block layers within a radius refined (two levels: 16 x 16
+    x 32, radius^2 40; three: 24 x 24 x 32, the centre 4 x 4 blocks, and the
+    inner 2 x 2 blocks of the first two layers once more)."""
+    m = np.zeros((nz // B, n // B, n // B), dtype=np.uint8)
+    if r2 is None:
+        r2 = 40.0 if levels == 2 else 72.0
+    for bz in range(4):
+        for by in range(n // B):
+            for bx in range(n // B):
+                cx, cy = (bx + 0.5) * B - n / 2, (by + 0.5) * B - n / 2
+                if cx * cx + cy * cy <= r2:
+                    m[bz, by, bx] = 1
+    if levels == 3:
+        h = n // B // 2
+        m[0:2, h - 1:h + 1, h - 1:h + 1] = 2
+    return m
+
+
+REFINED_CASES = {
+    # name: (levels, jet, faces, face_drho)
+    "jet2": (2, True, [W, W, W, W, I, O], None),
+    "jet3": (3, True, [W, W, W, W, I, O], None),
+    "slab": (2, False, [P] * 6, None),
+    "slab3": (3, False, [P] * 6, None),
+    "slip_pressure": (2, True, [W, W, W, F, I, PR], [0, 0, 0, 0, 0, -0.002]),
+    "slab_slip_pressure": (2, False, [F, F, PR, PR, P, P], [0, 0, 0.001, -0.001, 0, 0]),
+    # 24 x 24 x 32 with the centre 4 x 4 blocks of the first four layers
+    # refined: room for a nozzle inside the fine level
+    "jet2wide": (2, True, [W, W, W, W, I, O], None),
+}
+
+
+def refined_jet_geometry(case):
+    """(n, nz, B, level map) of a jet case."""
+    levels = REFINED_CASES[case][0]
+    n = 16 if (levels == 2 and case != "jet2wide") else 24
+    r2 = 72.0 if case == "jet2wide" else None
+    return n, 32, 4, jet_map(n, 32, 4, levels, r2)

@@ -18,8 +18,9 @@ rounded to the storage precision, exactly as the GPU stored it.
 The same is done for the jet with the round nozzle tube as curved walls
 (interpolated bounce-back), in boxes across the tube.
 
-The two-level refined workload is checked at full size through properties
-that hold at any size (uniform flow preserved exactly; FP32 against FP64).
+The two-level refined workload of the benchmark is compared at full size with
+the oracle's refined lattice (FP64 storage, two level-0 steps from noise) and
+keeps a uniform co-flow exactly uniform.
 A 512 x 512 x 256 FP64 lattice checks the path taken when 32-bit offsets
 cannot span a population and its opposite. The velocity time averages of
 the FCLB FP32 jet are checked in four of the boxes.
@@ -202,55 +203,102 @@ def test_jet256_statistics_boxes():
         assert dv <= 4 * STEPS * e * u2max, (lo, dv)
 
 
-@pytest.mark.parametrize("model", ["fclb", "mrt"])
-def test_refined_jet_full_size_properties(model):
-    """The 128 x 128 x 256 two-level jet of the benchmark: a uniform co-flow
-    through the whole configuration (inlet at the co-flow speed everywhere,
-    walls moving with it) stays exactly uniform on both levels in FP64; with
-    the benchmark's inlet and state, FP32 storage tracks FP64 storage within
-    the FP32 per-step tolerance over 3 coarse steps."""
+def _bench_refined(model, storage, u0=None):
+    """The benchmark's two-level 128 x 128 x 256 jet (16^3 blocks, 416 of 1024
+    refined); with u0 a uniform co-flow inlet instead of the jet's."""
     import bench
     import paper_1206_0389_amd as P
-    print("case refined full size", model, flush=True)
     nx, ny, nz, B = 128, 128, 256, 16
     mask = bench.refined_jet_mask(nx, ny, nz, B)
-    u0 = 0.002
-    iu = np.zeros((3, ny, nx))
-    iu[2] = u0
-    fiu = np.zeros((3, 2 * ny, 2 * nx))
-    fiu[2] = u0
-    fu = [[0.0, 0.0, u0]] * 4 + [[0.0, 0.0, 0.0]] * 2
-    lat = P.RefinedLattice(model=model, storage="f64", shape=(nx, ny, nz), nu=1e-4,
+    fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
+    if u0 is None:
+        iu, im = synth.jet_inlet(nx, ny, 16.0, 0.05, 0.002)
+        fiu, fim = synth.jet_inlet(2 * nx, 2 * ny, 32.0, 0.05, 0.002)
+        amp = 5e-4
+    else:
+        iu = np.zeros((3, ny, nx))
+        iu[2] = u0
+        fiu = np.zeros((3, 2 * ny, 2 * nx))
+        fiu[2] = u0
+        im = fim = None
+        amp = 0.0
+        fu = [[0.0, 0.0, u0]] * 4 + [[0.0, 0.0, 0.0]] * 2
+    lat = P.RefinedLattice(model=model, storage=storage, shape=(nx, ny, nz), nu=1e-4,
                            cs_smag=0.1, block=B, mask=mask,
                            faces=[P.WALL] * 4 + [P.INLET, P.OUTFLOW], face_u=fu,
-                           inlet_u=torch.from_numpy(iu), fine_inlet_u=torch.from_numpy(fiu))
+                           inlet_u=torch.from_numpy(iu),
+                           inlet_mask=None if im is None else torch.from_numpy(im),
+                           fine_inlet_u=torch.from_numpy(fiu),
+                           fine_inlet_mask=None if fim is None else torch.from_numpy(fim),
+                           inlet_amp=amp, seed=12060389)
+    return lat, (nx, ny, nz, B, mask, fu, iu, im, fiu, fim, amp)
+
+
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_refined_jet_full_size_uniform_flow(model):
+    """The 128 x 128 x 256 two-level jet of the benchmark: a uniform co-flow
+    through the whole configuration (inlet at the co-flow speed everywhere,
+    walls moving with it) stays exactly uniform on both levels in FP64."""
+    print("case refined full size uniform", model, flush=True)
+    u0 = 0.002
+    lat, _ = _bench_refined(model, "f64", u0=u0)
     for level in (0, 1):
         d, u = synth.uniform_fields(*lat.shape3(level)[::-1], u=(0.0, 0.0, u0))
         lat.init_equilibrium(level, torch.from_numpy(d), torch.from_numpy(u))
     f0 = [lat.populations(level) for level in (0, 1)]
     lat.step(3)
     for level in (0, 1):
+        live = torch.from_numpy(np.isin(lat.types(level), (1, 2))).cuda()
         d, u = lat.macroscopic(level)
         f1 = lat.populations(level)
-        # every updated node is unchanged; ghosts and covered nodes hold the
-        # same uniform values
-        assert float((f1 - f0[level]).abs().max()) < 1e-15, level
-        assert float((u[2] - u0).abs().max()) < 1e-15 and float(d.abs().max()) < 1e-15
+        assert float((f1 - f0[level])[:, live].abs().max()) < 1e-15, level
+        assert float((u[2][live] - u0).abs().max()) < 1e-15
+        assert float(d[live].abs().max()) < 1e-15
     del lat, f0
     torch.cuda.empty_cache()
-    # benchmark inlet and state: FP32 against FP64
-    out = {}
-    for storage in ("f64", "f32"):
-        lat, _ = bench.make_lattice("ref128-%s-%s" % (model, storage), P, torch, synth)
-        lat.step(3)
-        out[storage] = [lat.populations(level) for level in (0, 1)]
-        del lat
-        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_refined_jet_full_size_against_oracle(model):
+    """The benchmark's two-level jet (13.6 M fine nodes, 3,000+ ghost groups,
+    the full interface) in FP64 storage from a seeded noise state on both
+    levels, two level-0 steps, against the oracle's refined lattice element
+    by element on both levels (fluid and band nodes, injected covered nodes)
+    to 1e-12 relative."""
+    print("case refined full size vs oracle", model, flush=True)
+    lat, (nx, ny, nz, B, mask, fu, iu, im, fiu, fim, amp) = _bench_refined(model, "f64")
+    code = oracle.FCLB27 if model == "fclb" else oracle.MRT19
+    c = oracle.Lattice(code, nx, ny, nz, nu=1e-4, cs_smag=0.1,
+                       faces=[W, W, W, W, I, O], face_u=fu, inlet_u=iu, inlet_mask=im,
+                       inlet_amp=amp, seed=12060389)
+    R = oracle.Refined(c, B, mask, 2, inlet_u=[None, fiu], inlet_mask=[None, fim])
+    Q = c.Q
     for level in (0, 1):
-        a, b = out["f32"][level], out["f64"][level]
-        err = float((a - b).abs().max() / b.abs().max())
-        print("refined", model, "level", level, "FP32 vs FP64", err, flush=True)
-        assert err <= 3 * 2 * TOL["f32"]  # two fine substeps per coarse step
+        assert np.array_equal(lat.types(level), lat.to_box(level, R.types(level))), level
+        shape = lat.shape3(level)
+        f = synth.random_populations(Q, shape, 1e-2, seed=SEED + level)
+        lat.set_populations(level, torch.from_numpy(f), T0)
+        full = np.zeros((Q,) + R.levels[level]["shape"])
+        sz, sy, sx, wx = lat.box_slices(level)
+        full[:, sz, sy, sx] = f[..., :wx]
+        R.set_state(level, full)
+        del f, full
+    lat.step(2)
+    R.run(T0, 2)
+    ok1 = np.isin(R.types(1), (1, 2))
+    kids = ok1.reshape(nz, 2, ny, 2, nx, 2).all(axis=(1, 3, 5))
+    for level in (0, 1):
+        keep = np.isin(lat.types(level), (1, 2))
+        if level == 0:
+            keep |= lat.to_box(0, (R.types(0) == 3) & kids).astype(bool)
+        got = lat.populations(level).cpu().numpy()[:, keep]
+        want = lat.to_box(level, R.state(level))[:, keep]
+        err = rel_err(got, want)
+        print("refined full size", model, "level", level, "nodes", int(keep.sum()),
+              "error", err, flush=True)
+        assert err <= 1e-12, (level, err)
+    del lat, R
+    torch.cuda.empty_cache()
 
 
 def test_lattice_beyond_the_offset_span_takes_the_general_path():
