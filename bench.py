@@ -76,7 +76,7 @@ def workload(name):
     """(model, storage, shape, kind) from a name like jet256-fclb-f32."""
     kind, model, storage = name.split("-")
     shapes = {"jet256": (256, 256, 512), "tgv256": (256, 256, 512), "tgv128": (128, 128, 128),
-              "jet128": (128, 128, 256), "ref128": (128, 128, 256),
+              "jet128": (128, 128, 256), "ref128": (128, 128, 256), "ref3l128": (128, 128, 256),
               "nozzle256": (256, 256, 512), "nozzlecurved256": (256, 256, 512)}
     return model, storage, shapes[kind], kind
 
@@ -121,34 +121,48 @@ def make_lattice(name, P, torch, synth):
     import numpy as np
     model, storage, shape, kind = workload(name)
     nx, ny, nz = shape
-    if kind == "ref128":
+    if kind in ("ref128", "ref3l128"):
         nu, cs, B = 1e-4, 0.1, 16
-        mask = refined_jet_mask(nx, ny, nz, B)
+        levels = 2 if kind == "ref128" else 3
+        lmap = refined_jet_mask(nx, ny, nz, B)
+        if levels == 3:
+            lmap = lmap + refined_jet_mask(nx, ny, nz, B, layers=4, radius=34.0)
         iu, im = synth.jet_inlet(nx, ny, 16.0, 0.05, 0.002)
-        fiu, fim = synth.jet_inlet(2 * nx, 2 * ny, 32.0, 0.05, 0.002)
+        lius, lims = [None], [None]
+        for l in range(1, levels):
+            a, b = synth.jet_inlet(nx << l, ny << l, 16.0 * 2 ** l, 0.05, 0.002)
+            lius.append(torch.from_numpy(a))
+            lims.append(torch.from_numpy(b))
         fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
         lat = P.RefinedLattice(model=model, storage=storage, shape=shape, nu=nu, cs_smag=cs,
-                               block=B, mask=mask,
+                               block=B, level_map=lmap, nlevels=levels,
                                faces=[P.WALL] * 4 + [P.INLET, P.OUTFLOW], face_u=fu,
                                inlet_u=torch.from_numpy(iu), inlet_mask=torch.from_numpy(im),
-                               fine_inlet_u=torch.from_numpy(fiu),
-                               fine_inlet_mask=torch.from_numpy(fim), inlet_amp=5e-4,
+                               level_inlet_u=lius, level_inlet_mask=lims, inlet_amp=5e-4,
                                seed=12060389)
-        for level in (0, 1):
+        for level in range(levels):
             d, u = synth.uniform_fields(*lat.shape3(level)[::-1], u=(0.0, 0.0, 0.002),
                                         dtype=np.float32)
             lat.init_equilibrium(level, torch.from_numpy(d), torch.from_numpy(u))
-        c = lat.counts
-        desc = {"workload": "two-level refined round jet, coarse %dx%dx%d, 16^3 blocks, %d of %d "
-                            "blocks refined (layers 0-7, centre radius <= 62), D=16 coarse / 32 "
-                            "fine inlet u=0.05 +1%% perturbation, co-flow 0.002, nu_c=1e-4"
-                            % (nx, ny, nz, int(mask.sum()), mask.size),
+        # node updates per level-0 step: level l updates its fluid and band
+        # nodes 2^l times
+        per = [v["counts"]["fluid"] + v["counts"]["band"] for v in lat.levels]
+        ups = sum(n_l << l for l, n_l in enumerate(per))
+        desc = {"workload": "%d-level refined round jet, level 0 %dx%dx%d, 16^3 blocks, level map "
+                            "%s blocks at levels 1..%d (level 1: layers 0-7, centre radius <= 62%s), "
+                            "D=16 at level 0 inlet u=0.05 +1%% perturbation, co-flow 0.002, "
+                            "nu_0=1e-4"
+                            % (levels, nx, ny, nz,
+                               "/".join(str(int((lmap >= l).sum())) for l in range(1, levels)),
+                               levels - 1, "; level 2: layers 0-3, radius <= 34"
+                               if levels == 3 else ""),
                 "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
-                "fine_nodes": c["fluid"], "ghost_nodes": c["ghost"],
-                "covered_coarse": c["covered"],
-                "updates_per_coarse_step": nx * ny * nz - c["covered"] + 2 * c["fluid"],
+                "updated_nodes_per_level": per, "ghost_nodes_per_level":
+                    [v["counts"]["ghost"] for v in lat.levels],
+                "covered_per_level": [v["counts"]["covered"] for v in lat.levels],
+                "updates_per_level0_step": ups,
                 "cs_smag": cs if model == "mrt" else None}
-        lat.updates_per_step = desc["updates_per_coarse_step"]
+        lat.updates_per_step = ups
         return lat, desc
     if kind.startswith("jet") or kind.startswith("nozzle"):
         js = jet_setup(nx, ny, synth)
@@ -420,7 +434,7 @@ def main():
                      "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
-                     "ref128-mrt-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:
+                     "ref128-mrt-f32", "ref3l128-fclb-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:
             if name == args.workload:
                 continue
             r = measure(name, P, torch, synth, args.other_steps, 10)

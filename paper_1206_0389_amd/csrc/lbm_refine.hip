@@ -26,9 +26,10 @@ struct HostLevel {
   uint32_t span = 0;
   size_t Nbox = 0;
   std::vector<uint8_t> type;
-  // tiles (3 ints each) in the order plain+inj | plain | general+inj | general
+  // tiles (3 ints each) by class: general, walls, plain
   std::vector<int32_t> tiles;
-  size_t nt[4] = {0, 0, 0, 0};
+  size_t nt[3] = {0, 0, 0};
+  std::vector<int32_t> inj;  // covered nodes read by this level's steps
   std::vector<int32_t> ghosts, gcode;
   std::vector<GhostGroup> groups;
   std::vector<uint8_t> solid;               // host copy over the box (empty: none)
@@ -39,10 +40,11 @@ struct HostLevel {
   std::vector<float> pre_q;
   // device offsets
   size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
-         off_groups = 0, off_G[3] = {0, 0, 0}, off_pre_nodes = 0, off_pre_dirs = 0,
-         off_pre_q = 0;
+         off_groups = 0, off_G[3] = {0, 0, 0}, off_H = 0, off_pre_nodes = 0, off_pre_dirs = 0,
+         off_pre_q = 0, off_inj = 0;
   int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
   bool have_cur = false, have_prev = false;
+  bool ghost_pending = false;  // next-step ghosts queued on the second stream
   Lev dev;
   double tau0 = 0.5;
 };
@@ -64,6 +66,13 @@ struct lbm_refined {
   char* base = nullptr;
   size_t req = 0, off_partial = 0, off_result = 0, max_rblocks = 1;
   hipStream_t stream = nullptr;
+  // second stream (default priority) for the general tiles of a step and a
+  // child's interface interpolation, joined to the lattice's stream by
+  // events; created at the first step
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_sub1 = nullptr;
+  hipEvent_t ev_ghost[kMaxLevels] = {nullptr};  // a child's next-step ghosts done
+  bool side_tried = false;
   int64_t t = 0;
 };
 
@@ -193,51 +202,98 @@ void group_ghosts(lbm_refined* R, int l) {
   for (size_t gi = 0; gi < it.size(); ++gi) V.ghosts[gi] = it[gi].k;
 }
 
-// Tile lists of level l: aligned 32 x 4 x 2 tiles holding fluid or band
-// nodes; plain if every active node lies on no domain face and reads only
-// in-box neighbours without wrapping; inj if a parent node of the tile is
-// covered (the child's second substep then injects).
+// log2 of the tile width of a level: the widest power-of-two row run up to
+// 256 nodes that divides the row pitch (a multiple of 64), so that no tile
+// hangs over the end of a row.
+int tile_shift(const HostLevel& V) { return V.M[0] % 256 == 0 ? 8 : (V.M[0] % 128 == 0 ? 7 : 6); }
+
+// Tile lists of level l: tiles of TW x (256 / TW) x 1 nodes holding fluid or
+// band nodes, by class: plain (every active node reads only in-box neighbours
+// without wrapping and lies on no domain face), walls (as plain except that
+// sources may lie beyond x or y WALL faces; no node on a z face), general.
 void build_tiles(lbm_refined* R, int l) {
   HostLevel& V = R->lev[l];
-  std::vector<int32_t> lists[4];
-  const int tx0 = V.o[0], ty0 = floor_div(V.o[1], 4) * 4, tz0 = floor_div(V.o[2], 2) * 2;
-  for (int tz = tz0; tz < V.o[2] + V.M[2]; tz += 2)
-    for (int ty = ty0; ty < V.o[1] + V.M[1]; ty += 4)
-      for (int tx = tx0; tx < V.o[0] + V.M[0]; tx += 32) {
-        bool any = false, plain = true, inj = false;
+  std::vector<int32_t> lists[3];
+  const uint32_t np = R->bc.nonper, wall = R->bc.wall;
+  // the wall kernel addresses a population and its opposite from the lower
+  // slab with 32-bit offsets
+  const double span = 1.0 + (R->Q == 27 ? max_opposite_distance<27>() : max_opposite_distance<19>());
+  const bool o32 = span * (double)V.Nbox * (double)R->elem < 4294967296.0;
+  const int sh = tile_shift(V), tw = 1 << sh, th = 256 / tw;
+  for (int tz = V.o[2]; tz < V.o[2] + V.M[2]; ++tz)
+    for (int ty = V.o[1]; ty < V.o[1] + V.M[1]; ty += th)
+      for (int tx = V.o[0]; tx < V.o[0] + V.M[0]; tx += tw) {
+        bool any = false, plain = true, walls = o32;
         for (int k = 0; k < 256; ++k) {
-          const int g[3] = {tx + (k & 31), ty + ((k >> 5) & 3), tz + (k >> 7)};
+          const int g[3] = {tx + (k & (tw - 1)), ty + (k >> sh), tz};
           const long bi = box_index(V, g);
           if (bi < 0) continue;
           const uint8_t ty_ = V.type[bi];
           if (ty_ != RT_FLUID && ty_ != RT_BAND) continue;
           any = true;
-          for (int d = 0; d < 3 && plain; ++d)
-            if (g[d] == 0 || g[d] == V.n[d] - 1) plain = false;
-          for (int c = 0; c < 27 && plain; ++c) {
-            const int h[3] = {g[0] + c % 3 - 1, g[1] + (c / 3) % 3 - 1, g[2] + c / 9 - 1};
-            if (box_index(V, h) < 0) plain = false;
+          for (int c = 0; c < 27; ++c) {
+            const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+            const int h[3] = {g[0] + d[0], g[1] + d[1], g[2] + d[2]};
+            uint32_t crossed = 0;
+            for (int a = 0; a < 3; ++a) {
+              if (h[a] < 0) crossed |= 1u << (2 * a);
+              if (h[a] >= V.n[a]) crossed |= 1u << (2 * a + 1);
+            }
+            if (crossed) {
+              plain = false;
+              // beyond x/y WALL faces only
+              if ((crossed & 48u) || (crossed & ~(np & wall))) walls = false;
+            } else if (box_index(V, h) < 0) {
+              plain = walls = false;
+            }
           }
+          if ((np & 48u) && (g[2] == 0 || g[2] == V.n[2] - 1)) walls = false;
         }
         if (!any) continue;
-        if (l > 0) {
-          const HostLevel& P = R->lev[l - 1];
-          for (int k = 0; k < 32 && !inj; ++k) {
-            const int pg[3] = {tx / 2 + (k & 15), ty / 2 + (k >> 4), tz / 2};
-            const long pi = box_index(P, pg);
-            if (pi >= 0 && P.type[pi] == RT_COVERED) inj = true;
-          }
-        }
-        const int which = (plain ? 0 : 2) + (inj ? 0 : 1);
+        const int which = plain ? 2 : (walls ? 1 : 0);
         lists[which].push_back(tx);
         lists[which].push_back(ty);
         lists[which].push_back(tz);
       }
   V.tiles.clear();
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 3; ++k) {
     V.nt[k] = lists[k].size() / 3;
     V.tiles.insert(V.tiles.end(), lists[k].begin(), lists[k].end());
   }
+}
+
+// Covered nodes of level l that its fluid or band nodes pull from (their
+// 26 neighbourhoods); their eight children must be fluid or band.
+bool build_inject(lbm_refined* R, int l) {
+  HostLevel& V = R->lev[l];
+  V.inj.clear();
+  if (l + 1 >= R->L) return true;
+  const HostLevel& C = R->lev[l + 1];
+  std::vector<uint8_t> mark(V.Nbox, 0);
+  for (size_t k = 0; k < V.Nbox; ++k) {
+    if (V.type[k] != RT_FLUID && V.type[k] != RT_BAND) continue;
+    int g[3];
+    box_coords(V, (long)k, g);
+    for (int c = 0; c < 27; ++c) {
+      const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+      int y[3];
+      if (!neighbour(R, l, g, d, y)) continue;
+      const long yi = box_index(V, y);
+      if (yi >= 0 && V.type[yi] == RT_COVERED) mark[yi] = 1;
+    }
+  }
+  for (size_t k = 0; k < V.Nbox; ++k) {
+    if (!mark[k]) continue;
+    int g[3];
+    box_coords(V, (long)k, g);
+    for (int c = 0; c < 8; ++c) {
+      const int z[3] = {2 * g[0] + (c & 1), 2 * g[1] + ((c >> 1) & 1), 2 * g[2] + (c >> 2)};
+      const long zi = box_index(C, z);
+      if (zi < 0 || (C.type[zi] != RT_FLUID && C.type[zi] != RT_BAND)) return false;
+    }
+    V.inj.push_back((int32_t)k);
+  }
+  return true;
 }
 
 // Geometry of every level from the block map, the periodic axes, the solids
@@ -298,8 +354,8 @@ bool build_geometry(lbm_refined* R) {
       lo[d] = std::max(0, blo[d] * s - 1);
       hi[d] = std::min(V.n[d], bhi[d] * s + 1);
     }
-    V.o[0] = floor_div(lo[0], 32) * 32;
-    V.M[0] = hi[0] > lo[0] ? ((hi[0] - V.o[0] + 31) / 32) * 32 : 0;
+    V.o[0] = floor_div(lo[0], 64) * 64;
+    V.M[0] = hi[0] > lo[0] ? ((hi[0] - V.o[0] + 63) / 64) * 64 : 0;
     V.o[1] = lo[1];
     V.M[1] = hi[1] - lo[1];
     V.o[2] = lo[2];
@@ -439,6 +495,8 @@ bool build_geometry(lbm_refined* R) {
     }
   }
   for (int l = 0; l < L; ++l) build_tiles(R, l);
+  for (int l = 0; l < L; ++l)
+    if (!build_inject(R, l)) return false;
   for (int l = 1; l < L; ++l) group_ghosts(R, l);
   return true;
 }
@@ -461,6 +519,8 @@ void layout(lbm_refined* R) {
       V.off_G[k] = o;
       o += align256(ng * R->Q * R->relem);
     }
+    V.off_H = o; o += align256(ng * R->Q * R->relem);
+    V.off_inj = o; o += align256(V.inj.size() * 4);
     V.off_pre_nodes = o; o += align256(V.pre_nodes.size() * 4);
     V.off_pre_dirs = o; o += align256(V.pre_dirs.size() * 4);
     V.off_pre_q = o; o += align256(V.pre_q.size() * 4);
@@ -501,6 +561,7 @@ void make_levels(lbm_refined* R) {
       D.n[d] = V.n[d];
     }
     D.span = V.span;
+    D.tw_shift = tile_shift(V);
     D.Nbox = (long long)V.Nbox;
     level_physics(R, l, D);
     V.tau0 = D.mrt.tau0;
@@ -568,120 +629,154 @@ RescaleArgs rescale_args(const lbm_refined* R, int l) {
   return a;
 }
 
-template <int KIND, typename S>
-void* G_ptr(const lbm_refined* R, const HostLevel& V, int which) {
-  return R->base + V.off_G[V.gi[which]];
-}
 
-// Ghosts of child level l in array ff := rescale(c0 G(t-1) + c1 G(t) + c2
-// Gnew), Gnew = the interpolation of parent state fp, stored as G(t+1) (or
-// as G(t) when `init`).
+// Child level l's ghosts in array ff := rescale(c0 G(t-1) + c1 G(t) + c2
+// Gnew), Gnew = the interpolation of parent state fp, kept as G(t+1) (or as
+// G(t) when `init`).
 template <int KIND, typename S>
 void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, double c1, double c2,
-                 bool init) {
+                 bool init, hipStream_t stream) {
   using Rt = typename Compute<S>::type;
   HostLevel& V = R->lev[l];
   if (V.groups.empty()) return;
   const GhostArgs ga = ghost_args(R, l);
-  const RescaleArgs ra = rescale_args(R, l);
-  void* Gn = G_ptr<KIND, S>(R, V, init ? 1 : 2);
+  void* Gn = R->base + V.off_G[V.gi[init ? 1 : 2]];
+  Rt* H = (Rt*)(R->base + V.off_H);
   hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
-                     dim3(256), 0, R->stream, ga, (const S*)fp, (Rt*)Gn,
-                     (const Rt*)G_ptr<KIND, S>(R, V, 1), (const Rt*)G_ptr<KIND, S>(R, V, 0), c0,
-                     c1, c2, ra, (S*)ff);
+                     dim3(256), 0, stream, ga, (const S*)fp, (Rt*)Gn,
+                     (const Rt*)(R->base + V.off_G[V.gi[1]]),
+                     (const Rt*)(R->base + V.off_G[V.gi[0]]), c0, c1, c2, H);
+  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
+                     stream, ga, (const Rt*)H, rescale_args(R, l), (S*)ff);
 }
 
+// Child level l's ghosts in array ff := rescale(G(t+1)).
 template <int KIND, typename S>
-void ghost_rescale(lbm_refined* R, int l, int which, void* ff) {
+void ghost_rescale(lbm_refined* R, int l, void* ff, hipStream_t stream) {
   using Rt = typename Compute<S>::type;
   HostLevel& V = R->lev[l];
   if (V.groups.empty()) return;
-  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
-                     dim3(256), 0, R->stream, ghost_args(R, l),
-                     (const Rt*)G_ptr<KIND, S>(R, V, which), rescale_args(R, l), (S*)ff);
+  const GhostArgs ga = ghost_args(R, l);
+  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
+                     stream, ga, (const Rt*)(R->base + V.off_G[V.gi[2]]), rescale_args(R, l),
+                     (S*)ff);
 }
 
+// Covered nodes of level l read by its steps := the rescaled mean of their
+// children in level l+1's current state.
 template <int KIND, typename S>
-void level_step(lbm_refined* R, int l, long long t, bool second) {
+void inject(lbm_refined* R, int l, hipStream_t stream) {
+  HostLevel& V = R->lev[l];
+  const HostLevel& C = R->lev[l + 1];
+  if (V.inj.empty()) return;
+  InjArgs ia;
+  ia.dst = V.dev.b;
+  ia.nodes = (const int*)(R->base + V.off_inj);
+  ia.n = (long long)V.inj.size();
+  ia.src = C.dev.a;
+  for (int d = 0; d < 3; ++d) {
+    ia.po[d] = V.o[d];
+    ia.pM[d] = V.M[d];
+    ia.co[d] = C.o[d];
+    ia.cM[d] = C.M[d];
+  }
+  ia.pN = (long long)V.Nbox;
+  ia.cN = (long long)C.Nbox;
+  hipLaunchKernelGGL((inject_kernel<KIND, S>), dim3(blocks_for(ia.n)), dim3(256), 0, stream, ia,
+                     rescale_args(R, l + 1));
+}
+
+// One step of level l: the solid pre-pass, then the tile classes; with a
+// second stream the (few, long-latency) general tiles run there beside the
+// wall and plain tiles, joined before returning.
+template <int KIND, typename S>
+void level_step(lbm_refined* R, int l, long long t) {
   HostLevel& V = R->lev[l];
   if (V.Nbox == 0) return;
   const Lev& D = V.dev;
+  hipStream_t main = R->stream;
   if (!V.pre_nodes.empty()) {
     constexpr int Q = Model<KIND>::Q;
     hipLaunchKernelGGL((solid_prepass_kernel<Q, S>), dim3(blocks_for((long long)V.pre_nodes.size())),
-                       dim3(256), 0, R->stream, D, (const int*)(R->base + V.off_pre_nodes),
+                       dim3(256), 0, main, D, (const int*)(R->base + V.off_pre_nodes),
                        (const uint32_t*)(R->base + V.off_pre_dirs),
                        (const float*)(R->base + V.off_pre_q), (long long)V.pre_nodes.size());
   }
-  InjArgs inj;
-  std::memset(&inj, 0, sizeof(inj));
-  const bool do_inj = second && l > 0;
-  if (do_inj) {
-    const HostLevel& P = R->lev[l - 1];
-    inj.dst = P.dev.b;
-    inj.type = P.dev.type;
-    for (int d = 0; d < 3; ++d) {
-      inj.o[d] = P.o[d];
-      inj.M[d] = P.M[d];
-    }
-    inj.Nbox = (long long)P.Nbox;
-    inj.tau0_c = P.tau0;
-    inj.tau0_f = V.tau0;
-    inj.cs = R->cfg.cs_smag;
-    inj.rinv = (2.0 * (P.tau0 - 1.0)) / (V.tau0 - 1.0);
-    for (int k = 0; k < 5; ++k) inj.rates[k] = D.mrt.rates[k];
-  }
   const int* tiles = (const int*)(R->base + V.off_tiles);
+  const bool split = R->side != nullptr && V.nt[0] > 0 && V.nt[1] + V.nt[2] > 0;
+  if (split) {
+    (void)hipEventRecord(R->ev_fork, main);
+    (void)hipStreamWaitEvent(R->side, R->ev_fork, 0);
+  }
   size_t start = 0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 3; ++k) {
     const size_t n = V.nt[k];
     const int* tl = tiles + 3 * start;
     start += n;
     if (n == 0) continue;
-    const bool gen = k >= 2, inj_list = (k & 1) == 0;
     const dim3 grid((unsigned)n), block(256);
-    if (do_inj && inj_list) {
-      if (gen)
-        hipLaunchKernelGGL((level_step_kernel<KIND, S, true, true>), grid, block, 0, R->stream, D,
-                           tl, t, inj);
-      else
-        hipLaunchKernelGGL((level_step_kernel<KIND, S, false, true>), grid, block, 0, R->stream,
-                           D, tl, t, inj);
-    } else {
-      if (gen)
-        hipLaunchKernelGGL((level_step_kernel<KIND, S, true, false>), grid, block, 0, R->stream,
-                           D, tl, t, inj);
-      else
-        hipLaunchKernelGGL((level_step_kernel<KIND, S, false, false>), grid, block, 0, R->stream,
-                           D, tl, t, inj);
-    }
+    if (k == 0)
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_GENERAL>), grid, block, 0,
+                         split ? R->side : main, D, tl, t);
+    else if (k == 1)
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_WALLS>), grid, block, 0, main, D, tl, t);
+    else
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_PLAIN>), grid, block, 0, main, D, tl, t);
+  }
+  if (split) {
+    (void)hipEventRecord(R->ev_join, R->side);
+    (void)hipStreamWaitEvent(main, R->ev_join, 0);
   }
 }
 
 void swap_arrays(HostLevel& V) { std::swap(V.dev.a, V.dev.b); }
 
 // Advance level l by one of its steps (index t), and recursively the finer
-// levels by two steps each; `second`: the second step of level l within its
-// parent's step (it injects into the parent's covered nodes).
+// levels by two steps each. With a second stream the child's interface
+// interpolation (latency-bound) runs there beside the child's first
+// substep, which reads only ghosts prepared in the previous step (ghost
+// slots are written only by the interface kernels, fluid slots only by the
+// steps); the main stream waits for it before the second substep.
 template <int KIND, typename S>
-void advance(lbm_refined* R, int l, long long t, bool second) {
+void advance(lbm_refined* R, int l, long long t) {
   HostLevel& V = R->lev[l];
   const bool child = l + 1 < R->L && R->lev[l + 1].Nbox > 0;
   if (child && !R->lev[l + 1].have_cur) {
     HostLevel& C = R->lev[l + 1];
-    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true);
+    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true, R->stream);
     C.have_cur = true;
     C.have_prev = false;
   }
-  level_step<KIND, S>(R, l, t, second);
+  level_step<KIND, S>(R, l, t);
   if (child) {
     HostLevel& C = R->lev[l + 1];
     const double c0 = C.have_prev ? -0.125 : 0.0, c1 = C.have_prev ? 0.75 : 0.5,
                  c2 = C.have_prev ? 0.375 : 0.5;
-    ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false);
-    advance<KIND, S>(R, l + 1, 2 * t, false);
-    advance<KIND, S>(R, l + 1, 2 * t + 1, true);
-    ghost_rescale<KIND, S>(R, l + 1, 2, C.dev.a);
+    hipStream_t side = R->side ? R->side : R->stream;
+    if (R->side) {
+      (void)hipEventRecord(R->ev_fork, R->stream);
+      (void)hipStreamWaitEvent(side, R->ev_fork, 0);
+    }
+    ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false, side);
+    if (R->side) (void)hipEventRecord(R->ev_sub1, side);
+    if (C.ghost_pending) {  // the first substep reads the ghosts of the last step
+      (void)hipStreamWaitEvent(R->stream, R->ev_ghost[l + 1], 0);
+      C.ghost_pending = false;
+    }
+    advance<KIND, S>(R, l + 1, 2 * t);
+    if (R->side) (void)hipStreamWaitEvent(R->stream, R->ev_sub1, 0);
+    advance<KIND, S>(R, l + 1, 2 * t + 1);
+    inject<KIND, S>(R, l, R->stream);
+    if (R->side) {
+      // the next step's first-substep ghosts, beside the following work
+      (void)hipEventRecord(R->ev_fork, R->stream);
+      (void)hipStreamWaitEvent(side, R->ev_fork, 0);
+      ghost_rescale<KIND, S>(R, l + 1, C.dev.a, side);
+      (void)hipEventRecord(R->ev_ghost[l + 1], side);
+      C.ghost_pending = true;
+    } else {
+      ghost_rescale<KIND, S>(R, l + 1, C.dev.a, R->stream);
+    }
     const int old = C.gi[0];
     C.gi[0] = C.gi[1];
     C.gi[1] = C.gi[2];
@@ -692,6 +787,12 @@ void advance(lbm_refined* R, int l, long long t, bool second) {
 }
 
 bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
+
+bool create_level_events(lbm_refined* R) {
+  for (int l = 0; l < R->L; ++l)
+    if (hipEventCreateWithFlags(&R->ev_ghost[l], hipEventDisableTiming) != hipSuccess) return false;
+  return true;
+}
 
 // A LatArgs view of one level's current state box (the uniform lattice's
 // init/set/get/macroscopic kernels, parity 0, no boundary pulls).
@@ -852,6 +953,7 @@ int lbm_refined_bind_memory(lbm_refined* R, void* dev, size_t bytes) {
     if (!rc) rc = upload(R, V.off_pre_nodes, V.pre_nodes.data(), V.pre_nodes.size() * 4);
     if (!rc) rc = upload(R, V.off_pre_dirs, V.pre_dirs.data(), V.pre_dirs.size() * 4);
     if (!rc) rc = upload(R, V.off_pre_q, V.pre_q.data(), V.pre_q.size() * 4);
+    if (!rc) rc = upload(R, V.off_inj, V.inj.data(), V.inj.size() * 4);
     if (rc) {
       R->base = nullptr;
       return rc;
@@ -1075,12 +1177,38 @@ int lbm_refined_get_macroscopic(lbm_refined* R, int level, void* rho, void* u, i
 int lbm_refined_step(lbm_refined* R, int64_t n) {
   if (!R || n < 0) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
+  if (!R->side_tried && R->L > 1) {
+    // without the second stream every kernel simply runs in order
+    R->side_tried = true;
+    if (hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&R->ev_sub1, hipEventDisableTiming) != hipSuccess ||
+        !create_level_events(R)) {
+      if (R->side) (void)hipStreamDestroy(R->side);
+      if (R->ev_fork) (void)hipEventDestroy(R->ev_fork);
+      if (R->ev_join) (void)hipEventDestroy(R->ev_join);
+      if (R->ev_sub1) (void)hipEventDestroy(R->ev_sub1);
+      for (int l = 0; l < kMaxLevels; ++l)
+        if (R->ev_ghost[l]) (void)hipEventDestroy(R->ev_ghost[l]);
+      R->side = nullptr;
+      R->ev_fork = R->ev_join = R->ev_sub1 = nullptr;
+      for (int l = 0; l < kMaxLevels; ++l) R->ev_ghost[l] = nullptr;
+      (void)hipGetLastError();
+    }
+  }
   for (int64_t k = 0; k < n; ++k) {
     with_kind_s(R, [&](auto kc, auto st_) {
-      advance<decltype(kc)::value, typename decltype(st_)::type>(R, 0, (long long)R->t, false);
+      advance<decltype(kc)::value, typename decltype(st_)::type>(R, 0, (long long)R->t);
     });
     R->t += 1;
   }
+  // callers see single-stream semantics: join the pending ghost work
+  for (int l = 0; l < R->L; ++l)
+    if (R->lev[l].ghost_pending) {
+      (void)hipStreamWaitEvent(R->stream, R->ev_ghost[l], 0);
+      R->lev[l].ghost_pending = false;
+    }
   return check_launch();
 }
 
@@ -1133,6 +1261,17 @@ int lbm_refined_set_stream(lbm_refined* R, void* stream) {
 }
 
 int lbm_refined_destroy(lbm_refined* R) {
+  if (R) {
+    if (R->side) {
+      (void)hipStreamSynchronize(R->side);
+      (void)hipStreamDestroy(R->side);
+    }
+    if (R->ev_fork) (void)hipEventDestroy(R->ev_fork);
+    if (R->ev_join) (void)hipEventDestroy(R->ev_join);
+    if (R->ev_sub1) (void)hipEventDestroy(R->ev_sub1);
+    for (int l = 0; l < kMaxLevels; ++l)
+      if (R->ev_ghost[l]) (void)hipEventDestroy(R->ev_ghost[l]);
+  }
   delete R;
   return LBM_OK;
 }

@@ -8,8 +8,8 @@
 // j/2 - 1/4 (a parent node's cell holds the children 2i, 2i+1 per axis), so
 // halfway walls and faces coincide on every level. Each level is stored
 // densely over a box (its refined region plus a ghost layer); the box's x
-// origin is a multiple of 32 nodes and its row pitch M[0] a multiple of 32,
-// so 32-node row segments are aligned. A type byte per box node says what a
+// origin is a multiple of 64 nodes and its row pitch M[0] a multiple of 64,
+// so 64-node row segments are aligned. A type byte per box node says what a
 // kernel does with it:
 //   0 unused, 1 fluid, 2 band (inside the next level's region, read by that
 //   level's ghost interpolation, so updated on this level), 3 covered
@@ -18,11 +18,11 @@
 //
 // Every level holds post-collision populations in two arrays and advances
 // by pull and collide (f_i(x, t+1) = f*_i(x - e_i, t), then the collision).
-// A level step runs over a list of tiles of 32 x 4 x 2 nodes that contain
-// fluid or band nodes; tiles whose nodes have all their neighbours inside
-// the box without wrapping and lie on no domain face take the plain kernel,
-// the others the general one (periodic wrap, the face rules of the uniform
-// lattice).
+// A level step runs over lists of tiles (row segments of up to 256 nodes) that contain
+// fluid or band nodes: tiles whose nodes read only in-box neighbours without
+// wrapping take the plain kernel, tiles with x or y WALL faces besides that
+// the wall kernel (the wall-row rule of the uniform lattice), the others the
+// general one (periodic wrap, every face rule).
 //
 // Interface per parent step t (dt_parent = 2 dt_child):
 //   G(t+1) = parent state at t+1 interpolated at the child's ghosts (tensor
@@ -34,8 +34,9 @@
 //   rescale: the non-equilibrium part scaled per Chapman-Enskog (FCLB one
 //   ratio r = (tau_f - 1)/(2 (tau_c - 1)); MRT per moment group, the shear
 //   group with the total relaxation times of Eq. (20));
-//   covered parent nodes whose eight children are fluid or band take the
-//   rescaled mean of the children, written by the child's second substep.
+//   the covered parent nodes that parent-updated nodes pull from take the
+//   rescaled mean of their eight children once the two child substeps are
+//   done (no other covered node is read by anything).
 // Solid nodes: before each step a pre-pass writes into each solid node's
 // slot i the value its fluid neighbour x = s + e_i pulls from it (halfway
 // bounce-back, or Bouzidi's interpolation along a curved link), so the step
@@ -53,27 +54,29 @@ struct Lev {
   void* a;              // [Q][Nbox] state read by the next step
   void* b;              // [Q][Nbox] state written by it
   const uint8_t* type;  // [Nbox]
-  int o[3];             // box origin (level coordinates); o[0] % 32 == 0
-  int M[3];             // box extent; M[0] (the row pitch) % 32 == 0
+  int o[3];             // box origin (level coordinates); o[0] % 64 == 0
+  int M[3];             // box extent; M[0] (the row pitch) % 64 == 0
   int n[3];             // domain extent of the level
   uint32_t span;        // bit d: the box spans periodic axis d (wraps at n[d])
+  int tw_shift;         // log2 of the tile width (64, 128 or 256 nodes)
   long long Nbox;
   MrtParams mrt;
   double omega;
   BcArgs bc;
 };
 
-// Parent side of the fused injection: covered parent nodes receive the
-// rescaled mean of their eight children from the child's second substep.
+// Injection into a parent level: the covered parent nodes that parent-
+// updated nodes pull from receive the rescaled mean of their eight children
+// once the two child substeps are done (no other covered node is read).
 struct InjArgs {
   void* dst;            // parent array being written this parent step
-  const uint8_t* type;  // parent types
-  int o[3], M[3];
-  long long Nbox;
-  // rescale back to the parent: tau0 of both levels and C_S (MRT), or the
-  // inverse of the FCLB ratio
-  double tau0_c, tau0_f, cs, rinv;
-  double rates[5];
+  const int* nodes;     // parent box indices of the nodes to inject
+  long long n;
+  int po[3], pM[3];     // parent box
+  long long pN;
+  const void* src;      // child state after its two substeps
+  int co[3], cM[3];     // child box
+  long long cN;
 };
 
 // One interface ratio set (parent c -> child f).
@@ -270,15 +273,16 @@ __device__ __forceinline__ void gen_pressure(const Lev& L, const S* A, const Box
   });
 }
 
-// Lane -> node of a 32 x 4 x 2 tile: x fastest (a half wave is one aligned
-// 32-node row segment), then y, then z; tiles are aligned to even
-// coordinates, so the eight children of a parent node lie in one tile.
-__device__ __forceinline__ void tile_node(const int* tiles, int (&g)[3]) {
+// Lane -> node of a tile of TW x (256 / TW) nodes (TW = 2^tw_shift, 64 to
+// 256; x fastest): whole row segments per workgroup, so each population is
+// read and written in runs of TW nodes (the widest runs move the most bytes
+// per second).
+__device__ __forceinline__ void tile_node(const Lev& L, const int* tiles, int (&g)[3]) {
   const int* t = tiles + 3 * (size_t)blockIdx.x;
   const int lane = threadIdx.x;
-  g[0] = t[0] + (lane & 31);
-  g[1] = t[1] + ((lane >> 5) & 3);
-  g[2] = t[2] + (lane >> 7);
+  g[0] = t[0] + (lane & ((1 << L.tw_shift) - 1));
+  g[1] = t[1] + (lane >> L.tw_shift);
+  g[2] = t[2];
 }
 
 __device__ __forceinline__ bool in_box(const Lev& L, const int (&g)[3], int& self) {
@@ -288,32 +292,61 @@ __device__ __forceinline__ bool in_box(const Lev& L, const int (&g)[3], int& sel
   return true;
 }
 
+// Pull of population I at a node whose sources lie in the box without
+// wrapping except across x or y WALL faces (wall tiles): across such a face
+// the node's own slot opp(I) plus the wall term 6 w_I e_I.u_w (the x face
+// first where a node lies on both); both candidate slots are offsets from
+// the lower of the two population slabs, so one scalar-base load serves.
+template <int Q, int I, typename real, typename S>
+__device__ __forceinline__ real walls_pull(const Lev& L, const S* A, int self, int src,
+                                           uint32_t atface) {
+  constexpr int IO = opposite<Q>(I);
+  constexpr uint32_t XB = pull_faces(I) & 3u, YB = pull_faces(I) & 12u;
+  const uint32_t sz = sizeof(S);
+  if constexpr ((XB | YB) == 0) {
+    return ldo<real, cx(I) == 0>(A + (size_t)I * L.Nbox, (uint32_t)src * sz);
+  } else {
+    constexpr int LO = I < IO ? I : IO;
+    const uint32_t slab = (uint32_t)L.Nbox * sz;
+    const bool bx = (atface & XB) != 0, by = (atface & YB) != 0;
+    const bool bb = bx || by;
+    const uint32_t off = bb ? (uint32_t)(IO - LO) * slab + (uint32_t)self * sz
+                            : (uint32_t)(I - LO) * slab + (uint32_t)src * sz;
+    const real v = ldo<real, cx(I) == 0>(A + (size_t)LO * L.Nbox, off);
+    const real term =
+        wall_row_term<I, real, XB, YB>(L.bc, bx, cx(I) > 0 ? 0 : 1, cy(I) > 0 ? 2 : 3);
+    return bb ? v + term : v;
+  }
+}
+
 // ------------------------------------------------------------- level step
+enum { TILE_PLAIN = 0, TILE_WALLS = 1, TILE_GENERAL = 2 };
+
 // One pull-and-collide step of level L at its step index t over a tile
-// list. GEN: periodic wrap and the domain-face rules (else plain offsets:
-// every source of a tile's active nodes lies in the box without wrapping).
-// INJ: also the fused injection into the parent's covered nodes (the
-// child's second substep of a parent step).
-template <int KIND, typename S, bool GEN, bool INJ>
+// list. KINDT: TILE_PLAIN (every source of the tile's active nodes lies in
+// the box without wrapping, no node on a domain face), TILE_WALLS (as plain
+// but with x or y WALL faces, the wall-row rule) or TILE_GENERAL (periodic
+// wrap and every face rule).
+template <int KIND, typename S, int KINDT>
 __global__ __launch_bounds__(256) void level_step_kernel(const Lev L, const int* tiles,
-                                                         long long t, const InjArgs inj) {
+                                                         long long t) {
   using M = Model<KIND>;
   using real = typename Compute<S>::type;
   constexpr int Q = M::Q;
   int g[3], self = 0;
-  tile_node(tiles, g);
+  tile_node(L, tiles, g);
   bool active = in_box(L, g, self);
   if (active) {
     const uint8_t ty = L.type[self];
     active = ty == RT_FLUID || ty == RT_BAND;
   }
-  if (!INJ && !active) return;
+  if (!active) return;
   const S* A = (const S*)L.a;
   S* B = (S*)L.b;
   const size_t N = (size_t)L.Nbox;
   real f[Q];
   if (active) {
-    if constexpr (GEN) {
+    if constexpr (KINDT == TILE_GENERAL) {
       const BoxNode n = make_box_node(L, g);
       static_for<0, Q>([&](auto ic) {
         constexpr int I = decltype(ic)::value;
@@ -329,6 +362,19 @@ __global__ __launch_bounds__(256) void level_step_kernel(const Lev L, const int*
         });
         if (n.atface & L.bc.pressure) gen_pressure<KIND, real, S>(L, A, n, f);
       }
+    } else if constexpr (KINDT == TILE_WALLS) {
+      const int sy = L.M[0], sz = L.M[0] * L.M[1];
+      uint32_t m = 0;
+      m |= g[0] == 0 ? 1u : 0u;
+      m |= g[0] == L.n[0] - 1 ? 2u : 0u;
+      m |= g[1] == 0 ? 4u : 0u;
+      m |= g[1] == L.n[1] - 1 ? 8u : 0u;
+      m &= L.bc.wall;
+      static_for<0, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const int src = self - cx(I) - cy(I) * sy - cz(I) * sz;
+        f[I] = walls_pull<Q, I, real, S>(L, A, self, src, m);
+      });
     } else {
       const int sy = L.M[0], sz = L.M[0] * L.M[1];
       static_for<0, Q>([&](auto ic) {
@@ -344,47 +390,37 @@ __global__ __launch_bounds__(256) void level_step_kernel(const Lev L, const int*
       sto<true>(B + (size_t)I * N, so, f[I]);
     });
   }
-  if constexpr (INJ) {
-    // children sums: x pairs (lanes 2i, 2i+1), y pairs (lanes +32) by
-    // cross-lane exchange, z pairs (waves w, w+2) through LDS; the stored
-    // (rounded) values are averaged, as a separate pass would read them
-    __shared__ real red[4][Q][16];
-    __shared__ int okz[4][16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int ok = active ? 1 : 0;
-    ok &= __shfl_xor(ok, 1);
-    ok &= __shfl_xor(ok, 32);
-    const bool head = (lane & 33) == 0;  // even x, first y row of the wave
-    static_for<0, Q>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      real v = active ? real(S(f[I])) : real(0);
-      v += __shfl_xor(v, 1);
-      v += __shfl_xor(v, 32);
-      if (head) red[w][I][(lane & 31) >> 1] = v;
-    });
-    if (head) okz[w][(lane & 31) >> 1] = ok;
-    __syncthreads();
-    if (threadIdx.x < 32) {
-      const int k = threadIdx.x & 15, py = threadIdx.x >> 4;
-      const int* tl = tiles + 3 * (size_t)blockIdx.x;
-      const int pg[3] = {(tl[0] >> 1) + k, (tl[1] >> 1) + py, tl[2] >> 1};
-      const int b0 = pg[0] - inj.o[0], b1 = pg[1] - inj.o[1], b2 = pg[2] - inj.o[2];
-      if (okz[py][k] && okz[py + 2][k] && b0 >= 0 && b1 >= 0 && b2 >= 0 && b0 < inj.M[0] &&
-          b1 < inj.M[1] && b2 < inj.M[2]) {
-        const size_t pi = ((size_t)b2 * inj.M[1] + b1) * inj.M[0] + b0;
-        if (inj.type[pi] == RT_COVERED) {
-          real m[Q];
+}
+
+// Covered parent nodes := f_eq + rescaled-back (m - f_eq), m = the mean of
+// the eight children (summed x fastest, then y, then z).
+template <int KIND, typename S>
+__global__ __launch_bounds__(256) void inject_kernel(const InjArgs ia, const RescaleArgs ra) {
+  using R = typename Compute<S>::type;
+  constexpr int Q = Model<KIND>::Q;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ia.n) return;
+  const int pi = ia.nodes[e];
+  const int b0 = pi % ia.pM[0], b1 = (pi / ia.pM[0]) % ia.pM[1], b2 = pi / (ia.pM[0] * ia.pM[1]);
+  const int c0 = 2 * (b0 + ia.po[0]) - ia.co[0], c1 = 2 * (b1 + ia.po[1]) - ia.co[1],
+            c2 = 2 * (b2 + ia.po[2]) - ia.co[2];
+  const S* C = (const S*)ia.src;
+  R m[Q];
 #pragma unroll
-          for (int q = 0; q < Q; ++q) m[q] = real(0.125) * (red[py][q][k] + red[py + 2][q][k]);
-          rescale_node<KIND, -1, real>(m, inj.tau0_c, inj.tau0_f, inj.cs, 1.0 / inj.rinv,
-                                       inj.rates);
-          S* P = (S*)inj.dst;
+  for (int q = 0; q < Q; ++q) m[q] = 0;
 #pragma unroll
-          for (int q = 0; q < Q; ++q) st(P + (size_t)q * (size_t)inj.Nbox + pi, m[q]);
-        }
-      }
-    }
+  for (int c = 0; c < 8; ++c) {
+    const size_t k = ((size_t)(c2 + (c >> 2)) * ia.cM[1] + (c1 + ((c >> 1) & 1))) * ia.cM[0] +
+                     (c0 + (c & 1));
+#pragma unroll
+    for (int q = 0; q < Q; ++q) m[q] += ld<R>(C + (size_t)q * (size_t)ia.cN + k);
   }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) m[q] *= R(0.125);
+  rescale_node<KIND, -1, R>(m, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
+  S* P = (S*)ia.dst;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) st(P + (size_t)q * (size_t)ia.pN + pi, m[q]);
 }
 
 // --------------------------------------------------------- solid pre-pass
@@ -504,37 +540,17 @@ __device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01
   return s;
 }
 
-// Rescaled ghosts of one group: thread gl < ngg takes ghost gl's Q values
-// from sv, rescales them to the child level and writes them to ff.
-template <int KIND, typename S, typename R>
-__device__ __forceinline__ void rescale_group(const GhostArgs& ga, long long gbeg, int ngg,
-                                              R (&sv)[Model<KIND>::Q][kGhostMax],
-                                              const RescaleArgs& ra, S* ff) {
-  constexpr int Q = Model<KIND>::Q;
-  for (int gl = threadIdx.x; gl < ngg; gl += blockDim.x) {
-    R f[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = sv[q][gl];
-    rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
-    const int l = ga.ghosts[gbeg + gl];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
-  }
-}
-
-// Interface update of one ghost group per workgroup: the parent patch of
-// the parent state fp is staged in LDS, every (ghost, population) is
-// interpolated from it into Gn (kept for the following steps), and the
-// ghosts of ff receive rescale(c0 Gm + c1 Gc + c2 Gn) (Gm, Gc not read where
-// their weight is 0).
+// Interface interpolation of one ghost group per workgroup: the parent
+// patch of the parent state fp is staged in LDS, every (ghost, population)
+// is interpolated from it into Gn (kept for the following steps), and H
+// receives the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc not read
+// where their weight is 0), all [Q][ng].
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* fp, R* Gn,
                                                           const R* Gc, const R* Gm, double c0,
-                                                          double c1, double c2,
-                                                          const RescaleArgs ra, S* ff) {
+                                                          double c1, double c2, R* H) {
   constexpr int Q = Model<KIND>::Q;
   __shared__ S sp[Q][kPatchMax];
-  __shared__ R sv[Q][kGhostMax];
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
@@ -568,27 +584,25 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
     R s = R(c2) * v;
     if (c1 != 0.0) s += R(c1) * Gc[kk];
     if (c0 != 0.0) s += R(c0) * Gm[kk];
-    sv[q][gl] = s;
+    H[kk] = s;
   }
-  __syncthreads();
-  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, ra, ff);
 }
 
-// Ghosts of ff := rescale(G) from stored interpolated values, by group.
+// Ghosts of ff := rescale(G), one thread per ghost (G: [Q][ng] values in
+// the ghost list order).
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
                                                             const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  __shared__ R sv[Q][kGhostMax];
-  const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
-  const long long gbeg = grp->gbeg;
-  const int ngg = grp->gend - grp->gbeg;
-  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
-    const int q = k / kGhostMax, gl = k % kGhostMax;
-    if (gl < ngg) sv[q][gl] = G[(size_t)q * ga.ng + gbeg + gl];
-  }
-  __syncthreads();
-  rescale_group<KIND, S, R>(ga, gbeg, ngg, sv, ra, ff);
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= ga.ng) return;
+  R f[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) f[q] = G[(size_t)q * ga.ng + gi];
+  rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
+  const int l = ga.ghosts[gi];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
 }
 
 // ------------------------------------------------------------- reductions

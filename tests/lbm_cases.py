@@ -131,3 +131,27 @@ def refined_jet_geometry(case):
     n = 16 if (levels == 2 and case != "jet2wide") else 24
     r2 = 72.0 if case == "jet2wide" else None
     return n, 32, 4, jet_map(n, 32, 4, levels, r2)
+
+
+def read_covered(types, faces):
+    """Covered nodes (type 3) in the 26-neighbourhood of fluid or band nodes
+    (types 1, 2) of a level's whole domain: the covered nodes a refined
+    step reads, the ones the library injects into. faces: the six face types
+    (periodic axes wrap)."""
+    act = np.isin(types, (1, 2))
+    near = np.zeros_like(act)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                sh = act
+                for ax, d in ((0, dz), (1, dy), (2, dx)):
+                    if d == 0:
+                        continue
+                    per = faces[2 * (2 - ax)] == P
+                    sh = np.roll(sh, d, axis=ax)
+                    if not per:  # no wrap: clear the layer rolled in
+                        idx = [slice(None)] * 3
+                        idx[ax] = 0 if d > 0 else -1
+                        sh[tuple(idx)] = False
+                near |= sh
+    return near & (types == 3)

@@ -3,8 +3,8 @@ C ABI.
 
 FP64 storage: every level element by element to 1e-12 relative (rounding
 order only). FP32 storage: a few units of FP32 rounding per step. Compared
-nodes: fluid and band nodes, and covered nodes whose eight children are
-fluid or band (those the library injects); ghost nodes hold interface values
+nodes: fluid and band nodes, and the covered nodes they read (the library
+injects into those only: no other covered node is read); ghost nodes hold interface values
 prepared ahead for the next substep, so they are left out, but every fluid
 node next to a ghost pulls from it, so a wrong ghost value shows up in the
 fluid nodes one substep later. The node types of every level are compared
@@ -16,7 +16,7 @@ import pytest
 import oracle
 import synth
 from lbm_cases import (MODELS, REFINED_CASES as CASES, REFINED_FACE_U as FACE_U,  # noqa: F401
-                       REFINED_MODELS, jet_map, refined_jet_geometry, rel_err)
+                       REFINED_MODELS, jet_map, read_covered, refined_jet_geometry, rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -81,15 +81,12 @@ def make_pair(name, storage, case, nu=0.02, cs=0.1, solids=None, links=None):
     return g, R
 
 
-def compared(g, R, l):
-    """Box mask of the nodes compared on level l."""
-    t = g.types(l)
-    keep = np.isin(t, (1, 2))
+def compared(g, R, l, faces):
+    """Box mask of the nodes compared on level l: fluid and band nodes and
+    the covered nodes they read."""
+    keep = np.isin(g.types(l), (1, 2))
     if l + 1 < R.L:
-        ok = np.isin(R.types(l + 1), (1, 2))
-        nz, ny, nx = ok.shape
-        kids = ok.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).all(axis=(1, 3, 5))
-        keep |= g.to_box(l, (R.types(l) == 3) & kids).astype(bool)
+        keep |= g.to_box(l, read_covered(R.types(l), faces)).astype(bool)
     return keep
 
 
@@ -105,8 +102,9 @@ def seed_states(g, R, seed):
 
 def level_errors(g, R):
     out = []
+    faces = [int(R.coarse.p.face_type[k]) for k in range(6)]
     for l in range(R.L):
-        keep = compared(g, R, l)
+        keep = compared(g, R, l, faces)
         got = g.populations(l).cpu().numpy()[:, keep]
         want = g.to_box(l, R.state(l))[:, keep]
         out.append(rel_err(got, want))
