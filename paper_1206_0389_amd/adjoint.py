@@ -121,7 +121,9 @@ class InletProbeObjective:
         if self.forward_count == 0:
             raise RuntimeError("backward needs a forward pass first")
         lat = self.lat
-        buf, t, parity = self._ckpt[0]
+        nseg = (self.nsteps + self.every - 1) // self.every
+        # the first checkpoint, or with no step the final (= initial) state
+        buf, t, parity = self._ckpt[0] if nseg > 0 else self._final
         lat.load_state(buf, t, parity)
         lat.set_boundaries(self.faces, face_u=self.face_u, inlet_u=self._fwd_inlet)
         self._inlet = self._fwd_inlet
@@ -134,7 +136,6 @@ class InletProbeObjective:
         grad = torch.zeros_like(self._inlet)
         while len(self._rec) < self.every:
             self._rec.append(torch.empty(shape, dtype=dt, device=lat.device))
-        nseg = (self.nsteps + self.every - 1) // self.every
         for s in reversed(range(nseg)):
             buf, t, parity = self._ckpt[s]
             lat.load_state(buf, t, parity)
