@@ -259,6 +259,21 @@ int lbm_get_macroscopic(lbm_lattice* lat, void* rho, void* u, int dtype,
  * (out is still written). */
 int lbm_reduce(lbm_lattice* lat, double out[5]);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the sums of lbm_reduce written to the caller's DEVICE buffer out[5]
+ * (FP64), stream-ordered on the lattice's stream, no host copy and no
+ * synchronisation; the caller checks finiteness. The partial sums live in a
+ * library-owned static device array (16384 rows of five doubles, about
+ * 640 KiB per device, held until the process ends): z planes fold into the
+ * blocks of one x-y plane, so the summation order differs from lbm_reduce's
+ * (equal up to FP64 rounding). Nothing is allocated. Returns LBM_EINVAL if
+ * an x-y plane needs more than 16384 blocks of 256 nodes
+ * (ceil(nx / bx) * ceil(ny / by), bx = min(nx, 256), by = 256 / bx).
+ * Every call on one device shares the array: calls that overlap on one
+ * device (different streams, threads or lattices) race. */
+int lbm_reduce_static(lbm_lattice* lat, double* out);
+
 /* Time averages of the velocity: the jet statistics of Section 3 (mean
  * velocity; turbulent intensity, Eq. (25)). The caller owns an FP64 device
  * buffer sums of 6 x N values ([6][N]: running sums of u_x, u_y, u_z and of

@@ -83,6 +83,7 @@ _SIGS = {
     "lbm_get_macroscopic": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                             ctypes.c_int],
     "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
+    "lbm_reduce_static": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_links": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
@@ -481,6 +482,21 @@ class Lattice:
 
     def reduce(self, check=True):
         return reduce(self.h, check)[0]
+
+    def reduce_static(self, out):
+        """The sums of reduce() into a device float64 tensor of 5 elements,
+        stream-ordered, with the library's static partial-sum buffer (no
+        allocation, no synchronisation)."""
+        if out.dtype != torch.float64 or out.numel() < 5 or not out.is_cuda \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA float64 tensor of 5 elements")
+        rc = lib().lbm_reduce_static(self.h, ctypes.c_void_p(out.data_ptr()))
+        where = "lbm_reduce_static"
+        if rc == EINVAL:
+            where += " (an x-y plane of %d x %d nodes above the static buffer's 16384 " \
+                     "blocks of 256?)" % (self.nx, self.ny)
+        _check(rc, where)
+        return out
 
     def set_solids(self, solid):
         """Interior solid nodes from a [nz][ny][nx] mask (nonzero = solid;

@@ -1031,23 +1031,27 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const LatArgs a, in
   const int nthreads = blockDim.x * blockDim.y;
   double v[5] = {0, 0, 0, 0, 0};
   int x, y, z;
+  // a block sums the planes z = blockIdx.z + k gridDim.z (one plane when the
+  // grid spans every plane)
   if (node_coords(a, x, y, z)) {
-    const Node n = make_node(a, x, y, z);
-    double f[Q];
-    fetch_natural<Q, S, BC>(a, n, parity, t, f);
-    double d = 0, j[3] = {0, 0, 0};
-    for (int i = 0; i < Q; ++i) {
-      d += f[i];
-      j[0] += cx(i) * f[i];
-      j[1] += cy(i) * f[i];
-      j[2] += cz(i) * f[i];
+    for (; z < a.nz; z += gridDim.z) {
+      const Node n = make_node(a, x, y, z);
+      double f[Q];
+      fetch_natural<Q, S, BC>(a, n, parity, t, f);
+      double d = 0, j[3] = {0, 0, 0};
+      for (int i = 0; i < Q; ++i) {
+        d += f[i];
+        j[0] += cx(i) * f[i];
+        j[1] += cy(i) * f[i];
+        j[2] += cz(i) * f[i];
+      }
+      const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
+      v[0] += d;
+      v[1] += j[0];
+      v[2] += j[1];
+      v[3] += j[2];
+      v[4] += 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / r;
     }
-    const double r = (Model<KIND>::Q == 27) ? 1.0 + d : 1.0;
-    v[0] = d;
-    v[1] = j[0];
-    v[2] = j[1];
-    v[3] = j[2];
-    v[4] = 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / r;
   }
   for (int k = 0; k < 5; ++k) sh[k][tid] = v[k];
   __syncthreads();

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/lbm.h"
@@ -268,6 +269,39 @@ void default_bc(BcArgs& b) {
   std::memset(&b, 0, sizeof(b));
   b.inlet_axis = 2;
   b.ghost_n = 1;
+}
+
+}  // namespace
+
+// Library-owned partial sums for lbm_reduce_static: one row of five per block
+// of an x-y plane of the reduce launch, then the five results. Each device
+// holds its own copy for the life of the process; every call on a device
+// shares it.
+constexpr size_t kStaticPartials = 16384;
+static __device__ __align__(256) double scratch[kStaticPartials * 5 + 8];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The device address of the current device's scratch array, looked up once
+// per device (the array's name in host code is not a device address).
+int static_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return LBM_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
 }
 
 }  // namespace
@@ -700,6 +734,32 @@ int lbm_reduce(lbm_lattice* L, double out[5]) {
   for (int k = 0; k < 5; ++k)
     if (!std::isfinite(out[k])) return LBM_ENONFINITE;
   return LBM_OK;
+}
+
+int lbm_reduce_static(lbm_lattice* L, double* out) {
+  if (!L || !out) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  // fold z planes into the blocks of one plane so the partials fit
+  const size_t plane = (size_t)L->grid.x * L->grid.y;
+  if (plane > kStaticPartials) return LBM_EINVAL;
+  double* partial = nullptr;
+  int rc = static_scratch(&partial);
+  if (rc) return rc;
+  size_t gz = kStaticPartials / plane;
+  if (gz > (size_t)L->grid.z) gz = L->grid.z;
+  const dim3 grid(L->grid.x, L->grid.y, (unsigned)gz);
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), grid, L->block, 0, L->stream,
+                       L->args, L->parity, (long long)L->t, partial);
+  });
+  rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
+                     plane * gz, out);
+  return check_launch();
 }
 
 int lbm_state_bytes(const lbm_lattice* L, size_t* bytes) {
