@@ -38,13 +38,17 @@ struct HostLevel {
   std::vector<int32_t> pre_nodes;           // solid pre-pass list
   std::vector<uint32_t> pre_dirs;
   std::vector<float> pre_q;
+  std::vector<int32_t> gsorted, gperm;      // ghosts in box order, their group positions
+  std::vector<int32_t> unodes;              // parent box indices the ghost stencils read
+  std::vector<int32_t> pidx;                // per group patch: indices into unodes
   // device offsets
   size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
          off_groups = 0, off_G[3] = {0, 0, 0}, off_H = 0, off_pre_nodes = 0, off_pre_dirs = 0,
-         off_pre_q = 0, off_inj = 0;
+         off_pre_q = 0, off_inj = 0, off_unodes = 0, off_pidx = 0, off_pc = 0, off_gperm = 0;
   int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
   bool have_cur = false, have_prev = false;
-  bool ghost_pending = false;  // next-step ghosts queued on the second stream
+  bool ghost_pending = false;  // next-step ghosts queued on the parent's stream
+  bool tail_pending = false;   // injection into this level queued on its stream
   Lev dev;
   double tau0 = 0.5;
 };
@@ -66,13 +70,18 @@ struct lbm_refined {
   char* base = nullptr;
   size_t req = 0, off_partial = 0, off_result = 0, max_rblocks = 1;
   hipStream_t stream = nullptr;
-  // second stream (default priority) for the general tiles of a step and a
-  // child's interface interpolation, joined to the lattice's stream by
-  // events; created at the first step
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_sub1 = nullptr;
-  hipEvent_t ev_ghost[kMaxLevels] = {nullptr};  // a child's next-step ghosts done
-  bool side_tried = false;
+  // One more stream per parent level l (default priority), created at the
+  // first step: level l's step and its child's interface work run there
+  // beside the child's first substep on the lattice's stream, joined by
+  // events (see advance).
+  hipStream_t aux[kMaxLevels] = {nullptr};
+  hipEvent_t ev_fork[kMaxLevels] = {nullptr};   // lattice stream -> aux[l]
+  hipEvent_t ev_done[kMaxLevels] = {nullptr};   // aux[l]: step and interface done
+  hipEvent_t ev_sub1[kMaxLevels] = {nullptr};   // lattice stream: child substep 1 done
+  hipEvent_t ev_sub2[kMaxLevels] = {nullptr};   // lattice stream: child substep 2 done
+  hipEvent_t ev_tail[kMaxLevels] = {nullptr};   // aux[l]: injection into level l done
+  hipEvent_t ev_ghost[kMaxLevels] = {nullptr};  // aux[l-1]: level l's next ghosts done
+  bool aux_tried = false;
   int64_t t = 0;
 };
 
@@ -200,6 +209,46 @@ void group_ghosts(lbm_refined* R, int l) {
     b = e;
   }
   for (size_t gi = 0; gi < it.size(); ++gi) V.ghosts[gi] = it[gi].k;
+  // the rescale visits the ghosts in box order
+  V.gperm.resize(it.size());
+  for (size_t gi = 0; gi < it.size(); ++gi) V.gperm[gi] = (int32_t)gi;
+  std::sort(V.gperm.begin(), V.gperm.end(),
+            [&](int32_t a, int32_t b) { return V.ghosts[a] < V.ghosts[b]; });
+  V.gsorted.resize(it.size());
+  for (size_t t = 0; t < it.size(); ++t) V.gsorted[t] = V.ghosts[V.gperm[t]];
+  // The parent nodes of the stencils (union, in parent box order) and each
+  // group's patch as indices into it (-1: a patch node no stencil reads).
+  const HostLevel& P = R->lev[l - 1];
+  std::vector<int32_t> umap(P.Nbox, -1);
+  for (size_t gi = 0; gi < it.size(); ++gi) {
+    int g[3], idx[3][4], st, cd;
+    box_coords(V, V.ghosts[gi], g);
+    for (int d = 0; d < 3; ++d) child_stencil(R, l - 1, d, g[d], idx[d], st, cd);
+    for (int c = 0; c < 64; ++c) {
+      const int h[3] = {idx[0][c & 3], idx[1][(c >> 2) & 3], idx[2][c >> 4]};
+      const long pb = box_index(P, h);
+      if (pb >= 0) umap[pb] = 0;
+    }
+  }
+  V.unodes.clear();
+  for (size_t k = 0; k < P.Nbox; ++k)
+    if (umap[k] == 0) {
+      umap[k] = (int32_t)V.unodes.size();
+      V.unodes.push_back((int32_t)k);
+    }
+  V.pidx.clear();
+  for (GhostGroup& gr : V.groups) {
+    gr.poff = (int)V.pidx.size();
+    for (int pz = 0; pz < gr.m[2]; ++pz)
+      for (int py = 0; py < gr.m[1]; ++py)
+        for (int px = 0; px < gr.m[0]; ++px) {
+          int h[3] = {gr.lo[0] + px, gr.lo[1] + py, gr.lo[2] + pz};
+          for (int d = 0; d < 3; ++d)
+            if ((P.span >> d) & 1u) h[d] = (h[d] % P.n[d] + P.n[d]) % P.n[d];
+          const long pb = box_index(P, h);
+          V.pidx.push_back(pb >= 0 ? umap[pb] : -1);
+        }
+  }
 }
 
 // log2 of the tile width of a level: the widest power-of-two row run up to
@@ -514,6 +563,7 @@ void layout(lbm_refined* R) {
     V.off_tiles = o; o += align256(V.tiles.size() * 4);
     V.off_ghosts = o; o += align256(ng * 4);
     V.off_gcode = o; o += align256(ng * 4);
+    V.off_gperm = o; o += align256(ng * 4);
     V.off_groups = o; o += align256(V.groups.size() * sizeof(GhostGroup));
     for (int k = 0; k < 3; ++k) {
       V.off_G[k] = o;
@@ -521,6 +571,9 @@ void layout(lbm_refined* R) {
     }
     V.off_H = o; o += align256(ng * R->Q * R->relem);
     V.off_inj = o; o += align256(V.inj.size() * 4);
+    V.off_unodes = o; o += align256(V.unodes.size() * 4);
+    V.off_pidx = o; o += align256(V.pidx.size() * 4);
+    V.off_pc = o; o += align256(V.unodes.size() * R->Q * R->elem);
     V.off_pre_nodes = o; o += align256(V.pre_nodes.size() * 4);
     V.off_pre_dirs = o; o += align256(V.pre_dirs.size() * 4);
     V.off_pre_q = o; o += align256(V.pre_q.size() * 4);
@@ -604,10 +657,14 @@ GhostArgs ghost_args(const lbm_refined* R, int l) {
   const HostLevel& P = R->lev[l - 1];
   GhostArgs g;
   g.ghosts = (const int*)(R->base + V.off_ghosts);
+  g.gperm = (const int*)(R->base + V.off_gperm);
   g.ng = (long long)V.ghosts.size();
   g.gcode = (const int*)(R->base + V.off_gcode);
   g.groups = (const int*)(R->base + V.off_groups);
   g.ngroups = (long long)V.groups.size();
+  g.unodes = (const int*)(R->base + V.off_unodes);
+  g.nu = (long long)V.unodes.size();
+  g.pidx = (const int*)(R->base + V.off_pidx);
   for (int d = 0; d < 3; ++d) {
     g.po[d] = P.o[d];
     g.pM[d] = P.M[d];
@@ -642,8 +699,11 @@ void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, dou
   const GhostArgs ga = ghost_args(R, l);
   void* Gn = R->base + V.off_G[V.gi[init ? 1 : 2]];
   Rt* H = (Rt*)(R->base + V.off_H);
+  S* Pc = (S*)(R->base + V.off_pc);
+  hipLaunchKernelGGL((ghost_gather_kernel<KIND, S>), dim3(blocks_for(ga.nu)), dim3(256), 0,
+                     stream, ga, (const S*)fp, Pc);
   hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
-                     dim3(256), 0, stream, ga, (const S*)fp, (Rt*)Gn,
+                     dim3(256), 0, stream, ga, (const S*)Pc, (Rt*)Gn,
                      (const Rt*)(R->base + V.off_G[V.gi[1]]),
                      (const Rt*)(R->base + V.off_G[V.gi[0]]), c0, c1, c2, H);
   hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
@@ -686,28 +746,21 @@ void inject(lbm_refined* R, int l, hipStream_t stream) {
                      rescale_args(R, l + 1));
 }
 
-// One step of level l: the solid pre-pass, then the tile classes; with a
-// second stream the (few, long-latency) general tiles run there beside the
-// wall and plain tiles, joined before returning.
+// One step of level l on stream st: the solid pre-pass, then the tile
+// classes.
 template <int KIND, typename S>
-void level_step(lbm_refined* R, int l, long long t) {
+void level_step(lbm_refined* R, int l, long long t, hipStream_t st) {
   HostLevel& V = R->lev[l];
   if (V.Nbox == 0) return;
   const Lev& D = V.dev;
-  hipStream_t main = R->stream;
   if (!V.pre_nodes.empty()) {
     constexpr int Q = Model<KIND>::Q;
     hipLaunchKernelGGL((solid_prepass_kernel<Q, S>), dim3(blocks_for((long long)V.pre_nodes.size())),
-                       dim3(256), 0, main, D, (const int*)(R->base + V.off_pre_nodes),
+                       dim3(256), 0, st, D, (const int*)(R->base + V.off_pre_nodes),
                        (const uint32_t*)(R->base + V.off_pre_dirs),
                        (const float*)(R->base + V.off_pre_q), (long long)V.pre_nodes.size());
   }
   const int* tiles = (const int*)(R->base + V.off_tiles);
-  const bool split = R->side != nullptr && V.nt[0] > 0 && V.nt[1] + V.nt[2] > 0;
-  if (split) {
-    (void)hipEventRecord(R->ev_fork, main);
-    (void)hipStreamWaitEvent(R->side, R->ev_fork, 0);
-  }
   size_t start = 0;
   for (int k = 0; k < 3; ++k) {
     const size_t n = V.nt[k];
@@ -716,83 +769,119 @@ void level_step(lbm_refined* R, int l, long long t) {
     if (n == 0) continue;
     const dim3 grid((unsigned)n), block(256);
     if (k == 0)
-      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_GENERAL>), grid, block, 0,
-                         split ? R->side : main, D, tl, t);
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_GENERAL>), grid, block, 0, st, D, tl, t);
     else if (k == 1)
-      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_WALLS>), grid, block, 0, main, D, tl, t);
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_WALLS>), grid, block, 0, st, D, tl, t);
     else
-      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_PLAIN>), grid, block, 0, main, D, tl, t);
-  }
-  if (split) {
-    (void)hipEventRecord(R->ev_join, R->side);
-    (void)hipStreamWaitEvent(main, R->ev_join, 0);
+      hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_PLAIN>), grid, block, 0, st, D, tl, t);
   }
 }
 
 void swap_arrays(HostLevel& V) { std::swap(V.dev.a, V.dev.b); }
 
 // Advance level l by one of its steps (index t), and recursively the finer
-// levels by two steps each. With a second stream the child's interface
-// interpolation (latency-bound) runs there beside the child's first
-// substep, which reads only ghosts prepared in the previous step (ghost
-// slots are written only by the interface kernels, fluid slots only by the
-// steps); the main stream waits for it before the second substep.
+// levels by two steps each, on the lattice's stream M. The child's first
+// substep reads only ghosts prepared from the parent's state before this
+// step, so with the parent's own stream X = aux[l] the parent's work runs
+// there beside the child's substeps:
+//   X: parent step, interpolation of the ghosts for substep 2;
+//   M: substep 1;
+//   X: after substep 1, the ghosts of the next first substep (slots that
+//      substep 1 read and substep 2 does not touch);
+//   M: after the interpolation, substep 2;
+//   X: after substep 2, injection into the parent (beside the next first
+//      substep on M, which does not read the parent).
+// Ghost slots are written only by the interface kernels, fluid slots only
+// by the steps, covered slots only by the injection.
 template <int KIND, typename S>
 void advance(lbm_refined* R, int l, long long t) {
   HostLevel& V = R->lev[l];
+  hipStream_t M = R->stream;
   const bool child = l + 1 < R->L && R->lev[l + 1].Nbox > 0;
-  if (child && !R->lev[l + 1].have_cur) {
-    HostLevel& C = R->lev[l + 1];
-    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true, R->stream);
+  if (!child) {
+    level_step<KIND, S>(R, l, t, M);
+    swap_arrays(V);
+    return;
+  }
+  HostLevel& C = R->lev[l + 1];
+  if (!C.have_cur) {
+    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true, M);
     C.have_cur = true;
     C.have_prev = false;
   }
-  level_step<KIND, S>(R, l, t);
-  if (child) {
-    HostLevel& C = R->lev[l + 1];
-    const double c0 = C.have_prev ? -0.125 : 0.0, c1 = C.have_prev ? 0.75 : 0.5,
-                 c2 = C.have_prev ? 0.375 : 0.5;
-    hipStream_t side = R->side ? R->side : R->stream;
-    if (R->side) {
-      (void)hipEventRecord(R->ev_fork, R->stream);
-      (void)hipStreamWaitEvent(side, R->ev_fork, 0);
-    }
-    ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false, side);
-    if (R->side) (void)hipEventRecord(R->ev_sub1, side);
-    if (C.ghost_pending) {  // the first substep reads the ghosts of the last step
-      (void)hipStreamWaitEvent(R->stream, R->ev_ghost[l + 1], 0);
-      C.ghost_pending = false;
-    }
-    advance<KIND, S>(R, l + 1, 2 * t);
-    if (R->side) (void)hipStreamWaitEvent(R->stream, R->ev_sub1, 0);
-    advance<KIND, S>(R, l + 1, 2 * t + 1);
-    inject<KIND, S>(R, l, R->stream);
-    if (R->side) {
-      // the next step's first-substep ghosts, beside the following work
-      (void)hipEventRecord(R->ev_fork, R->stream);
-      (void)hipStreamWaitEvent(side, R->ev_fork, 0);
-      ghost_rescale<KIND, S>(R, l + 1, C.dev.a, side);
-      (void)hipEventRecord(R->ev_ghost[l + 1], side);
-      C.ghost_pending = true;
-    } else {
-      ghost_rescale<KIND, S>(R, l + 1, C.dev.a, R->stream);
-    }
-    const int old = C.gi[0];
-    C.gi[0] = C.gi[1];
-    C.gi[1] = C.gi[2];
-    C.gi[2] = old;
-    C.have_prev = true;
+  hipStream_t X = R->aux[l] ? R->aux[l] : M;
+  const bool two = X != M;
+  auto to = [&](hipStream_t from, hipStream_t dst, hipEvent_t e) {
+    if (!two) return;
+    (void)hipEventRecord(e, from);
+    (void)hipStreamWaitEvent(dst, e, 0);
+  };
+  to(M, X, R->ev_fork[l]);
+  level_step<KIND, S>(R, l, t, X);
+  const double c0 = C.have_prev ? -0.125 : 0.0, c1 = C.have_prev ? 0.75 : 0.5,
+               c2 = C.have_prev ? 0.375 : 0.5;
+  ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false, X);
+  if (two) (void)hipEventRecord(R->ev_done[l], X);
+  if (C.ghost_pending) {  // the first substep reads the ghosts of the last step
+    (void)hipStreamWaitEvent(M, R->ev_ghost[l + 1], 0);
+    C.ghost_pending = false;
   }
+  advance<KIND, S>(R, l + 1, 2 * t);
+  to(M, X, R->ev_sub1[l]);
+  ghost_rescale<KIND, S>(R, l + 1, C.dev.b, X);  // C's arrays swapped once since substep 1
+  if (two) {
+    (void)hipEventRecord(R->ev_ghost[l + 1], X);
+    C.ghost_pending = true;
+    (void)hipStreamWaitEvent(M, R->ev_done[l], 0);
+  }
+  advance<KIND, S>(R, l + 1, 2 * t + 1);
+  to(M, X, R->ev_sub2[l]);
+  inject<KIND, S>(R, l, X);
+  if (two) {
+    (void)hipEventRecord(R->ev_tail[l], X);
+    V.tail_pending = true;
+  }
+  const int old = C.gi[0];
+  C.gi[0] = C.gi[1];
+  C.gi[1] = C.gi[2];
+  C.gi[2] = old;
+  C.have_prev = true;
   swap_arrays(V);
 }
 
-bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
-
-bool create_level_events(lbm_refined* R) {
-  for (int l = 0; l < R->L; ++l)
-    if (hipEventCreateWithFlags(&R->ev_ghost[l], hipEventDisableTiming) != hipSuccess) return false;
-  return true;
+void destroy_streams(lbm_refined* R) {
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (R->aux[l]) {
+      (void)hipStreamSynchronize(R->aux[l]);
+      (void)hipStreamDestroy(R->aux[l]);
+    }
+    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub1[l], &R->ev_sub2[l],
+                          &R->ev_tail[l], &R->ev_ghost[l]})
+      if (*e) (void)hipEventDestroy(*e);
+    R->aux[l] = nullptr;
+    R->ev_fork[l] = R->ev_done[l] = R->ev_sub1[l] = R->ev_sub2[l] = R->ev_tail[l] =
+        R->ev_ghost[l] = nullptr;
+  }
 }
+
+// The parent levels' streams and events; without them every kernel runs in
+// order on the lattice's stream.
+void create_streams(lbm_refined* R) {
+  bool ok = true;
+  for (int l = 0; l < R->L && ok; ++l) {
+    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub1[l], &R->ev_sub2[l],
+                          &R->ev_tail[l], &R->ev_ghost[l]})
+      ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (l + 1 < R->L)
+      ok = ok && hipStreamCreateWithFlags(&R->aux[l], hipStreamNonBlocking) == hipSuccess;
+  }
+  if (!ok) {
+    destroy_streams(R);
+    (void)hipGetLastError();
+  }
+}
+
+bool valid_dtype(int d) { return d == LBM_DTYPE_F64 || d == LBM_DTYPE_F32; }
 
 // A LatArgs view of one level's current state box (the uniform lattice's
 // init/set/get/macroscopic kernels, parity 0, no boundary pulls).
@@ -947,13 +1036,16 @@ int lbm_refined_bind_memory(lbm_refined* R, void* dev, size_t bytes) {
     HostLevel& V = R->lev[l];
     int rc = upload(R, V.off_type, V.type.data(), V.Nbox);
     if (!rc) rc = upload(R, V.off_tiles, V.tiles.data(), V.tiles.size() * 4);
-    if (!rc) rc = upload(R, V.off_ghosts, V.ghosts.data(), V.ghosts.size() * 4);
+    if (!rc) rc = upload(R, V.off_ghosts, V.gsorted.data(), V.gsorted.size() * 4);
+    if (!rc) rc = upload(R, V.off_gperm, V.gperm.data(), V.gperm.size() * 4);
     if (!rc) rc = upload(R, V.off_gcode, V.gcode.data(), V.gcode.size() * 4);
     if (!rc) rc = upload(R, V.off_groups, V.groups.data(), V.groups.size() * sizeof(GhostGroup));
     if (!rc) rc = upload(R, V.off_pre_nodes, V.pre_nodes.data(), V.pre_nodes.size() * 4);
     if (!rc) rc = upload(R, V.off_pre_dirs, V.pre_dirs.data(), V.pre_dirs.size() * 4);
     if (!rc) rc = upload(R, V.off_pre_q, V.pre_q.data(), V.pre_q.size() * 4);
     if (!rc) rc = upload(R, V.off_inj, V.inj.data(), V.inj.size() * 4);
+    if (!rc) rc = upload(R, V.off_unodes, V.unodes.data(), V.unodes.size() * 4);
+    if (!rc) rc = upload(R, V.off_pidx, V.pidx.data(), V.pidx.size() * 4);
     if (rc) {
       R->base = nullptr;
       return rc;
@@ -1177,25 +1269,9 @@ int lbm_refined_get_macroscopic(lbm_refined* R, int level, void* rho, void* u, i
 int lbm_refined_step(lbm_refined* R, int64_t n) {
   if (!R || n < 0) return LBM_EINVAL;
   if (!R->base) return LBM_EUNBOUND;
-  if (!R->side_tried && R->L > 1) {
-    // without the second stream every kernel simply runs in order
-    R->side_tried = true;
-    if (hipStreamCreateWithFlags(&R->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&R->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&R->ev_join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&R->ev_sub1, hipEventDisableTiming) != hipSuccess ||
-        !create_level_events(R)) {
-      if (R->side) (void)hipStreamDestroy(R->side);
-      if (R->ev_fork) (void)hipEventDestroy(R->ev_fork);
-      if (R->ev_join) (void)hipEventDestroy(R->ev_join);
-      if (R->ev_sub1) (void)hipEventDestroy(R->ev_sub1);
-      for (int l = 0; l < kMaxLevels; ++l)
-        if (R->ev_ghost[l]) (void)hipEventDestroy(R->ev_ghost[l]);
-      R->side = nullptr;
-      R->ev_fork = R->ev_join = R->ev_sub1 = nullptr;
-      for (int l = 0; l < kMaxLevels; ++l) R->ev_ghost[l] = nullptr;
-      (void)hipGetLastError();
-    }
+  if (!R->aux_tried && R->L > 1) {
+    R->aux_tried = true;
+    create_streams(R);
   }
   for (int64_t k = 0; k < n; ++k) {
     with_kind_s(R, [&](auto kc, auto st_) {
@@ -1203,12 +1279,18 @@ int lbm_refined_step(lbm_refined* R, int64_t n) {
     });
     R->t += 1;
   }
-  // callers see single-stream semantics: join the pending ghost work
-  for (int l = 0; l < R->L; ++l)
+  // callers see single-stream semantics: join the work still queued on the
+  // parent levels' streams
+  for (int l = 0; l < R->L; ++l) {
     if (R->lev[l].ghost_pending) {
       (void)hipStreamWaitEvent(R->stream, R->ev_ghost[l], 0);
       R->lev[l].ghost_pending = false;
     }
+    if (R->lev[l].tail_pending) {
+      (void)hipStreamWaitEvent(R->stream, R->ev_tail[l], 0);
+      R->lev[l].tail_pending = false;
+    }
+  }
   return check_launch();
 }
 
@@ -1261,17 +1343,7 @@ int lbm_refined_set_stream(lbm_refined* R, void* stream) {
 }
 
 int lbm_refined_destroy(lbm_refined* R) {
-  if (R) {
-    if (R->side) {
-      (void)hipStreamSynchronize(R->side);
-      (void)hipStreamDestroy(R->side);
-    }
-    if (R->ev_fork) (void)hipEventDestroy(R->ev_fork);
-    if (R->ev_join) (void)hipEventDestroy(R->ev_join);
-    if (R->ev_sub1) (void)hipEventDestroy(R->ev_sub1);
-    for (int l = 0; l < kMaxLevels; ++l)
-      if (R->ev_ghost[l]) (void)hipEventDestroy(R->ev_ghost[l]);
-  }
+  if (R) destroy_streams(R);
   delete R;
   return LBM_OK;
 }

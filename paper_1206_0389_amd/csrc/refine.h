@@ -468,11 +468,15 @@ __global__ __launch_bounds__(256) void solid_prepass_kernel(const Lev L, const i
 
 // ------------------------------------------------------------- interface
 struct GhostArgs {
-  const int* ghosts;  // child box indices of the ghost nodes
+  const int* ghosts;  // child box indices of the ghost nodes, ascending
+  const int* gperm;   // position of each of them in the group order
   long long ng;
   const int* groups;  // GhostGroup records
   const int* gcode;   // per ghost: stencil start and code per axis
   long long ngroups;
+  const int* unodes;  // parent box indices read by the stencils (nu)
+  long long nu;
+  const int* pidx;    // per group patch node: index into unodes, or -1
   // parent box
   int po[3], pM[3], pn[3];
   uint32_t pspan;
@@ -482,7 +486,9 @@ struct GhostArgs {
 // Ghosts are grouped by the parent cube of kGhostCube^3 nodes holding their
 // stencil starts (at most kGhostMax per group); a group's stencils read the
 // parent patch [lo, lo + m) (level coordinates, wrapped on spanned periodic
-// axes; m <= kGhostCube + 3 per axis), staged in LDS by one workgroup. A
+// axes; m <= kGhostCube + 3 per axis), staged in LDS by one workgroup from
+// a compact node-major copy of the parent nodes the stencils read (patch
+// node p of a group: entry pidx[poff + p] of that copy, x fastest). A
 // ghost's code holds per axis d, in bits 6d..6d+5, the stencil start
 // relative to lo (3 bits) and the stencil code c (3 bits): the child lies at
 // t = (2c - 1)/4 of the window s..s+3.
@@ -493,6 +499,7 @@ constexpr int kPatchMax = kPatchEdge * kPatchEdge * kPatchEdge;
 struct GhostGroup {
   int gbeg, gend;
   int lo[3], m[3];
+  int poff;
 };
 
 // Cubic Lagrange weights (dyadic, exact) at t = (2c - 1)/4, c = 0..7, on
@@ -540,13 +547,30 @@ __device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01
   return s;
 }
 
+// The parent nodes the stencils read, node-major: Pc[u][q] = fp[q][unodes[u]]
+// (rows of the parent box read once, where the group patches overlap and
+// cover only part of each memory line).
+template <int KIND, typename S>
+__global__ __launch_bounds__(256) void ghost_gather_kernel(const GhostArgs ga, const S* fp,
+                                                           S* Pc) {
+  constexpr int Q = Model<KIND>::Q;
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= ga.nu) return;
+  const size_t k = (size_t)ga.unodes[u];
+  S v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = fp[(size_t)q * (size_t)ga.pN + k];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) Pc[(size_t)u * Q + q] = v[q];
+}
+
 // Interface interpolation of one ghost group per workgroup: the parent
-// patch of the parent state fp is staged in LDS, every (ghost, population)
-// is interpolated from it into Gn (kept for the following steps), and H
-// receives the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc not read
-// where their weight is 0), all [Q][ng].
+// patch is staged in LDS from the gathered copy Pc, every (ghost,
+// population) is interpolated from it into Gn (kept for the following
+// steps), and H receives the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc
+// not read where their weight is 0), all [Q][ng].
 template <int KIND, typename S, typename R>
-__global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* fp, R* Gn,
+__global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* Pc, R* Gn,
                                                           const R* Gc, const R* Gm, double c0,
                                                           double c1, double c2, R* H) {
   constexpr int Q = Model<KIND>::Q;
@@ -554,53 +578,61 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
-  const int lo[3] = {grp->lo[0], grp->lo[1], grp->lo[2]};
   const int m0 = grp->m[0], m1 = grp->m[1], m01 = m0 * m1;
   const int P = m01 * grp->m[2];
-  for (int p = threadIdx.x; p < P; p += blockDim.x) {
-    const int pz = p / m01, rem = p - pz * m01, py = rem / m0, px = rem - py * m0;
-    const int g3[3] = {lo[0] + px, lo[1] + py, lo[2] + pz};
-    int c[3];
+  const int* pidx = ga.pidx + grp->poff;
+  // this thread's (population, ghost) items: k = threadIdx.x + 256 it, their
+  // history values loaded ahead of the staging so the latencies overlap
+  constexpr int kItems = (Q * kGhostMax + 255) / 256;
+  R hist[kItems];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int v = g3[d];
-      if ((ga.pspan >> d) & 1u) v = v < 0 ? v + ga.pn[d] : (v >= ga.pn[d] ? v - ga.pn[d] : v);
-      c[d] = v - ga.po[d];
+  for (int it = 0; it < kItems; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    const int q = k / kGhostMax, gl = k % kGhostMax;
+    hist[it] = R(0);
+    if (k < Q * kGhostMax && gl < ngg) {
+      const size_t kk = (size_t)q * ga.ng + gbeg + gl;
+      if (c1 != 0.0) hist[it] = R(c1) * Gc[kk];
+      if (c0 != 0.0) hist[it] += R(c0) * Gm[kk];
     }
-    const size_t idx = ((size_t)c[2] * ga.pM[1] + c[1]) * ga.pM[0] + c[0];
+  }
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const int u = pidx[p];
+    const S* src = Pc + (size_t)(u < 0 ? 0 : u) * Q;
     static_for<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      sp[I][p] = fp[(size_t)I * (size_t)ga.pN + idx];
+      sp[I][p] = u < 0 ? S(0) : src[I];
     });
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < Q * kGhostMax; k += blockDim.x) {
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int k = threadIdx.x + 256 * it;
     const int q = k / kGhostMax, gl = k % kGhostMax;
-    if (gl >= ngg) continue;
+    if (k >= Q * kGhostMax || gl >= ngg) continue;
     const long long gi = gbeg + gl;
     const R v = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
     const size_t kk = (size_t)q * ga.ng + gi;
     Gn[kk] = v;
-    R s = R(c2) * v;
-    if (c1 != 0.0) s += R(c1) * Gc[kk];
-    if (c0 != 0.0) s += R(c0) * Gm[kk];
-    H[kk] = s;
+    H[kk] = R(c2) * v + hist[it];
   }
 }
 
-// Ghosts of ff := rescale(G), one thread per ghost (G: [Q][ng] values in
-// the ghost list order).
+// Ghosts of ff := rescale(G), one thread per ghost in box order (runs of
+// neighbouring slots per store); G: [Q][ng] in the group order, ghost t at
+// position gperm[t].
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
                                                             const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ga.ng) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ga.ng) return;
+  const long long gi = ga.gperm[t];
   R f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = G[(size_t)q * ga.ng + gi];
   rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
-  const int l = ga.ghosts[gi];
+  const int l = ga.ghosts[t];
 #pragma unroll
   for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
 }
