@@ -434,7 +434,7 @@ def main():
                      "jet256-mrt-f16",
                      "jet256-mrt-f64", "tgv256-fclb-f32", "tgv256-mrt-f32", "tgv256-mrt-f16",
                      "tgv256-mrt-f64", "tgv128-fclb-f32", "tgv128-mrt-f32", "ref128-fclb-f32",
-                     "ref128-mrt-f32", "ref3l128-fclb-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:
+                     "ref128-fclb-f16", "ref128-mrt-f32", "ref128-mrt-f16", "ref3l128-fclb-f32", "nozzle256-fclb-f32", "nozzlecurved256-fclb-f32"]:
             if name == args.workload:
                 continue
             r = measure(name, P, torch, synth, args.other_steps, 10)
@@ -446,15 +446,21 @@ def main():
         print("bench: adjoint gradient %.2f s (f32)" % adjoint[0]["gradient_s"], flush=True)
     stats = measure_stats(P, torch, synth) if not args.no_others else None
     copy_gbs = copy_bandwidth(P, torch)
-    model, storage, shape, _ = workload(args.workload)
-    alg_per_launch = main_res["bytes_per_lup"] * shape[0] * shape[1] * shape[2]
+    model, storage, shape, kind = workload(args.workload)
+    refined = kind.startswith("ref")
+    # a refined coarse step is a sequence of launches on several streams: its
+    # algorithmic bytes are those of every node update of the step
+    alg_per_launch = main_res["bytes_per_lup"] * (
+        main_res["config"]["updates_per_level0_step"] if refined else
+        shape[0] * shape[1] * shape[2])
     roof = {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": main_res["achieved_GBs"] / HBM_PEAK_GBS,
             "traffic": (MEASURED_TRAFFIC["bytes_per_step"]
                         if (MEASURED_TRAFFIC["sources_sha256_16"] == sources_hash()
                             and MEASURED_TRAFFIC["workload"] == args.workload) else None),
             "traffic_unit": "bytes per step (one even launch, or the two odd launches)",
-            "kernel": "step_kernel<%s,%s>" % (model, storage),
+            "kernel": ("refined coarse step (level steps and interface kernels) <%s,%s>"
+                       if refined else "step_kernel<%s,%s>") % (model, storage),
             "algorithmic_bytes_per_launch": alg_per_launch,
             "copy_probe_GBs": copy_gbs,
             "frac_of_copy_probe": main_res["achieved_GBs"] / copy_gbs}

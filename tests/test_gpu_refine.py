@@ -177,6 +177,20 @@ def test_refined_fp32_within_tolerance(name, case):
     assert max(errs) <= 1e-5, errs
 
 
+@pytest.mark.parametrize("name", ["fclb", "mrt_table1"])
+@pytest.mark.parametrize("case", ["jet2", "jet3"])
+def test_refined_fp16_within_tolerance(name, case):
+    """FP16 storage of the deviations (FP32 arithmetic, FP32 interface
+    buffers): each stored value carries 2^-11 relative rounding, a few units
+    of it per step against the largest deviation."""
+    g, R = make_pair(name, "f16", case)
+    seed_states(g, R, 3)
+    g.step(2)
+    R.run(4, 2)
+    errs = level_errors(g, R)
+    assert max(errs) <= 3e-3, errs
+
+
 @pytest.mark.parametrize("name", REFINED_MODELS)
 @pytest.mark.parametrize("levels", [2, 3])
 def test_refined_uniform_flow_and_readouts(name, levels):
