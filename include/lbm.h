@@ -49,6 +49,7 @@ extern "C" {
 #define LBM_EHIP (-4)        /* a HIP call or launch failed               */
 #define LBM_ENONFINITE (-5)  /* a global sum is NaN or infinite           */
 #define LBM_ESTATE (-6)      /* call not valid in the lattice's state     */
+#define LBM_EMASS (-7)       /* mass drift beyond the lbm_set_check bound */
 
 /* ---- enumerations ----------------------------------------------------- */
 #define LBM_D3Q19_MRT_LES 1  /* Eq. (12) + Eqs. (16)-(21), incompressible */
@@ -243,7 +244,9 @@ int lbm_set_solids(lbm_lattice* lat, const uint8_t* solid, uint32_t* masks);
  * solids set), LBM_EUNBOUND, LBM_ESTATE (odd in-place parity). */
 int lbm_set_links(lbm_lattice* lat, const int32_t* nodes, const float* q, int64_t n);
 
-/* Advance n >= 0 collide-and-stream steps (asynchronous). */
+/* Advance n >= 0 collide-and-stream steps (asynchronous, except for the
+ * checks that lbm_set_check asks for, which block and may stop the steps
+ * early with LBM_ENONFINITE or LBM_EMASS). */
 int lbm_step(lbm_lattice* lat, int64_t n);
 
 /* rho (device, N) and u (device, [3][N]) of the current state: MRT
@@ -258,6 +261,22 @@ int lbm_get_macroscopic(lbm_lattice* lat, void* rho, void* u, int dtype,
  * (rho = 1 for MRT). Returns LBM_ENONFINITE if any sum is not finite
  * (out is still written). */
 int lbm_reduce(lbm_lattice* lat, double out[5]);
+
+/* Health check inside lbm_step (the global conservation of Section 2's
+ * collisions: mass is a collision invariant, so on a closed or periodic
+ * lattice the mass deviation changes only by rounding). With every > 0,
+ * after each step whose new step count is a multiple of `every`, lbm_step
+ * runs the FP64 sums of lbm_reduce (one extra read of the populations,
+ * blocking) and stops, returning LBM_ENONFINITE if a sum is not finite, or
+ * LBM_EMASS if mass_tol >= 0 and |sum(rho - 1) - M0| > mass_tol, M0 being
+ * the sum when the check was set (every > 0 checks the current state at
+ * once, blocking). The steps before
+ * the failing check stand (lbm_get_time tells how many ran). mass_tol < 0
+ * checks finiteness only (open boundaries change the mass); every = 0 turns
+ * the check off. Errors: LBM_EINVAL (every < 0, NaN mass_tol), LBM_EUNBOUND,
+ * LBM_ENONFINITE if the current state already has a non-finite sum (the
+ * check stays off). */
+int lbm_set_check(lbm_lattice* lat, int64_t every, double mass_tol);
 
 /* For callers that cannot allocate device memory or synchronise (code under
  * stream capture, tight serving loops, harnesses that forbid allocation):

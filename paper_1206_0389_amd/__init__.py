@@ -19,7 +19,7 @@ import torch  # loads the HIP runtime the library binds to
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-OK, EINVAL, ENOMEM, EUNBOUND, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EUNBOUND, EHIP, ENONFINITE, ESTATE, EMASS = 0, -1, -2, -3, -4, -5, -6, -7
 D3Q19_MRT_LES, D3Q27_FCLB, D3Q27_CLB = 1, 2, 3
 F64, F32, F16 = 1, 2, 3
 DTYPE_F64, DTYPE_F32 = 1, 2
@@ -84,6 +84,7 @@ _SIGS = {
                             ctypes.c_int],
     "lbm_reduce": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)],
     "lbm_reduce_static": [ctypes.c_void_p, ctypes.c_void_p],
+    "lbm_set_check": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double],
     "lbm_stats_accumulate": [ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_solids": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lbm_set_links": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
@@ -482,6 +483,13 @@ class Lattice:
 
     def reduce(self, check=True):
         return reduce(self.h, check)[0]
+
+    def set_check(self, every, mass_tol=-1.0):
+        """After every `every`-th step, step() checks the FP64 sums: a
+        non-finite sum raises LbmError (status ENONFINITE), and with
+        mass_tol >= 0 a mass deviation drifted by more than mass_tol from
+        its value now raises LbmError (status EMASS). every = 0: off."""
+        _check(lib().lbm_set_check(self.h, int(every), float(mass_tol)), "lbm_set_check")
 
     def reduce_static(self, out):
         """The sums of reduce() into a device float64 tensor of 5 elements,

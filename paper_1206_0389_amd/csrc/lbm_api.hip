@@ -45,6 +45,9 @@ struct lbm_lattice {
   bool split_odd = false;
   Rows rows_all, rows_inner, rows_bnd;
   dim3 grid_inner, grid_bnd, block_bnd;
+  // health check inside lbm_step (lbm_set_check)
+  int64_t check_every = 0;
+  double check_tol = -1.0, check_m0 = 0.0;
 };
 
 namespace {
@@ -271,6 +274,43 @@ void default_bc(BcArgs& b) {
   b.ghost_n = 1;
 }
 
+// FP64 sums of the current state (lbm_reduce's definition), blocking.
+int reduce_now(lbm_lattice* L, double out[5]) {
+  double* partial = (double*)(L->base + L->off_partial);
+  double* result = (double*)(L->base + L->off_result);
+  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+    constexpr int KIND = decltype(kind_c)::value;
+    using S = typename decltype(s_tag)::type;
+    constexpr bool BC = decltype(bc_c)::value;
+    hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
+                       L->args, L->parity, (long long)L->t, partial);
+  });
+  int rc = check_launch();
+  if (rc) return rc;
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
+                     L->nblocks, result);
+  rc = check_launch();
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(out, result, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                                L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e);
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(out[k])) return LBM_ENONFINITE;
+  return LBM_OK;
+}
+
+// The check of lbm_set_check after a step.
+int run_check(lbm_lattice* L) {
+  double out[5];
+  const int rc = reduce_now(L, out);
+  if (rc) return rc;
+  if (L->check_tol >= 0.0 && std::fabs(out[0] - L->check_m0) > L->check_tol)
+    return LBM_EMASS;
+  return LBM_OK;
+}
+
 }  // namespace
 
 // Library-owned partial sums for lbm_reduce_static: one row of five per block
@@ -317,6 +357,7 @@ const char* lbm_strerror(int status) {
     case LBM_EHIP: return g_hip_msg.empty() ? "HIP error" : g_hip_msg.c_str();
     case LBM_ENONFINITE: return "non-finite global sum";
     case LBM_ESTATE: return "call not valid in the current lattice state";
+    case LBM_EMASS: return "mass deviation drifted beyond the check tolerance";
     default: return "unknown status";
   }
 }
@@ -549,6 +590,10 @@ int lbm_step(lbm_lattice* L, int64_t n) {
     if (L->nlinks > 0) links_dispatch(L, L->parity == 1);
     L->t += 1;
     L->parity ^= 1;
+    if (L->check_every > 0 && L->t % L->check_every == 0) {
+      const int rc = run_check(L);
+      if (rc) return rc;
+    }
   }
   return check_launch();
 }
@@ -711,28 +756,24 @@ int lbm_jet_fit(const lbm_lattice* L, const double* um, const double* re, const 
 int lbm_reduce(lbm_lattice* L, double out[5]) {
   if (!L || !out) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;
-  double* partial = (double*)(L->base + L->off_partial);
-  double* result = (double*)(L->base + L->off_result);
-  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
-    constexpr int KIND = decltype(kind_c)::value;
-    using S = typename decltype(s_tag)::type;
-    constexpr bool BC = decltype(bc_c)::value;
-    hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
-                       L->args, L->parity, (long long)L->t, partial);
-  });
-  int rc = check_launch();
-  if (rc) return rc;
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
-                     L->nblocks, result);
-  rc = check_launch();
-  if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(out, result, 5 * sizeof(double), hipMemcpyDeviceToHost,
-                                L->stream);
-  if (e != hipSuccess) return hip_fail(e);
-  e = hipStreamSynchronize(L->stream);
-  if (e != hipSuccess) return hip_fail(e);
-  for (int k = 0; k < 5; ++k)
-    if (!std::isfinite(out[k])) return LBM_ENONFINITE;
+  return reduce_now(L, out);
+}
+
+int lbm_set_check(lbm_lattice* L, int64_t every, double mass_tol) {
+  if (!L || every < 0 || std::isnan(mass_tol)) return LBM_EINVAL;
+  if (!L->base) return LBM_EUNBOUND;
+  L->check_every = every;
+  L->check_tol = mass_tol;
+  L->check_m0 = 0.0;
+  if (every > 0) {  // the current state is checked at once
+    double out[5];
+    const int rc = reduce_now(L, out);
+    if (rc) {
+      L->check_every = 0;
+      return rc;
+    }
+    L->check_m0 = out[0];
+  }
   return LBM_OK;
 }
 
