@@ -38,13 +38,12 @@ struct HostLevel {
   std::vector<int32_t> pre_nodes;           // solid pre-pass list
   std::vector<uint32_t> pre_dirs;
   std::vector<float> pre_q;
-  std::vector<int32_t> gsorted, gperm;      // ghosts in box order, their group positions
   std::vector<int32_t> unodes;              // parent box indices the ghost stencils read
   std::vector<int32_t> pidx;                // per group patch: indices into unodes
   // device offsets
   size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
          off_groups = 0, off_G[3] = {0, 0, 0}, off_H = 0, off_pre_nodes = 0, off_pre_dirs = 0,
-         off_pre_q = 0, off_inj = 0, off_unodes = 0, off_pidx = 0, off_pc = 0, off_gperm = 0;
+         off_pre_q = 0, off_inj = 0, off_unodes = 0, off_pidx = 0, off_pc = 0;
   int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
   bool have_cur = false, have_prev = false;
   bool ghost_pending = false;  // next-step ghosts queued on the parent's stream
@@ -209,13 +208,6 @@ void group_ghosts(lbm_refined* R, int l) {
     b = e;
   }
   for (size_t gi = 0; gi < it.size(); ++gi) V.ghosts[gi] = it[gi].k;
-  // the rescale visits the ghosts in box order
-  V.gperm.resize(it.size());
-  for (size_t gi = 0; gi < it.size(); ++gi) V.gperm[gi] = (int32_t)gi;
-  std::sort(V.gperm.begin(), V.gperm.end(),
-            [&](int32_t a, int32_t b) { return V.ghosts[a] < V.ghosts[b]; });
-  V.gsorted.resize(it.size());
-  for (size_t t = 0; t < it.size(); ++t) V.gsorted[t] = V.ghosts[V.gperm[t]];
   // The parent nodes of the stencils (union, in parent box order) and each
   // group's patch as indices into it (-1: a patch node no stencil reads).
   const HostLevel& P = R->lev[l - 1];
@@ -563,7 +555,6 @@ void layout(lbm_refined* R) {
     V.off_tiles = o; o += align256(V.tiles.size() * 4);
     V.off_ghosts = o; o += align256(ng * 4);
     V.off_gcode = o; o += align256(ng * 4);
-    V.off_gperm = o; o += align256(ng * 4);
     V.off_groups = o; o += align256(V.groups.size() * sizeof(GhostGroup));
     for (int k = 0; k < 3; ++k) {
       V.off_G[k] = o;
@@ -657,7 +648,6 @@ GhostArgs ghost_args(const lbm_refined* R, int l) {
   const HostLevel& P = R->lev[l - 1];
   GhostArgs g;
   g.ghosts = (const int*)(R->base + V.off_ghosts);
-  g.gperm = (const int*)(R->base + V.off_gperm);
   g.ng = (long long)V.ghosts.size();
   g.gcode = (const int*)(R->base + V.off_gcode);
   g.groups = (const int*)(R->base + V.off_groups);
@@ -1036,8 +1026,7 @@ int lbm_refined_bind_memory(lbm_refined* R, void* dev, size_t bytes) {
     HostLevel& V = R->lev[l];
     int rc = upload(R, V.off_type, V.type.data(), V.Nbox);
     if (!rc) rc = upload(R, V.off_tiles, V.tiles.data(), V.tiles.size() * 4);
-    if (!rc) rc = upload(R, V.off_ghosts, V.gsorted.data(), V.gsorted.size() * 4);
-    if (!rc) rc = upload(R, V.off_gperm, V.gperm.data(), V.gperm.size() * 4);
+    if (!rc) rc = upload(R, V.off_ghosts, V.ghosts.data(), V.ghosts.size() * 4);
     if (!rc) rc = upload(R, V.off_gcode, V.gcode.data(), V.gcode.size() * 4);
     if (!rc) rc = upload(R, V.off_groups, V.groups.data(), V.groups.size() * sizeof(GhostGroup));
     if (!rc) rc = upload(R, V.off_pre_nodes, V.pre_nodes.data(), V.pre_nodes.size() * 4);

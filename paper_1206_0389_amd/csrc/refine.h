@@ -468,8 +468,7 @@ __global__ __launch_bounds__(256) void solid_prepass_kernel(const Lev L, const i
 
 // ------------------------------------------------------------- interface
 struct GhostArgs {
-  const int* ghosts;  // child box indices of the ghost nodes, ascending
-  const int* gperm;   // position of each of them in the group order
+  const int* ghosts;  // child box indices of the ghost nodes (group order)
   long long ng;
   const int* groups;  // GhostGroup records
   const int* gcode;   // per ghost: stencil start and code per axis
@@ -618,21 +617,19 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
   }
 }
 
-// Ghosts of ff := rescale(G), one thread per ghost in box order (runs of
-// neighbouring slots per store); G: [Q][ng] in the group order, ghost t at
-// position gperm[t].
+// Ghosts of ff := rescale(G), one thread per ghost in the group order (G:
+// [Q][ng] read in order; the stores follow the groups' small boxes).
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
                                                             const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ga.ng) return;
-  const long long gi = ga.gperm[t];
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= ga.ng) return;
   R f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = G[(size_t)q * ga.ng + gi];
   rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
-  const int l = ga.ghosts[t];
+  const int l = ga.ghosts[gi];
 #pragma unroll
   for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
 }
