@@ -458,7 +458,7 @@ int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next,
  * recursively (each level steps once, then its child level twice). Every
  * level holds post-collision populations (deviations, ABI order) in a box:
  * R_l plus the layer of ghost nodes around it, with its x origin and row
- * pitch rounded to multiples of 32 nodes (extra nodes are unused).
+ * pitch rounded to multiples of 64 nodes (extra nodes are unused).
  * Interface per parent step t:
  *   child ghosts, first substep:  rescale(G(t)),
  *   child ghosts, second substep: rescale(-1/8 G(t-1) + 3/4 G(t) + 3/8
@@ -474,8 +474,9 @@ int lbm_adjoint_step(lbm_lattice* lat, const void* f_t, const void* lambda_next,
  *     post-collision traceless stress, tau_f,tot = tau0_f + (tau_c,tot -
  *     tau0_c)/2);
  *   covered parent nodes (inside R_{l+1}, read by no ghost interpolation)
- *     whose eight children are fluid take the mean of the children,
- *     rescaled back, after the two child substeps.
+ *     that a parent fluid or band node pulls from take the mean of their
+ *     eight children, rescaled back, after the two child substeps (no other
+ *     covered node is ever read; its slots are left as they are).
  * Node types (lbm_refined_types): 0 unused, 1 fluid, 2 band (inside the
  * next level's region but updated on this level, read by its ghost
  * interpolation), 3 covered, 4 ghost, 5 solid.
@@ -496,7 +497,7 @@ int lbm_refined_create(const lbm_config* cfg, int32_t block, int32_t nlevels,
                        const uint8_t* level_map, lbm_refined** out);
 
 /* Box of level l: origin lo (level coordinates), extent dims (dims[0] is the
- * row pitch, a multiple of 32); counts = {fluid, band, covered, ghost,
+ * row pitch, a multiple of 64); counts = {fluid, band, covered, ghost,
  * solid} nodes. LBM_ESTATE while the configuration waits for boundaries. */
 int lbm_refined_geometry(const lbm_refined* r, int32_t level, int32_t lo[3], int32_t dims[3],
                          int64_t counts[5]);

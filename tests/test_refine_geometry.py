@@ -99,7 +99,7 @@ def test_library_geometry_matches_oracle(case, model):
                        inlet_u=np.zeros((3, shape[1], shape[0])) if I in faces else None)
     R = oracle.Refined(c, B, m, levels, inlet_u=iu if I in faces else None)
     for l, (lo, dims, t) in enumerate(lv):
-        assert dims[0] % 32 == 0 and lo[0] % 32 == 0
+        assert dims[0] % 64 == 0 and lo[0] % 64 == 0
         want = _box(lo, dims, R.types(l), shape[0] << l)
         assert np.array_equal(t, want), l
         # every used node of the oracle lies in the library's box
