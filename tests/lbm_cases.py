@@ -122,12 +122,21 @@ REFINED_CASES = {
     # 24 x 24 x 32 with the centre 4 x 4 blocks of the first four layers
     # refined: room for a nozzle inside the fine level
     "jet2wide": (2, True, [W, W, W, W, I, O], None),
+    # the paper's 11^3 blocks: 44 x 44 x 44, three levels
+    "jet3b11": (3, True, [W, W, W, W, I, O], None),
 }
 
 
 def refined_jet_geometry(case):
     """(n, nz, B, level map) of a jet case."""
     levels = REFINED_CASES[case][0]
+    if case == "jet3b11":
+        # level 1 over the whole cross-section of the first three block
+        # layers, level 2 on the inner 2 x 2 blocks of the first two
+        m = np.zeros((4, 4, 4), dtype=np.uint8)
+        m[0:3] = 1
+        m[0:2, 1:3, 1:3] = 2
+        return 44, 44, 11, m
     n = 16 if (levels == 2 and case != "jet2wide") else 24
     r2 = 72.0 if case == "jet2wide" else None
     return n, 32, 4, jet_map(n, 32, 4, levels, r2)
