@@ -738,6 +738,56 @@ __global__ __launch_bounds__(256) void step_kernel(const LatArgs a, const Rows r
   }
 }
 
+// Even step of FP16 storage with two x-neighbouring nodes per lane (x even):
+// one 4-byte load and store per population serve both, where one node per
+// lane moves 2 bytes per access. Each node collides in FP32 exactly as in
+// step_kernel (bitwise the same result). No solids, links, pressure faces or
+// recording (those lattices take step_kernel).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+template <int KIND, bool BC>
+__global__ __launch_bounds__(256) void step_even_pair_kernel(const LatArgs a) {
+  using M = Model<KIND>;
+  constexpr int Q = M::Q;
+  const int x = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int y = (int)(blockIdx.y * blockDim.y + threadIdx.y);
+  const int z = (int)blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  _Float16* __restrict__ F = (_Float16*)a.f;
+  const size_t N = (size_t)a.N;
+  const uint32_t off = (uint32_t)((((size_t)z * a.ny + y) * a.nx + x) * sizeof(_Float16));
+  half2_t v[Q];
+  static_for<0, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    v[I] = __builtin_nontemporal_load((const half2_t*)((const char*)(F + (size_t)I * N) + off));
+  });
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    float f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = float(v[i][k]);
+    M::collide(f, a);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][k] = _Float16(f[i]);
+    if constexpr (BC) {
+      const Node n = make_node(a, x + k, y, z);
+      if (n.atface & a.bc.outflow) {
+        _Float16* G = (_Float16*)a.ghost;
+        const long long g = n.yo[1] + n.xo[1];
+        static_for<0, Q>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          if (n.atface & a.bc.outflow & pull_faces(I))
+            st(G + (size_t)I * (size_t)a.bc.ghost_n + g, f[I]);
+        });
+      }
+    }
+  }
+  static_for<0, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    __builtin_nontemporal_store(v[I],
+                                (half2_t*)((char*)(F + (size_t)opposite<Q>(I) * N) + off));
+  });
+}
+
 // Natural (pre-collision) populations of a node in double precision; zero
 // (the rest state) at a solid node, whose populations are not updated.
 template <int Q, typename S, bool BC>

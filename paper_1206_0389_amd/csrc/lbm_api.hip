@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "../../include/lbm.h"
 #include "adjoint.h"
@@ -118,6 +119,24 @@ template <int KIND, typename S>
 void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
   const bool ext = odd ? (L->solids || L->args.bc.freeslip || L->args.bc.pressure)
                        : L->args.bc.pressure != 0;
+  if constexpr (std::is_same_v<S, _Float16>) {
+    // FP16 even steps: two nodes per lane (the pair kernel's rows)
+    if (!odd && !ext && rec == nullptr && L->cfg.nx % 2 == 0) {
+      const int hx = L->cfg.nx / 2;
+      const int bx = hx < 256 ? hx : 256;
+      int by = 256 / bx;
+      if (by > L->cfg.ny) by = L->cfg.ny;
+      const dim3 block(bx, by, 1);
+      const dim3 grid((hx + bx - 1) / bx, (L->cfg.ny + by - 1) / by, L->cfg.nz);
+      if (L->has_bc)
+        hipLaunchKernelGGL((step_even_pair_kernel<KIND, true>), grid, block, 0, L->stream,
+                           L->args);
+      else
+        hipLaunchKernelGGL((step_even_pair_kernel<KIND, false>), grid, block, 0, L->stream,
+                           L->args);
+      return;
+    }
+  }
   if (ext)
     step_model_ext<KIND, S, true>(L, odd, t, rec);
   else

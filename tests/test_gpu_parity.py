@@ -319,3 +319,38 @@ def test_bgk_as_mrt_with_equal_rates():
     ref = np.stack([np.roll(post[i], shift=(e[i][2], e[i][1], e[i][0]), axis=(0, 1, 2))
                     for i in range(19)])
     assert rel_err(g.populations().cpu().numpy(), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("faces", [None, "jet"])
+def test_fp16_even_step_two_nodes_per_lane_is_the_one_node_step(name, faces):
+    """The FP16 even step runs two x-neighbouring nodes per lane when the x
+    extent is even and one node per lane otherwise. An even step touches only
+    each node's own slots, so on a 32-wide lattice and a 33-wide one holding
+    the same populations in x < 32 it must give the same values there (read
+    back away from x = 0 and 31, whose natural populations come from the
+    wrapped neighbours after the step), up to the final rounding to FP16: the
+    compiler may fuse the last FP32 operation with the conversion (one
+    rounding instead of two), so the two kernels may differ by one FP16 unit
+    in the last place, no more."""
+    Q = 19 if MODELS[name][0] == oracle.MRT19 else 27
+    ny, nz = 8, 6
+    f33 = synth.random_populations(Q, (nz, ny, 33), 1e-2, seed=17)
+    iu, im = synth.jet_inlet(33, ny, 3.0, 0.05, 0.002)  # one inlet field for both
+    out = {}
+    for nx in (32, 33):
+        kw = {}
+        if faces == "jet":
+            kw = dict(faces=JET_FACES, face_u=face_velocities(),
+                      inlet=(np.ascontiguousarray(iu[..., :nx]),
+                             np.ascontiguousarray(im[..., :nx])))
+        _say("case fp16 even step", name, nx, faces)
+        g = gpu_lattice(name, "f16", (nx, ny, nz), 0.02, cs=0.1, **kw)
+        g.set_populations(torch.from_numpy(np.ascontiguousarray(f33[..., :nx])))
+        g.step(1)
+        out[nx] = g.populations().cpu().numpy()
+    a, b = out[32][..., 1:31], out[33][..., 1:31]
+    ulp = np.spacing(np.maximum(np.abs(a), np.abs(b)).astype(np.float16)).astype(np.float64)
+    d = np.abs(a - b)
+    print(name, faces, "values differing:", int((d > 0).sum()), "of", d.size, flush=True)
+    assert np.all(d <= ulp), float((d / ulp).max())
