@@ -468,7 +468,8 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": storage, "data": "synthetic", "config": main_res["config"],
-            "roofline": roof, "others": others, "adjoint": adjoint, "statistics": stats}
+            "roofline": roof, "timing": main_res["timing"], "others": others,
+            "adjoint": adjoint, "statistics": stats}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", flush=True)
         line["cpu_baseline"] = cpu_baseline(model)
