@@ -36,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LLC_BYTES = 256 << 20  # MI355X last-level (Infinity) cache
 METRIC = "MLUPS and % of HBM roofline, D3Q19-MRT and D3Q27-FCLB, FP32/FP16 vs FP64"
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
 # HBM bytes per step of the default workload measured with rocprofv3 --pmc
@@ -70,6 +71,10 @@ def parse():
     p.add_argument("--other-steps", type=int, default=50)
     p.add_argument("--no-adjoint", action="store_true")
     return p.parse_args()
+
+
+def kind_refined(name):
+    return name.split("-")[0].startswith("ref")
 
 
 def workload(name):
@@ -241,6 +246,11 @@ def measure(name, P, torch, synth, steps, warmup):
            "achieved_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS,
            "bytes_per_lup": 2 * q * BYTES[storage], "finite": all(map(lambda v: v == v, red)),
            "timing": spread, "config": desc}
+    # populations that fit the 256 MB last-level cache are not an HBM figure
+    pop_bytes = q * BYTES[storage] * shape[0] * shape[1] * shape[2]
+    if not kind_refined(name) and pop_bytes < LLC_BYTES:
+        out["note"] = ("populations (%.0f MB) fit the %d MB last-level cache: the rate is "
+                       "not bound by HBM" % (pop_bytes / 1e6, LLC_BYTES // (1 << 20)))
     del lat
     torch.cuda.empty_cache()
     return out
