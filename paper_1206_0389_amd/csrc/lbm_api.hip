@@ -345,17 +345,26 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 double* g_scratch_ptr[kMaxDevices] = {nullptr};
 
-// The device address of the current device's scratch array, looked up once
-// per device (the array's name in host code is not a device address).
-int static_scratch(double** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
+// The device address of the scratch array on the device that runs the
+// lattice's stream (the current device for the null stream), looked up once
+// per device with that device current (the array's name in host code is not
+// a device address).
+int static_scratch(hipStream_t stream, double** out) {
+  int cur = 0, dev = 0;
+  hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e);
+  dev = cur;
+  if (stream) {
+    e = hipStreamGetDevice(stream, &dev);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   if (dev < 0 || dev >= kMaxDevices) return LBM_EINVAL;
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (!g_scratch_ptr[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return hip_fail(e);
     void* ptr = nullptr;
     e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
     if (e != hipSuccess) return hip_fail(e);
     g_scratch_ptr[dev] = (double*)ptr;
   }
@@ -803,7 +812,7 @@ int lbm_reduce_static(lbm_lattice* L, double* out) {
   const size_t plane = (size_t)L->grid.x * L->grid.y;
   if (plane > kStaticPartials) return LBM_EINVAL;
   double* partial = nullptr;
-  int rc = static_scratch(&partial);
+  int rc = static_scratch(L->stream, &partial);
   if (rc) return rc;
   size_t gz = kStaticPartials / plane;
   if (gz > (size_t)L->grid.z) gz = L->grid.z;
