@@ -42,7 +42,7 @@ struct HostLevel {
   std::vector<int32_t> pidx;                // per group patch: indices into unodes
   // device offsets
   size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
-         off_groups = 0, off_G[3] = {0, 0, 0}, off_H = 0, off_pre_nodes = 0, off_pre_dirs = 0,
+         off_groups = 0, off_G[3] = {0, 0, 0}, off_pre_nodes = 0, off_pre_dirs = 0,
          off_pre_q = 0, off_inj = 0, off_unodes = 0, off_pidx = 0, off_pc = 0;
   int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
   bool have_cur = false, have_prev = false;
@@ -560,7 +560,6 @@ void layout(lbm_refined* R) {
       V.off_G[k] = o;
       o += align256(ng * R->Q * R->relem);
     }
-    V.off_H = o; o += align256(ng * R->Q * R->relem);
     V.off_inj = o; o += align256(V.inj.size() * 4);
     V.off_unodes = o; o += align256(V.unodes.size() * 4);
     V.off_pidx = o; o += align256(V.pidx.size() * 4);
@@ -688,16 +687,14 @@ void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, dou
   if (V.groups.empty()) return;
   const GhostArgs ga = ghost_args(R, l);
   void* Gn = R->base + V.off_G[V.gi[init ? 1 : 2]];
-  Rt* H = (Rt*)(R->base + V.off_H);
   S* Pc = (S*)(R->base + V.off_pc);
   hipLaunchKernelGGL((ghost_gather_kernel<KIND, S>), dim3(blocks_for(ga.nu)), dim3(256), 0,
                      stream, ga, (const S*)fp, Pc);
   hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
                      dim3(256), 0, stream, ga, (const S*)Pc, (Rt*)Gn,
                      (const Rt*)(R->base + V.off_G[V.gi[1]]),
-                     (const Rt*)(R->base + V.off_G[V.gi[0]]), c0, c1, c2, H);
-  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
-                     stream, ga, (const Rt*)H, rescale_args(R, l), (S*)ff);
+                     (const Rt*)(R->base + V.off_G[V.gi[0]]), c0, c1, c2, rescale_args(R, l),
+                     (S*)ff);
 }
 
 // Child level l's ghosts in array ff := rescale(G(t+1)).

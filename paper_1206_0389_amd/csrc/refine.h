@@ -563,17 +563,25 @@ __global__ __launch_bounds__(256) void ghost_gather_kernel(const GhostArgs ga, c
   for (int q = 0; q < Q; ++q) Pc[(size_t)u * Q + q] = v[q];
 }
 
-// Interface interpolation of one ghost group per workgroup: the parent
-// patch is staged in LDS from the gathered copy Pc, every (ghost,
-// population) is interpolated from it into Gn (kept for the following
-// steps), and H receives the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc
-// not read where their weight is 0), all [Q][ng].
+// Interface interpolation of one ghost group per workgroup (launched with
+// 256 threads): the parent patch is staged in LDS from the gathered copy Pc,
+// every (ghost, population) is interpolated from it into Gn (kept for the
+// following steps), and the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc
+// not read where their weight is 0; G* are [Q][ng]) goes back to LDS, where
+// one thread per ghost rescales it and stores the ghost into the child array
+// ff.
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* Pc, R* Gn,
                                                           const R* Gc, const R* Gm, double c0,
-                                                          double c1, double c2, R* H) {
+                                                          double c1, double c2,
+                                                          const RescaleArgs ra, S* ff) {
   constexpr int Q = Model<KIND>::Q;
-  __shared__ S sp[Q][kPatchMax];
+  // the patch, then (after it is read) the ghosts' combined values
+  constexpr size_t kPatchBytes = sizeof(S) * Q * kPatchMax;
+  constexpr size_t kHBytes = sizeof(R) * Q * kGhostMax;
+  __shared__ __align__(16) unsigned char lds[kPatchBytes > kHBytes ? kPatchBytes : kHBytes];
+  S(&sp)[Q][kPatchMax] = *reinterpret_cast<S(*)[Q][kPatchMax]>(lds);
+  R(&hs)[Q][kGhostMax] = *reinterpret_cast<R(*)[Q][kGhostMax]>(lds);
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
@@ -604,16 +612,34 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
     });
   }
   __syncthreads();
+  R h[kItems];
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int k = threadIdx.x + 256 * it;
     const int q = k / kGhostMax, gl = k % kGhostMax;
+    h[it] = R(0);
     if (k >= Q * kGhostMax || gl >= ngg) continue;
     const long long gi = gbeg + gl;
     const R v = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
-    const size_t kk = (size_t)q * ga.ng + gi;
-    Gn[kk] = v;
-    H[kk] = R(c2) * v + hist[it];
+    Gn[(size_t)q * ga.ng + gi] = v;
+    h[it] = R(c2) * v + hist[it];
+  }
+  __syncthreads();  // the patch is read: its space takes the combined values
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    if (k < Q * kGhostMax) hs[k / kGhostMax][k % kGhostMax] = h[it];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < ngg) {
+    const int gl = threadIdx.x;
+    R f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = hs[q][gl];
+    rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
+    const int l = ga.ghosts[gbeg + gl];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
   }
 }
 
