@@ -503,12 +503,15 @@ struct GhostGroup {
 
 // Cubic Lagrange weights (dyadic, exact) at t = (2c - 1)/4, c = 0..7, on
 // the nodes 0..3 of a window.
-__host__ __device__ inline void stencil_weights(int c, double w[4]) {
-  const double t = (2.0 * c - 1.0) * 0.25;
-  w[0] = -(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0;
-  w[1] = t * (t - 2.0) * (t - 3.0) / 2.0;
-  w[2] = -t * (t - 1.0) * (t - 3.0) / 2.0;
-  w[3] = t * (t - 1.0) * (t - 2.0) / 6.0;
+template <typename T>
+__host__ __device__ inline void stencil_weights(int c, T w[4]) {
+  // exact in FP32 too: dyadic values with a few bits, the division by 6 of
+  // a multiple of 3 correctly rounded
+  const T t = (T(2) * T(c) - T(1)) * T(0.25);
+  w[0] = -(t - T(1)) * (t - T(2)) * (t - T(3)) / T(6);
+  w[1] = t * (t - T(2)) * (t - T(3)) / T(2);
+  w[2] = -t * (t - T(1)) * (t - T(3)) / T(2);
+  w[3] = t * (t - T(1)) * (t - T(2)) / T(6);
 }
 
 // Window start s and code c of child coordinate j on a parent axis of n
@@ -526,7 +529,7 @@ __host__ __device__ inline int child_window(int j, int n, bool periodic, int& s)
 template <typename S, typename R>
 __device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01) {
   int a[3];
-  double w[3][4];
+  R w[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int cd = (code >> (6 * d)) & 63;
@@ -538,10 +541,10 @@ __device__ __forceinline__ R patch_interp(const S* sp, int code, int m0, int m01
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const R wbc = R(w[1][b] * w[2][c]);
+      const R wbc = w[1][b] * w[2][c];
       const S* row = sp + (a[2] + c) * m01 + (a[1] + b) * m0 + a[0];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) s += R(w[0][x]) * wbc * R(row[x]);
+      for (int x = 0; x < 4; ++x) s += w[0][x] * wbc * R(row[x]);
     }
   return s;
 }
