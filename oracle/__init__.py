@@ -26,6 +26,11 @@ Parity status of each oracle function (what pins it, see tests/):
   collide_jvp (FCLB)          central differences, rest-state relaxation
                               spectrum (1 - omega shear, trace removed),
                               conservation, equilibrium tangent fixed
+  collide_jvp (MRT-LES)       central differences in both bases with the
+                              eddy viscosity on, rest-state spectrum (each
+                              non-conserved moment mode scaled by 1 - s_k),
+                              conservation, the strain derivative of tau
+                              against Eq. (21) differentiated by hand
   tangent_step / adjoint_step central differences of run; dot-product identity;
                               periodic mass/momentum adjoint invariants
   probe_ke, inlet_gradient    central differences of J through many steps
@@ -495,24 +500,25 @@ class Lattice:
         lib().orc_reduce(ctypes.byref(self.p), _dp(_f64(f)), _dp(out))
         return out
 
-    # ---- adjoint of the FCLB model (exact Jacobian-vector products by
-    # dual numbers; the transpose of streaming is the scatter of the pull) ----
-    def _need_fclb(self):
-        if self.model != FCLB27:
-            raise ValueError("the oracle's adjoint covers the FCLB model only")
+    # ---- adjoint of the FCLB and MRT-LES models (exact Jacobian-vector
+    # products by dual numbers; the transpose of streaming is the scatter of
+    # the pull) ----
+    def _need_adjoint(self):
+        if self.model not in (FCLB27, MRT19):
+            raise ValueError("the oracle's adjoint covers the FCLB and MRT-LES models only")
         if self.solid is not None:
             raise ValueError("the oracle's adjoint has no interior solids")
         if FREESLIP in tuple(self.p.face_type) or PRESSURE in tuple(self.p.face_type):
             raise ValueError("the oracle's adjoint has no free-slip or pressure faces")
 
     def collide_jvp(self, f, v):
-        self._need_fclb()
+        self._need_adjoint()
         out = np.zeros(self.Q)
         lib().orc_collide_jvp(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(v)), _dp(out))
         return out
 
     def tangent_step(self, f, v):
-        self._need_fclb()
+        self._need_adjoint()
         out = np.zeros((self.Q,) + self.shape)
         lib().orc_tangent_step(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(v)), _dp(out))
         return out
@@ -520,7 +526,7 @@ class Lattice:
     def adjoint_step(self, f, lam_next, grad):
         """Adjoint at t from the state f_t and the adjoint at t+1; grad
         ([3][nb][na], float64) is accumulated in place."""
-        self._need_fclb()
+        self._need_adjoint()
         lam = np.zeros((self.Q,) + self.shape)
         assert grad.dtype == np.float64 and grad.flags.c_contiguous
         lib().orc_adjoint_step(ctypes.byref(self.p), _dp(_f64(f)), _dp(_f64(lam_next)), _dp(lam),
@@ -541,7 +547,7 @@ class Lattice:
         at time t0, and dJ/du_in ([3][nb][na]) of a static additive inlet
         velocity, by the discrete adjoint. States are checkpointed every
         `every` steps and recomputed segment by segment in reverse."""
-        self._need_fclb()
+        self._need_adjoint()
         ckpt = {}
         f = _f64(f0).copy()
         for t in range(nsteps):

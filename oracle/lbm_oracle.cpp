@@ -111,6 +111,13 @@ inline Dual operator/(Dual a, Dual b) {
 }
 inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
 inline Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+// Square root; at 0 the derivative is taken as 0 (the strain magnitude of
+// Eq. (19) is not differentiable at zero strain: this picks the subgradient
+// 0 there).
+inline Dual sqrt(Dual a) {
+  const double r = std::sqrt(a.v);
+  return Dual(r, r > 0.0 ? a.d / (2.0 * r) : 0.0);
+}
 inline double value_of(double x) { return x; }
 inline double value_of(Dual x) { return x.v; }
 inline bool is_zero(double x) { return x == 0.0; }
@@ -166,11 +173,12 @@ void dense_inverse(int n, const double* A, double* Ainv) {
 // ---------------------------------------------------------------------------
 // Eq. (2): He-Luo incompressible equilibrium, deviation form (rho0 = 1, the
 // lattice speed c = 1 so the printed c_s denominators read as c).
-void feq_incomp(int Q, double drho, const double u[3], double* feq) {
-  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+template <typename T>
+void feq_incomp(int Q, T drho, const T u[3], T* feq) {
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int i = 0; i < Q; ++i) {
-    const double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
-    feq[i] = weight(Q, i) * (drho + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    const T eu = T(E[i][0]) * u[0] + T(E[i][1]) * u[1] + T(E[i][2]) * u[2];
+    feq[i] = T(weight(Q, i)) * (drho + T(3.0) * eu + T(4.5) * eu * eu - T(1.5) * uu);
   }
 }
 
@@ -258,8 +266,9 @@ const MrtBasis& get_basis(int basis) {
 }
 
 // Relaxation rate of each moment row; shear rows get 1/tau_total.
-void mrt_rates(int basis, const double* rates, double s_shear, double* s) {
-  for (int k = 0; k < 19; ++k) s[k] = 0.0;
+template <typename T>
+void mrt_rates(int basis, const double* rates, T s_shear, T* s) {
+  for (int k = 0; k < 19; ++k) s[k] = T(0.0);
   if (basis == ORC_BASIS_TABLE1) {
     for (int k = 4; k <= 8; ++k) s[k] = s_shear;  // s1
     s[9] = rates[0];                               // s2
@@ -277,53 +286,56 @@ void mrt_rates(int basis, const double* rates, double s_shear, double* s) {
 }
 
 // Eqs. (3)-(5), (16)-(21): strain-rate-dependent total relaxation time.
-double smagorinsky_tau(const double* f, double tau0, double cs, double* Q_out) {
-  double drho = 0, u[3] = {0, 0, 0};
+template <typename T>
+T smagorinsky_tau(const T* f, double tau0, double cs, T* Q_out) {
+  using std::sqrt;
+  T drho = 0.0, u[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 19; ++i) {
     drho += f[i];
-    for (int a = 0; a < 3; ++a) u[a] += f[i] * E[i][a];
+    for (int a = 0; a < 3; ++a) u[a] += f[i] * T(E[i][a]);
   }
-  double feq[19];
+  T feq[19];
   feq_incomp(19, drho, u, feq);
-  double pi2 = 0.0;
+  T pi2 = 0.0;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
-      double p = 0.0;
-      for (int i = 0; i < 19; ++i) p += E[i][a] * E[i][b] * (f[i] - feq[i]);
+      T p = 0.0;
+      for (int i = 0; i < 19; ++i) p += T(E[i][a] * E[i][b]) * (f[i] - feq[i]);
       pi2 += p * p;
     }
-  const double Q = std::sqrt(2.0 * pi2);
+  const T Q = sqrt(T(2.0) * pi2);
   if (Q_out) *Q_out = Q;
-  return 0.5 * (tau0 + std::sqrt(tau0 * tau0 + 18.0 * cs * cs * Q));
+  return T(0.5) * (T(tau0) + sqrt(T(tau0 * tau0) + T(18.0 * cs * cs) * Q));
 }
 
 // Eq. (12), read with the sign of a relaxation: f* = f - M^-1 S (M f - M f_eq).
-void mrt_collide(const double* f, double tau0, double cs, int basis,
-                 const double* rates, double* fout, double* tau_out) {
+template <typename T>
+void mrt_collide(const T* f, double tau0, double cs, int basis, const double* rates, T* fout,
+                 T* tau_out) {
   const MrtBasis& B = get_basis(basis);
-  double drho = 0, u[3] = {0, 0, 0};
+  T drho = 0.0, u[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 19; ++i) {
     drho += f[i];
-    for (int a = 0; a < 3; ++a) u[a] += f[i] * E[i][a];
+    for (int a = 0; a < 3; ++a) u[a] += f[i] * T(E[i][a]);
   }
-  double feq[19];
+  T feq[19];
   feq_incomp(19, drho, u, feq);
-  const double tau = smagorinsky_tau(f, tau0, cs, nullptr);
+  const T tau = smagorinsky_tau(f, tau0, cs, (T*)nullptr);
   if (tau_out) *tau_out = tau;
-  double s[19];
-  mrt_rates(basis, rates, 1.0 / tau, s);
-  double d[19];
+  T s[19];
+  mrt_rates(basis, rates, T(1.0) / tau, s);
+  T d[19];
   for (int k = 0; k < 19; ++k) {
-    double m = 0.0, meq = 0.0;
+    T m = 0.0, meq = 0.0;
     for (int i = 0; i < 19; ++i) {
-      m += B.M[k * 19 + i] * f[i];
-      meq += B.M[k * 19 + i] * feq[i];
+      m += T(B.M[k * 19 + i]) * f[i];
+      meq += T(B.M[k * 19 + i]) * feq[i];
     }
     d[k] = s[k] * (m - meq);
   }
   for (int i = 0; i < 19; ++i) {
-    double c = 0.0;
-    for (int k = 0; k < 19; ++k) c += B.Minv[i * 19 + k] * d[k];
+    T c = 0.0;
+    for (int k = 0; k < 19; ++k) c += T(B.Minv[i * 19 + k]) * d[k];
     fout[i] = f[i] - c;
   }
 }
@@ -414,7 +426,7 @@ void fclb_collide(const T* f, double omega, T* fout, bool gaussian = false) {
 void collide_node(const orc_params* p, const double* f, double* fout) {
   const double tau0 = 3.0 * p->nu + 0.5;
   if (p->model == ORC_MRT19)
-    mrt_collide(f, tau0, p->cs_smag, p->mrt_basis, p->rates, fout, nullptr);
+    mrt_collide(f, tau0, p->cs_smag, p->mrt_basis, p->rates, fout, (double*)nullptr);
   else
     fclb_collide(f, 1.0 / tau0, fout, p->model == ORC_CLB27);
 }
@@ -601,14 +613,20 @@ double pull(const orc_params* p, const double* fpost, int Q, int i, int x, int y
   return fpost[io * N + src.node] + 6.0 * weight(Q, i) * eu;
 }
 
-// Exact Jacobian-vector product of the FCLB collision of one node, by
-// forward-mode dual numbers through the same code as the collision.
+// Exact Jacobian-vector product of the FCLB or MRT-LES collision of one node,
+// by forward-mode dual numbers through the same code as the collision (for
+// MRT-LES with the strain-dependent relaxation time of Eqs. (16)-(21); at zero
+// strain the derivative of the strain magnitude is taken as 0).
 void collide_jvp(const orc_params* p, const double* f, const double* v, double* out) {
   const double tau0 = 3.0 * p->nu + 0.5;
+  const int Q = nq(p->model);
   Dual a[27], b[27];
-  for (int i = 0; i < 27; ++i) a[i] = Dual(f[i], v[i]);
-  fclb_collide(a, 1.0 / tau0, b);
-  for (int i = 0; i < 27; ++i) out[i] = b[i].d;
+  for (int i = 0; i < Q; ++i) a[i] = Dual(f[i], v[i]);
+  if (p->model == ORC_MRT19)
+    mrt_collide(a, tau0, p->cs_smag, p->mrt_basis, p->rates, b, (Dual*)nullptr);
+  else
+    fclb_collide(a, 1.0 / tau0, b);
+  for (int i = 0; i < Q; ++i) out[i] = b[i].d;
 }
 
 }  // namespace
@@ -1490,8 +1508,8 @@ void orc_mlref_reduce(void* h, double* out) {
 }  // extern "C"
 
 // ===========================================================================
-// Discrete adjoint of the FCLB collide-and-stream map (used to check the GPU's
-// hand-written adjoint): step t maps the pre-collision state f_t to
+// Discrete adjoint of the FCLB and MRT-LES collide-and-stream maps (used to
+// check the GPU's hand-written adjoint): step t maps the pre-collision state f_t to
 // f_{t+1} = S(C(f_t), u_in); for an objective J(f_T) the adjoint runs
 // lambda_t = J_C(f_t)^T S^T lambda_{t+1}, and the inlet velocity's gradient
 // collects the bounce-back terms 6 w_i e_i lambda_{t+1,i}.
