@@ -43,12 +43,12 @@ BYTES = {"f64": 8, "f32": 4, "f16": 2}
 # FETCH_SIZE and WRITE_SIZE (scaled by a copy kernel of known size), valid only
 # for the step kernel's sources whose hash is recorded with it.
 STEP_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "lbm_api.hip")
-MEASURED_TRAFFIC = {"bytes_per_step": 7.385e9, "sources_sha256_16": "20c8867b4c5f4549",
+MEASURED_TRAFFIC = {"bytes_per_step": 7.385e9, "sources_sha256_16": "e6b53aeec129398c",
                     "workload": "jet256-fclb-f32"}
-# The same for one adjoint step of the 128 x 128 x 256 jet (FP32).
-ADJOINT_SOURCES = ("stencil.h", "fclb.h", "kernels.h", "adjoint.h", "lbm_api.hip")
-MEASURED_ADJOINT_TRAFFIC = {"bytes_per_step": 1.386e9, "sources_sha256_16": "b746306344bcea4b",
-                            "storage": "f32"}
+# The same for one adjoint step of the 128 x 128 x 256 jet (FP32), per model.
+ADJOINT_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "adjoint.h", "lbm_api.hip")
+MEASURED_ADJOINT_TRAFFIC = {"sources_sha256_16": "232e08b96a3ca9a0", "storage": "f32",
+                            "bytes_per_step": {"fclb": 1.386e9, "mrt": 0.966e9}}
 
 
 def sources_hash(names=STEP_SOURCES):
@@ -256,16 +256,20 @@ def measure(name, P, torch, synth, steps, warmup):
     return out
 
 
-def measure_adjoint(P, torch, synth, storage="f32", steps=50):
-    """Inlet-sensitivity gradient of the 128 x 128 x 256 FCLB jet (D = 16,
-    u = 0.05, nu = 2e-4, co-flow 0.002), 400 steps from rest with checkpoints
+def measure_adjoint(P, torch, synth, storage="f32", steps=50, model="fclb"):
+    """Inlet-sensitivity gradient of the 128 x 128 x 256 jet (D = 16, u =
+    0.05, nu = 2e-4, co-flow 0.002), 400 steps from rest with checkpoints
     every 20, u_z perturbed on the 16 x 16 nozzle square (N(0, 0.005^2), seed
-    389), J = mean kinetic energy of the 32^3 probe at z in [80, 112)."""
+    389), J = mean kinetic energy of the 32^3 probe at z in [80, 112).
+    model: "fclb" (D3Q27 FCLB) or "mrt" (D3Q19 MRT-LES, Table 1 basis, C_S =
+    0.1)."""
     from paper_1206_0389_amd.adjoint import InletProbeObjective
     n, nz, d, nsteps = 128, 256, 16, 400
     c = synth.jet_adjoint_case(n, nz, d, u_jet=0.05, u_coflow=0.002, sigma=0.005, seed=389)
     fu = [[0.0, 0.0, 0.002]] * 4 + [[0.0, 0.0, 0.0]] * 2
-    lat = P.Lattice(model="fclb", storage=storage, shape=(n, n, nz), nu=2e-4)
+    cs = 0.1 if model == "mrt" else 0.0
+    lat = P.Lattice(model=model, storage=storage, shape=(n, n, nz), nu=2e-4, cs_smag=cs)
+    Q = lat.Q
     obj = InletProbeObjective(lat, [P.WALL] * 4 + [P.INLET, P.OUTFLOW], fu,
                               torch.from_numpy(c["base_u"]), c["square"], c["probe_lo"],
                               c["probe_hi"], nsteps, every=20)
@@ -302,17 +306,18 @@ def measure_adjoint(P, torch, synth, storage="f32", steps=50):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nodes = n * n * nz
-    bpn = 3 * 27 * (8 if storage == "f64" else 4)
+    bpn = 3 * Q * (8 if storage == "f64" else 4)
     gbs = bpn * nodes / (ms * 1e-3) / 1e9
-    out = {"workload": "inlet-sensitivity jet 128x128x256 FCLB, D=16 u=0.05 nu=2e-4, 400 "
+    name = "FCLB" if model == "fclb" else "MRT-LES (C_S 0.1)"
+    out = {"workload": "inlet-sensitivity jet 128x128x256 %s, D=16 u=0.05 nu=2e-4, 400 "
                        "steps, checkpoints every 20, 16x16 u_z perturbation (sigma 0.005, seed "
-                       "389), probe 32^3 at z in [80,112)",
-           "storage": storage, "J": J, "grad_l2": gnorm, "gradient_s": t2 - t0,
+                       "389), probe 32^3 at z in [80,112)" % name,
+           "model": model, "storage": storage, "J": J, "grad_l2": gnorm, "gradient_s": t2 - t0,
            "forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_step_ms": ms,
            "adjoint_mlups": nodes / (ms * 1e-3) / 1e6, "adjoint_bytes_per_node": bpn,
            "adjoint_GBs": gbs, "adjoint_frac_of_8TBs": gbs / HBM_PEAK_GBS,
            "kernel": "adjoint_kernel<%s>" % ("double" if storage == "f64" else "float"),
-           "traffic": (MEASURED_ADJOINT_TRAFFIC["bytes_per_step"]
+           "traffic": (MEASURED_ADJOINT_TRAFFIC["bytes_per_step"][model]
                        if (MEASURED_ADJOINT_TRAFFIC["storage"] == storage and
                            MEASURED_ADJOINT_TRAFFIC["sources_sha256_16"] ==
                            sources_hash(ADJOINT_SOURCES)) else None)}
@@ -453,6 +458,7 @@ def main():
     adjoint = None
     if not args.no_adjoint:
         adjoint = [measure_adjoint(P, torch, synth, st) for st in ("f32", "f64")]
+        adjoint.append(measure_adjoint(P, torch, synth, "f32", model="mrt"))
         print("bench: adjoint gradient %.2f s (f32)" % adjoint[0]["gradient_s"], flush=True)
     stats = measure_stats(P, torch, synth) if not args.no_others else None
     copy_gbs = copy_bandwidth(P, torch)

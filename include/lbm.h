@@ -389,11 +389,13 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
 
 
 /* ======================================================================
- * Discrete adjoint of the D3Q27 FCLB collide-and-stream step (the FCLB
- * collision of Section 2 with the streaming and boundary rules above).
- * Not an operation of the paper: it differentiates the paper's uniform
- * FCLB update so that gradients of a flow objective with respect to the
- * inlet velocity can be taken through many steps.
+ * Discrete adjoint of the D3Q27 FCLB and D3Q19 MRT-LES collide-and-stream
+ * steps (the collisions of Section 2, Eq. (12) with the Smagorinsky
+ * relaxation time of Eqs. (16)-(21) for MRT-LES, with the streaming and
+ * boundary rules above). Not an operation of the paper: it differentiates
+ * the paper's uniform updates so that gradients of a flow objective with
+ * respect to the inlet velocity can be taken through many steps. Where the
+ * strain magnitude Q of Eq. (19) is zero its derivative is taken as 0.
  *
  * One step maps the pre-collision state f_t to f_{t+1} = S(C(f_t); u_in).
  * For an objective J(f_T), lambda_T = dJ/df_T and
@@ -402,7 +404,7 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
  * inlet-face node and each step, 6 w_i e_i lambda_{t+1,i} over the
  * directions i that bounce back through the inlet face.
  *
- * Layout of f_t and lambda: natural pre-collision order [27][nz][ny][nx] in
+ * Layout of f_t and lambda: natural pre-collision order [Q][nz][ny][nx] in
  * the velocity order of Section 2, as returned by lbm_get_populations (full
  * deviations f_i - w_i for f_t). dtype is the adjoint's arithmetic and
  * storage type: LBM_DTYPE_F64 or LBM_DTYPE_F32, the same for f_t and both
@@ -418,17 +420,19 @@ int lbm_stream_copy(void* dst, const void* src, size_t n, void* stream);
 int lbm_probe_ke(lbm_lattice* lat, const int32_t lo[3], const int32_t hi[3], void* lambda,
                  int dtype, double* J);
 
-/* One FCLB step (as lbm_step with n = 1) that also writes the natural
- * pre-collision state it collides, i.e. what lbm_get_populations would have
- * returned before the step, into rec ([27][nz][ny][nx], device). dtype must
- * be the adjoint's type: LBM_DTYPE_F64 for FP64 storage, LBM_DTYPE_F32 for
- * FP32 storage; FP16 storage and the MRT model give LBM_EINVAL. At inlet and
+/* One FCLB or MRT-LES step (as lbm_step with n = 1) that also writes the
+ * natural pre-collision state it collides, i.e. what lbm_get_populations
+ * would have returned before the step, into rec ([Q][nz][ny][nx], device).
+ * dtype must be the adjoint's type: LBM_DTYPE_F64 for FP64 storage,
+ * LBM_DTYPE_F32 for FP32 storage; FP16 storage, the CLB model, solid nodes
+ * and free-slip or pressure faces give LBM_EINVAL. At inlet and
  * wall nodes of FP32 storage the bounce-back term is added in FP32, as the
  * step computes it (lbm_get_populations adds it in FP64). Asynchronous. */
 int lbm_step_record(lbm_lattice* lat, void* rec, int dtype);
 
 /* One adjoint step: lambda = J_C(f_t)^T S^T lambda_next for the lattice's
- * configuration and boundaries (FCLB only, else LBM_EINVAL). grad_inlet,
+ * configuration and boundaries (FCLB or MRT-LES, without solid nodes,
+ * free-slip or pressure faces, else LBM_EINVAL). grad_inlet,
  * if not NULL, is a device double array [3][nb][na] laid out like the
  * inlet velocity field of lbm_boundaries, to which this step's inlet terms
  * are added. lambda must not alias lambda_next or f_t; one population of an

@@ -1,5 +1,6 @@
 """Gradient of a downstream kinetic-energy probe with respect to an inlet
-velocity perturbation, through many FCLB steps, as a torch.autograd.Function.
+velocity perturbation, through many FCLB or MRT-LES steps, as a
+torch.autograd.Function.
 
 The forward pass runs the lattice from a given state with the inlet's u_z
 raised by ``delta`` on a square of the inlet face, keeps a copy of the raw
@@ -28,7 +29,7 @@ from . import INLET, Lattice, save_state, state_bytes
 class InletProbeObjective:
     """J(delta) for a lattice with an INLET face.
 
-    lattice: a Lattice (FCLB; FP64 or FP32 storage).
+    lattice: a Lattice (FCLB or MRT-LES; FP64 or FP32 storage).
     faces, face_u: boundary description as for Lattice.set_boundaries.
     base_inlet_u: [3, nb, na] float64 inlet velocity without the perturbation.
     square: (b0, b1, a0, a1) index bounds of the perturbed square on the face.

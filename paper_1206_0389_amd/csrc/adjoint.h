@@ -1,4 +1,5 @@
-// Discrete adjoint of the D3Q27 FCLB collide-and-stream step for gfx950.
+// Discrete adjoint of the D3Q27 FCLB and D3Q19 MRT-LES collide-and-stream
+// steps for gfx950.
 //
 // One step maps the pre-collision state f_t to f_{t+1} = S(C(f_t); u_in):
 // collide every node, then stream with the boundary rules (periodic wrap,
@@ -24,10 +25,16 @@
 // be kept. Then the post-collision moment formulas, the shear relaxation,
 // the second-order central moments (dD_ab/du from the first central moments,
 // which for deviations equal u) and u = j / rho are differentiated by hand.
+//
+// The MRT-LES collision (Eq. 12 with the relaxation time of Eqs. 16-21) is
+// reversed the same way in mrt_vjp: the moment relaxation is a fixed linear
+// map apart from the shear rate 1/tau, whose dependence on the node runs
+// through the strain magnitude Q of the non-equilibrium momentum flux.
 #pragma once
 
 #include "fclb.h"
 #include "kernels.h"
+#include "mrt.h"
 
 namespace lbm {
 
@@ -162,17 +169,131 @@ __device__ __forceinline__ void fclb_vjp(const real (&f)[27], real (&g)[27], rea
   }
 }
 
+// g <- J_C(f)^T g for the MRT-LES collision of one node (deviation form),
+// the reverse of mrt_collide: with d = f - f_eq(f), acc_k = (M d)_k and
+// f* = f - M^-1 S(tau(d)) M d,
+//   acc_bar_k = -s_k (M^-T g)_k,  s_bar = -sum over shear rows of (M^-T g)_k acc_k,
+//   d_bar = M^T acc_bar + dPi/dd^T Pi_bar,  Pi_bar from s = 1/tau, Eq. (21) for
+//   tau(Q) and Q = sqrt(2 Pi:Pi) (no strain term where Q = 0),
+//   g <- g + d_bar - J_eq^T d_bar,  J_eq the Jacobian of the incompressible
+//   equilibrium in (drho, j).
+template <typename real, int BASIS>
+__device__ __forceinline__ void mrt_vjp(const real (&f)[19], real (&g)[19], const MrtParams& p) {
+  using T = MrtTables<BASIS>;
+  // forward recomputation: j, d, Pi, Q and tau as in mrt_collide
+  real drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    drho += f[i];
+    if (cx(i)) jx += cx(i) > 0 ? f[i] : -f[i];
+    if (cy(i)) jy += cy(i) > 0 ? f[i] : -f[i];
+    if (cz(i)) jz += cz(i) > 0 ? f[i] : -f[i];
+  }
+  const real uu = jx * jx + jy * jy + jz * jz;
+  real d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const real eu = real(cx(i)) * jx + real(cy(i)) * jy + real(cz(i)) * jz;
+    const real feq = real(weight<19>(i)) *
+                     (drho + real(3) * eu + real(4.5) * eu * eu - real(1.5) * uu);
+    d[i] = f[i] - feq;
+  }
+  real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    if (cx(i)) pxx += d[i];
+    if (cy(i)) pyy += d[i];
+    if (cz(i)) pzz += d[i];
+    if (cx(i) * cy(i)) pxy += cx(i) * cy(i) > 0 ? d[i] : -d[i];
+    if (cx(i) * cz(i)) pxz += cx(i) * cz(i) > 0 ? d[i] : -d[i];
+    if (cy(i) * cz(i)) pyz += cy(i) * cz(i) > 0 ? d[i] : -d[i];
+  }
+  const real pi2 = pxx * pxx + pyy * pyy + pzz * pzz +
+                   real(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+  const real Qs = sqrt(real(2) * pi2);
+  const real tau0 = real(p.tau0);
+  const real root = sqrt(tau0 * tau0 + real(p.cs18) * Qs);
+  const real tau = real(0.5) * (tau0 + root);
+  const real s_shear = real(1) / tau;
+  real rate[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) rate[k] = real(p.rates[k]);
+  // reverse of the relaxation: h = M^-T g over the relaxed rows
+  real db[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) db[i] = 0;
+  real sb = 0;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const int grp = row_group(BASIS, k);
+    if (grp == 0) continue;
+    real h = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      if (is_nonzero(T::Minv.a[i][k])) h += real(T::Minv.a[i][k]) * g[i];
+    if (grp == 1) {
+      real acc = 0;
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        if (is_nonzero(T::M.a[k][i])) acc += real(T::M.a[k][i]) * d[i];
+      sb -= h * acc;
+    }
+    const real ab = -h * (grp == 1 ? s_shear : rate[grp - 2]);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      if (is_nonzero(T::M.a[k][i])) db[i] += real(T::M.a[k][i]) * ab;
+  }
+  // s = 1/tau, tau = (tau0 + sqrt(tau0^2 + cs18 Q)) / 2, Q = sqrt(2 pi2)
+  if (Qs > real(0)) {
+    const real taub = -sb * s_shear * s_shear;
+    const real qb = taub * real(p.cs18) / (real(4) * root);
+    const real pb = qb / Qs;  // d pi2 -> d Q: 1 / Q
+    const real bxx = real(2) * pxx * pb, byy = real(2) * pyy * pb, bzz = real(2) * pzz * pb;
+    const real bxy = real(4) * pxy * pb, bxz = real(4) * pxz * pb, byz = real(4) * pyz * pb;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      real v = 0;
+      if (cx(i)) v += bxx;
+      if (cy(i)) v += byy;
+      if (cz(i)) v += bzz;
+      if (cx(i) * cy(i)) v += cx(i) * cy(i) > 0 ? bxy : -bxy;
+      if (cx(i) * cz(i)) v += cx(i) * cz(i) > 0 ? bxz : -bxz;
+      if (cy(i) * cz(i)) v += cy(i) * cz(i) > 0 ? byz : -byz;
+      db[i] += v;
+    }
+  }
+  // d = f - f_eq(drho, j): the equilibrium's inputs receive -d_bar
+  real rb = 0, jbx = 0, jby = 0, jbz = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const real eu = real(cx(i)) * jx + real(cy(i)) * jy + real(cz(i)) * jz;
+    const real wq = real(weight<19>(i)) * db[i];
+    rb += wq;
+    const real c = wq * (real(3) + real(9) * eu);
+    if (cx(i)) jbx += cx(i) > 0 ? c : -c;
+    if (cy(i)) jby += cy(i) > 0 ? c : -c;
+    if (cz(i)) jbz += cz(i) > 0 ? c : -c;
+  }
+  jbx -= real(3) * jx * rb;
+  jby -= real(3) * jy * rb;
+  jbz -= real(3) * jz * rb;
+#pragma unroll
+  for (int i = 0; i < 19; ++i)
+    g[i] += db[i] - rb - (real(cx(i)) * jbx + real(cy(i)) * jby + real(cz(i)) * jbz);
+}
+
 // One adjoint step over the rows selected by r. f: natural pre-collision
 // state at t; ln: adjoint at t+1; l: adjoint at t (all [27][N]); grad:
 // [3][nb][na] inlet-velocity gradient, accumulated by the inlet-plane nodes
 // (each owns its own entry: at most one inlet face).
-template <typename real, int BCM, int ROWS>
+template <int KIND, typename real, int BCM, int ROWS>
 __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Rows r,
                                                       const real* __restrict__ f,
                                                       const real* __restrict__ ln,
                                                       real* __restrict__ l,
                                                       double* __restrict__ grad) {
-  constexpr int Q = 27;
+  static_assert(KIND >= 0 && KIND <= 2, "the adjoint covers MRT-LES and FCLB");
+  constexpr int Q = Model<KIND>::Q;
   int x, y, z;
   if (!row_coords<ROWS>(a, r, x, y, z)) return;
   const Node n = make_node(a, x, y, z);
@@ -242,7 +363,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LatArgs a, const Row
       });
     }
   }
-  fclb_vjp<real>(fv, m, real(a.omega));
+  if constexpr (KIND == 2)
+    fclb_vjp<real>(fv, m, real(a.omega));
+  else
+    mrt_vjp<real, KIND>(fv, m, a.mrt);
   static_for<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     sto<BCM != BC_GENERAL>(l + (size_t)I * N, self_off, m[I]);

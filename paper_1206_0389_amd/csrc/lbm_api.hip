@@ -188,13 +188,22 @@ void links_dispatch(const lbm_lattice* L, bool after_odd) {
   }
 }
 
-// One FCLB step that also records the pre-collision state (FP64 and FP32
-// storage: the adjoint's recomputation).
-void step_record_dispatch(lbm_lattice* L, bool odd, long long t, void* rec) {
+// One FCLB or MRT-LES step that also records the pre-collision state (FP64
+// and FP32 storage: the adjoint's recomputation).
+template <int KIND>
+void step_record_kind(lbm_lattice* L, bool odd, long long t, void* rec) {
   if (L->cfg.storage == LBM_F64)
-    step_model<2, double>(L, odd, t, rec);
+    step_model<KIND, double>(L, odd, t, rec);
   else
-    step_model<2, float>(L, odd, t, rec);
+    step_model<KIND, float>(L, odd, t, rec);
+}
+
+void step_record_dispatch(lbm_lattice* L, bool odd, long long t, void* rec) {
+  switch (L->kind) {
+    case 0: step_record_kind<0>(L, odd, t, rec); break;
+    case 1: step_record_kind<1>(L, odd, t, rec); break;
+    default: step_record_kind<2>(L, odd, t, rec); break;
+  }
 }
 
 // Slabs spanned by a population and its opposite (see max_opposite_distance).
@@ -629,7 +638,7 @@ int lbm_step(lbm_lattice* L, int64_t n) {
 int lbm_step_record(lbm_lattice* L, void* rec, int dtype) {
   if (!L || !rec || !valid_dtype(dtype)) return LBM_EINVAL;
   if (!L->base) return LBM_EUNBOUND;
-  if (L->kind != 2 || L->cfg.storage == LBM_F16 || L->solids || L->args.bc.freeslip ||
+  if (L->kind > 2 || L->cfg.storage == LBM_F16 || L->solids || L->args.bc.freeslip ||
       L->args.bc.pressure)
     return LBM_EINVAL;
   if (dtype != (L->cfg.storage == LBM_F64 ? LBM_DTYPE_F64 : LBM_DTYPE_F32)) return LBM_EINVAL;
@@ -912,7 +921,7 @@ int lbm_probe_ke(lbm_lattice* L, const int32_t lo[3], const int32_t hi[3], void*
 int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, void* lambda,
                      int dtype, double* grad_inlet) {
   if (!L || !f_t || !lambda_next || !lambda || !valid_dtype(dtype)) return LBM_EINVAL;
-  if (L->kind != 2 || L->solids || L->args.bc.freeslip || L->args.bc.pressure)
+  if (L->kind > 2 || L->solids || L->args.bc.freeslip || L->args.bc.pressure)
     return LBM_EINVAL;
   if (lambda == lambda_next || lambda == f_t) return LBM_EINVAL;
   // the kernels address the adjoint arrays with 32-bit byte offsets: one
@@ -921,32 +930,41 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
   // general kernel takes every row
   const double rsz = dtype == LBM_DTYPE_F64 ? 8.0 : 4.0;
   if ((double)L->N * rsz >= 4294967296.0) return LBM_EINVAL;
-  const bool split = L->split_odd && slab_span(27) * (double)L->N * rsz < 4294967296.0;
-  auto run = [&](auto real_tag) {
+  const int Q = L->kind == 2 ? 27 : 19;
+  const bool split = L->split_odd && slab_span(Q) * (double)L->N * rsz < 4294967296.0;
+  auto run = [&](auto kind_c, auto real_tag) {
+    constexpr int K = decltype(kind_c)::value;
     using R = typename decltype(real_tag)::type;
     const R* f = (const R*)f_t;
     const R* ln = (const R*)lambda_next;
     R* l = (R*)lambda;
     if (!L->has_bc) {
-      hipLaunchKernelGGL((adjoint_kernel<R, BC_NONE, ROWS_BOX>), L->grid, L->block, 0,
+      hipLaunchKernelGGL((adjoint_kernel<K, R, BC_NONE, ROWS_BOX>), L->grid, L->block, 0,
                          L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
     } else if (!split) {
-      hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_BOX>), L->grid, L->block, 0,
+      hipLaunchKernelGGL((adjoint_kernel<K, R, BC_GENERAL, ROWS_BOX>), L->grid, L->block, 0,
                          L->stream, L->args, L->rows_all, f, ln, l, grad_inlet);
     } else {
       if (L->grid_inner.y > 0 && L->grid_inner.z > 0)
-        hipLaunchKernelGGL((adjoint_kernel<R, BC_WALLS, ROWS_BOX>), L->grid_inner, L->block, 0,
-                           L->stream, L->args, L->rows_inner, f, ln, l, grad_inlet);
+        hipLaunchKernelGGL((adjoint_kernel<K, R, BC_WALLS, ROWS_BOX>), L->grid_inner, L->block,
+                           0, L->stream, L->args, L->rows_inner, f, ln, l, grad_inlet);
       if (L->grid_bnd.y > 0)
-        hipLaunchKernelGGL((adjoint_kernel<R, BC_GENERAL, ROWS_LIST>), L->grid_bnd,
+        hipLaunchKernelGGL((adjoint_kernel<K, R, BC_GENERAL, ROWS_LIST>), L->grid_bnd,
                            L->block_bnd, 0, L->stream, L->args, L->rows_bnd, f, ln, l,
                            grad_inlet);
     }
   };
-  if (dtype == LBM_DTYPE_F64)
-    run(std::type_identity<double>{});
-  else
-    run(std::type_identity<float>{});
+  auto by_type = [&](auto kind_c) {
+    if (dtype == LBM_DTYPE_F64)
+      run(kind_c, std::type_identity<double>{});
+    else
+      run(kind_c, std::type_identity<float>{});
+  };
+  switch (L->kind) {
+    case 0: by_type(std::integral_constant<int, 0>{}); break;
+    case 1: by_type(std::integral_constant<int, 1>{}); break;
+    default: by_type(std::integral_constant<int, 2>{}); break;
+  }
   return check_launch();
 }
 

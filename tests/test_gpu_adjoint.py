@@ -1,12 +1,13 @@
-"""Hand-written FCLB adjoint on the GPU against the oracle's dual-number
-adjoint and against finite differences, through the C ABI.
+"""Hand-written FCLB and MRT-LES adjoints on the GPU against the oracle's
+dual-number adjoint and against finite differences, through the C ABI.
 
 FP64: one adjoint step element by element to 1e-12 relative (rounding order
 only), the inlet-gradient terms likewise; the 400-step inlet gradient of the
 cut-down jet against the stored oracle gradient to 1e-10 and against central
 differences of J (GPU, FP64) to 1e-4. FP32: one step to 2e-5 of the largest
 adjoint entry (FP32 rounding of inputs and arithmetic, conditioned like the
-forward collision).
+forward collision). The MRT-LES adjoint (both bases, C_S = 0.1) to the
+same bars, and its multi-step inlet gradient against the oracle's driver.
 """
 import os
 
@@ -36,31 +37,42 @@ FACE_SETS = {
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_jet_32x32x64.txt")
 
 
-def _pair(faces, shape, storage="f64", nu=0.02):
+# name: (library model, oracle model, basis, Smagorinsky constant)
+MODELS = {
+    "fclb": ("fclb", oracle.FCLB27, oracle.BASIS_TABLE1, 0.0),
+    "mrt_table1": ("mrt", oracle.MRT19, oracle.BASIS_TABLE1, 0.1),
+    "mrt_dhumieres": ("mrt", oracle.MRT19, oracle.BASIS_DHUMIERES, 0.1),
+}
+
+
+def _pair(faces, shape, storage="f64", nu=0.02, model="fclb"):
     import paper_1206_0389_amd as Pk
     nx, ny, nz = shape
-    print("case adjoint", faces, shape, storage, flush=True)
+    name, code, basis, cs = MODELS[model]
+    print("case adjoint", model, faces, shape, storage, flush=True)
     iu = None
     if I in faces:
         ax = faces.index(I) // 2
         na = ny if ax == 0 else nx
         nb = ny if ax == 2 else nz
         iu = synth.jet_inlet(na, nb, 2.0, 0.05, 0.002)[0]
-    g = Pk.Lattice(model="fclb", storage=storage, shape=shape, nu=nu)
+    g = Pk.Lattice(model=name, storage=storage, shape=shape, nu=nu, cs_smag=cs, mrt_basis=basis)
     if faces != [P] * 6:
         g.set_boundaries(faces, face_u=FACE_U,
                          inlet_u=None if iu is None else torch.from_numpy(iu))
-    o = oracle.Lattice(oracle.FCLB27, nx, ny, nz, nu=nu, faces=faces, face_u=FACE_U, inlet_u=iu)
+    o = oracle.Lattice(code, nx, ny, nz, nu=nu, faces=faces, face_u=FACE_U, inlet_u=iu,
+                       cs_smag=cs, basis=basis)
     return g, o, iu
 
 
+@pytest.mark.parametrize("model", list(MODELS))
 @pytest.mark.parametrize("faces", list(FACE_SETS))
 @pytest.mark.parametrize("shape", [(6, 5, 7), (37, 9, 11), (300, 3, 4)])
-def test_adjoint_step_parity_fp64(faces, shape):
-    g, o, iu = _pair(FACE_SETS[faces], shape)
+def test_adjoint_step_parity_fp64(faces, shape, model):
+    g, o, iu = _pair(FACE_SETS[faces], shape, model=model)
     nx, ny, nz = shape
-    f = synth.random_populations(27, (nz, ny, nx), 1e-2, seed=8)
-    ln = synth.random_populations(27, (nz, ny, nx), 1.0, seed=9)
+    f = synth.random_populations(g.Q, (nz, ny, nx), 1e-2, seed=8)
+    ln = synth.random_populations(g.Q, (nz, ny, nx), 1.0, seed=9)
     gshape = (3,) + (iu.shape[1:] if iu is not None else (1, 1))
     go = np.zeros(gshape)
     ref = o.adjoint_step(f, ln, go)
@@ -78,13 +90,14 @@ def test_adjoint_step_parity_fp64(faces, shape):
         assert float(np.abs(gg.cpu().numpy() - 2 * go).max()) <= 1e-12 * np.abs(go).max()
 
 
+@pytest.mark.parametrize("model", list(MODELS))
 @pytest.mark.parametrize("faces", ["jet", "periodic"])
-def test_adjoint_step_fp32(faces):
+def test_adjoint_step_fp32(faces, model):
     shape = (37, 9, 11)
-    g, o, iu = _pair(FACE_SETS[faces], shape, storage="f32")
+    g, o, iu = _pair(FACE_SETS[faces], shape, storage="f32", model=model)
     nx, ny, nz = shape
-    f = synth.random_populations(27, (nz, ny, nx), 1e-2, seed=10).astype(np.float32)
-    ln = synth.random_populations(27, (nz, ny, nx), 1.0, seed=11).astype(np.float32)
+    f = synth.random_populations(g.Q, (nz, ny, nx), 1e-2, seed=10).astype(np.float32)
+    ln = synth.random_populations(g.Q, (nz, ny, nx), 1.0, seed=11).astype(np.float32)
     gshape = (3,) + (iu.shape[1:] if iu is not None else (1, 1))
     go = np.zeros(gshape)
     ref = o.adjoint_step(f.astype(np.float64), ln.astype(np.float64), go)
@@ -93,23 +106,25 @@ def test_adjoint_step_fp32(faces):
     gg = torch.zeros(gshape, dtype=torch.float64, device="cuda")
     g.adjoint_step(ft, lt, out, gg if iu is not None else None)
     err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
+    print("FP32 adjoint relative error", err, flush=True)
     assert err <= 2e-5, err
     if iu is not None:
         assert float(np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max()) <= 2e-5
 
 
+@pytest.mark.parametrize("model", ["fclb", "mrt_table1"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_probe_ke_and_seed(storage):
+def test_probe_ke_and_seed(storage, model):
     shape = (12, 10, 14)
-    g, o, _ = _pair(FACE_SETS["jet"], shape, storage=storage)
+    g, o, _ = _pair(FACE_SETS["jet"], shape, storage=storage, model=model)
     nx, ny, nz = shape
-    f = synth.random_populations(27, (nz, ny, nx), 1e-2, seed=12)
+    f = synth.random_populations(g.Q, (nz, ny, nx), 1e-2, seed=12)
     g.set_populations(torch.from_numpy(f))
     g.step(3)  # odd parity: the probe reads the state through the pull rules
     fo = o.run(f, 0, 3)
     lo, hi = (2, 3, 4), (9, 8, 12)
     dt = g.adjoint_dtype
-    lam = torch.empty((27, nz, ny, nx), dtype=dt, device="cuda")
+    lam = torch.empty((g.Q, nz, ny, nx), dtype=dt, device="cuda")
     J = g.probe_ke(lo, hi, lam)
     Jo, lamo = o.probe_ke(fo, lo, hi, grad=True)
     tol = 1e-12 if storage == "f64" else 2e-5
@@ -117,12 +132,12 @@ def test_probe_ke_and_seed(storage):
     assert float(np.abs(lam.double().cpu().numpy() - lamo).max()) <= tol * np.abs(lamo).max()
 
 
-def test_adjoint_rejects_mrt_and_aliasing():
+def test_adjoint_rejects_unsupported_cases_and_aliasing():
     import paper_1206_0389_amd as Pk
-    g = Pk.Lattice(model="mrt", storage="f64", shape=(4, 4, 4), nu=0.02)
-    f = torch.zeros((19, 4, 4, 4), dtype=torch.float64, device="cuda")
+    # no recording step with FP16 storage (the adjoint needs FP32 or FP64)
+    g = Pk.Lattice(model="mrt", storage="f16", shape=(4, 4, 4), nu=0.02)
     with pytest.raises(Pk.LbmError):
-        g.adjoint_step(f, f.clone(), torch.empty_like(f))
+        g.step_record(torch.empty((19, 4, 4, 4), dtype=torch.float32, device="cuda"))
     h = Pk.Lattice(model="fclb", storage="f64", shape=(4, 4, 4), nu=0.02)
     f = torch.zeros((27, 4, 4, 4), dtype=torch.float64, device="cuda")
     lam = torch.zeros_like(f)
@@ -319,21 +334,22 @@ def test_full_jet_gradient_matches_finite_differences(part):
     assert rel <= 1e-4
 
 
+@pytest.mark.parametrize("model", ["fclb", "mrt_dhumieres"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("faces", ["jet", "periodic"])
-def test_step_record_matches_get_populations(storage, faces):
+def test_step_record_matches_get_populations(storage, faces, model):
     """lbm_step_record writes the state lbm_get_populations returns before the
     step (FP64: exactly; FP32: the bounce-back term is added in FP32) and
     advances the lattice exactly like lbm_step."""
     shape = (37, 9, 11)
     nx, ny, nz = shape
-    g1, _, _ = _pair(FACE_SETS[faces], shape, storage=storage)
-    g2, _, _ = _pair(FACE_SETS[faces], shape, storage=storage)
-    f = synth.random_populations(27, (nz, ny, nx), 1e-2, seed=14)
+    g1, _, _ = _pair(FACE_SETS[faces], shape, storage=storage, model=model)
+    g2, _, _ = _pair(FACE_SETS[faces], shape, storage=storage, model=model)
+    f = synth.random_populations(g1.Q, (nz, ny, nx), 1e-2, seed=14)
     for g in (g1, g2):
         g.set_populations(torch.from_numpy(f))
     dt = g1.adjoint_dtype
-    rec = torch.empty((27, nz, ny, nx), dtype=dt, device="cuda")
+    rec = torch.empty((g1.Q, nz, ny, nx), dtype=dt, device="cuda")
     for k in range(3):  # even and odd parities
         want = g1.populations(dt)
         g1.step_record(rec)
@@ -373,3 +389,38 @@ def test_objective_with_zero_and_one_step():
         else:
             assert float(np.abs(grad.cpu().numpy() - go).max()) <= 1e-12 * np.abs(go).max()
         assert float(np.abs(lam0.cpu().numpy() - lo0).max()) <= 1e-12 * np.abs(lo0).max()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["mrt_table1", "mrt_dhumieres"])
+def test_mrt_objective_gradient_matches_oracle(model, storage):
+    """J and dJ/du_in through 24 MRT-LES steps (C_S = 0.1) of a small jet
+    from a random state, checkpoints every 5 steps: FP64 against the
+    oracle's driver to 1e-10, FP32 storage and adjoint to 1e-4."""
+    import paper_1206_0389_amd as Pk
+    from paper_1206_0389_amd.adjoint import InletProbeObjective
+    name, code, basis, cs = MODELS[model]
+    n, nz, D, nsteps, nu = 12, 16, 4, 24, 0.01
+    c = synth.jet_adjoint_case(n, nz, D, u_jet=0.05, u_coflow=COFLOW, sigma=0.005, seed=17)
+    lo, hi = (3, 3, 6), (9, 9, 12)
+    face_u = [[0.0, 0.0, COFLOW] for _ in range(4)] + [[0.0, 0.0, 0.0]] * 2
+    f0 = synth.random_populations(19, (nz, n, n), 1e-3, seed=5)
+    print("case mrt objective", model, storage, flush=True)
+    lat = Pk.Lattice(model=name, storage=storage, shape=(n, n, nz), nu=nu, cs_smag=cs,
+                     mrt_basis=basis)
+    obj = InletProbeObjective(lat, [W, W, W, W, I, O], face_u, torch.from_numpy(c["base_u"]),
+                              c["square"], lo, hi, nsteps, every=5,
+                              f0=torch.from_numpy(f0.astype(np.float32 if storage == "f32"
+                                                            else np.float64)))
+    J = obj.forward(torch.from_numpy(c["delta"]).cuda())
+    grad, lam0 = obj.backward()
+    o = oracle.Lattice(code, n, n, nz, nu=nu, faces=[W, W, W, W, I, O], face_u=face_u,
+                       inlet_u=c["inlet_u"], cs_smag=cs, basis=basis)
+    f0o = f0.astype(np.float32).astype(np.float64) if storage == "f32" else f0
+    Jo, go, lo0 = o.inlet_gradient(f0o, 0, nsteps, lo, hi, every=5)
+    gerr = float(np.linalg.norm(grad.cpu().numpy() - go) / np.linalg.norm(go))
+    lerr = float(np.abs(lam0.double().cpu().numpy() - lo0).max() / np.abs(lo0).max())
+    print("J", J, Jo, "gradient", gerr, "lambda_0", lerr, flush=True)
+    tol = 1e-10 if storage == "f64" else 1e-4
+    assert abs(J - Jo) <= tol * abs(Jo)
+    assert gerr <= tol and lerr <= tol
