@@ -167,7 +167,16 @@ typedef struct lbm_boundaries {
  * left untouched. Limits: fewer than 2^31 nodes, nz <= 65535, and one
  * population's storage (nodes x element size) below 4 GiB: 537 M nodes in
  * FP64, 1.07 G in FP32 (the kernels address a population with 32-bit byte
- * offsets). */
+ * offsets).
+ *
+ * Tracing: with the environment variable LBM_TRACE=1 at creation (here and
+ * in lbm_refined_create), the handle times each step-kernel launch (and the
+ * link, reduction, adjoint and refinement-interface launches) with HIP events
+ * on the stream it runs on, and lbm_destroy / lbm_refined_destroy print per
+ * kernel the calls, total, mean, minimum and maximum time to stderr. The
+ * events are resolved in batches of 1024 launches (the host waits for that
+ * batch); without LBM_TRACE nothing is recorded. Not an operation of the
+ * paper. */
 int lbm_create_lattice(const lbm_config* cfg, lbm_lattice** out);
 
 /* Bytes of device memory the lattice needs (populations, the outflow ghost

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -14,6 +15,7 @@
 #include "adjoint.h"
 #include "jetprofile.h"
 #include "kernels.h"
+#include "trace.h"
 
 using namespace lbm;
 
@@ -49,6 +51,8 @@ struct lbm_lattice {
   // health check inside lbm_step (lbm_set_check)
   int64_t check_every = 0;
   double check_tol = -1.0, check_m0 = 0.0;
+  // per-launch timing (LBM_TRACE=1 at creation)
+  std::unique_ptr<Tracer> tracer = std::make_unique<Tracer>();
 };
 
 namespace {
@@ -76,6 +80,7 @@ void launch_shape(lbm_lattice* L) {
 template <int KIND, typename S, bool ODD, int BCM, int ROWS, bool EXT = false>
 void launch_step(const lbm_lattice* L, dim3 grid, dim3 block, const Rows& r, long long t,
                  void* rec) {
+  TraceScope ts(L->tracer.get(), L->stream, LBM_TRACE_LABEL("step_kernel"));
   hipLaunchKernelGGL((step_kernel<KIND, S, ODD, BCM, ROWS, EXT>), grid, block, 0, L->stream,
                      L->args, r, t, (typename Compute<S>::type*)rec);
 }
@@ -128,6 +133,9 @@ void step_model(const lbm_lattice* L, bool odd, long long t, void* rec) {
       if (by > L->cfg.ny) by = L->cfg.ny;
       const dim3 block(bx, by, 1);
       const dim3 grid((hx + bx - 1) / bx, (L->cfg.ny + by - 1) / by, L->cfg.nz);
+      TraceScope ts(L->tracer.get(), L->stream,
+                    L->has_bc ? "step_even_pair_kernel (FP16, boundaries)"
+                              : "step_even_pair_kernel (FP16)");
       if (L->has_bc)
         hipLaunchKernelGGL((step_even_pair_kernel<KIND, true>), grid, block, 0, L->stream,
                            L->args);
@@ -165,6 +173,7 @@ void step_dispatch(lbm_lattice* L, bool odd, long long t) {
 template <typename S>
 void links_dispatch_s(const lbm_lattice* L, bool after_odd) {
   const dim3 grid((unsigned)((L->nlinks + 7) / 8)), block(256);  // 32 lanes per node
+  TraceScope ts(L->tracer.get(), L->stream, "link_kernel (interpolated bounce-back)");
   auto go = [&](auto q_c, auto odd_c) {
     constexpr int Q = decltype(q_c)::value;
     constexpr bool ODD = decltype(odd_c)::value;
@@ -306,18 +315,19 @@ void default_bc(BcArgs& b) {
 int reduce_now(lbm_lattice* L, double out[5]) {
   double* partial = (double*)(L->base + L->off_partial);
   double* result = (double*)(L->base + L->off_result);
-  with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
-    constexpr int KIND = decltype(kind_c)::value;
-    using S = typename decltype(s_tag)::type;
-    constexpr bool BC = decltype(bc_c)::value;
-    hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
-                       L->args, L->parity, (long long)L->t, partial);
-  });
-  int rc = check_launch();
-  if (rc) return rc;
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
-                     L->nblocks, result);
-  rc = check_launch();
+  {
+    TraceScope ts(L->tracer.get(), L->stream, "reduce_partial_kernel + reduce_final_kernel");
+    with_config(L, [&](auto kind_c, auto s_tag, auto bc_c) {
+      constexpr int KIND = decltype(kind_c)::value;
+      using S = typename decltype(s_tag)::type;
+      constexpr bool BC = decltype(bc_c)::value;
+      hipLaunchKernelGGL((reduce_partial_kernel<KIND, S, BC>), L->grid, L->block, 0, L->stream,
+                         L->args, L->parity, (long long)L->t, partial);
+    });
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, L->stream, partial,
+                       L->nblocks, result);
+  }
+  const int rc = check_launch();
   if (rc) return rc;
   hipError_t e = hipMemcpyAsync(out, result, 5 * sizeof(double), hipMemcpyDeviceToHost,
                                 L->stream);
@@ -877,6 +887,7 @@ int lbm_get_time(const lbm_lattice* L, int64_t* t) {
 }
 
 int lbm_destroy(lbm_lattice* L) {
+  if (L) L->tracer->report("lattice");
   delete L;
   return LBM_OK;
 }
@@ -932,6 +943,7 @@ int lbm_adjoint_step(lbm_lattice* L, const void* f_t, const void* lambda_next, v
   if ((double)L->N * rsz >= 4294967296.0) return LBM_EINVAL;
   const int Q = L->kind == 2 ? 27 : 19;
   const bool split = L->split_odd && slab_span(Q) * (double)L->N * rsz < 4294967296.0;
+  TraceScope ts(L->tracer.get(), L->stream, "adjoint step (adjoint_kernel launches)");
   auto run = [&](auto kind_c, auto real_tag) {
     constexpr int K = decltype(kind_c)::value;
     using R = typename decltype(real_tag)::type;

@@ -8,12 +8,14 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "../../include/lbm.h"
 #include "refine.h"
+#include "trace.h"
 
 using namespace lbm;
 
@@ -82,6 +84,8 @@ struct lbm_refined {
   hipEvent_t ev_ghost[kMaxLevels] = {nullptr};  // aux[l-1]: level l's next ghosts done
   bool aux_tried = false;
   int64_t t = 0;
+  // per-launch timing (LBM_TRACE=1 at creation)
+  std::unique_ptr<Tracer> tracer = std::make_unique<Tracer>();
 };
 
 namespace {
@@ -688,8 +692,12 @@ void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, dou
   const GhostArgs ga = ghost_args(R, l);
   void* Gn = R->base + V.off_G[V.gi[init ? 1 : 2]];
   S* Pc = (S*)(R->base + V.off_pc);
-  hipLaunchKernelGGL((ghost_gather_kernel<KIND, S>), dim3(blocks_for(ga.nu)), dim3(256), 0,
-                     stream, ga, (const S*)fp, Pc);
+  {
+    TraceScope ts(R->tracer.get(), stream, "ghost_gather_kernel", l);
+    hipLaunchKernelGGL((ghost_gather_kernel<KIND, S>), dim3(blocks_for(ga.nu)), dim3(256), 0,
+                       stream, ga, (const S*)fp, Pc);
+  }
+  TraceScope ts(R->tracer.get(), stream, "ghost_patch_kernel", l);
   hipLaunchKernelGGL((ghost_patch_kernel<KIND, S, Rt>), dim3((unsigned)V.groups.size()),
                      dim3(256), 0, stream, ga, (const S*)Pc, (Rt*)Gn,
                      (const Rt*)(R->base + V.off_G[V.gi[1]]),
@@ -704,6 +712,7 @@ void ghost_rescale(lbm_refined* R, int l, void* ff, hipStream_t stream) {
   HostLevel& V = R->lev[l];
   if (V.groups.empty()) return;
   const GhostArgs ga = ghost_args(R, l);
+  TraceScope ts(R->tracer.get(), stream, "ghost_rescale_kernel", l);
   hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
                      stream, ga, (const Rt*)(R->base + V.off_G[V.gi[2]]), rescale_args(R, l),
                      (S*)ff);
@@ -729,6 +738,7 @@ void inject(lbm_refined* R, int l, hipStream_t stream) {
   }
   ia.pN = (long long)V.Nbox;
   ia.cN = (long long)C.Nbox;
+  TraceScope ts(R->tracer.get(), stream, "inject_kernel", l);
   hipLaunchKernelGGL((inject_kernel<KIND, S>), dim3(blocks_for(ia.n)), dim3(256), 0, stream, ia,
                      rescale_args(R, l + 1));
 }
@@ -742,6 +752,7 @@ void level_step(lbm_refined* R, int l, long long t, hipStream_t st) {
   const Lev& D = V.dev;
   if (!V.pre_nodes.empty()) {
     constexpr int Q = Model<KIND>::Q;
+    TraceScope ts(R->tracer.get(), st, "solid_prepass_kernel", l);
     hipLaunchKernelGGL((solid_prepass_kernel<Q, S>), dim3(blocks_for((long long)V.pre_nodes.size())),
                        dim3(256), 0, st, D, (const int*)(R->base + V.off_pre_nodes),
                        (const uint32_t*)(R->base + V.off_pre_dirs),
@@ -755,6 +766,10 @@ void level_step(lbm_refined* R, int l, long long t, hipStream_t st) {
     start += n;
     if (n == 0) continue;
     const dim3 grid((unsigned)n), block(256);
+    static const char* const names[3] = {"level_step_kernel (general tiles)",
+                                         "level_step_kernel (wall tiles)",
+                                         "level_step_kernel (plain tiles)"};
+    TraceScope ts(R->tracer.get(), st, names[k], l);
     if (k == 0)
       hipLaunchKernelGGL((level_step_kernel<KIND, S, TILE_GENERAL>), grid, block, 0, st, D, tl, t);
     else if (k == 1)
@@ -1329,6 +1344,7 @@ int lbm_refined_set_stream(lbm_refined* R, void* stream) {
 }
 
 int lbm_refined_destroy(lbm_refined* R) {
+  if (R) R->tracer->report("refined lattice");
   if (R) destroy_streams(R);
   delete R;
   return LBM_OK;
