@@ -42,12 +42,13 @@ BYTES = {"f64": 8, "f32": 4, "f16": 2}
 # HBM bytes per step of the default workload measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (scaled by a copy kernel of known size), valid only
 # for the step kernel's sources whose hash is recorded with it.
-STEP_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "lbm_api.hip")
-MEASURED_TRAFFIC = {"bytes_per_step": 7.385e9, "sources_sha256_16": "e6b53aeec129398c",
+STEP_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "trace.h", "lbm_api.hip")
+MEASURED_TRAFFIC = {"bytes_per_step": 7.385e9, "sources_sha256_16": "bb6d12c17aa84cc6",
                     "workload": "jet256-fclb-f32"}
 # The same for one adjoint step of the 128 x 128 x 256 jet (FP32), per model.
-ADJOINT_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "adjoint.h", "lbm_api.hip")
-MEASURED_ADJOINT_TRAFFIC = {"sources_sha256_16": "232e08b96a3ca9a0", "storage": "f32",
+ADJOINT_SOURCES = ("stencil.h", "mrt.h", "fclb.h", "kernels.h", "adjoint.h", "trace.h",
+                   "lbm_api.hip")
+MEASURED_ADJOINT_TRAFFIC = {"sources_sha256_16": "53cad682a266f8d5", "storage": "f32",
                             "bytes_per_step": {"fclb": 1.386e9, "mrt": 0.966e9}}
 
 
