@@ -169,15 +169,16 @@ def test_adjoint_rejects_unsupported_cases_and_aliasing():
 N, NZ, D, NSTEPS, NU, COFLOW = 32, 64, 4, 400, 2e-4, 0.002
 
 
-def _jet_objective(storage, every=20, scale=4):
+def _jet_objective(storage, every=20, scale=4, model="fclb"):
     """The inlet-sensitivity jet (128 x 128 x 256, D = 16) with every length
-    divided by scale."""
+    divided by scale (MRT-LES: Table 1 basis, C_S = 0.1)."""
     import paper_1206_0389_amd as Pk
     from paper_1206_0389_amd.adjoint import InletProbeObjective
     n, nz, d = 4 * N // scale, 4 * NZ // scale, 4 * D // scale
     c = synth.jet_adjoint_case(n, nz, d, u_jet=0.05, u_coflow=COFLOW, sigma=0.005, seed=389)
     face_u = [[0.0, 0.0, COFLOW] for _ in range(4)] + [[0.0, 0.0, 0.0]] * 2
-    lat = Pk.Lattice(model="fclb", storage=storage, shape=(n, n, nz), nu=NU)
+    lat = Pk.Lattice(model=model, storage=storage, shape=(n, n, nz), nu=NU,
+                     cs_smag=0.1 if model == "mrt" else 0.0)
     obj = InletProbeObjective(lat, [W, W, W, W, I, O], face_u, torch.from_numpy(c["base_u"]),
                               c["square"], c["probe_lo"], c["probe_hi"], NSTEPS, every=every)
     return obj, c
@@ -215,9 +216,13 @@ def test_cutdown_gradient_fp64_matches_oracle():
     assert np.abs(gf - go).max() <= 1e-10 * np.abs(go).max()
 
 
-def test_cutdown_gradient_matches_finite_differences():
-    """Central differences of J (GPU, FP64, h = 1e-6) for all 16 components."""
-    obj, c = _jet_objective("f64")
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_cutdown_gradient_matches_finite_differences(model):
+    """Central differences of J (GPU, FP64, h = 1e-6) for all 16 components
+    (MRT-LES with the eddy viscosity on: the strain magnitude is zero where
+    the flow has not arrived, where the adjoint takes derivative 0 and the
+    differences see only second-order changes)."""
+    obj, c = _jet_objective("f64", model=model)
     delta = torch.from_numpy(c["delta"]).cuda()
     obj.forward(delta)
     grad, _ = obj.backward()
@@ -232,7 +237,24 @@ def test_cutdown_gradient_matches_finite_differences():
             dm[b, a] -= h
             fd[b, a] = (obj.value(dp) - obj.value(dm)) / (2 * h)
     rel = float(np.linalg.norm(g - fd) / np.linalg.norm(fd))
-    print("adjoint vs FD relative L2", rel, flush=True)
+    print(model, "adjoint vs FD relative L2", rel, flush=True)
+    assert rel <= 1e-4
+
+
+def test_mrt_cutdown_gradient_fp32_close_to_fp64():
+    """MRT-LES: FP32 storage and adjoint against the FP64 gradient (1e-4)."""
+    out = {}
+    for storage in ("f64", "f32"):
+        obj, c = _jet_objective(storage, model="mrt")
+        delta = torch.from_numpy(c["delta"]).cuda()
+        J = obj.forward(delta)
+        grad, _ = obj.backward()
+        b0, b1, a0, a1 = c["square"]
+        out[storage] = (J, grad[2, b0:b1, a0:a1].cpu().numpy())
+    (J64, g64), (J32, g32) = out["f64"], out["f32"]
+    rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    print("MRT FP32 vs FP64 gradient relative L2", rel, "J", J32, J64, flush=True)
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
     assert rel <= 1e-4
 
 
