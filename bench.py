@@ -15,8 +15,9 @@ Prints one JSON line. ``roofline`` prices the step kernel's algorithmic
 traffic, 2 Q b bytes per node update (Q populations of b bytes read and
 written once), against the 8 TB/s HBM peak. ``others`` holds the same
 measurement for the other model/storage combinations. ``adjoint`` times the
-inlet-sensitivity gradient (FCLB adjoint, 128 x 128 x 256 jet, 400 steps,
-checkpoints every 20) and the adjoint step kernel alone, priced at 3 Q b
+inlet-sensitivity gradient (128 x 128 x 256 jet, 400 steps, checkpoints
+every 20; FCLB adjoint in FP32 and FP64, MRT-LES adjoint in FP32) and the
+adjoint step kernel alone, priced at 3 Q b
 bytes per node (state and adjoint read, adjoint written). ``statistics``
 times the velocity time-average accumulation on the default workload.
 ``cpu_baseline``
