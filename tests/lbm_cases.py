@@ -117,6 +117,8 @@ REFINED_CASES = {
     "jet3": (3, True, [W, W, W, W, I, O], None),
     "slab": (2, False, [P] * 6, None),
     "slab3": (3, False, [P] * 6, None),
+    # four nested z bands (level 3 has eight times the resolution)
+    "slab4": (4, False, [P] * 6, None),
     "slip_pressure": (2, True, [W, W, W, F, I, PR], [0, 0, 0, 0, 0, -0.002]),
     "slab_slip_pressure": (2, False, [F, F, PR, PR, P, P], [0, 0, 0.001, -0.001, 0, 0]),
     # 24 x 24 x 32 with the centre 4 x 4 blocks of the first four layers
@@ -125,6 +127,30 @@ REFINED_CASES = {
     # the paper's 11^3 blocks: 44 x 44 x 44, three levels
     "jet3b11": (3, True, [W, W, W, W, I, O], None),
 }
+
+
+# Level-0 viscosity per case (default 0.02). With four levels tau doubles its
+# excess over 1/2 three times: at 0.02 the finest level has tau = 0.98, where
+# the rescaling of the non-equilibrium parts from it back to level 2 (the
+# injection) multiplies them, and their rounding, by 2 (tau_c - 1) / (tau_f -
+# 1) = 26; at 0.005 the levels have tau = 0.515, 0.53, 0.56, 0.62 and the
+# factor is 2.3.
+REFINED_NU = {"slab4": 0.005}
+
+
+def slab_map(levels):
+    """Level map of the 4 x 4 x 64 slab (blocks of 4): nested bands in z."""
+    m = np.zeros((16, 1, 1), dtype=np.uint8)
+    if levels == 2:
+        m[6:10] = 1
+    elif levels == 3:
+        m[4:12] = 1
+        m[7:9] = 2
+    else:
+        m[2:14] = 1
+        m[5:11] = 2
+        m[7:9] = 3
+    return m
 
 
 def refined_jet_geometry(case):

@@ -16,7 +16,8 @@ import pytest
 import oracle
 import synth
 from lbm_cases import (MODELS, REFINED_CASES as CASES, REFINED_FACE_U as FACE_U,  # noqa: F401
-                       REFINED_MODELS, jet_map, read_covered, refined_jet_geometry, rel_err)
+                       REFINED_MODELS, REFINED_NU, jet_map, read_covered, refined_jet_geometry,
+                       rel_err, slab_map)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +33,8 @@ def make_pair(name, storage, case, nu=0.02, cs=0.1, solids=None, links=None):
     import paper_1206_0389_amd as Pk
     model, basis = MODELS[name]
     levels, jet, faces, drho = CASES[case]
-    print("case refine", name, storage, case, flush=True)
+    nu = REFINED_NU.get(case, nu)
+    print("case refine", name, storage, case, "nu", nu, flush=True)
     if jet:
         n, nz, B, m = refined_jet_geometry(case)
         nx = ny = n
@@ -45,11 +47,7 @@ def make_pair(name, storage, case, nu=0.02, cs=0.1, solids=None, links=None):
     else:
         nx = ny = B = 4
         nz = 64
-        m = np.zeros((16, 1, 1), dtype=np.uint8)
-        m[6:10] = 1
-        if levels == 3:
-            m[4:12] = 1
-            m[7:9] = 2
+        m = slab_map(levels)
         iu = im = None
         lius = lims = None
     g = Pk.RefinedLattice(

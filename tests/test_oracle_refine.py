@@ -314,6 +314,29 @@ def test_uniform_flow_is_preserved_through_interfaces(model, levels):
 
 
 @pytest.mark.parametrize("model", MODELS)
+def test_uniform_flow_through_four_levels(model):
+    """A periodic 4 x 4 x 64 slab with three nested refined z bands (levels
+    1-3, level 3 eight times finer) keeps a uniform flow crossing every
+    interface exactly, on every level, over two level-0 steps (16 level-3
+    steps)."""
+    u0 = 0.002
+    c = oracle.Lattice(model, 4, 4, 64, nu=0.02, cs_smag=0.1)
+    m = _slab_map(64, 4, [(2, 14, 1), (5, 11, 2), (7, 9, 3)])
+    R = oracle.Refined(c, 4, m, 4)
+    f0 = []
+    for l in range(4):
+        lat = R.level_lattice(l)
+        d, u = synth.uniform_fields(*R.levels[l]["n"], u=(0.0005, -0.001, u0))
+        f0.append(lat.collide(lat.init_equilibrium(d, u)))
+        R.set_state(l, f0[-1])
+    R.run(0, 2)
+    for l in range(4):
+        act = np.isin(R.types(l), (1, 2))
+        assert act.any(), l
+        assert np.abs((R.state(l) - f0[l])[:, act]).max() < 1e-15, l
+
+
+@pytest.mark.parametrize("model", MODELS)
 def test_nothing_refined_is_the_uniform_lattice(model):
     n = 8
     faces = [W, W, P, P, I, O]

@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 import synth
-from lbm_cases import REFINED_CASES as CASES, REFINED_FACE_U as FACE_U, jet_map, refined_jet_geometry
+from lbm_cases import (REFINED_CASES as CASES, REFINED_FACE_U as FACE_U, jet_map,
+                       refined_jet_geometry, slab_map)
 
 P_ = pytest.importorskip("paper_1206_0389_amd")
 
@@ -87,11 +88,7 @@ def test_library_geometry_matches_oracle(case, model):
         shape = (n, n, nz)
     else:
         shape, B = (4, 4, 64), 4
-        m = np.zeros((16, 1, 1), dtype=np.uint8)
-        m[6:10] = 1
-        if levels == 3:
-            m[4:12] = 1
-            m[7:9] = 2
+        m = slab_map(levels)
     rc, lv = _library_levels(model, oracle.BASIS_TABLE1, shape, B, m, levels, faces, drho)
     assert rc == 0
     iu = [None] + [np.zeros((3, shape[1] << l, shape[0] << l)) for l in range(1, levels)]
