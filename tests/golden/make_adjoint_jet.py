@@ -1,6 +1,6 @@
 """Write the stored FP64 CPU adjoint of the cut-down inlet-sensitivity jet.
 
-    python tests/golden/make_adjoint_jet.py [--fd]
+    python tests/golden/make_adjoint_jet.py [--fd] [--model mrt]
 
 Calls only the oracle (and the seeded input generators). The case is the
 128 x 128 x 256 round jet of the inlet-sensitivity study with every length
@@ -13,7 +13,8 @@ x, y in [12, 20), z in [20, 28) after the last step.
 
 The file holds J and dJ/du on the 4 x 4 square for each velocity component.
 With --fd it also checks the z-components against central differences of J
-(h = 1e-6) and records them.
+(h = 1e-6) and records them. --model mrt writes the same case for the D3Q19
+MRT-LES model (Table 1 basis, C_S = 0.1) into adjoint_jet_mrt_32x32x64.txt.
 """
 import argparse
 import os
@@ -28,8 +29,11 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_jet_32x32x64.txt")
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = {"fclb": os.path.join(HERE, "adjoint_jet_32x32x64.txt"),
+       "mrt": os.path.join(HERE, "adjoint_jet_mrt_32x32x64.txt")}
 N, NZ, D, NSTEPS, NU, COFLOW = 32, 64, 4, 400, 2e-4, 0.002
+MODEL = "fclb"
 
 
 def case():
@@ -40,31 +44,38 @@ def case():
 
 def lattice(inlet_u, face_u):
     W, I, O = oracle.WALL, oracle.INLET, oracle.OUTFLOW
-    return oracle.Lattice(oracle.FCLB27, N, N, NZ, nu=NU, faces=[W, W, W, W, I, O],
-                          face_u=face_u, inlet_u=inlet_u)
+    model, cs = (oracle.FCLB27, 0.0) if MODEL == "fclb" else (oracle.MRT19, 0.1)
+    return oracle.Lattice(model, N, N, NZ, nu=NU, cs_smag=cs, basis=oracle.BASIS_TABLE1,
+                          faces=[W, W, W, W, I, O], face_u=face_u, inlet_u=inlet_u)
 
 
 def objective(inlet_u, face_u, c):
     lat = lattice(inlet_u, face_u)
-    f = lat.run(np.zeros((27, NZ, N, N)), 0, NSTEPS)
+    f = lat.run(np.zeros((lat.Q, NZ, N, N)), 0, NSTEPS)
     return lat.probe_ke(f, c["probe_lo"], c["probe_hi"])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--fd", action="store_true")
+    ap.add_argument("--model", choices=["fclb", "mrt"], default="fclb")
     args = ap.parse_args()
+    global MODEL
+    MODEL = args.model
     oracle.build(force=False)
     c, face_u = case()
     t0 = time.time()
     lat = lattice(c["inlet_u"], face_u)
-    J, grad, _ = lat.inlet_gradient(np.zeros((27, NZ, N, N)), 0, NSTEPS, c["probe_lo"],
+    J, grad, _ = lat.inlet_gradient(np.zeros((lat.Q, NZ, N, N)), 0, NSTEPS, c["probe_lo"],
                                     c["probe_hi"], every=20)
     print(f"adjoint done in {time.time() - t0:.0f} s, J = {J:.17e}", flush=True)
     b0, b1, a0, a1 = c["square"]
     g = grad[:, b0:b1, a0:a1]
-    lines = ["# FP64 CPU adjoint (oracle) of the cut-down inlet-sensitivity jet,",
-             "# written by tests/golden/make_adjoint_jet.py; see its docstring for the case.",
+    name = "FCLB" if MODEL == "fclb" else "MRT-LES (Table 1 basis, C_S = 0.1)"
+    lines = [f"# FP64 CPU adjoint (oracle) of the cut-down inlet-sensitivity jet, {name},",
+             "# written by tests/golden/make_adjoint_jet.py"
+             + ("" if MODEL == "fclb" else " --model mrt")
+             + "; see its docstring for the case.",
              f"J {J:.17e}"]
     for comp in range(3):
         for b in range(D):
@@ -84,9 +95,9 @@ def main():
         assert rel <= 1e-6, rel
         for b in range(D):
             lines.append(f"fd 2 {b} " + " ".join(f"{v:.17e}" for v in fd[b]))
-    with open(OUT, "w") as fh:
+    with open(OUT[MODEL], "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print("wrote", OUT)
+    print("wrote", OUT[MODEL])
 
 
 if __name__ == "__main__":
