@@ -34,7 +34,9 @@ FACE_SETS = {
     "walls_z": [P, P, P, P, W, O],
     "x_inlet": [I, W, P, P, W, O],
 }
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_jet_32x32x64.txt")
+GOLDEN = {m: os.path.join(os.path.dirname(__file__), "golden", f)
+          for m, f in (("fclb", "adjoint_jet_32x32x64.txt"),
+                       ("mrt", "adjoint_jet_mrt_32x32x64.txt"))}
 
 
 # name: (library model, oracle model, basis, Smagorinsky constant)
@@ -184,11 +186,12 @@ def _jet_objective(storage, every=20, scale=4, model="fclb"):
     return obj, c
 
 
-def _golden():
-    if not os.path.exists(GOLDEN):
+def _golden(model="fclb"):
+    path = GOLDEN[model]
+    if not os.path.exists(path):
         pytest.skip("stored oracle gradient not written")
     J, grad, fd = None, np.zeros((3, D, D)), np.zeros((D, D))
-    for line in open(GOLDEN):
+    for line in open(path):
         p = line.split()
         if not p or p[0].startswith("#"):
             continue
@@ -201,9 +204,12 @@ def _golden():
     return J, grad, fd
 
 
-def test_cutdown_gradient_fp64_matches_oracle():
-    Jo, go, _ = _golden()
-    obj, c = _jet_objective("f64")
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_cutdown_gradient_fp64_matches_oracle(model):
+    """J and dJ/du_in (every component) of the 400-step cut-down jet against
+    the oracle's stored FP64 adjoint (MRT-LES: Table 1 basis, C_S = 0.1)."""
+    Jo, go, _ = _golden(model)
+    obj, c = _jet_objective("f64", model=model)
     delta = torch.from_numpy(c["delta"]).cuda().requires_grad_(True)
     J = obj(delta)
     assert abs(float(J.detach()) - Jo) <= 1e-10 * abs(Jo)
