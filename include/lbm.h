@@ -518,7 +518,7 @@ int lbm_refined_geometry(const lbm_refined* r, int32_t level, int32_t lo[3], int
 /* Node types of level l's box (host uint8 [dims z][y][x], codes above). */
 int lbm_refined_types(const lbm_refined* r, int32_t level, uint8_t* types);
 
-/* Bytes of device memory (two arrays per level, node types, tile lists,
+/* Bytes of device memory (three state arrays per level, node types, tile lists,
  * ghost lists and interface history, solid lists, reduction scratch). Valid
  * after the last set_boundaries / set_solids / set_links. */
 int lbm_refined_required_bytes(const lbm_refined* r, size_t* bytes);

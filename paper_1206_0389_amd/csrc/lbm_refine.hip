@@ -43,12 +43,15 @@ struct HostLevel {
   std::vector<int32_t> unodes;              // parent box indices the ghost stencils read
   std::vector<int32_t> pidx;                // per group patch: indices into unodes
   // device offsets
-  size_t off_a = 0, off_b = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
+  size_t off_a = 0, off_b = 0, off_c = 0, off_type = 0, off_tiles = 0, off_ghosts = 0, off_gcode = 0,
          off_groups = 0, off_G[3] = {0, 0, 0}, off_pre_nodes = 0, off_pre_dirs = 0,
          off_pre_q = 0, off_inj = 0, off_unodes = 0, off_pidx = 0, off_pc = 0;
   int gi[3] = {0, 1, 2};  // history buffers holding G(t-1), G(t), G(t+1)
   bool have_cur = false, have_prev = false;
-  bool ghost_pending = false;  // next-step ghosts queued on the parent's stream
+  // The level's three state arrays rotate over its steps: dev.a is read, dev.b
+  // written, c3 is the array the step after next reads (its ghosts are
+  // written ahead by the interpolation of the parent's step).
+  void* c3 = nullptr;
   bool tail_pending = false;   // injection into this level queued on its stream
   Lev dev;
   double tau0 = 0.5;
@@ -78,10 +81,8 @@ struct lbm_refined {
   hipStream_t aux[kMaxLevels] = {nullptr};
   hipEvent_t ev_fork[kMaxLevels] = {nullptr};   // lattice stream -> aux[l]
   hipEvent_t ev_done[kMaxLevels] = {nullptr};   // aux[l]: step and interface done
-  hipEvent_t ev_sub1[kMaxLevels] = {nullptr};   // lattice stream: child substep 1 done
   hipEvent_t ev_sub2[kMaxLevels] = {nullptr};   // lattice stream: child substep 2 done
   hipEvent_t ev_tail[kMaxLevels] = {nullptr};   // aux[l]: injection into level l done
-  hipEvent_t ev_ghost[kMaxLevels] = {nullptr};  // aux[l-1]: level l's next ghosts done
   bool aux_tried = false;
   int64_t t = 0;
   // per-launch timing (LBM_TRACE=1 at creation)
@@ -555,6 +556,7 @@ void layout(lbm_refined* R) {
     const size_t ng = V.ghosts.size();
     V.off_a = o; o += pa;
     V.off_b = o; o += pa;
+    V.off_c = o; o += pa;
     V.off_type = o; o += align256(V.Nbox);
     V.off_tiles = o; o += align256(V.tiles.size() * 4);
     V.off_ghosts = o; o += align256(ng * 4);
@@ -601,6 +603,7 @@ void make_levels(lbm_refined* R) {
     std::memset(&D, 0, sizeof(Lev));
     D.a = R->base ? R->base + V.off_a : nullptr;
     D.b = R->base ? R->base + V.off_b : nullptr;
+    V.c3 = R->base ? R->base + V.off_c : nullptr;
     D.type = R->base ? (const uint8_t*)(R->base + V.off_type) : nullptr;
     for (int d = 0; d < 3; ++d) {
       D.o[d] = V.o[d];
@@ -682,10 +685,10 @@ RescaleArgs rescale_args(const lbm_refined* R, int l) {
 
 // Child level l's ghosts in array ff := rescale(c0 G(t-1) + c1 G(t) + c2
 // Gnew), Gnew = the interpolation of parent state fp, kept as G(t+1) (or as
-// G(t) when `init`).
+// G(t) when `init`), and, if fn is given, in array fn := rescale(Gnew).
 template <int KIND, typename S>
-void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, double c1, double c2,
-                 bool init, hipStream_t stream) {
+void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, void* fn, double c0, double c1,
+                 double c2, bool init, hipStream_t stream) {
   using Rt = typename Compute<S>::type;
   HostLevel& V = R->lev[l];
   if (V.groups.empty()) return;
@@ -702,20 +705,7 @@ void ghost_patch(lbm_refined* R, int l, const void* fp, void* ff, double c0, dou
                      dim3(256), 0, stream, ga, (const S*)Pc, (Rt*)Gn,
                      (const Rt*)(R->base + V.off_G[V.gi[1]]),
                      (const Rt*)(R->base + V.off_G[V.gi[0]]), c0, c1, c2, rescale_args(R, l),
-                     (S*)ff);
-}
-
-// Child level l's ghosts in array ff := rescale(G(t+1)).
-template <int KIND, typename S>
-void ghost_rescale(lbm_refined* R, int l, void* ff, hipStream_t stream) {
-  using Rt = typename Compute<S>::type;
-  HostLevel& V = R->lev[l];
-  if (V.groups.empty()) return;
-  const GhostArgs ga = ghost_args(R, l);
-  TraceScope ts(R->tracer.get(), stream, "ghost_rescale_kernel", l);
-  hipLaunchKernelGGL((ghost_rescale_kernel<KIND, S, Rt>), dim3(blocks_for(ga.ng)), dim3(256), 0,
-                     stream, ga, (const Rt*)(R->base + V.off_G[V.gi[2]]), rescale_args(R, l),
-                     (S*)ff);
+                     (S*)ff, (S*)fn);
 }
 
 // Covered nodes of level l read by its steps := the rescaled mean of their
@@ -779,17 +769,25 @@ void level_step(lbm_refined* R, int l, long long t, hipStream_t st) {
   }
 }
 
-void swap_arrays(HostLevel& V) { std::swap(V.dev.a, V.dev.b); }
+// After a step of level V: the array written becomes the one read, the one
+// the step after next reads becomes the one written.
+void rotate_arrays(HostLevel& V) {
+  void* read = V.dev.a;
+  V.dev.a = V.dev.b;
+  V.dev.b = V.c3;
+  V.c3 = read;
+}
 
 // Advance level l by one of its steps (index t), and recursively the finer
 // levels by two steps each, on the lattice's stream M. The child's first
 // substep reads only ghosts prepared from the parent's state before this
 // step, so with the parent's own stream X = aux[l] the parent's work runs
 // there beside the child's substeps:
-//   X: parent step, interpolation of the ghosts for substep 2;
+//   X: parent step, interpolation of the ghosts for substep 2 (into the
+//      array substep 1 writes and substep 2 reads) and of the ghosts of the
+//      next parent step's first substep (into the child's third array, which
+//      substep 2 writes and nothing reads before that step);
 //   M: substep 1;
-//   X: after substep 1, the ghosts of the next first substep (slots that
-//      substep 1 read and substep 2 does not touch);
 //   M: after the interpolation, substep 2;
 //   X: after substep 2, injection into the parent (beside the next first
 //      substep on M, which does not read the parent).
@@ -802,12 +800,12 @@ void advance(lbm_refined* R, int l, long long t) {
   const bool child = l + 1 < R->L && R->lev[l + 1].Nbox > 0;
   if (!child) {
     level_step<KIND, S>(R, l, t, M);
-    swap_arrays(V);
+    rotate_arrays(V);
     return;
   }
   HostLevel& C = R->lev[l + 1];
   if (!C.have_cur) {
-    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, 0.0, 0.0, 1.0, true, M);
+    ghost_patch<KIND, S>(R, l + 1, V.dev.a, C.dev.a, nullptr, 0.0, 0.0, 1.0, true, M);
     C.have_cur = true;
     C.have_prev = false;
   }
@@ -822,20 +820,10 @@ void advance(lbm_refined* R, int l, long long t) {
   level_step<KIND, S>(R, l, t, X);
   const double c0 = C.have_prev ? -0.125 : 0.0, c1 = C.have_prev ? 0.75 : 0.5,
                c2 = C.have_prev ? 0.375 : 0.5;
-  ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, c0, c1, c2, false, X);
+  ghost_patch<KIND, S>(R, l + 1, V.dev.b, C.dev.b, C.c3, c0, c1, c2, false, X);
   if (two) (void)hipEventRecord(R->ev_done[l], X);
-  if (C.ghost_pending) {  // the first substep reads the ghosts of the last step
-    (void)hipStreamWaitEvent(M, R->ev_ghost[l + 1], 0);
-    C.ghost_pending = false;
-  }
   advance<KIND, S>(R, l + 1, 2 * t);
-  to(M, X, R->ev_sub1[l]);
-  ghost_rescale<KIND, S>(R, l + 1, C.dev.b, X);  // C's arrays swapped once since substep 1
-  if (two) {
-    (void)hipEventRecord(R->ev_ghost[l + 1], X);
-    C.ghost_pending = true;
-    (void)hipStreamWaitEvent(M, R->ev_done[l], 0);
-  }
+  if (two) (void)hipStreamWaitEvent(M, R->ev_done[l], 0);
   advance<KIND, S>(R, l + 1, 2 * t + 1);
   to(M, X, R->ev_sub2[l]);
   inject<KIND, S>(R, l, X);
@@ -848,7 +836,7 @@ void advance(lbm_refined* R, int l, long long t) {
   C.gi[1] = C.gi[2];
   C.gi[2] = old;
   C.have_prev = true;
-  swap_arrays(V);
+  rotate_arrays(V);
 }
 
 void destroy_streams(lbm_refined* R) {
@@ -857,12 +845,10 @@ void destroy_streams(lbm_refined* R) {
       (void)hipStreamSynchronize(R->aux[l]);
       (void)hipStreamDestroy(R->aux[l]);
     }
-    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub1[l], &R->ev_sub2[l],
-                          &R->ev_tail[l], &R->ev_ghost[l]})
+    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub2[l], &R->ev_tail[l]})
       if (*e) (void)hipEventDestroy(*e);
     R->aux[l] = nullptr;
-    R->ev_fork[l] = R->ev_done[l] = R->ev_sub1[l] = R->ev_sub2[l] = R->ev_tail[l] =
-        R->ev_ghost[l] = nullptr;
+    R->ev_fork[l] = R->ev_done[l] = R->ev_sub2[l] = R->ev_tail[l] = nullptr;
   }
 }
 
@@ -871,8 +857,7 @@ void destroy_streams(lbm_refined* R) {
 void create_streams(lbm_refined* R) {
   bool ok = true;
   for (int l = 0; l < R->L && ok; ++l) {
-    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub1[l], &R->ev_sub2[l],
-                          &R->ev_tail[l], &R->ev_ghost[l]})
+    for (hipEvent_t* e : {&R->ev_fork[l], &R->ev_done[l], &R->ev_sub2[l], &R->ev_tail[l]})
       ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     if (l + 1 < R->L)
       ok = ok && hipStreamCreateWithFlags(&R->aux[l], hipStreamNonBlocking) == hipSuccess;
@@ -1283,10 +1268,6 @@ int lbm_refined_step(lbm_refined* R, int64_t n) {
   // callers see single-stream semantics: join the work still queued on the
   // parent levels' streams
   for (int l = 0; l < R->L; ++l) {
-    if (R->lev[l].ghost_pending) {
-      (void)hipStreamWaitEvent(R->stream, R->ev_ghost[l], 0);
-      R->lev[l].ghost_pending = false;
-    }
     if (R->lev[l].tail_pending) {
       (void)hipStreamWaitEvent(R->stream, R->ev_tail[l], 0);
       R->lev[l].tail_pending = false;

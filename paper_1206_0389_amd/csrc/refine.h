@@ -570,21 +570,26 @@ __global__ __launch_bounds__(256) void ghost_gather_kernel(const GhostArgs ga, c
 // 256 threads): the parent patch is staged in LDS from the gathered copy Pc,
 // every (ghost, population) is interpolated from it into Gn (kept for the
 // following steps), and the time combination c0 Gm + c1 Gc + c2 Gn (Gm, Gc
-// not read where their weight is 0; G* are [Q][ng]) goes back to LDS, where
-// one thread per ghost rescales it and stores the ghost into the child array
-// ff.
+// not read where their weight is 0; G* are [Q][ng]) goes back to LDS with
+// Gn itself; one thread per ghost rescales the combination into the child
+// array ff (the next substep's ghosts) and, if fn is given, another rescales
+// Gn into the child array fn (the ghosts of the first substep of the next
+// parent step).
 template <int KIND, typename S, typename R>
 __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, const S* Pc, R* Gn,
                                                           const R* Gc, const R* Gm, double c0,
                                                           double c1, double c2,
-                                                          const RescaleArgs ra, S* ff) {
+                                                          const RescaleArgs ra, S* ff, S* fn) {
+  static_assert(2 * kGhostMax <= 256, "one thread per ghost and value set");
   constexpr int Q = Model<KIND>::Q;
-  // the patch, then (after it is read) the ghosts' combined values
+  // the patch, then (after it is read) the ghosts' combined and new values
   constexpr size_t kPatchBytes = sizeof(S) * Q * kPatchMax;
   constexpr size_t kHBytes = sizeof(R) * Q * kGhostMax;
-  __shared__ __align__(16) unsigned char lds[kPatchBytes > kHBytes ? kPatchBytes : kHBytes];
+  __shared__ __align__(16) unsigned char
+      lds[kPatchBytes > 2 * kHBytes ? kPatchBytes : 2 * kHBytes];
   S(&sp)[Q][kPatchMax] = *reinterpret_cast<S(*)[Q][kPatchMax]>(lds);
   R(&hs)[Q][kGhostMax] = *reinterpret_cast<R(*)[Q][kGhostMax]>(lds);
+  R(&gs)[Q][kGhostMax] = *reinterpret_cast<R(*)[Q][kGhostMax]>(lds + kHBytes);
   const GhostGroup* grp = (const GhostGroup*)ga.groups + blockIdx.x;
   const long long gbeg = grp->gbeg;
   const int ngg = grp->gend - grp->gbeg;
@@ -615,52 +620,45 @@ __global__ __launch_bounds__(256) void ghost_patch_kernel(const GhostArgs ga, co
     });
   }
   __syncthreads();
-  R h[kItems];
+  R h[kItems], g[kItems];
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int k = threadIdx.x + 256 * it;
     const int q = k / kGhostMax, gl = k % kGhostMax;
     h[it] = R(0);
+    g[it] = R(0);
     if (k >= Q * kGhostMax || gl >= ngg) continue;
     const long long gi = gbeg + gl;
     const R v = patch_interp<S, R>(sp[q], ga.gcode[gi], m0, m01);
     Gn[(size_t)q * ga.ng + gi] = v;
+    g[it] = v;
     h[it] = R(c2) * v + hist[it];
   }
-  __syncthreads();  // the patch is read: its space takes the combined values
+  __syncthreads();  // the patch is read: its space takes the ghosts' values
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int k = threadIdx.x + 256 * it;
-    if (k < Q * kGhostMax) hs[k / kGhostMax][k % kGhostMax] = h[it];
+    if (k < Q * kGhostMax) {
+      hs[k / kGhostMax][k % kGhostMax] = h[it];
+      gs[k / kGhostMax][k % kGhostMax] = g[it];
+    }
   }
   __syncthreads();
-  if ((int)threadIdx.x < ngg) {
-    const int gl = threadIdx.x;
+  // threads [0, ngg): the combined values into ff; threads [kGhostMax,
+  // kGhostMax + ngg): the new values into fn (when given)
+  const int tl = threadIdx.x;
+  const bool second = tl >= kGhostMax;
+  const int gl = second ? tl - kGhostMax : tl;
+  if (gl < ngg && (!second || fn != nullptr)) {
     R f[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = hs[q][gl];
+    for (int q = 0; q < Q; ++q) f[q] = second ? gs[q][gl] : hs[q][gl];
     rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
     const int l = ga.ghosts[gbeg + gl];
+    S* dst = second ? fn : ff;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
+    for (int q = 0; q < Q; ++q) st(dst + (size_t)q * (size_t)ga.cN + l, f[q]);
   }
-}
-
-// Ghosts of ff := rescale(G), one thread per ghost in the group order (G:
-// [Q][ng] read in order; the stores follow the groups' small boxes).
-template <int KIND, typename S, typename R>
-__global__ __launch_bounds__(256) void ghost_rescale_kernel(const GhostArgs ga, const R* G,
-                                                            const RescaleArgs ra, S* ff) {
-  constexpr int Q = Model<KIND>::Q;
-  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ga.ng) return;
-  R f[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = G[(size_t)q * ga.ng + gi];
-  rescale_node<KIND, +1, R>(f, ra.tau0_c, ra.tau0_f, ra.cs, ra.r, ra.rates);
-  const int l = ga.ghosts[gi];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) st(ff + (size_t)q * (size_t)ga.cN + l, f[q]);
 }
 
 // ------------------------------------------------------------- reductions
