@@ -205,3 +205,15 @@ def test_binding_mirrors_every_declared_entry_point():
     import paper_1206_0389_amd as P
     missing = [n for n in _declared() if n not in P._SIGS]
     assert not missing, missing
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU: --gpus N with N > 1 exits non-zero with a
+    message, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=root)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
