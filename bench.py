@@ -13,7 +13,9 @@ the stream the kernels run on, bracketed by device synchronisation.
 
 Prints one JSON line. ``roofline`` prices the step kernel's algorithmic
 traffic, 2 Q b bytes per node update (Q populations of b bytes read and
-written once), against the 8 TB/s HBM peak. ``others`` holds the same
+written once), against the 8 TB/s HBM peak; its ``traffic`` is the HBM
+traffic per step measured in the same run by two rocprofv3 counter passes
+over a short child run (``--traffic off`` skips them). ``others`` holds the same
 measurement for the other model/storage combinations. ``adjoint`` times the
 inlet-sensitivity gradient (128 x 128 x 256 jet, 400 steps, checkpoints
 every 20; FCLB adjoint in FP32 and FP64, MRT-LES adjoint in FP32) and the
@@ -27,10 +29,16 @@ workload.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import json
 import os
+import re
+import shutil
+import signal
 import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -72,7 +80,98 @@ def parse():
     p.add_argument("--no-others", action="store_true")
     p.add_argument("--other-steps", type=int, default=50)
     p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--traffic", choices=["auto", "off"], default="auto",
+                   help="measure the step kernels' HBM traffic with rocprofv3 counter passes "
+                        "over a short child run (auto: when rocprofv3 is available)")
     return p.parse_args()
+
+
+COPY_BYTES = 4 << 30  # the copy probe's size (copy_bandwidth)
+
+
+def _run_counter_pass(exe, counter, workload, outdir, timeout):
+    """One rocprofv3 --pmc pass over a short child run of this script;
+    returns the rows of its counter csv (or raises RuntimeError)."""
+    cmd = [exe, "--pmc", counter, "--output-format", "csv", "-d", outdir, "-o", counter.lower(),
+           "--", sys.executable, os.path.abspath(__file__), "--workload", workload, "--steps",
+           "3", "--warmup", "1", "--no-others", "--no-adjoint", "--no-cpu-baseline",
+           "--traffic", "off"]
+    env = dict(os.environ, TMPDIR=os.environ.get("TMPDIR", "/tmp"))
+    proc = subprocess.Popen(cmd, cwd="/tmp", env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.STDOUT, text=True, start_new_session=True)
+    try:
+        out, _ = proc.communicate(timeout=timeout)
+    except subprocess.TimeoutExpired:
+        os.killpg(proc.pid, signal.SIGKILL)
+        proc.communicate()
+        raise RuntimeError("%s pass timed out" % counter)
+    files = glob.glob(os.path.join(outdir, "**", "%s_counter_collection.csv" % counter.lower()),
+                      recursive=True)
+    # the profiler may end with a non-zero status after the program's
+    # results are complete: accept the run when the child printed its line
+    if not files or '"metric"' not in out:
+        raise RuntimeError("%s pass failed (status %s)" % (counter, proc.returncode))
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _step_kernel_kib(rows):
+    """Sum of the counter over the step-kernel dispatches, the number of
+    steps they make (even launches plus odd steps, counted by the widest odd
+    launch) and the copy probe's mean value per dispatch."""
+    total, even, odd, copies = 0.0, 0, {}, []
+    for r in rows:
+        name, v = r["Kernel_Name"], float(r["Counter_Value"])
+        grid = r.get("Grid_Size", r.get("Grid_Size_X", "0"))
+        if "copy_kernel" in name:
+            copies.append(v)
+            continue
+        m = re.search(r"step_kernel<[^,]+, [^,]+, (true|false)", name)
+        if "step_even_pair_kernel<" in name:
+            even += 1
+        elif m and "level_step" not in name:
+            if m.group(1) == "false":
+                even += 1
+            else:
+                odd[int(grid)] = odd.get(int(grid), 0) + 1
+        elif "link_kernel" not in name:
+            continue
+        total += v
+    steps = even + (odd[max(odd)] if odd else 0)
+    return total, steps, (sum(copies) / len(copies) if copies else None)
+
+
+def live_traffic(workload, timeout=300):
+    """HBM bytes per step of the workload's step kernels (and link kernel),
+    from two counter passes (FETCH_SIZE, then WRITE_SIZE) over a short child
+    run, each scaled by what the counter reads for the copy kernel of known
+    size in the same run. Runs before this process touches the GPU. Returns
+    (bytes per step, description) or (None, reason)."""
+    exe = shutil.which("rocprofv3")
+    if exe is None:
+        return None, "rocprofv3 not available"
+    outdir = tempfile.mkdtemp(prefix="lbm_traffic_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        parts = {}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            print("bench: traffic pass", counter, flush=True)
+            total, steps, copy_kib = _step_kernel_kib(
+                _run_counter_pass(exe, counter, workload, outdir, timeout))
+            if steps == 0 or not copy_kib:
+                return None, "no step or copy dispatches in the %s pass" % counter
+            scale = (COPY_BYTES / 1024.0) / copy_kib
+            parts[counter] = (total * scale * 1024.0 / steps, scale, steps)
+        f, w = parts["FETCH_SIZE"], parts["WRITE_SIZE"]
+        return f[0] + w[0], ("measured in this run: rocprofv3 --pmc FETCH_SIZE (x%.3f) and "
+                             "WRITE_SIZE (x%.3f, the copy kernel's ratios) over %d steps of "
+                             "a child run" % (f[1], w[1], f[2]))
+    except (RuntimeError, OSError, KeyError, ValueError) as e:
+        return None, str(e)
+    finally:
+        shutil.rmtree(outdir, ignore_errors=True)
 
 
 def kind_refined(name):
@@ -437,6 +536,9 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    live = (None, "off")
+    if args.traffic == "auto" and not kind_refined(args.workload):
+        live = live_traffic(args.workload)  # child runs, before this process uses the GPU
     import torch
     import paper_1206_0389_amd as P
     import synth
@@ -473,15 +575,23 @@ def main():
         shape[0] * shape[1] * shape[2])
     roof = {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": main_res["achieved_GBs"] / HBM_PEAK_GBS,
-            "traffic": (MEASURED_TRAFFIC["bytes_per_step"]
-                        if (MEASURED_TRAFFIC["sources_sha256_16"] == sources_hash()
-                            and MEASURED_TRAFFIC["workload"] == args.workload) else None),
+            "traffic": None,
             "traffic_unit": "bytes per step (one even launch, or the two odd launches)",
             "kernel": ("refined coarse step (level steps and interface kernels) <%s,%s>"
                        if refined else "step_kernel<%s,%s>") % (model, storage),
             "algorithmic_bytes_per_launch": alg_per_launch,
             "copy_probe_GBs": copy_gbs,
             "frac_of_copy_probe": main_res["achieved_GBs"] / copy_gbs}
+    stored_ok = (MEASURED_TRAFFIC["sources_sha256_16"] == sources_hash()
+                 and MEASURED_TRAFFIC["workload"] == args.workload)
+    if live[0] is not None:
+        roof["traffic"], roof["traffic_source"] = live[0], live[1]
+    elif stored_ok:
+        roof["traffic"] = MEASURED_TRAFFIC["bytes_per_step"]
+        roof["traffic_source"] = ("stored counter passes of these sources (hash %s; live "
+                                  "measurement: %s)" % (sources_hash(), live[1]))
+    else:
+        roof["traffic_source"] = "not measured (%s)" % live[1]
     line = {"metric": METRIC, "value": main_res["mlups"], "unit": "MLUPS", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
