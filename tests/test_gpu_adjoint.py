@@ -392,20 +392,24 @@ def test_step_record_matches_get_populations(storage, faces, model):
         g1.step_record(rec.to(torch.float32 if dt == torch.float64 else torch.float64))
 
 
-def test_objective_with_zero_and_one_step():
+@pytest.mark.parametrize("model", ["fclb", "mrt_dhumieres"])
+def test_objective_with_zero_and_one_step(model):
     """nsteps = 0: J is the probe of the initial state and nothing depends on
     the inlet; nsteps = 1: J and dJ/du_in against the oracle's driver."""
     import paper_1206_0389_amd as Pk
     from paper_1206_0389_amd.adjoint import InletProbeObjective
+    name, code, basis, cs = MODELS[model]
     n, nz, D = 12, 16, 4
     c = synth.jet_adjoint_case(n, nz, D, u_jet=0.05, u_coflow=COFLOW, sigma=0.005, seed=7)
     lo, hi = (3, 3, 2), (9, 9, 6)
     face_u = [[0.0, 0.0, COFLOW] for _ in range(4)] + [[0.0, 0.0, 0.0]] * 2
-    f0 = synth.random_populations(27, (nz, n, n), 1e-2, seed=4)
-    o = oracle.Lattice(oracle.FCLB27, n, n, nz, nu=0.02, faces=[W, W, W, W, I, O], face_u=face_u,
-                       inlet_u=c["inlet_u"])
+    q = 27 if code == oracle.FCLB27 else 19
+    f0 = synth.random_populations(q, (nz, n, n), 1e-2, seed=4)
+    o = oracle.Lattice(code, n, n, nz, nu=0.02, faces=[W, W, W, W, I, O], face_u=face_u,
+                       inlet_u=c["inlet_u"], cs_smag=cs, basis=basis)
     for nsteps in (0, 1):
-        lat = Pk.Lattice(model="fclb", storage="f64", shape=(n, n, nz), nu=0.02)
+        lat = Pk.Lattice(model=name, storage="f64", shape=(n, n, nz), nu=0.02, cs_smag=cs,
+                         mrt_basis=basis)
         obj = InletProbeObjective(lat, [W, W, W, W, I, O], face_u, torch.from_numpy(c["base_u"]),
                                   c["square"], lo, hi, nsteps, every=1, f0=torch.from_numpy(f0))
         J = obj.forward(torch.from_numpy(c["delta"]).cuda())
