@@ -314,37 +314,46 @@ def test_checkpoint_spacing_does_not_change_gradient():
 _FULL = {}
 
 
-def _full_gradients():
-    """FP64 and FP32 adjoint gradients of the full-size jet, computed once."""
-    if not _FULL:
+def _full_gradients(model="fclb"):
+    """FP64 and FP32 adjoint gradients of the full-size jet, computed once
+    per model (the FP64 objective kept for the difference quotients)."""
+    if model not in _FULL:
+        for other in list(_FULL):  # one model's checkpoints at a time
+            del _FULL[other]
+        torch.cuda.empty_cache()
+        r = {}
         for storage in ("f64", "f32"):
-            obj, c = _jet_objective(storage, scale=1)
+            obj, c = _jet_objective(storage, scale=1, model=model)
             delta = torch.from_numpy(c["delta"]).cuda()
             J = obj.forward(delta)
             grad, _ = obj.backward()
             b0, b1, a0, a1 = c["square"]
-            _FULL[storage] = (J, grad[2, b0:b1, a0:a1].cpu().numpy())
+            r[storage] = (J, grad[2, b0:b1, a0:a1].cpu().numpy())
             if storage == "f64":
-                _FULL["obj"], _FULL["delta"] = obj, delta
+                r["obj"], r["delta"] = obj, delta
             del obj
             torch.cuda.empty_cache()
-    return _FULL
+        _FULL[model] = r
+    return _FULL[model]
 
 
-def test_full_jet_fp32_gradient_close_to_fp64():
-    r = _full_gradients()
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_full_jet_fp32_gradient_close_to_fp64(model):
+    r = _full_gradients(model)
     (J64, g64), (J32, g32) = r["f64"], r["f32"]
     rel = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
-    print("full jet: J", J64, J32, "FP32 vs FP64 gradient relative L2", rel, flush=True)
+    print("full jet", model, ": J", J64, J32, "FP32 vs FP64 gradient relative L2", rel,
+          flush=True)
     assert abs(J32 - J64) <= 1e-4 * abs(J64)
     assert rel <= 1e-4
 
 
 @pytest.mark.parametrize("part", range(4))
-def test_full_jet_gradient_matches_finite_differences(part):
+@pytest.mark.parametrize("model", ["fclb", "mrt"])
+def test_full_jet_gradient_matches_finite_differences(part, model):
     """Central differences of J (FP64, h = 1e-6) for all 256 components,
-    a quarter per test."""
-    r = _full_gradients()
+    a quarter per test (MRT-LES: Table 1 basis, C_S = 0.1)."""
+    r = _full_gradients(model)
     obj, delta = r["obj"], r["delta"]
     g = r["f64"][1]
     h = 1e-6
@@ -358,7 +367,7 @@ def test_full_jet_gradient_matches_finite_differences(part):
             fd[k, a] = (obj.value(dp) - obj.value(dm)) / (2 * h)
     ga = g[4 * part:4 * part + 4]
     rel = float(np.linalg.norm(ga - fd) / np.linalg.norm(fd))
-    print("full jet rows", list(rows), "adjoint vs FD relative L2", rel, flush=True)
+    print("full jet", model, "rows", list(rows), "adjoint vs FD relative L2", rel, flush=True)
     assert rel <= 1e-4
 
 
