@@ -27,10 +27,11 @@ Parity status of each oracle function (what pins it, see tests/):
                               spectrum (1 - omega shear, trace removed),
                               conservation, equilibrium tangent fixed
   collide_jvp (MRT-LES)       central differences in both bases with the
-                              eddy viscosity on, rest-state spectrum (each
-                              non-conserved moment mode scaled by 1 - s_k),
-                              conservation, the strain derivative of tau
-                              against Eq. (21) differentiated by hand
+                              eddy viscosity on (and differing from the
+                              product without it), rest-state spectrum (each
+                              non-conserved moment mode scaled by 1 - s_k,
+                              Table 1 multiplicities), conservation, the
+                              incompressible equilibrium tangent fixed
   tangent_step / adjoint_step central differences of run; dot-product identity;
                               periodic mass/momentum adjoint invariants
   probe_ke, inlet_gradient    central differences of J through many steps
