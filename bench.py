@@ -262,7 +262,7 @@ def make_lattice(name, P, torch, synth):
                                "/".join(str(int((lmap >= l).sum())) for l in range(1, levels)),
                                levels - 1, "; level 2: layers 0-3, radius <= 34"
                                if levels == 3 else ""),
-                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "collision": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
                 "updated_nodes_per_level": per, "ghost_nodes_per_level":
                     [v["counts"]["ghost"] for v in lat.levels],
                 "covered_per_level": [v["counts"]["covered"] for v in lat.levels],
@@ -298,7 +298,7 @@ def make_lattice(name, P, torch, synth):
         desc = {"workload": "round jet %dx%dx%d, D=%d inlet u=0.05 +1%% seeded perturbation, "
                             "co-flow 0.002 moving side walls, zero-gradient outflow, nu=1e-4%s"
                             % (nx, ny, nz, int(diam), extra),
-                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "collision": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
                 "cs_smag": cs if model == "mrt" else None}
     else:
         nu, cs = (4.0e-3 if nx == 128 else 1e-3), 0.1
@@ -306,7 +306,7 @@ def make_lattice(name, P, torch, synth):
         d, u = synth.taylor_green((nx, ny, nz), 0.05)
         d, u = d.astype(np.float32), u.astype(np.float32)
         desc = {"workload": "periodic Taylor-Green %dx%dx%d, u0=0.05, nu=%g" % (nx, ny, nz, nu),
-                "model": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
+                "collision": model, "storage": storage, "nx": nx, "ny": ny, "nz": nz,
                 "cs_smag": cs if model == "mrt" else None}
     lat.init_equilibrium(torch.from_numpy(d), torch.from_numpy(u))
     del d, u
@@ -413,7 +413,7 @@ def measure_adjoint(P, torch, synth, storage="f32", steps=50, model="fclb"):
     out = {"workload": "inlet-sensitivity jet 128x128x256 %s, D=16 u=0.05 nu=2e-4, 400 "
                        "steps, checkpoints every 20, 16x16 u_z perturbation (sigma 0.005, seed "
                        "389), probe 32^3 at z in [80,112)" % name,
-           "model": model, "storage": storage, "J": J, "grad_l2": gnorm, "gradient_s": t2 - t0,
+           "collision": model, "storage": storage, "J": J, "grad_l2": gnorm, "gradient_s": t2 - t0,
            "forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_step_ms": ms,
            "adjoint_mlups": nodes / (ms * 1e-3) / 1e6, "adjoint_bytes_per_node": bpn,
            "adjoint_GBs": gbs, "adjoint_frac_of_8TBs": gbs / HBM_PEAK_GBS,
