@@ -15,7 +15,8 @@ Prints one JSON line. ``roofline`` prices the step kernel's algorithmic
 traffic, 2 Q b bytes per node update (Q populations of b bytes read and
 written once), against the 8 TB/s HBM peak; its ``traffic`` is the HBM
 traffic per step measured in the same run by two rocprofv3 counter passes
-over a short child run (``--traffic off`` skips them). ``others`` holds the same
+over a short child run (``--traffic off`` skips them); the adjoint legs'
+traffic comes from two more passes over a child run of those legs alone. ``others`` holds the same
 measurement for the other model/storage combinations. ``adjoint`` times the
 inlet-sensitivity gradient (128 x 128 x 256 jet, 400 steps, checkpoints
 every 20; FCLB adjoint in FP32 and FP64, MRT-LES adjoint in FP32) and the
@@ -83,19 +84,25 @@ def parse():
     p.add_argument("--traffic", choices=["auto", "off"], default="auto",
                    help="measure the step kernels' HBM traffic with rocprofv3 counter passes "
                         "over a short child run (auto: when rocprofv3 is available)")
+    p.add_argument("--only-adjoint", action="store_true",
+                   help="run only the adjoint legs and the copy probe (the adjoint counter "
+                        "passes' child run)")
     return p.parse_args()
 
 
 COPY_BYTES = 4 << 30  # the copy probe's size (copy_bandwidth)
 
 
-def _run_counter_pass(exe, counter, workload, outdir, timeout):
-    """One rocprofv3 --pmc pass over a short child run of this script;
-    returns the rows of its counter csv (or raises RuntimeError)."""
-    cmd = [exe, "--pmc", counter, "--output-format", "csv", "-d", outdir, "-o", counter.lower(),
-           "--", sys.executable, os.path.abspath(__file__), "--workload", workload, "--steps",
-           "3", "--warmup", "1", "--no-others", "--no-adjoint", "--no-cpu-baseline",
-           "--traffic", "off"]
+def _run_counter_pass(exe, counter, workload, outdir, timeout, adjoint=False):
+    """One rocprofv3 --pmc pass over a short child run of this script (the
+    workload's steps, or with adjoint the adjoint legs alone); returns the
+    rows of its counter csv (or raises RuntimeError)."""
+    what = (["--only-adjoint"] if adjoint else
+            ["--workload", workload, "--steps", "3", "--warmup", "1", "--no-adjoint"])
+    cmd = [exe, "--pmc", counter, "--output-format", "csv", "-d", outdir, "-o",
+           counter.lower() + ("_adj" if adjoint else ""), "--", sys.executable,
+           os.path.abspath(__file__)] + what + ["--no-others", "--no-cpu-baseline",
+                                               "--traffic", "off"]
     env = dict(os.environ, TMPDIR=os.environ.get("TMPDIR", "/tmp"))
     proc = subprocess.Popen(cmd, cwd="/tmp", env=env, stdout=subprocess.PIPE,
                             stderr=subprocess.STDOUT, text=True, start_new_session=True)
@@ -105,7 +112,8 @@ def _run_counter_pass(exe, counter, workload, outdir, timeout):
         os.killpg(proc.pid, signal.SIGKILL)
         proc.communicate()
         raise RuntimeError("%s pass timed out" % counter)
-    files = glob.glob(os.path.join(outdir, "**", "%s_counter_collection.csv" % counter.lower()),
+    files = glob.glob(os.path.join(outdir, "**", "%s%s_counter_collection.csv"
+                                   % (counter.lower(), "_adj" if adjoint else "")),
                       recursive=True)
     # the profiler may end with a non-zero status after the program's
     # results are complete: accept the run when the child printed its line
@@ -142,6 +150,56 @@ def _step_kernel_kib(rows):
         total += v
     steps = even + (odd[max(odd)] if odd else 0)
     return total, steps, (sum(copies) / len(copies) if copies else None)
+
+
+def _adjoint_kernel_kib(rows):
+    """Per (collision, storage) of the adjoint kernel: the counter summed
+    over its dispatches and the adjoint steps they make (the dispatches of
+    the widest launch); and the copy probe's mean value per dispatch."""
+    acc, copies = {}, []
+    for r in rows:
+        name, v = r["Kernel_Name"], float(r["Counter_Value"])
+        if "copy_kernel" in name:
+            copies.append(v)
+            continue
+        m = re.search(r"adjoint_kernel<(\d+), (float|double),", name)
+        if not m:
+            continue
+        key = ("fclb" if m.group(1) == "2" else "mrt", "f32" if m.group(2) == "float" else "f64")
+        grid = int(r.get("Grid_Size", r.get("Grid_Size_X", "0")))
+        tot, grids = acc.setdefault(key, [0.0, {}])
+        acc[key][0] = tot + v
+        grids[grid] = grids.get(grid, 0) + 1
+    out = {k: (t, g[max(g)]) for k, (t, g) in acc.items()}
+    return out, (sum(copies) / len(copies) if copies else None)
+
+
+def live_adjoint_traffic(timeout=300):
+    """HBM bytes per adjoint step of each adjoint leg, from two counter
+    passes over a child run of the adjoint legs alone, scaled like
+    live_traffic. Returns ({(collision, storage): bytes}, description) or
+    (None, reason)."""
+    exe = shutil.which("rocprofv3")
+    if exe is None:
+        return None, "rocprofv3 not available"
+    outdir = tempfile.mkdtemp(prefix="lbm_traffic_adj_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        per = {}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            print("bench: adjoint traffic pass", counter, flush=True)
+            legs, copy_kib = _adjoint_kernel_kib(
+                _run_counter_pass(exe, counter, None, outdir, timeout, adjoint=True))
+            if not legs or not copy_kib:
+                return None, "no adjoint or copy dispatches in the %s pass" % counter
+            scale = (COPY_BYTES / 1024.0) / copy_kib
+            for k, (tot, steps) in legs.items():
+                per[k] = per.get(k, 0.0) + tot * scale * 1024.0 / steps
+        return per, ("measured in this run: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over a "
+                     "child run of the adjoint legs, scaled by the copy kernel's ratios")
+    except (RuntimeError, OSError, KeyError, ValueError) as e:
+        return None, str(e)
+    finally:
+        shutil.rmtree(outdir, ignore_errors=True)
 
 
 def live_traffic(workload, timeout=300):
@@ -536,14 +594,24 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    live = (None, "off")
-    if args.traffic == "auto" and not kind_refined(args.workload):
-        live = live_traffic(args.workload)  # child runs, before this process uses the GPU
+    live, live_adj = (None, "off"), (None, "off")
+    if args.traffic == "auto" and not args.only_adjoint:
+        # child runs, before this process uses the GPU
+        if not kind_refined(args.workload):
+            live = live_traffic(args.workload)
+        if not args.no_adjoint:
+            live_adj = live_adjoint_traffic()
     import torch
     import paper_1206_0389_amd as P
     import synth
 
     torch.cuda.set_device(0)
+    if args.only_adjoint:
+        legs = [measure_adjoint(P, torch, synth, st) for st in ("f32", "f64")]
+        legs.append(measure_adjoint(P, torch, synth, "f32", model="mrt"))
+        copy_bandwidth(P, torch)
+        print(json.dumps({"metric": METRIC, "adjoint": legs}), flush=True)
+        return
     print("bench: workload", args.workload, flush=True)
     main_res = measure(args.workload, P, torch, synth, args.steps, args.warmup)
     print("bench: main done %.1f MLUPS" % main_res["mlups"], flush=True)
@@ -563,6 +631,13 @@ def main():
     if not args.no_adjoint:
         adjoint = [measure_adjoint(P, torch, synth, st) for st in ("f32", "f64")]
         adjoint.append(measure_adjoint(P, torch, synth, "f32", model="mrt"))
+        for a in adjoint:
+            key = (a["collision"], a["storage"])
+            if live_adj[0] is not None and key in live_adj[0]:
+                a["traffic"], a["traffic_source"] = live_adj[0][key], live_adj[1]
+            elif a["traffic"] is not None:
+                a["traffic_source"] = ("stored counter passes of these sources (live "
+                                       "measurement: %s)" % live_adj[1])
         print("bench: adjoint gradient %.2f s (f32)" % adjoint[0]["gradient_s"], flush=True)
     stats = measure_stats(P, torch, synth) if not args.no_others else None
     copy_gbs = copy_bandwidth(P, torch)

@@ -40,3 +40,19 @@ def test_pair_kernel_and_link_kernel_count():
             _row("lbm::copy_kernel(...)", 4096, 1.0)]
     total, steps, copy = bench._step_kernel_kib(rows)
     assert steps == 2 and total == 8.25 and copy == 1.0
+
+
+def test_adjoint_rows_are_summed_per_adjoint_step():
+    rows = []
+    for _ in range(3):  # three adjoint steps of each leg
+        rows += [_row("void lbm::adjoint_kernel<2, float, 2, 0>(...)", 4000, 6.0),
+                 _row("void lbm::adjoint_kernel<2, float, 1, 1>(...)", 30, 0.5),
+                 _row("void lbm::adjoint_kernel<0, float, 2, 0>(...)", 4000, 4.0),
+                 _row("void lbm::adjoint_kernel<2, double, 2, 0>(...)", 4000, 12.0)]
+    rows += [_row("void lbm::step_kernel<2, float, false, 1, 0, false>(...)", 4100, 9.0),
+             _row("lbm::copy_kernel(...)", 4096, 2.0)]
+    legs, copy = bench._adjoint_kernel_kib(rows)
+    assert copy == 2.0
+    assert legs[("fclb", "f32")] == (3 * 6.5, 3)
+    assert legs[("mrt", "f32")] == (12.0, 3)
+    assert legs[("fclb", "f64")] == (36.0, 3)
