@@ -174,7 +174,7 @@ def _adjoint_kernel_kib(rows):
     return out, (sum(copies) / len(copies) if copies else None)
 
 
-def live_adjoint_traffic(timeout=300):
+def live_adjoint_traffic(timeout=120):
     """HBM bytes per adjoint step of each adjoint leg, from two counter
     passes over a child run of the adjoint legs alone, scaled like
     live_traffic. Returns ({(collision, storage): bytes}, description) or
@@ -202,7 +202,7 @@ def live_adjoint_traffic(timeout=300):
         shutil.rmtree(outdir, ignore_errors=True)
 
 
-def live_traffic(workload, timeout=300):
+def live_traffic(workload, timeout=120):
     """HBM bytes per step of the workload's step kernels (and link kernel),
     from two counter passes (FETCH_SIZE, then WRITE_SIZE) over a short child
     run, each scaled by what the counter reads for the copy kernel of known
@@ -599,7 +599,8 @@ def main():
         # child runs, before this process uses the GPU
         if not kind_refined(args.workload):
             live = live_traffic(args.workload)
-        if not args.no_adjoint:
+        # a pass that timed out is not tried again (a normal pass takes seconds)
+        if not args.no_adjoint and "timed out" not in str(live[1]):
             live_adj = live_adjoint_traffic()
     import torch
     import paper_1206_0389_amd as P
